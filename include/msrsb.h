@@ -1,0 +1,247 @@
+/*
+ * msrsb.h - C ABI of the MI355X multiscale restricted-smoothing (MsRSB)
+ * pressure solver.
+ *
+ * The library solves the single-phase pressure system A p = q of a two-point
+ * flux (TPFA) discretisation on a Cartesian box, as posed in the paper's
+ * "Multiscale methods" section (eq. pressure_system), by the iterative
+ * multiscale-multibasis method of its subsection "Iterative multiscale
+ * multibasis solver" (eq. multiscale-multibasis): a sequence of
+ * prolongation/restriction pairs (P^l, R^l = (P^l)^T), each with its own
+ * smoother step and Galerkin coarse correction (eq. pressure_system_reduced).
+ * Paper: Klemetsdal, Moyner & Lie, arXiv 2001.01624.
+ *
+ * Conventions shared by every call:
+ *  - Cells are numbered in the full box, x fastest: idx = i + nx*(j + ny*k).
+ *    Inactive cells keep their index; every per-cell array has N = nx*ny*nz
+ *    entries and the library writes 0 to inactive entries of its outputs.
+ *  - "host" arrays are read during the call only and copied; the caller
+ *    keeps ownership.  "device" arrays are HIP device pointers on the
+ *    context's device; they must stay valid until the call returns (calls
+ *    are synchronous with respect to the host unless named *_async).
+ *  - Every call returns MSRSB_OK (0) or a negative status; the message of
+ *    the last failure on the calling thread is msrsb_last_error().
+ *  - A context is not thread-safe.  Distinct contexts may be used from
+ *    distinct threads at the same time, each on its own stream.
+ *  - All device work of a context runs on the stream given at setup (or the
+ *    null stream).  The library allocates its device memory with hipMalloc
+ *    at setup and when dynamic bases are added; msrsb_footprint_bytes tells
+ *    the amount in advance.
+ */
+#ifndef MSRSB_H
+#define MSRSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MSRSB_OK = 0,
+    MSRSB_E_INVAL = -1,    /* malformed input (sizes, NaN, negative T, ...) */
+    MSRSB_E_NOMEM = -2,    /* device allocation failed */
+    MSRSB_E_DEVICE = -3,   /* a HIP call failed */
+    MSRSB_E_SINGULAR = -4, /* A or a coarse operator is singular / not SPD,
+                              or a basis row sum is not positive */
+    MSRSB_E_NOCONV = -5,   /* tolerance not met within the iteration limit;
+                              the outputs hold the last iterate */
+    MSRSB_E_STATE = -6     /* call out of order (e.g. solve before basis) */
+};
+
+/* Opaque solver context; owns every device allocation of one problem. */
+typedef struct msrsb_ctx msrsb_ctx;
+
+/*
+ * Fine grid and its two-point operator (paper section "Discrete equations":
+ * two-point flux approximation; mobility 1).  The operator is
+ *   A_ii = sum of T over the faces of i + sum of bc_trans on i,
+ *   A_ij = -T_f for the face f between i and j,
+ *   b_i  = source_i + sum of bc_trans*bc_value on i.
+ * All arrays are HOST arrays.
+ */
+typedef struct {
+    int32_t nx, ny, nz;        /* box size, each >= 1 */
+    const uint8_t *active;     /* [N] 1 = active, 0 = inactive; NULL = all active */
+    const double *tx;          /* [N] T of the face between i and i+1 (x); 0 = none */
+    const double *ty;          /* [N] T of the face between i and i+nx (y) */
+    const double *tz;          /* [N] T of the face between i and i+nx*ny (z) */
+    const uint8_t *fault;      /* [3*N] fault[d*N+i] = 1 if the +d face of i lies on
+                                  a fault (used by FAULT_CUT partitions); may be NULL */
+    int32_t n_bc;              /* Dirichlet faces and bottom-hole-pressure connections */
+    const int32_t *bc_cell;    /* [n_bc] cell of each connection (active) */
+    const double *bc_trans;    /* [n_bc] >= 0 */
+    const double *bc_value;    /* [n_bc] prescribed pressure */
+    const double *source;      /* [N] injection rate q (> 0 injects); NULL = 0 */
+} msrsb_grid;
+
+/*
+ * Coarse partitions (paper "Multiscale methods": requirements 1-3 on each
+ * operator pair; "General" and "Static" partition types).
+ *   CARTESIAN: rectilinear blocks, cell i of an axis of n cells goes to block
+ *     floor(i*m/n); blocks without active cells are dropped.  Supports: per
+ *     axis, i is in S_J iff 2c_{J-1} < 2i+1 < 2c_{J+1}, 2c_J = e_J + e_{J+1},
+ *     e_J = ceil(J*n/m); the support is the product of the three axis sets,
+ *     restricted to active cells.  The first partition must be CARTESIAN.
+ *   FAULT_CUT: the connected pieces of each block of stage `parent` over the
+ *     faces not on a fault, numbered by (parent block, smallest cell); the
+ *     support of a piece is the part of its parent's support reachable from
+ *     it without crossing a fault face.
+ */
+enum { MSRSB_PART_CARTESIAN = 0, MSRSB_PART_FAULT_CUT = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t coarse_dims[3];    /* CARTESIAN: blocks per axis, 1 <= m <= n */
+    int32_t parent;            /* FAULT_CUT: index of the parent stage */
+} msrsb_partition;
+
+enum { MSRSB_SMOOTH_JACOBI = 0, MSRSB_SMOOTH_ILU0_RB = 1 };
+enum { MSRSB_FP64 = 0, MSRSB_MIXED = 1 };
+enum { MSRSB_RICHARDSON = 0, MSRSB_GMRES = 1 };
+
+typedef struct {
+    double omega;           /* basis damping, default 2/3 */
+    double omega_s;         /* Jacobi smoother damping, default 2/3 */
+    int32_t smoother;       /* MSRSB_SMOOTH_*; default JACOBI */
+    int32_t precision;      /* MSRSB_FP64 (default) or MSRSB_MIXED: FP32 basis
+                               sweeps and smoother, BF16 basis storage; residual,
+                               norms, coarse operators and coarse solves in FP64 */
+    int32_t n_bins;         /* dynamic-basis bins, default 4 */
+    int32_t max_dyn_blocks; /* cap on blocks of one dynamic stage, default 4096 */
+    int32_t outer;          /* MSRSB_RICHARDSON (default) or MSRSB_GMRES */
+    int32_t restart;        /* GMRES restart length, default 30, <= 64 */
+} msrsb_options;
+
+/* Fill *opt with the defaults listed above. */
+void msrsb_default_options(msrsb_options *opt);
+
+/* Device bytes msrsb_setup will allocate for this input (dynamic stages
+ * excluded: each adds about 12*N + 16*M^2 bytes).  Returns 0 on invalid input. */
+size_t msrsb_footprint_bytes(const msrsb_grid *grid, int n_part, const msrsb_partition *parts,
+                             const msrsb_options *opt);
+
+/*
+ * Validate the grid, assemble A and b on the device (two-point operator, see
+ * msrsb_grid), build every partition and support, and factor the smoother.
+ * hip_stream: a hipStream_t (NULL = null stream).  On success *out owns all
+ * device memory of the context.  Errors: E_INVAL (bad sizes, non-finite or
+ * negative T, a face touching an inactive cell or leaving the box, a BC on
+ * an inactive cell), E_SINGULAR (an active connected component without any
+ * bc connection), E_NOMEM, E_DEVICE.
+ */
+int msrsb_setup(const msrsb_grid *grid, int n_part, const msrsb_partition *parts,
+                const msrsb_options *opt, void *hip_stream, msrsb_ctx **out);
+
+/*
+ * Build the restricted-smoothing basis of one stage (stage >= 0) or of every
+ * general/static stage (stage = -1), then its Galerkin coarse operator
+ * A_c = P^T A P and the coarse inverse.  The basis starts from the block
+ * indicator (warm = 0) or from the current basis (warm = 1: "a few extra"
+ * smoothing iterations for local updates, subsection "Iterative multiscale
+ * multibasis solver").  Sweeps stop after the first sweep whose largest
+ * entry change is <= tol, or after max_sweeps (>= 0).  sweeps_done and
+ * last_change (may be NULL) report the last stage processed.
+ * Errors: E_INVAL, E_SINGULAR (row sum <= 0 or A_c not SPD), E_DEVICE.
+ */
+int msrsb_update_basis(msrsb_ctx *ctx, int stage, int max_sweeps, double tol, int warm,
+                       int *sweeps_done, double *last_change);
+
+/*
+ * Dynamic stages (subsection "Iterative multiscale multibasis solver", type
+ * "Dynamic"; constant basis functions).  d_dp[k] (device, [N] doubles) are
+ * pressure increments, newest first, n_incr in {1, 2}.  For each: a = |dp|,
+ * cells get bin = #{k = 1..n_bins-1 : a <= ldexp(max a, -2k)}, cells with
+ * the same (stage-0 block, bin) key that are face connected form one block,
+ * blocks are numbered by (stage-0 block, smallest cell index); if more than
+ * max_dyn_blocks result, n_bins is halved and the binning repeated.  An
+ * increment with max |dp| = 0 or non-finite adds no stage (count 0).
+ * Replaces any previous dynamic stages.  n_dyn_blocks[k] (host, may be NULL)
+ * receives the block count of each increment.
+ */
+int msrsb_add_dynamic_basis(msrsb_ctx *ctx, int n_incr, const double *const *d_dp, int *n_dyn_blocks);
+
+/* Remove all dynamic stages. */
+int msrsb_clear_dynamic_basis(msrsb_ctx *ctx);
+
+/*
+ * Solve A p = b to ||b - A p||_2 <= rtol * ||b||_2 (||b|| = 1 if b = 0).
+ * d_source: device [N] new source vector (b is rebuilt) or NULL to keep.
+ * d_p: device [N], initial guess in, solution out.
+ * outer = RICHARDSON: cycles of eq. multiscale-multibasis, stages in the
+ * order general, static, dynamic (newest first); each stage applies the
+ * smoother once to b - A x and then x += P A_c^{-1} P^T (b - A x); the test
+ * runs after every full cycle.  outer = GMRES: restarted GMRES with one such
+ * cycle (from a zero guess) as right preconditioner (section "Description of
+ * the solution procedure").  max_iters bounds cycles / GMRES iterations.
+ * iters, relres (host, may be NULL): iterations used and final relative
+ * residual (FP64, recomputed from the final iterate for Richardson; the
+ * least-squares estimate for GMRES).  Returns E_NOCONV with the last
+ * iterate in d_p if the limit is reached; E_STATE before update_basis.
+ */
+int msrsb_solve(msrsb_ctx *ctx, const double *d_source, double *d_p, double rtol, int max_iters,
+                int *iters, double *relres);
+
+/*
+ * Apply one operator of the path to a device vector (for testing single
+ * steps; d_in, d_out device [N], distinct):
+ *   op 0 RESIDUAL:  d_out = b - A d_in
+ *   op 1 SMOOTH:    d_out = S(d_in), the smoother correction for residual d_in
+ *   op 2 PRECOND:   d_out = one multistage cycle from zero with rhs d_in
+ *   op 3 MATVEC:    d_out = A d_in
+ */
+enum { MSRSB_OP_RESIDUAL = 0, MSRSB_OP_SMOOTH = 1, MSRSB_OP_PRECOND = 2, MSRSB_OP_MATVEC = 3 };
+int msrsb_apply(msrsb_ctx *ctx, int op, const double *d_in, double *d_out);
+
+/*
+ * Face fluxes v_f = T_f (p_a - p_b) in the structured layout
+ * d_face_flux[d*N + i] (face between i and its +d neighbour) and
+ * connection fluxes d_bc_flux[c] = bc_trans[c] (p_i - bc_value[c]) (device
+ * arrays; either may be NULL).  Per-cell balance: outflow - q = -(b - A p).
+ */
+int msrsb_fluxes(msrsb_ctx *ctx, const double *d_p, double *d_face_flux, double *d_bc_flux);
+
+/* Number of stages (general + static + dynamic) and, for one stage, its
+ * block count M, its kind (0 general, 2 fault cut, 3 dynamic) and the
+ * number of basis slots per cell. */
+int msrsb_num_stages(msrsb_ctx *ctx);
+int msrsb_stage_info(msrsb_ctx *ctx, int stage, int *M, int *kind, int *n_slots);
+
+/*
+ * Copy one stage to host arrays (tests and inspection):
+ *   h_block [N]           block of each cell (-1 inactive)
+ *   h_slot_block [S*N]    block held by slot s of cell i (-1 none), slot-major
+ *   h_vals [S*N]          basis value of that slot, in FP64 (BF16 upcast)
+ *   h_Ac [M*M]            Galerkin coarse operator, row-major
+ * (S = n_slots; any pointer may be NULL).
+ */
+int msrsb_export_stage(msrsb_ctx *ctx, int stage, int32_t *h_block, int32_t *h_slot_block, double *h_vals,
+                       double *h_Ac);
+
+/*
+ * Host-only helpers (no device needed):
+ * msrsb_validate_grid: the checks msrsb_setup applies to a grid (E_INVAL,
+ *   E_SINGULAR as documented there).
+ * msrsb_axis_support: 1-D support tables of a rectilinear partition of n
+ *   cells into m blocks (paper requirement 2; rule of msrsb_partition):
+ *   lo[i] (host [n]) first block whose support holds cell i, nv[i] in {1,2}
+ *   number of consecutive blocks from lo[i] whose supports hold it,
+ *   slo[J], shi[J] (host [m]) first and last cell of the support of block J.
+ *   Any pointer may be NULL.  E_INVAL unless 1 <= m <= n.
+ */
+int msrsb_validate_grid(const msrsb_grid *grid);
+int msrsb_axis_support(int n, int m, int32_t *lo, int32_t *nv, int32_t *slo, int32_t *shi);
+
+/* Change the stream used by later calls (hipStream_t). */
+int msrsb_set_stream(msrsb_ctx *ctx, void *hip_stream);
+
+/* Free all device memory of the context (NULL is ignored). */
+void msrsb_destroy(msrsb_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *msrsb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSRSB_H */

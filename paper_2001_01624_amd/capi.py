@@ -1,0 +1,287 @@
+"""ctypes binding of ``libmsrsb.so`` (declared in ``include/msrsb.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (the tensors passed to ``solve``, ``apply``,
+``fluxes`` and ``add_dynamic_basis``) and the stream.  Importing this module
+raises if the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsrsb.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
+PART_CARTESIAN, PART_FAULT_CUT = 0, 2
+SMOOTH_JACOBI, SMOOTH_ILU0_RB = 0, 1
+FP64, MIXED = 0, 1
+RICHARDSON, GMRES = 0, 1
+OP_RESIDUAL, OP_SMOOTH, OP_PRECOND, OP_MATVEC = 0, 1, 2, 3
+_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_SINGULAR", -5: "E_NOCONV", -6: "E_STATE"}
+
+
+class MsrsbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("active", C.POINTER(C.c_uint8)),
+                ("tx", C.POINTER(C.c_double)), ("ty", C.POINTER(C.c_double)), ("tz", C.POINTER(C.c_double)),
+                ("fault", C.POINTER(C.c_uint8)),
+                ("n_bc", C.c_int32), ("bc_cell", C.POINTER(C.c_int32)),
+                ("bc_trans", C.POINTER(C.c_double)), ("bc_value", C.POINTER(C.c_double)),
+                ("source", C.POINTER(C.c_double))]
+
+
+class Partition(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("coarse_dims", C.c_int32 * 3), ("parent", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("omega", C.c_double), ("omega_s", C.c_double), ("smoother", C.c_int32),
+                ("precision", C.c_int32), ("n_bins", C.c_int32), ("max_dyn_blocks", C.c_int32),
+                ("outer", C.c_int32), ("restart", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2001_01624_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, VP = C.POINTER, C.c_int, C.c_double, C.c_void_p
+    sig = {
+        "msrsb_last_error": (C.c_char_p, []),
+        "msrsb_default_options": (None, [P(Options)]),
+        "msrsb_footprint_bytes": (C.c_size_t, [P(Grid), I, P(Partition), P(Options)]),
+        "msrsb_setup": (I, [P(Grid), I, P(Partition), P(Options), VP, P(VP)]),
+        "msrsb_update_basis": (I, [VP, I, I, D, I, P(I), P(D)]),
+        "msrsb_add_dynamic_basis": (I, [VP, I, P(VP), P(I)]),
+        "msrsb_clear_dynamic_basis": (I, [VP]),
+        "msrsb_solve": (I, [VP, VP, VP, D, I, P(I), P(D)]),
+        "msrsb_apply": (I, [VP, I, VP, VP]),
+        "msrsb_fluxes": (I, [VP, VP, VP, VP]),
+        "msrsb_num_stages": (I, [VP]),
+        "msrsb_stage_info": (I, [VP, I, P(I), P(I), P(I)]),
+        "msrsb_export_stage": (I, [VP, I, P(C.c_int32), P(C.c_int32), P(D), P(D)]),
+        "msrsb_set_stream": (I, [VP, VP]),
+        "msrsb_destroy": (None, [VP]),
+        "msrsb_validate_grid": (I, [P(Grid)]),
+        "msrsb_axis_support": (I, [I, I, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib, list(sig)
+
+
+_lib, EXPORTED = _load()
+
+
+def last_error() -> str:
+    return (_lib.msrsb_last_error() or b"").decode()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise MsrsbError(rc, last_error())
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _lib.msrsb_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "smoother" and isinstance(v, str):
+            v = {"jacobi": SMOOTH_JACOBI, "ilu0_rb": SMOOTH_ILU0_RB}[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": FP64, "mixed": MIXED}[v]
+        if k == "outer" and isinstance(v, str):
+            v = {"richardson": RICHARDSON, "gmres": GMRES}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+class _GridArrays:
+    """Keeps the numpy arrays alive while the C struct points into them."""
+
+    def __init__(self, prob):
+        nx, ny, nz = prob.dims
+        self.active = np.ascontiguousarray(prob.active, dtype=np.uint8)
+        self.tx = np.ascontiguousarray(prob.tx, dtype=np.float64)
+        self.ty = np.ascontiguousarray(prob.ty, dtype=np.float64)
+        self.tz = np.ascontiguousarray(prob.tz, dtype=np.float64)
+        fault = getattr(prob, "fault", None)
+        self.fault = None if fault is None else np.ascontiguousarray(fault, dtype=np.uint8).reshape(-1)
+        self.bc_cell = np.ascontiguousarray(prob.bc_cell, dtype=np.int32)
+        self.bc_trans = np.ascontiguousarray(prob.bc_trans, dtype=np.float64)
+        self.bc_value = np.ascontiguousarray(prob.bc_value, dtype=np.float64)
+        self.source = np.ascontiguousarray(prob.source, dtype=np.float64)
+        g = Grid()
+        g.nx, g.ny, g.nz = int(nx), int(ny), int(nz)
+        g.active = _ptr(self.active, C.c_uint8)
+        g.tx, g.ty, g.tz = _ptr(self.tx, C.c_double), _ptr(self.ty, C.c_double), _ptr(self.tz, C.c_double)
+        g.fault = _ptr(self.fault, C.c_uint8)
+        g.n_bc = int(self.bc_cell.size)
+        g.bc_cell = _ptr(self.bc_cell, C.c_int32)
+        g.bc_trans = _ptr(self.bc_trans, C.c_double)
+        g.bc_value = _ptr(self.bc_value, C.c_double)
+        g.source = _ptr(self.source, C.c_double)
+        self.grid = g
+
+
+def _parts(partitions):
+    arr = (Partition * len(partitions))()
+    for k, p in enumerate(partitions):
+        kind = p.get("kind", "cartesian")
+        arr[k].kind = {"cartesian": PART_CARTESIAN, "fault_cut": PART_FAULT_CUT}.get(kind, kind)
+        cd = p.get("coarse_dims", (1, 1, 1))
+        arr[k].coarse_dims[0], arr[k].coarse_dims[1], arr[k].coarse_dims[2] = (int(x) for x in cd)
+        arr[k].parent = int(p.get("parent", 0))
+    return arr
+
+
+def validate_grid(prob) -> int:
+    ga = _GridArrays(prob)
+    return _lib.msrsb_validate_grid(C.byref(ga.grid))
+
+
+def axis_support(n: int, m: int):
+    lo = np.zeros(n, np.int32)
+    nv = np.zeros(n, np.int32)
+    slo = np.zeros(m, np.int32)
+    shi = np.zeros(m, np.int32)
+    _check(_lib.msrsb_axis_support(n, m, _ptr(lo, C.c_int32), _ptr(nv, C.c_int32), _ptr(slo, C.c_int32),
+                                   _ptr(shi, C.c_int32)))
+    return lo, nv, slo, shi
+
+
+def footprint_bytes(prob, partitions, options=None) -> int:
+    ga = _GridArrays(prob)
+    parts = _parts(partitions)
+    o = options if options is not None else default_options()
+    return int(_lib.msrsb_footprint_bytes(C.byref(ga.grid), len(partitions), parts, C.byref(o)))
+
+
+def _dptr(t, dtype="float64"):
+    import torch
+
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == f"torch.{dtype}"):
+        raise MsrsbError(E_INVAL, f"expected a contiguous {dtype} device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One problem on the device (``msrsb_setup`` ... ``msrsb_destroy``)."""
+
+    def __init__(self, prob, partitions, options=None, stream=None):
+        import torch
+
+        self.prob_dims = tuple(prob.dims)
+        self.N = int(np.prod(prob.dims))
+        self.n_bc = int(np.asarray(prob.bc_cell).size)
+        self.options = options if options is not None else default_options()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ga = _GridArrays(prob)
+        parts = _parts(partitions)
+        h = C.c_void_p()
+        _check(_lib.msrsb_setup(C.byref(ga.grid), len(partitions), parts, C.byref(self.options),
+                                C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.msrsb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_basis(self, stage=-1, max_sweeps=100, tol=1e-3, warm=False):
+        sw = C.c_int(0)
+        ch = C.c_double(0.0)
+        _check(_lib.msrsb_update_basis(self.h, stage, max_sweeps, tol, int(warm), C.byref(sw), C.byref(ch)))
+        return sw.value, ch.value
+
+    def add_dynamic_basis(self, increments):
+        ptrs = (C.c_void_p * len(increments))(*[_dptr(t).value for t in increments])
+        counts = (C.c_int * len(increments))()
+        _check(_lib.msrsb_add_dynamic_basis(self.h, len(increments), ptrs, counts))
+        return list(counts)
+
+    def clear_dynamic_basis(self):
+        _check(_lib.msrsb_clear_dynamic_basis(self.h))
+
+    def solve(self, p, source=None, rtol=1e-6, max_iters=500):
+        """Solve in place on the device tensor ``p``; returns (iters, relres, status)."""
+        it = C.c_int(0)
+        rel = C.c_double(0.0)
+        rc = _check(_lib.msrsb_solve(self.h, _dptr(source), _dptr(p), rtol, max_iters, C.byref(it), C.byref(rel)),
+                    allow=(E_NOCONV,))
+        return it.value, rel.value, rc
+
+    def apply(self, op, x, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(_lib.msrsb_apply(self.h, op, _dptr(x), _dptr(out)))
+        return out
+
+    def fluxes(self, p):
+        import torch
+
+        face = torch.empty(3 * self.N, dtype=torch.float64, device=p.device)
+        bcf = torch.empty(max(self.n_bc, 1), dtype=torch.float64, device=p.device)
+        _check(_lib.msrsb_fluxes(self.h, _dptr(p), _dptr(face), _dptr(bcf)))
+        return face.view(3, self.N), bcf[: self.n_bc]
+
+    def num_stages(self):
+        return _lib.msrsb_num_stages(self.h)
+
+    def stage_info(self, k):
+        M, kind, ns = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.msrsb_stage_info(self.h, k, C.byref(M), C.byref(kind), C.byref(ns)))
+        return M.value, kind.value, ns.value
+
+    def export_stage(self, k, values=True, coarse=True):
+        M, kind, ns = self.stage_info(k)
+        block = np.zeros(self.N, np.int32)
+        slots = np.zeros(ns * self.N, np.int32)
+        vals = np.zeros(ns * self.N) if values else None
+        Ac = np.zeros(M * M) if coarse else None
+        _check(_lib.msrsb_export_stage(self.h, k, _ptr(block, C.c_int32), _ptr(slots, C.c_int32),
+                                       _ptr(vals, C.c_double), _ptr(Ac, C.c_double)))
+        out = {"M": M, "kind": kind, "n_slots": ns, "block": block, "slot_block": slots.reshape(ns, self.N)}
+        if values:
+            out["values"] = vals.reshape(ns, self.N)
+        if coarse:
+            out["Ac"] = Ac.reshape(M, M)
+        return out
+
+    def dense_basis(self, k):
+        """``N x M`` dense basis of stage k (tests / inspection)."""
+        e = self.export_stage(k, coarse=False)
+        P = np.zeros((self.N, e["M"]))
+        for s in range(e["n_slots"]):
+            blk = e["slot_block"][s]
+            m = blk >= 0
+            P[np.nonzero(m)[0], blk[m]] += e["values"][s][m]
+        return P

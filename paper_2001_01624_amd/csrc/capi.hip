@@ -1,0 +1,899 @@
+// Host side of the library: input validation, setup of the rectilinear
+// partitions (integer tables, built once on the host and uploaded), the
+// solver drivers and every extern "C" entry point of msrsb.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "dev_util.h"
+#include "msrsb_internal.h"
+
+namespace msrsb {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? MSRSB_E_NOMEM : MSRSB_E_DEVICE;
+}
+
+void *ctx_alloc(Ctx &c, size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        set_error("hipMalloc of %zu bytes failed", bytes);
+        return nullptr;
+    }
+    c.allocs.push_back(p);
+    return p;
+}
+
+// ------------------------------------------------------------ validation ----
+
+struct DSU {
+    std::vector<int> p;
+    explicit DSU(int n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+    int find(int a) {
+        while (p[a] != a) a = p[a] = p[p[a]];
+        return a;
+    }
+    void unite(int a, int b) {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+static int validate(const msrsb_grid *g) {
+    if (!g) {
+        set_error("grid is NULL");
+        return MSRSB_E_INVAL;
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || (long)g->nx * g->ny * g->nz > 0x7fffffffL / 8) {
+        set_error("bad grid dimensions %d x %d x %d", g->nx, g->ny, g->nz);
+        return MSRSB_E_INVAL;
+    }
+    if (!g->tx || !g->ty || !g->tz) {
+        set_error("tx/ty/tz must be given");
+        return MSRSB_E_INVAL;
+    }
+    const int nx = g->nx, ny = g->ny, nz = g->nz, N = nx * ny * nz, nxy = nx * ny;
+    auto act = [&](int i) { return g->active ? g->active[i] != 0 : true; };
+    const double *T[3] = {g->tx, g->ty, g->tz};
+    const int step[3] = {1, nx, nxy};
+    for (int i = 0; i < N; ++i) {
+        const int c[3] = {i % nx, (i / nx) % ny, i / nxy};
+        const int n[3] = {nx, ny, nz};
+        for (int a = 0; a < 3; ++a) {
+            const double t = T[a][i];
+            if (!(t >= 0.0) || !std::isfinite(t)) {
+                set_error("transmissibility %c[%d] = %g is negative or not finite", "xyz"[a], i, t);
+                return MSRSB_E_INVAL;
+            }
+            if (t != 0.0) {
+                if (c[a] == n[a] - 1) {
+                    set_error("face %c[%d] leaves the grid", "xyz"[a], i);
+                    return MSRSB_E_INVAL;
+                }
+                if (!act(i) || !act(i + step[a])) {
+                    set_error("face %c[%d] touches an inactive cell", "xyz"[a], i);
+                    return MSRSB_E_INVAL;
+                }
+            }
+        }
+        if (g->source && !std::isfinite(g->source[i])) {
+            set_error("source[%d] not finite", i);
+            return MSRSB_E_INVAL;
+        }
+    }
+    if (g->n_bc < 0 || (g->n_bc > 0 && (!g->bc_cell || !g->bc_trans || !g->bc_value))) {
+        set_error("bad boundary-connection arrays");
+        return MSRSB_E_INVAL;
+    }
+    for (int k = 0; k < g->n_bc; ++k) {
+        const int i = g->bc_cell[k];
+        if (i < 0 || i >= N || !act(i)) {
+            set_error("boundary connection %d on a missing or inactive cell %d", k, i);
+            return MSRSB_E_INVAL;
+        }
+        if (!(g->bc_trans[k] >= 0.0) || !std::isfinite(g->bc_trans[k]) || !std::isfinite(g->bc_value[k])) {
+            set_error("boundary connection %d: transmissibility/value negative or not finite", k);
+            return MSRSB_E_INVAL;
+        }
+    }
+    // every active connected component needs a boundary/well connection
+    DSU d(N);
+    for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < N; ++i)
+            if (T[a][i] != 0.0) d.unite(i, i + step[a]);
+    std::vector<char> anchored(N, 0);
+    for (int k = 0; k < g->n_bc; ++k)
+        if (g->bc_trans[k] > 0.0) anchored[d.find(g->bc_cell[k])] = 1;
+    for (int i = 0; i < N; ++i)
+        if (act(i) && !anchored[d.find(i)]) {
+            set_error("active cell %d lies in a connected component without boundary or well connection", i);
+            return MSRSB_E_SINGULAR;
+        }
+    return MSRSB_OK;
+}
+
+// Per-axis tables of a rectilinear partition (see CartDev).
+static void axis_tables(int n, int m, std::vector<int32_t> &lo, std::vector<int32_t> &nv, std::vector<int32_t> &slo,
+                        std::vector<int32_t> &shi, std::vector<int32_t> &be) {
+    be.resize(m + 1);
+    for (int J = 0; J <= m; ++J) be[J] = (int32_t)(((long)J * n + m - 1) / m);  // ceil(J n / m)
+    std::vector<long> c2(m);
+    for (int J = 0; J < m; ++J) c2[J] = (long)be[J] + be[J + 1];
+    lo.assign(n, 0);
+    nv.assign(n, 1);
+    slo.assign(m, n);
+    shi.assign(m, -1);
+    for (int i = 0; i < n; ++i) {
+        const int blk = (int)(((long)i * m) / n);
+        const long t = 2L * i + 1;
+        if (blk > 0 && t < c2[blk]) {
+            lo[i] = blk - 1;
+            nv[i] = 2;
+        } else if (blk < m - 1 && t > c2[blk]) {
+            lo[i] = blk;
+            nv[i] = 2;
+        } else {
+            lo[i] = blk;
+            nv[i] = 1;
+        }
+        for (int J = lo[i]; J < lo[i] + nv[i]; ++J) {
+            slo[J] = std::min(slo[J], i);
+            shi[J] = std::max(shi[J], i);
+        }
+    }
+}
+
+static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
+    const int n[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a)
+        if (p.coarse_dims[a] < 1 || p.coarse_dims[a] > n[a]) {
+            set_error("coarse_dims[%d] = %d outside [1, %d]", a, p.coarse_dims[a], n[a]);
+            return MSRSB_E_INVAL;
+        }
+    s.kind = 0;
+    CartDev &cd = s.cart;
+    int nbits = 0;
+    for (int a = 0; a < 3; ++a) {
+        cd.n[a] = n[a];
+        cd.m[a] = p.coarse_dims[a];
+        cd.bit[a] = cd.m[a] > 1 ? nbits++ : -1;
+    }
+    cd.ns = s.ns = 1 << nbits;
+    std::vector<int32_t> tab;
+    for (int a = 0; a < 3; ++a) {
+        std::vector<int32_t> lo, nv, slo, shi, be;
+        axis_tables(n[a], cd.m[a], lo, nv, slo, shi, be);
+        s.tab_off[a][0] = (int)tab.size(); tab.insert(tab.end(), lo.begin(), lo.end());
+        s.tab_off[a][1] = (int)tab.size(); tab.insert(tab.end(), nv.begin(), nv.end());
+        s.tab_off[a][2] = (int)tab.size(); tab.insert(tab.end(), slo.begin(), slo.end());
+        s.tab_off[a][3] = (int)tab.size(); tab.insert(tab.end(), shi.begin(), shi.end());
+        s.tab_off[a][4] = (int)tab.size(); tab.insert(tab.end(), be.begin(), be.end());
+    }
+    // blocks with active cells, compacted in Cartesian order; active cells per block
+    const int M0 = cd.m[0] * cd.m[1] * cd.m[2];
+    std::vector<int64_t> cnt(M0, 0);
+    for (int i = 0; i < c.N; ++i) {
+        if (!c.h_active[i]) continue;
+        const int cx = i % c.nx, cy = (i / c.nx) % c.ny, cz = i / (c.nx * c.ny);
+        const int J = (int)((long)cx * cd.m[0] / c.nx) + cd.m[0] * ((int)((long)cy * cd.m[1] / c.ny) +
+                                                                    cd.m[1] * (int)((long)cz * cd.m[2] / c.nz));
+        cnt[J]++;
+    }
+    const int cmap_off = (int)tab.size();
+    s.h_present.clear();
+    for (int J = 0; J < M0; ++J) {
+        tab.push_back(cnt[J] > 0 ? (int32_t)s.h_present.size() : -1);
+        if (cnt[J] > 0) s.h_present.push_back(J);
+    }
+    const int pres_off = (int)tab.size();
+    tab.insert(tab.end(), s.h_present.begin(), s.h_present.end());
+    const int gbase_off = (int)tab.size();
+    int64_t run = 0;
+    for (int J = 0; J < M0; ++J) {
+        tab.push_back((int32_t)run);
+        run += cnt[J];
+    }
+    tab.push_back((int32_t)run);
+    s.M = (int)s.h_present.size();
+    s.Mp = cdiv(s.M, kTile) * kTile;
+    s.h_tab = tab;
+    s.d_tab = (int32_t *)ctx_alloc(c, sizeof(int32_t) * tab.size());
+    if (!s.d_tab) return MSRSB_E_NOMEM;
+    if (hipMemcpy(s.d_tab, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return hip_fail(hipGetLastError(), "upload tables");
+    for (int a = 0; a < 3; ++a) {
+        cd.lo[a] = s.d_tab + s.tab_off[a][0];
+        cd.nv[a] = s.d_tab + s.tab_off[a][1];
+        cd.slo[a] = s.d_tab + s.tab_off[a][2];
+        cd.shi[a] = s.d_tab + s.tab_off[a][3];
+        cd.be[a] = s.d_tab + s.tab_off[a][4];
+    }
+    cd.cmap = s.d_tab + cmap_off;
+    cd.present = s.d_tab + pres_off;
+    s.gbase = s.d_tab + gbase_off;
+    const size_t nsN = (size_t)s.ns * c.N;
+    if (c.opt.precision == MSRSB_MIXED) {
+        s.P32[0] = (float *)ctx_alloc(c, sizeof(float) * nsN);
+        s.P32[1] = (float *)ctx_alloc(c, sizeof(float) * nsN);
+        s.Pbf = (uint16_t *)ctx_alloc(c, sizeof(uint16_t) * nsN);
+        if (!s.P32[0] || !s.P32[1] || !s.Pbf) return MSRSB_E_NOMEM;
+    } else {
+        s.P64[0] = (double *)ctx_alloc(c, sizeof(double) * nsN);
+        s.P64[1] = (double *)ctx_alloc(c, sizeof(double) * nsN);
+        if (!s.P64[0] || !s.P64[1]) return MSRSB_E_NOMEM;
+    }
+    s.Ac = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    s.Ainv = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    s.dvec = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
+    s.pc = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
+    if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
+    return MSRSB_OK;
+}
+
+static size_t cart_bytes(const Ctx &c, const msrsb_partition &p) {
+    int nbits = 0;
+    long M = 1;
+    for (int a = 0; a < 3; ++a) {
+        nbits += p.coarse_dims[a] > 1;
+        M *= p.coarse_dims[a];
+    }
+    const long Mp = cdiv(M, kTile) * kTile;
+    const size_t nsN = ((size_t)1 << nbits) * c.N;
+    size_t b = (c.opt.precision == MSRSB_MIXED) ? nsN * 10 : nsN * 16;
+    b += 16 * (size_t)Mp * Mp + 16 * Mp + 4 * (size_t)(c.nx + c.ny + c.nz) * 5 + 12 * (size_t)M;
+    return b;
+}
+
+// ---------------------------------------------------------- solve driver ----
+
+__global__ void k_reset(Status *st, int *flag) {
+    st->done = 0;
+    st->iters = 0;
+    st->flag = 0;
+    st->jcur = 0;
+    st->relres = 0.0;
+    *flag = 0;
+}
+
+__global__ void k_set_bnorm(Status *st, const double *sq) {
+    const double n = sqrt(*sq);
+    st->bnorm = n > 0.0 ? n : 1.0;
+}
+
+__global__ void k_zero(int N, double *__restrict__ x, const int *done) {
+    if (done && *done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) x[i] = 0.0;
+}
+
+static void zero_vec(Ctx &c, double *x, const int *done) {
+    hipLaunchKernelGGL(k_zero, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, x, done);
+}
+
+static std::vector<Stage *> cycle_stages(Ctx &c) {
+    std::vector<Stage *> v;
+    for (auto &s : c.stages) v.push_back(&s);
+    for (auto &s : c.dyn)
+        if (s.M > 0) v.push_back(&s);
+    return v;
+}
+
+// One cycle of eq. multiscale-multibasis on (b, x).  If r_valid, c.r already
+// holds b - A x on entry.
+static void cycle(Ctx &c, const double *b, double *x, bool r_valid, const int *done) {
+    auto st = cycle_stages(c);
+    for (size_t k = 0; k < st.size(); ++k) {
+        Stage &s = *st[k];
+        if (!(k == 0 && r_valid)) launch_residual(c, b, x, c.r, false, done);
+        launch_smooth(c, c.r, x, done);
+        launch_residual(c, b, x, c.r, false, done);
+        if (s.kind == 3) launch_dyn_restrict(c, s, c.r, done);
+        else launch_restrict(c, s, c.r, done);
+        launch_coarse_solve(c, s, done);
+        if (s.kind == 3) launch_dyn_prolong(c, s, x, done);
+        else launch_prolong(c, s, x, done);
+    }
+}
+
+static int read_status(Ctx &c) {
+    hipError_t e = hipMemcpyAsync(c.h_status, c.status, sizeof(Status), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return hip_fail(e, "status read");
+    return MSRSB_OK;
+}
+
+static void begin_solve(Ctx &c, const double *b, double *x) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, c.stream, c.status, c.flag);
+    launch_zero_inactive(c, x);
+    launch_multidot(c, b, 1, b, c.scal + 1, nullptr);  // ||b||^2 (b is 0 on inactive cells)
+    hipLaunchKernelGGL(k_set_bnorm, dim3(1), dim3(1), 0, c.stream, c.status, c.scal + 1);
+}
+
+static int solve_richardson(Ctx &c, const double *b, double *x, double rtol, int max_iters) {
+    launch_residual(c, b, x, c.r, true, nullptr);
+    launch_norm_finish(c, c.scal, nullptr);
+    launch_check(c, rtol, max_iters, 0);
+    int chunk = 2;
+    int rc;
+    for (;;) {
+        if ((rc = read_status(c))) return rc;
+        if (c.h_status->done) break;
+        for (int k = 0; k < chunk; ++k) {
+            const int *done = &c.status->done;
+            cycle(c, b, x, true, done);
+            launch_residual(c, b, x, c.r, true, done);
+            launch_norm_finish(c, c.scal, done);
+            launch_check(c, rtol, max_iters, 1);
+        }
+        chunk = std::min(chunk * 2, 16);
+    }
+    return MSRSB_OK;
+}
+
+static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_iters) {
+    const int m = std::max(1, std::min(c.opt.restart, kMaxRestart));
+    const long N = c.N;
+    double *w = c.tmp;
+    int rc;
+    for (;;) {
+        // restart: true residual of the current iterate
+        launch_residual(c, b, x, c.r, true, nullptr);
+        launch_norm_finish(c, c.scal, nullptr);
+        launch_gmres_begin(c, rtol, max_iters);
+        if ((rc = read_status(c))) return rc;
+        if (c.h_status->done) break;
+        launch_gmres_start(c, c.r, c.V, m);
+        int j = 0;
+        int chunk = 4;
+        while (j < m) {
+            const int jend = std::min(m, j + chunk);
+            for (; j < jend; ++j) {
+                const int *done = &c.status->done;
+                double *vj = c.V + (long)j * N;
+                zero_vec(c, c.z, done);
+                cycle(c, vj, c.z, false, done);
+                launch_matvec(c, c.z, w, false, done);
+                launch_multidot(c, c.V, j + 1, w, c.scal + 8, done);
+                launch_multiaxpy(c, c.V, j + 1, c.scal + 8, w, -1.0, false, done);
+                launch_multidot(c, c.V, j + 1, w, c.scal + 80, done);
+                launch_multiaxpy(c, c.V, j + 1, c.scal + 80, w, -1.0, true, done);
+                launch_norm_finish(c, c.scal, done);
+                launch_gmres_step(c, j, rtol, max_iters, m);
+                launch_gmres_scale(c, w, c.V + (long)(j + 1) * N, j);
+            }
+            if ((rc = read_status(c))) return rc;
+            if (c.h_status->done) break;
+            chunk = std::min(chunk * 2, 16);
+        }
+        // x += M^{-1} V y
+        const int k = c.h_status->jcur;
+        if (k > 0) {
+            launch_gmres_solve_small(c, m);
+            zero_vec(c, c.u, nullptr);
+            launch_multiaxpy(c, c.V, k, c.scal + 4608, c.u, 1.0, false, nullptr);
+            zero_vec(c, c.z, nullptr);
+            cycle(c, c.u, c.z, false, nullptr);
+            launch_axpy(c, x, c.z, nullptr);
+        }
+    }
+    return MSRSB_OK;
+}
+
+}  // namespace msrsb
+
+using namespace msrsb;
+
+struct msrsb_ctx : public Ctx {};
+
+extern "C" {
+
+const char *msrsb_last_error(void) { return g_err.c_str(); }
+
+void msrsb_default_options(msrsb_options *o) {
+    if (!o) return;
+    o->omega = 2.0 / 3.0;
+    o->omega_s = 2.0 / 3.0;
+    o->smoother = MSRSB_SMOOTH_JACOBI;
+    o->precision = MSRSB_FP64;
+    o->n_bins = 4;
+    o->max_dyn_blocks = 4096;
+    o->outer = MSRSB_RICHARDSON;
+    o->restart = 30;
+}
+
+static int check_options(const msrsb_options *o) {
+    if (!(o->omega > 0.0 && o->omega < 2.0) || !(o->omega_s > 0.0 && o->omega_s < 2.0)) {
+        set_error("omega and omega_s must lie in (0, 2)");
+        return MSRSB_E_INVAL;
+    }
+    if (o->smoother != MSRSB_SMOOTH_JACOBI && o->smoother != MSRSB_SMOOTH_ILU0_RB) {
+        set_error("unknown smoother %d", o->smoother);
+        return MSRSB_E_INVAL;
+    }
+    if (o->precision != MSRSB_FP64 && o->precision != MSRSB_MIXED) {
+        set_error("unknown precision %d", o->precision);
+        return MSRSB_E_INVAL;
+    }
+    if (o->n_bins < 1 || o->n_bins > 8 || o->max_dyn_blocks < 1) {
+        set_error("n_bins must lie in [1, 8] and max_dyn_blocks >= 1");
+        return MSRSB_E_INVAL;
+    }
+    if (o->outer != MSRSB_RICHARDSON && o->outer != MSRSB_GMRES) {
+        set_error("unknown outer solver %d", o->outer);
+        return MSRSB_E_INVAL;
+    }
+    if (o->restart < 1 || o->restart > kMaxRestart) {
+        set_error("restart must lie in [1, %d]", kMaxRestart);
+        return MSRSB_E_INVAL;
+    }
+    return MSRSB_OK;
+}
+
+static int check_parts(const msrsb_grid *g, int n_part, const msrsb_partition *parts) {
+    if (n_part < 1 || !parts || parts[0].kind != MSRSB_PART_CARTESIAN) {
+        set_error("at least one partition is needed and the first must be CARTESIAN");
+        return MSRSB_E_INVAL;
+    }
+    for (int k = 0; k < n_part; ++k) {
+        if (parts[k].kind != MSRSB_PART_CARTESIAN) {
+            set_error("partition %d: only CARTESIAN partitions are supported by this build", k);
+            return MSRSB_E_INVAL;
+        }
+        const int n[3] = {g->nx, g->ny, g->nz};
+        for (int a = 0; a < 3; ++a)
+            if (parts[k].coarse_dims[a] < 1 || parts[k].coarse_dims[a] > n[a]) {
+                set_error("partition %d: coarse_dims[%d] = %d outside [1, %d]", k, a, parts[k].coarse_dims[a], n[a]);
+                return MSRSB_E_INVAL;
+            }
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_validate_grid(const msrsb_grid *grid) {
+    g_err.clear();
+    return validate(grid);
+}
+
+int msrsb_axis_support(int n, int m, int32_t *lo, int32_t *nv, int32_t *slo, int32_t *shi) {
+    if (n < 1 || m < 1 || m > n) {
+        set_error("need 1 <= m <= n");
+        return MSRSB_E_INVAL;
+    }
+    std::vector<int32_t> a, b, c, d, e;
+    axis_tables(n, m, a, b, c, d, e);
+    if (lo) memcpy(lo, a.data(), sizeof(int32_t) * n);
+    if (nv) memcpy(nv, b.data(), sizeof(int32_t) * n);
+    if (slo) memcpy(slo, c.data(), sizeof(int32_t) * m);
+    if (shi) memcpy(shi, d.data(), sizeof(int32_t) * m);
+    return MSRSB_OK;
+}
+
+size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partition *parts, const msrsb_options *opt) {
+    msrsb_options o;
+    if (opt) o = *opt;
+    else msrsb_default_options(&o);
+    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || check_options(&o) || check_parts(g, n_part, parts)) return 0;
+    Ctx c;
+    c.opt = o;
+    c.nx = g->nx; c.ny = g->ny; c.nz = g->nz;
+    c.N = g->nx * g->ny * g->nz;
+    const size_t N = c.N;
+    size_t b = N * 8 * 3 + N * 4 * 3 + N * 8 * 6 + N * 4 * 2;  // T, T32, diag/b/src/bcdiag/bcrhs/dtil, f32 copies
+    b += N * 8 * 5;                                          // work vectors
+    b += (size_t)kRedBlocks * (kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
+    if (o.outer == MSRSB_GMRES) b += (size_t)(o.restart + 1) * N * 8;
+    b += (size_t)g->n_bc * 24;
+    long cb = 0;
+    for (int k = 0; k < n_part; ++k) {
+        b += cart_bytes(c, parts[k]);
+        long M = (long)parts[k].coarse_dims[0] * parts[k].coarse_dims[1] * parts[k].coarse_dims[2];
+        cb = std::max(cb, (long)cdiv(M, kTile) * kTile);
+    }
+    cb = std::max(cb, (long)cdiv(o.max_dyn_blocks, kTile) * kTile);
+    b += (size_t)cb * kTile * 8;
+    return b;
+}
+
+int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, const msrsb_options *opt,
+                void *hip_stream, msrsb_ctx **out) {
+    g_err.clear();
+    if (!out) {
+        set_error("out is NULL");
+        return MSRSB_E_INVAL;
+    }
+    *out = nullptr;
+    int rc = validate(g);
+    if (rc) return rc;
+    msrsb_options o;
+    if (opt) o = *opt;
+    else msrsb_default_options(&o);
+    if ((rc = check_options(&o)) || (rc = check_parts(g, n_part, parts))) return rc;
+    msrsb_ctx *c = new msrsb_ctx();
+    c->opt = o;
+    c->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&c->device);
+    c->nx = g->nx; c->ny = g->ny; c->nz = g->nz;
+    const int N = c->N = g->nx * g->ny * g->nz;
+    c->h_active.assign(N, 1);
+    if (g->active)
+        for (int i = 0; i < N; ++i) c->h_active[i] = g->active[i] ? 1 : 0;
+    c->n_active = 0;
+    for (int i = 0; i < N; ++i) c->n_active += c->h_active[i];
+    c->n_bc = g->n_bc;
+    c->h_bc_cell.assign(g->bc_cell, g->bc_cell + g->n_bc);
+    c->h_bc_trans.assign(g->bc_trans, g->bc_trans + g->n_bc);
+    c->h_bc_value.assign(g->bc_value, g->bc_value + g->n_bc);
+    // per-cell sums of the boundary connections
+    std::vector<double> bcd(N, 0.0), bcr(N, 0.0);
+    for (int k = 0; k < g->n_bc; ++k) {
+        bcd[g->bc_cell[k]] += g->bc_trans[k];
+        bcr[g->bc_cell[k]] += g->bc_trans[k] * g->bc_value[k];
+    }
+    std::vector<double> src(N, 0.0);
+    if (g->source)
+        for (int i = 0; i < N; ++i) src[i] = c->h_active[i] ? g->source[i] : 0.0;
+    std::vector<float> t32(N);
+    auto fail = [&](int code) {
+        msrsb_destroy(c);
+        return code;
+    };
+    auto up = [&](double *&dst, const double *h) -> bool {
+        dst = (double *)ctx_alloc(*c, sizeof(double) * N);
+        return dst && hipMemcpy(dst, h, sizeof(double) * N, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    auto up32 = [&](float *&dst, const double *h) -> bool {
+        for (int i = 0; i < N; ++i) t32[i] = (float)h[i];
+        dst = (float *)ctx_alloc(*c, sizeof(float) * N);
+        return dst && hipMemcpy(dst, t32.data(), sizeof(float) * N, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(c->tx, g->tx) || !up(c->ty, g->ty) || !up(c->tz, g->tz) || !up(c->bcdiag, bcd.data()) ||
+        !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !up32(c->tx32, g->tx) || !up32(c->ty32, g->ty) ||
+        !up32(c->tz32, g->tz))
+        return fail(MSRSB_E_NOMEM);
+    auto alloc = [&](size_t bytes) { return ctx_alloc(*c, bytes); };
+    c->diag = (double *)alloc(8 * (size_t)N);
+    c->b = (double *)alloc(8 * (size_t)N);
+    c->dtil = (double *)alloc(8 * (size_t)N);
+    c->dtil32 = (float *)alloc(4 * (size_t)N);
+    c->diag32 = (float *)alloc(4 * (size_t)N);
+    c->r = (double *)alloc(8 * (size_t)N);
+    c->e = (double *)alloc(8 * (size_t)N);
+    c->tmp = (double *)alloc(8 * (size_t)N);
+    c->z = (double *)alloc(8 * (size_t)N);
+    c->u = (double *)alloc(8 * (size_t)N);
+    c->partial = (double *)alloc(8 * (size_t)kRedBlocks * (kMaxRestart + 2));
+    c->scal = (double *)alloc(8 * 8192);
+    c->status = (Status *)alloc(sizeof(Status));
+    c->maxbits = (unsigned long long *)alloc(8 * 65536);
+    c->flag = (int *)alloc(sizeof(int));
+    if (!c->diag || !c->b || !c->dtil || !c->dtil32 || !c->diag32 || !c->r || !c->e || !c->tmp || !c->z || !c->u ||
+        !c->partial || !c->scal || !c->status || !c->maxbits || !c->flag)
+        return fail(MSRSB_E_NOMEM);
+    if (hipHostMalloc((void **)&c->h_status, sizeof(Status), 0) != hipSuccess) return fail(MSRSB_E_NOMEM);
+    if (g->n_bc > 0) {
+        c->bc_cell = (int32_t *)alloc(4 * (size_t)g->n_bc);
+        c->bc_trans = (double *)alloc(8 * (size_t)g->n_bc);
+        c->bc_value = (double *)alloc(8 * (size_t)g->n_bc);
+        if (!c->bc_cell || !c->bc_trans || !c->bc_value) return fail(MSRSB_E_NOMEM);
+        hipMemcpy(c->bc_cell, g->bc_cell, 4 * (size_t)g->n_bc, hipMemcpyHostToDevice);
+        hipMemcpy(c->bc_trans, g->bc_trans, 8 * (size_t)g->n_bc, hipMemcpyHostToDevice);
+        hipMemcpy(c->bc_value, g->bc_value, 8 * (size_t)g->n_bc, hipMemcpyHostToDevice);
+    }
+    if (o.outer == MSRSB_GMRES) {
+        c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
+        if (!c->V) return fail(MSRSB_E_NOMEM);
+    }
+    c->stages.resize(n_part);
+    long cb = cdiv(o.max_dyn_blocks, kTile) * kTile;
+    for (int k = 0; k < n_part; ++k) {
+        if ((rc = build_cart_stage(*c, parts[k], c->stages[k]))) return fail(rc);
+        cb = std::max(cb, (long)c->stages[k].Mp);
+    }
+    c->cbuf = (double *)alloc(8 * (size_t)cb * kTile);
+    c->cbuf_n = cb;
+    if (!c->cbuf) return fail(MSRSB_E_NOMEM);
+    hipMemsetAsync(c->tmp, 0, 8 * (size_t)N, c->stream);
+    launch_assemble(*c);
+    launch_ilu_factor(*c);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(hip_fail(e, "setup kernels"));
+    *out = c;
+    return MSRSB_OK;
+}
+
+static int finish_coarse(Ctx &c, Stage &s) {
+    hipMemsetAsync(c.flag, 0, sizeof(int), c.stream);
+    launch_coarse_inverse(c, s);
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, c.flag, sizeof(int), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "coarse inverse");
+    if (flag & 1) {
+        set_error("coarse operator is not symmetric positive definite");
+        return MSRSB_E_SINGULAR;
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_update_basis(msrsb_ctx *c, int stage, int max_sweeps, double tol, int warm, int *sweeps_done,
+                       double *last_change) {
+    g_err.clear();
+    if (!c) {
+        set_error("ctx is NULL");
+        return MSRSB_E_INVAL;
+    }
+    if (stage < -1 || stage >= (int)c->stages.size() || max_sweeps < 0 || max_sweeps > 65536 || !(tol >= 0.0)) {
+        set_error("bad stage/max_sweeps/tol");
+        return MSRSB_E_INVAL;
+    }
+    const int s0 = stage < 0 ? 0 : stage, s1 = stage < 0 ? (int)c->stages.size() : stage + 1;
+    for (int k = s0; k < s1; ++k) {
+        Stage &s = c->stages[k];
+        if (warm && !s.has_basis) {
+            set_error("warm start of stage %d before its basis exists", k);
+            return MSRSB_E_STATE;
+        }
+        int rc = launch_sweeps(*c, s, max_sweeps, tol, warm != 0, sweeps_done, last_change);
+        if (rc) return rc;
+        launch_rap(*c, s);
+        if ((rc = finish_coarse(*c, s))) return rc;
+        s.has_basis = true;
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_add_dynamic_basis(msrsb_ctx *c, int n_incr, const double *const *d_dp, int *n_dyn_blocks) {
+    g_err.clear();
+    if (!c || n_incr < 1 || n_incr > 2 || !d_dp) {
+        set_error("need 1 or 2 increments");
+        return MSRSB_E_INVAL;
+    }
+    {
+        const Stage &s0 = c->stages[0];
+        for (int J = 0; J < s0.cart.m[0] * s0.cart.m[1] * s0.cart.m[2]; ++J) {
+            const int Jx = J % s0.cart.m[0], Jy = (J / s0.cart.m[0]) % s0.cart.m[1],
+                      Jz = J / (s0.cart.m[0] * s0.cart.m[1]);
+            const int *be0 = s0.h_tab.data() + s0.tab_off[0][4], *be1 = s0.h_tab.data() + s0.tab_off[1][4],
+                      *be2 = s0.h_tab.data() + s0.tab_off[2][4];
+            const long vol = (long)(be0[Jx + 1] - be0[Jx]) * (be1[Jy + 1] - be1[Jy]) * (be2[Jz + 1] - be2[Jz]);
+            if (vol > 6144) {
+                set_error("general blocks of %ld cells exceed the 6144-cell limit of dynamic partitioning", vol);
+                return MSRSB_E_INVAL;
+            }
+        }
+    }
+    if ((int)c->dyn.size() < 2) c->dyn.resize(2);
+    for (int k = 0; k < 2; ++k) c->dyn[k].M = 0;
+    int slot = 0;
+    for (int k = 0; k < n_incr; ++k) {
+        int count = 0;
+        Stage &s = c->dyn[slot];
+        int rc = build_dynamic_stage(*c, d_dp[k], s, &count);
+        if (rc) return rc;
+        if (n_dyn_blocks) n_dyn_blocks[k] = count;
+        if (count == 0) continue;
+        if (s.Mp > c->cbuf_n) {
+            c->cbuf = (double *)ctx_alloc(*c, 8 * (size_t)s.Mp * kTile);
+            if (!c->cbuf) return MSRSB_E_NOMEM;
+            c->cbuf_n = s.Mp;
+        }
+        launch_dyn_rap(*c, s);
+        if ((rc = finish_coarse(*c, s))) return rc;
+        s.has_basis = true;
+        ++slot;
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_clear_dynamic_basis(msrsb_ctx *c) {
+    if (!c) return MSRSB_E_INVAL;
+    for (auto &s : c->dyn) s.M = 0;
+    return MSRSB_OK;
+}
+
+static bool ready(msrsb_ctx *c) {
+    for (auto &s : c->stages)
+        if (!s.has_basis) return false;
+    return true;
+}
+
+int msrsb_solve(msrsb_ctx *c, const double *d_source, double *d_p, double rtol, int max_iters, int *iters,
+                double *relres) {
+    g_err.clear();
+    if (!c || !d_p || !(rtol >= 0.0) || max_iters < 0) {
+        set_error("bad solve arguments");
+        return MSRSB_E_INVAL;
+    }
+    if (!ready(c)) {
+        set_error("solve called before update_basis");
+        return MSRSB_E_STATE;
+    }
+    if (d_source) launch_source_update(*c, d_source);
+    begin_solve(*c, c->b, d_p);
+    int rc = c->opt.outer == MSRSB_GMRES ? solve_gmres(*c, c->b, d_p, rtol, max_iters)
+                                         : solve_richardson(*c, c->b, d_p, rtol, max_iters);
+    if (rc) return rc;
+    if ((rc = read_status(*c))) return rc;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "solve kernels");
+    if (iters) *iters = c->h_status->iters;
+    if (relres) *relres = c->h_status->relres;
+    if (!(c->h_status->relres <= rtol)) {
+        set_error("tolerance %g not met after %d iterations (relative residual %g)", rtol, c->h_status->iters,
+                  c->h_status->relres);
+        return MSRSB_E_NOCONV;
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_apply(msrsb_ctx *c, int op, const double *d_in, double *d_out) {
+    g_err.clear();
+    if (!c || !d_in || !d_out || d_in == d_out) {
+        set_error("bad apply arguments");
+        return MSRSB_E_INVAL;
+    }
+    switch (op) {
+    case MSRSB_OP_RESIDUAL: launch_residual(*c, c->b, d_in, d_out, false, nullptr); break;
+    case MSRSB_OP_SMOOTH:
+        zero_vec(*c, d_out, nullptr);
+        launch_smooth(*c, d_in, d_out, nullptr);
+        break;
+    case MSRSB_OP_PRECOND:
+        if (!ready(c)) {
+            set_error("precondition before update_basis");
+            return MSRSB_E_STATE;
+        }
+        zero_vec(*c, d_out, nullptr);
+        cycle(*c, d_in, d_out, false, nullptr);
+        break;
+    case MSRSB_OP_MATVEC: launch_matvec(*c, d_in, d_out, false, nullptr); break;
+    default: set_error("unknown op %d", op); return MSRSB_E_INVAL;
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "apply");
+    return MSRSB_OK;
+}
+
+int msrsb_fluxes(msrsb_ctx *c, const double *d_p, double *d_face_flux, double *d_bc_flux) {
+    g_err.clear();
+    if (!c || !d_p) {
+        set_error("bad flux arguments");
+        return MSRSB_E_INVAL;
+    }
+    launch_fluxes(*c, d_p, d_face_flux, d_bc_flux);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fluxes");
+    return MSRSB_OK;
+}
+
+int msrsb_num_stages(msrsb_ctx *c) {
+    if (!c) return MSRSB_E_INVAL;
+    int n = (int)c->stages.size();
+    for (auto &s : c->dyn) n += s.M > 0;
+    return n;
+}
+
+static Stage *stage_at(msrsb_ctx *c, int k) {
+    auto v = cycle_stages(*c);
+    if (k < 0 || k >= (int)v.size()) return nullptr;
+    return v[k];
+}
+
+int msrsb_stage_info(msrsb_ctx *c, int stage, int *M, int *kind, int *n_slots) {
+    g_err.clear();
+    if (!c) return MSRSB_E_INVAL;
+    Stage *s = stage_at(c, stage);
+    if (!s) {
+        set_error("no stage %d", stage);
+        return MSRSB_E_INVAL;
+    }
+    if (M) *M = s->M;
+    if (kind) *kind = s->kind;
+    if (n_slots) *n_slots = s->ns;
+    return MSRSB_OK;
+}
+
+int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slot_block, double *h_vals,
+                       double *h_Ac) {
+    g_err.clear();
+    if (!c) return MSRSB_E_INVAL;
+    Stage *s = stage_at(c, stage);
+    if (!s) {
+        set_error("no stage %d", stage);
+        return MSRSB_E_INVAL;
+    }
+    const int N = c->N;
+    hipError_t e = hipSuccess;
+    if (s->kind == 3) {
+        std::vector<int32_t> blk(N);
+        e = hipMemcpy(blk.data(), s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "export");
+        if (h_block) memcpy(h_block, blk.data(), 4 * (size_t)N);
+        if (h_slot_block) memcpy(h_slot_block, blk.data(), 4 * (size_t)N);
+        if (h_vals)
+            for (int i = 0; i < N; ++i) h_vals[i] = blk[i] >= 0 ? 1.0 : 0.0;
+    } else {
+        const CartDev &cd = s->cart;
+        const int32_t *T = s->h_tab.data();
+        const int cmap_off = (int)(cd.cmap - s->d_tab);
+        for (int i = 0; i < N; ++i) {
+            const int c3[3] = {i % c->nx, (i / c->nx) % c->ny, i / (c->nx * c->ny)};
+            int J[3], lo[3], nv[3];
+            for (int a = 0; a < 3; ++a) {
+                J[a] = (int)(((long)c3[a] * cd.m[a]) / cd.n[a]);
+                lo[a] = T[s->tab_off[a][0] + c3[a]];
+                nv[a] = T[s->tab_off[a][1] + c3[a]];
+            }
+            const bool act = c->h_active[i] != 0;
+            if (h_block) h_block[i] = act ? T[cmap_off + J[0] + cd.m[0] * (J[1] + cd.m[1] * J[2])] : -1;
+            if (h_slot_block)
+                for (int sl = 0; sl < s->ns; ++sl) {
+                    int K[3];
+                    bool ok = act;
+                    for (int a = 0; a < 3; ++a) {
+                        const int bit = cd.bit[a] >= 0 ? (sl >> cd.bit[a]) & 1 : 0;
+                        if (bit >= nv[a]) ok = false;
+                        K[a] = lo[a] + bit;
+                    }
+                    h_slot_block[(long)sl * N + i] =
+                        ok ? T[cmap_off + K[0] + cd.m[0] * (K[1] + cd.m[1] * K[2])] : -1;
+                }
+        }
+        if (h_vals) {
+            double *dv = (double *)ctx_alloc(*c, 8 * (size_t)s->ns * N);
+            if (!dv) return MSRSB_E_NOMEM;
+            launch_export_cart(*c, *s, dv);
+            e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess) e = hipMemcpy(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost);
+            hipFree(dv);
+            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
+            if (e != hipSuccess) return hip_fail(e, "export");
+        }
+    }
+    if (h_Ac) {
+        e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy2D(h_Ac, 8 * (size_t)s->M, s->Ac, 8 * (size_t)s->Mp, 8 * (size_t)s->M, s->M,
+                            hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "export A_c");
+    }
+    return MSRSB_OK;
+}
+
+int msrsb_set_stream(msrsb_ctx *c, void *hip_stream) {
+    if (!c) return MSRSB_E_INVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return MSRSB_OK;
+}
+
+void msrsb_destroy(msrsb_ctx *c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    for (void *p : c->allocs) hipFree(p);
+    if (c->h_status) hipHostFree(c->h_status);
+    delete c;
+}
+
+}  // extern "C"

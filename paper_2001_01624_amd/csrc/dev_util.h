@@ -1,0 +1,69 @@
+// Device helpers shared by the kernel files: fixed-order wave/block
+// reductions (results never depend on timing), BF16 conversion and the
+// Cartesian cell-coordinate helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msrsb {
+
+// Sum over the 64 lanes of a wavefront; the tree shape is fixed, so the
+// result is the same on every run.  Valid in lane 0.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// Block-wide sum in a fixed order (waves in index order).  `lds` needs
+// blockDim.x/64 doubles.  Valid in thread 0.
+__device__ inline double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < nw; ++k) s += lds[k];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ inline double block_max(double v, double *lds) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < nw; ++k) s = fmax(s, lds[k]);
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ inline float bf16_to_float(uint16_t u) { return __uint_as_float(((uint32_t)u) << 16); }
+
+// Round-to-nearest-even FP32 -> BF16 (finite inputs).
+__device__ inline uint16_t float_to_bf16(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+template <typename T> __device__ inline double ld_basis(const T *p, long idx) { return (double)p[idx]; }
+template <> __device__ inline double ld_basis<uint16_t>(const uint16_t *p, long idx) {
+    return (double)bf16_to_float(p[idx]);
+}
+
+}  // namespace msrsb

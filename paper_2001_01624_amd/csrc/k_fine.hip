@@ -1,0 +1,501 @@
+// Fine-grid kernels: two-point operator assembly, residual r = b - A x
+// (eq. iterative_multiscale), smoothers S (damped Jacobi; ILU(0) in
+// red-black order, which for the 7-point two-point stencil reduces to a
+// diagonal-only modification), norms, fluxes and the GMRES vector kernels.
+//
+// Layout: every per-cell array is indexed in the full box, x fastest.  The
+// face array tx[i] holds the face to the +x neighbour and is 0 on the last
+// column, so tx[i-1] is automatically 0 on the first column (likewise ty
+// across rows); only the z neighbour below the first layer needs a bounds
+// test.  Inactive cells have diag = 0 and are skipped.
+#include <algorithm>
+
+#include "dev_util.h"
+#include "msrsb_internal.h"
+
+namespace msrsb {
+
+static Fine fine_of(const Ctx &c) {
+    Fine g;
+    g.nx = c.nx; g.ny = c.ny; g.nz = c.nz; g.nxy = c.nx * c.ny; g.N = c.N;
+    g.tx = c.tx; g.ty = c.ty; g.tz = c.tz; g.diag = c.diag;
+    return g;
+}
+
+static int red_grid(int N) { return std::min(kRedBlocks, cdiv(N, kBlock)); }
+
+// (A x)_i for an active cell with diagonal d.
+__device__ inline double ax_row(const Fine &g, const double *__restrict__ x, int i, double d) {
+    double s = d * x[i];
+    if (i >= 1) s -= g.tx[i - 1] * x[i - 1];
+    if (i + 1 < g.N) s -= g.tx[i] * x[i + 1];
+    if (i >= g.nx) s -= g.ty[i - g.nx] * x[i - g.nx];
+    if (i + g.nx < g.N) s -= g.ty[i] * x[i + g.nx];
+    if (i >= g.nxy) s -= g.tz[i - g.nxy] * x[i - g.nxy];
+    if (i + g.nxy < g.N) s -= g.tz[i] * x[i + g.nxy];
+    return s;
+}
+
+__global__ void k_assemble(Fine g, const double *__restrict__ bcdiag, const double *__restrict__ bcrhs,
+                           const double *__restrict__ src, double *__restrict__ diag, double *__restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    double d = g.tx[i] + g.ty[i] + g.tz[i];
+    if (i >= 1) d += g.tx[i - 1];
+    if (i >= g.nx) d += g.ty[i - g.nx];
+    if (i >= g.nxy) d += g.tz[i - g.nxy];
+    d += bcdiag[i];
+    diag[i] = d;
+    b[i] = d > 0.0 ? src[i] + bcrhs[i] : 0.0;
+}
+
+void launch_assemble(Ctx &c) {
+    Fine g = fine_of(c);
+    hipLaunchKernelGGL(k_assemble, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, c.bcdiag, c.bcrhs, c.src,
+                       c.diag, c.b);
+}
+
+__global__ void k_rhs(int N, const double *__restrict__ diag, const double *__restrict__ bcrhs,
+                      const double *__restrict__ src, double *__restrict__ b, double *__restrict__ keep) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double q = src[i];
+    keep[i] = q;
+    b[i] = diag[i] > 0.0 ? q + bcrhs[i] : 0.0;
+}
+
+void launch_source_update(Ctx &c, const double *d_source) {
+    hipLaunchKernelGGL(k_rhs, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag, c.bcrhs, d_source,
+                       c.b, c.src);
+}
+
+// Red-black ILU(0) pivots: red cells (i+j+k even) come first in the
+// elimination order and keep a_ii; every neighbour of a black cell is red and
+// earlier, so its pivot is a_ii - sum_j T_ij^2 / a_jj.  (Two cells of the
+// same colour are never coupled, so ILU(0) has no other non-zero change.)
+__global__ void k_ilu_factor(Fine g, double *__restrict__ dtil, float *__restrict__ dtil32,
+                             float *__restrict__ diag32) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    const double d = g.diag[i];
+    const int ix = i % g.nx, iy = (i / g.nx) % g.ny, iz = i / g.nxy;
+    double p = d;
+    if (d > 0.0 && ((ix + iy + iz) & 1)) {
+        double s = 0.0;
+        double t;
+        if (i >= 1 && (t = g.tx[i - 1]) != 0.0) s += t * t / g.diag[i - 1];
+        if ((t = g.tx[i]) != 0.0) s += t * t / g.diag[i + 1];
+        if (i >= g.nx && (t = g.ty[i - g.nx]) != 0.0) s += t * t / g.diag[i - g.nx];
+        if ((t = g.ty[i]) != 0.0) s += t * t / g.diag[i + g.nx];
+        if (i >= g.nxy && (t = g.tz[i - g.nxy]) != 0.0) s += t * t / g.diag[i - g.nxy];
+        if ((t = g.tz[i]) != 0.0) s += t * t / g.diag[i + g.nxy];
+        p = d - s;
+    }
+    dtil[i] = p;
+    dtil32[i] = (float)p;
+    diag32[i] = (float)d;
+}
+
+void launch_ilu_factor(Ctx &c) {
+    Fine g = fine_of(c);
+    hipLaunchKernelGGL(k_ilu_factor, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, c.dtil, c.dtil32,
+                       c.diag32);
+}
+
+template <bool NORM>
+__global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__restrict__ b,
+                                                     const double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ partial, const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+        const double d = g.diag[i];
+        double ri = 0.0;
+        if (d > 0.0) ri = b[i] - ax_row(g, x, i, d);
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    if (NORM) {
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done) {
+    Fine g = fine_of(c);
+    const int grid = red_grid(c.N);
+    if (norm)
+        hipLaunchKernelGGL(k_residual<true>, dim3(grid), dim3(kBlock), 0, c.stream, g, b, x, r, c.partial, done);
+    else
+        hipLaunchKernelGGL(k_residual<false>, dim3(grid), dim3(kBlock), 0, c.stream, g, b, x, r, c.partial, done);
+}
+
+template <bool NORM>
+__global__ __launch_bounds__(kBlock) void k_matvec(Fine g, const double *__restrict__ x, double *__restrict__ y,
+                                                   double *__restrict__ partial, const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+        const double d = g.diag[i];
+        const double v = d > 0.0 ? ax_row(g, x, i, d) : 0.0;
+        y[i] = v;
+        acc += v * v;
+    }
+    if (NORM) {
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done) {
+    Fine g = fine_of(c);
+    const int grid = red_grid(c.N);
+    if (norm)
+        hipLaunchKernelGGL(k_matvec<true>, dim3(grid), dim3(kBlock), 0, c.stream, g, x, y, c.partial, done);
+    else
+        hipLaunchKernelGGL(k_matvec<false>, dim3(grid), dim3(kBlock), 0, c.stream, g, x, y, c.partial, done);
+}
+
+// Damped Jacobi: x += omega_s r / a_ii.
+template <typename TT>
+__global__ void k_jacobi(int N, const TT *__restrict__ diag, TT omega, const double *__restrict__ r,
+                         double *__restrict__ x, const int *done) {
+    if (done && *done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const TT d = diag[i];
+    if (d > (TT)0) x[i] += (double)(omega * (TT)r[i] / d);
+}
+
+// Cell of colour `col` handled by thread t: rows (y,z) hold ceil(nx/2) slots.
+__device__ inline int colour_cell(const Fine &g, int col, int t) {
+    const int hx = (g.nx + 1) >> 1;
+    const int row = t / hx;
+    if (row >= g.ny * g.nz) return -1;
+    const int k = t - row * hx;
+    const int iy = row % g.ny, iz = row / g.ny;
+    const int ix = 2 * k + ((col + iy + iz) & 1);
+    if (ix >= g.nx) return -1;
+    return ix + g.nx * row;
+}
+
+// Forward sweep of (D~ + L) w = r restricted to black cells, which in
+// red-black order is also their final value e_b = w_b:
+//   e_b = (r_b + sum_j T_bj r_j / a_jj) / d~_b          (j red neighbours)
+template <typename TT>
+__global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
+                                                      const TT *__restrict__ tz, const TT *__restrict__ diag,
+                                                      const TT *__restrict__ dtil, const double *__restrict__ r,
+                                                      double *__restrict__ e, double *__restrict__ x,
+                                                      const int *done) {
+    if (done && *done) return;
+    const int i = colour_cell(g, 1, blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < 0) return;
+    const TT dt = dtil[i];
+    if (!(dt > (TT)0)) return;
+    TT s = (TT)r[i];
+    TT t;
+    if (i >= 1 && (t = tx[i - 1]) != (TT)0) s += t * (TT)r[i - 1] / diag[i - 1];
+    if ((t = tx[i]) != (TT)0) s += t * (TT)r[i + 1] / diag[i + 1];
+    if (i >= g.nx && (t = ty[i - g.nx]) != (TT)0) s += t * (TT)r[i - g.nx] / diag[i - g.nx];
+    if ((t = ty[i]) != (TT)0) s += t * (TT)r[i + g.nx] / diag[i + g.nx];
+    if (i >= g.nxy && (t = tz[i - g.nxy]) != (TT)0) s += t * (TT)r[i - g.nxy] / diag[i - g.nxy];
+    if ((t = tz[i]) != (TT)0) s += t * (TT)r[i + g.nxy] / diag[i + g.nxy];
+    const TT v = s / dt;
+    e[i] = (double)v;
+    x[i] += (double)v;
+}
+
+// Backward sweep for red cells: e_r = (r_r + sum_j T_rj e_j) / a_rr.
+template <typename TT>
+__global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
+                                                    const TT *__restrict__ tz, const TT *__restrict__ diag,
+                                                    const double *__restrict__ r, const double *__restrict__ e,
+                                                    double *__restrict__ x, const int *done) {
+    if (done && *done) return;
+    const int i = colour_cell(g, 0, blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < 0) return;
+    const TT d = diag[i];
+    if (!(d > (TT)0)) return;
+    TT s = (TT)r[i];
+    TT t;
+    if (i >= 1 && (t = tx[i - 1]) != (TT)0) s += t * (TT)e[i - 1];
+    if ((t = tx[i]) != (TT)0) s += t * (TT)e[i + 1];
+    if (i >= g.nx && (t = ty[i - g.nx]) != (TT)0) s += t * (TT)e[i - g.nx];
+    if ((t = ty[i]) != (TT)0) s += t * (TT)e[i + g.nx];
+    if (i >= g.nxy && (t = tz[i - g.nxy]) != (TT)0) s += t * (TT)e[i - g.nxy];
+    if ((t = tz[i]) != (TT)0) s += t * (TT)e[i + g.nxy];
+    x[i] += (double)(s / d);
+}
+
+void launch_smooth(Ctx &c, const double *r, double *x, const int *done) {
+    Fine g = fine_of(c);
+    const bool mixed = c.opt.precision == MSRSB_MIXED;
+    if (c.opt.smoother == MSRSB_SMOOTH_JACOBI) {
+        if (mixed)
+            hipLaunchKernelGGL(k_jacobi<float>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag32,
+                               (float)c.opt.omega_s, r, x, done);
+        else
+            hipLaunchKernelGGL(k_jacobi<double>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag,
+                               c.opt.omega_s, r, x, done);
+        return;
+    }
+    const int half = ((c.nx + 1) / 2) * c.ny * c.nz;
+    const dim3 grid(cdiv(half, kBlock));
+    if (mixed) {
+        hipLaunchKernelGGL(k_ilu_black<float>, grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32,
+                           c.dtil32, r, c.e, x, done);
+        hipLaunchKernelGGL(k_ilu_red<float>, grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32, r,
+                           c.e, x, done);
+    } else {
+        hipLaunchKernelGGL(k_ilu_black<double>, grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz, c.diag, c.dtil,
+                           r, c.e, x, done);
+        hipLaunchKernelGGL(k_ilu_red<double>, grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz, c.diag, r, c.e,
+                           x, done);
+    }
+}
+
+__global__ void k_zero_inactive(int N, const double *__restrict__ diag, double *__restrict__ x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && !(diag[i] > 0.0)) x[i] = 0.0;
+}
+
+void launch_zero_inactive(Ctx &c, double *x) {
+    hipLaunchKernelGGL(k_zero_inactive, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag, x);
+}
+
+// Fixed-order sum of the per-block partials of the last norm kernel.
+__global__ __launch_bounds__(kBlock) void k_norm_finish(const double *__restrict__ partial, int np, double *out,
+                                                        const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) s += partial[k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) *out = s;
+}
+
+void launch_norm_finish(Ctx &c, double *out_sq, const int *done) {
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kBlock), 0, c.stream, c.partial, red_grid(c.N), out_sq, done);
+}
+
+// Richardson test after a full cycle: relres = ||r|| / ||b||.  scal[0] holds
+// ||r||^2 of the current iterate.  `count` adds one iteration first.
+__global__ void k_check(Status *st, const double *scal, double rtol, int max_iters, int count) {
+    if (st->done) return;
+    if (count) st->iters += 1;
+    const double rel = sqrt(scal[0]) / st->bnorm;
+    st->relres = rel;
+    if (rel <= rtol || st->iters >= max_iters || !(rel == rel)) st->done = 1;
+}
+
+void launch_check(Ctx &c, double rtol, int max_iters, int count) {
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, rtol, max_iters, count);
+}
+
+__global__ void k_fluxes(Fine g, const double *__restrict__ p, double *__restrict__ face) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    const double pi = p[i];
+    double t;
+    face[i] = (t = g.tx[i]) != 0.0 ? t * (pi - p[i + 1]) : 0.0;
+    face[g.N + i] = (t = g.ty[i]) != 0.0 ? t * (pi - p[i + g.nx]) : 0.0;
+    face[2 * (long)g.N + i] = (t = g.tz[i]) != 0.0 ? t * (pi - p[i + g.nxy]) : 0.0;
+}
+
+__global__ void k_bc_fluxes(int n, const int32_t *__restrict__ cell, const double *__restrict__ tr,
+                            const double *__restrict__ val, const double *__restrict__ p, double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = tr[k] * (p[cell[k]] - val[k]);
+}
+
+void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf) {
+    Fine g = fine_of(c);
+    if (face) hipLaunchKernelGGL(k_fluxes, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, p, face);
+    if (bcf && c.n_bc > 0)
+        hipLaunchKernelGGL(k_bc_fluxes, dim3(cdiv(c.n_bc, kBlock)), dim3(kBlock), 0, c.stream, c.n_bc, c.bc_cell,
+                           c.bc_trans, c.bc_value, p, bcf);
+}
+
+// ---------------------------------------------------------------- GMRES ----
+// Classical Gram-Schmidt in two passes (CGS2): h = V^T w, w -= V h, twice.
+// Dots use a fixed grid and a fixed-order final sum.
+
+__global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__restrict__ V, int k,
+                                                     const double *__restrict__ w, double *__restrict__ partial,
+                                                     const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    for (int j = 0; j < k; ++j) {
+        const double *v = V + (long)j * N;
+        double acc = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) acc += v[i] * w[i];
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) partial[(long)j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_multidot_finish(const double *__restrict__ partial, int np,
+                                                            double *__restrict__ h, const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) s += partial[(long)j * np + k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) h[j] = s;
+}
+
+// Scalar layout in c.scal (device doubles):
+//   [0]               norm^2 scratch
+//   [8 .. 8+64)       h1 (first CGS pass)      [80 .. 144) h2 (second pass)
+//   [160 .. 160+65*64) Hessenberg H (column-major, ld 65)
+//   [4400 .. 4465)    g (rotated rhs)   [4480..4544) cs  [4544..4608) sn
+//   [4608 .. 4672)    y (least-squares solution)   [4700] 1/h_{j+1,j}
+constexpr int S_H1 = 8, S_H2 = 80, S_H = 160, S_G = 4400, S_CS = 4480, S_SN = 4544, S_Y = 4608, S_INV = 4700;
+
+void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_out, const int *done) {
+    const int grid = red_grid(c.N);
+    hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, w, c.partial, done);
+    hipLaunchKernelGGL(k_multidot_finish, dim3(k), dim3(kBlock), 0, c.stream, c.partial, grid, h_out, done);
+}
+
+template <bool NORM>
+__global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const double *__restrict__ V, int k,
+                                                      const double *__restrict__ h, double sign,
+                                                      double *__restrict__ w, double *__restrict__ partial,
+                                                      const int *done) {
+    __shared__ double hs[kMaxRestart + 1];
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
+    __syncthreads();
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < k; ++j) s += hs[j] * V[(long)j * N + i];
+        const double v = w[i] + sign * s;
+        w[i] = v;
+        acc += v * v;
+    }
+    if (NORM) {
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+void launch_multiaxpy(Ctx &c, const double *V, int k, const double *h, double *w, double sign, bool norm,
+                      const int *done) {
+    const int grid = red_grid(c.N);
+    if (norm)
+        hipLaunchKernelGGL(k_multiaxpy<true>, dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
+                           c.partial, done);
+    else
+        hipLaunchKernelGGL(k_multiaxpy<false>, dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
+                           c.partial, done);
+}
+
+// Start of a restart cycle: beta = ||r|| (scal[0] holds ||r||^2), v0 = r/beta,
+// g = beta e1.  Sets done when the current iterate already meets rtol or the
+// iteration budget is spent; clears it otherwise.
+__global__ void k_gmres_begin(Status *st, double *scal, double rtol, int max_iters) {
+    const double beta = sqrt(scal[0]);
+    const double rel = beta / st->bnorm;
+    st->relres = rel;
+    st->jcur = 0;
+    for (int j = 0; j <= kMaxRestart; ++j) scal[S_G + j] = 0.0;
+    scal[S_G] = beta;
+    scal[S_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
+    st->done = (rel <= rtol || st->iters >= max_iters || !(rel == rel)) ? 1 : 0;
+}
+
+__global__ void k_scale(int N, const double *__restrict__ w, double *__restrict__ v, const double *s, const int *done) {
+    if (done && *done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) v[i] = w[i] * (*s);
+}
+
+void launch_gmres_start(Ctx &c, const double *r, double *v0, int /*restart*/) {
+    hipLaunchKernelGGL(k_scale, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, r, v0, c.scal + S_INV,
+                       (const int *)&c.status->done);
+}
+
+// Arnoldi step j: H(:,j) = h1 + h2, H(j+1,j) = ||w||; apply the previous
+// Givens rotations, form rotation j, update g and the residual estimate.
+__global__ void k_gmres_step(Status *st, double *scal, int j, double rtol, int max_iters, int restart) {
+    if (st->done) return;
+    double *H = scal + S_H;
+    double *g = scal + S_G;
+    double *cs = scal + S_CS;
+    double *sn = scal + S_SN;
+    const int ld = kMaxRestart + 1;
+    for (int i = 0; i <= j; ++i) H[i + ld * j] = scal[S_H1 + i] + scal[S_H2 + i];
+    const double hn = sqrt(scal[0]);
+    H[j + 1 + ld * j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i + ld * j], b = H[i + 1 + ld * j];
+        H[i + ld * j] = cs[i] * a + sn[i] * b;
+        H[i + 1 + ld * j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[j + ld * j], b = H[j + 1 + ld * j];
+    const double rr = hypot(a, b);
+    const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? b / rr : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    H[j + ld * j] = rr;
+    H[j + 1 + ld * j] = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = cj * g[j];
+    st->iters += 1;
+    st->jcur = j + 1;
+    const double rel = fabs(g[j + 1]) / st->bnorm;
+    st->relres = rel;
+    scal[S_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (rel <= rtol || st->iters >= max_iters || j + 1 >= restart || hn == 0.0 || !(rel == rel)) st->done = 1;
+}
+
+void launch_gmres_step(Ctx &c, int j, double rtol, int max_iters, int restart) {
+    hipLaunchKernelGGL(k_gmres_step, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, j, rtol, max_iters, restart);
+}
+
+void launch_gmres_scale(Ctx &c, const double *w, double *v, int /*j*/) {
+    hipLaunchKernelGGL(k_scale, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, w, v, c.scal + S_INV,
+                       (const int *)&c.status->done);
+}
+
+// Back substitution R y = g over the jcur completed steps.
+__global__ void k_gmres_solve_small(Status *st, double *scal) {
+    const double *H = scal + S_H;
+    const double *g = scal + S_G;
+    double *y = scal + S_Y;
+    const int ld = kMaxRestart + 1;
+    const int k = st->jcur;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int m = i + 1; m < k; ++m) s -= H[i + ld * m] * y[m];
+        y[i] = s / H[i + ld * i];
+    }
+}
+
+void launch_gmres_solve_small(Ctx &c, int /*restart*/) {
+    hipLaunchKernelGGL(k_gmres_solve_small, dim3(1), dim3(1), 0, c.stream, c.status, c.scal);
+}
+
+__global__ void k_axpy(int N, double *__restrict__ x, const double *__restrict__ z, const int *done) {
+    if (done && *done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) x[i] += z[i];
+}
+
+void launch_axpy(Ctx &c, double *x, const double *z, const int *done) {
+    hipLaunchKernelGGL(k_axpy, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, x, z, done);
+}
+
+// exported for the solver driver
+void launch_gmres_begin(Ctx &c, double rtol, int max_iters) {
+    hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, rtol, max_iters);
+}
+
+}  // namespace msrsb

@@ -1,0 +1,163 @@
+// Internal declarations of the MI355X MsRSB library: context layout and the
+// launchers each kernel file provides.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/msrsb.h"
+
+namespace msrsb {
+
+constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
+constexpr int kRedBlocks = 2048;   // fixed grid of the norm/dot kernels (deterministic order)
+constexpr int kTile = 32;          // coarse inverse tile / panel width
+constexpr int kMaxRestart = 64;
+
+// Geometry of the fine box as the kernels see it.
+struct Fine {
+    int nx, ny, nz, nxy;
+    int N;
+    const double *tx, *ty, *tz;   // face T to the +x/+y/+z neighbour
+    const double *diag;           // A_ii (0 marks an inactive cell)
+};
+
+// Rectilinear stage tables (device).  For axis d with n_d cells and m_d
+// blocks: blk[i] = floor(i m/n); lo[i] = first block whose 1-D support holds
+// i; nv[i] in {1,2} = how many consecutive blocks from lo hold it;
+// slo/shi[J] = inclusive 1-D support range of block J.
+struct CartDev {
+    int n[3], m[3];
+    int bit[3];                   // slot bit of axis d, -1 if m_d == 1
+    int ns;                       // slots per cell = 2^(#axes with m_d > 1)
+    const int32_t *lo[3], *nv[3], *slo[3], *shi[3];
+    const int32_t *be[3];         // block start per axis (m+1 entries)
+    const int32_t *cmap;          // Cartesian block -> compact id (-1 dropped)
+    const int32_t *present;       // compact id -> Cartesian block
+};
+
+struct Stage {
+    int kind = 0;                 // 0 general (Cartesian), 3 dynamic
+    int M = 0, Mp = 0;            // blocks; padded to a multiple of kTile
+    int ns = 1;                   // slots per cell
+    // Cartesian tables
+    CartDev cart{};
+    int32_t *d_tab = nullptr;     // one allocation holding every table
+    std::vector<int32_t> h_present;
+    std::vector<int32_t> h_tab;   // host copy of the tables (export, checks)
+    int tab_off[3][5] = {};       // offsets of lo/nv/slo/shi/be per axis in h_tab
+    int32_t *gbase = nullptr;     // [m0*m1*m2+1] active cells before each Cartesian block
+    // basis values, slot-major [ns*N]
+    double *P64[2] = {nullptr, nullptr};
+    float *P32[2] = {nullptr, nullptr};
+    uint16_t *Pbf = nullptr;      // BF16 storage (mixed precision)
+    int cur = 0;                  // buffer holding the current basis
+    bool has_basis = false;
+    int sweeps = 0;
+    double change = 0.0;
+    // dynamic (constant basis)
+    int32_t *dblock = nullptr;    // [N] block per cell (-1 inactive)
+    int32_t *dptr = nullptr;      // [M+1] CSR of cells per block
+    int32_t *dcells = nullptr;    // [n_active]
+    // coarse operator and its inverse (Mp x Mp, row-major), coarse vectors
+    double *Ac = nullptr, *Ainv = nullptr;
+    double *dvec = nullptr, *pc = nullptr;
+};
+
+struct Status {                   // device-side solver status (one struct per context)
+    int done;                     // 1: converged or finished -> later kernels return
+    int iters;                    // iterations completed
+    int flag;                     // error bits (1: singular pivot, 2: row sum <= 0)
+    int jcur;                     // GMRES: inner index of the next Arnoldi step
+    double relres;
+    double bnorm;
+    double change_bits_dummy;
+};
+
+struct Ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    msrsb_options opt{};
+    int nx = 0, ny = 0, nz = 0, N = 0, n_active = 0;
+    // host copies needed later (dynamic stages, export)
+    std::vector<uint8_t> h_active;
+    std::vector<int32_t> h_bc_cell;
+    std::vector<double> h_bc_trans, h_bc_value;
+    int n_bc = 0;
+    // device operator
+    double *tx = nullptr, *ty = nullptr, *tz = nullptr;   // FP64
+    float *tx32 = nullptr, *ty32 = nullptr, *tz32 = nullptr;
+    double *diag = nullptr, *b = nullptr, *src = nullptr;
+    double *bcdiag = nullptr, *bcrhs = nullptr;
+    double *dtil = nullptr;       // red-black ILU(0) pivots
+    float *dtil32 = nullptr, *diag32 = nullptr;
+    int32_t *bc_cell = nullptr;
+    double *bc_trans = nullptr, *bc_value = nullptr;
+    // work vectors [N]
+    double *r = nullptr, *e = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr;
+    double *partial = nullptr;    // [kRedBlocks * (kMaxRestart + 2)]
+    double *cbuf = nullptr;       // coarse inverse column panel [max Mp * kTile]
+    long cbuf_n = 0;
+    double *scal = nullptr;       // small device scalars / GMRES Hessenberg state
+    Status *status = nullptr;     // device
+    Status *h_status = nullptr;   // pinned host mirror
+    unsigned long long *maxbits = nullptr;  // device max |change| bit pattern
+    int *flag = nullptr;          // device error flag
+    // GMRES Krylov basis [(restart+1) * N]
+    double *V = nullptr;
+    std::vector<Stage> stages;    // general + static
+    std::vector<Stage> dyn;       // dynamic, newest first
+    std::vector<void *> allocs;   // every device allocation (freed at destroy)
+};
+
+// ---- error helpers (capi.hip) ----
+void set_error(const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+// ---- fine-grid kernels (k_fine.hip) ----
+void launch_assemble(Ctx &c);
+void launch_source_update(Ctx &c, const double *d_source);
+void launch_ilu_factor(Ctx &c);
+void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done);
+void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done);
+void launch_smooth(Ctx &c, const double *r, double *x, const int *done);
+void launch_zero_inactive(Ctx &c, double *x);
+void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
+void launch_check(Ctx &c, double rtol, int max_iters, int count);
+void launch_gmres_begin(Ctx &c, double rtol, int max_iters);
+void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
+void *ctx_alloc(Ctx &c, size_t bytes);
+void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf);
+// GMRES helpers
+void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_out, const int *done);
+void launch_multiaxpy(Ctx &c, const double *V, int k, const double *h, double *w, double sign, bool norm,
+                      const int *done);
+void launch_gmres_start(Ctx &c, const double *r, double *v0, int restart);
+void launch_gmres_step(Ctx &c, int j, double rtol, int max_iters, int restart);
+void launch_gmres_scale(Ctx &c, const double *w, double *v, int j);
+void launch_gmres_solve_small(Ctx &c, int restart);
+void launch_axpy(Ctx &c, double *x, const double *z, const int *done);
+
+// ---- basis kernels (k_basis.hip) ----
+int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *sweeps, double *change);
+void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done);
+void launch_prolong(Ctx &c, Stage &s, double *x, const int *done);
+void launch_rap(Ctx &c, Stage &s);
+void launch_export_cart(Ctx &c, Stage &s, double *d_vals);
+
+// ---- coarse kernels (k_coarse.hip) ----
+void launch_coarse_inverse(Ctx &c, Stage &s);
+void launch_coarse_solve(Ctx &c, Stage &s, const int *done);
+
+// ---- dynamic basis kernels (k_dyn.hip) ----
+int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count);
+void launch_dyn_restrict(Ctx &c, Stage &s, const double *r, const int *done);
+void launch_dyn_prolong(Ctx &c, Stage &s, double *x, const int *done);
+void launch_dyn_rap(Ctx &c, Stage &s);
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace msrsb

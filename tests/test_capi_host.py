@@ -1,0 +1,97 @@
+"""Host-side checks of the C-ABI library that need no GPU: the shared library
+loads, exports every function ``include/msrsb.h`` declares, and its host logic
+(grid validation, rectilinear support tables) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.msrsb import support_1d
+from workloads import make_config0, make_config2, make_homogeneous
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+capi = pytest.importorskip("paper_2001_01624_amd.capi", reason="libmsrsb.so not built")
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "msrsb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(msrsb_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    import ctypes
+
+    lib = ctypes.CDLL(capi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(capi.EXPORTED)
+
+
+def test_default_options():
+    o = capi.default_options()
+    assert o.omega == pytest.approx(2 / 3) and o.omega_s == pytest.approx(2 / 3)
+    assert o.n_bins == 4 and o.max_dyn_blocks == 4096 and o.restart == 30
+    assert o.smoother == capi.SMOOTH_JACOBI and o.precision == capi.FP64 and o.outer == capi.RICHARDSON
+
+
+@pytest.mark.parametrize("n,m", [(15, 3), (8, 2), (10, 3), (5, 5), (7, 1), (60, 6), (220, 10), (85, 5), (37, 8),
+                                 (128, 8), (9, 4), (2, 2), (1, 1)])
+def test_axis_support_matches_oracle(n, m):
+    lo, nv, slo, shi = capi.axis_support(n, m)
+    sets = support_1d(n, m)
+    for J, members in enumerate(sets):
+        assert slo[J] == members[0] and shi[J] == members[-1]
+        assert members == list(range(members[0], members[-1] + 1))
+    for i in range(n):
+        mine = [J for J in range(m) if i in sets[J]]
+        assert mine == list(range(lo[i], lo[i] + nv[i]))
+
+
+def test_axis_support_rejects_bad_sizes():
+    with pytest.raises(capi.MsrsbError):
+        capi.axis_support(3, 4)
+    with pytest.raises(capi.MsrsbError):
+        capi.axis_support(3, 0)
+
+
+def test_validate_accepts_generated_models():
+    assert capi.validate_grid(make_config0(0)) == capi.OK
+    assert capi.validate_grid(make_config2(dims=(16, 20, 9), seed=1)) == capi.OK
+
+
+def test_validate_rejects_bad_input():
+    p = make_homogeneous((5, 4, 2))
+    q = p.with_source()
+    q.tx = p.tx.copy(); q.tx[3] = -1.0
+    assert capi.validate_grid(q) == capi.E_INVAL
+    q.tx = p.tx.copy(); q.tx[3] = np.nan
+    assert capi.validate_grid(q) == capi.E_INVAL
+    q.tx = p.tx.copy(); q.tx[4] = 1.0  # last column: face leaves the box
+    assert capi.validate_grid(q) == capi.E_INVAL
+    q.tx = p.tx.copy()
+    q.active = p.active.copy(); q.active[7] = False  # faces still touch it
+    assert capi.validate_grid(q) == capi.E_INVAL
+    q.active = p.active.copy()
+    q.bc_trans = np.zeros_like(p.bc_trans)  # no anchor: singular
+    assert capi.validate_grid(q) == capi.E_SINGULAR
+    q.bc_trans = p.bc_trans.copy()
+    q.bc_cell = p.bc_cell.copy(); q.bc_cell[0] = 10 ** 6
+    assert capi.validate_grid(q) == capi.E_INVAL
+    q.bc_cell = p.bc_cell.copy()
+    q.source = np.full(p.n_cells, np.inf)
+    assert capi.validate_grid(q) == capi.E_INVAL
+
+
+def test_footprint_is_positive_and_grows():
+    p = make_config0(0)
+    parts = [{"kind": "cartesian", "coarse_dims": (6, 6, 1)}]
+    f64 = capi.footprint_bytes(p, parts)
+    mixed = capi.footprint_bytes(p, parts, capi.default_options(precision="mixed"))
+    gm = capi.footprint_bytes(p, parts, capi.default_options(outer="gmres"))
+    assert f64 > 3600 * 8 * 10 and gm > f64 and mixed > 0
+    assert capi.footprint_bytes(p, [{"kind": "cartesian", "coarse_dims": (100, 1, 1)}]) == 0
