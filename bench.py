@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X MsRSB pressure solver: fine cells solved per
+second to 1e-6 relative residual on the layered five-spot model
+(60 x 220 x 85 = 1,122,000 cells, 20 x 10 x 2 cells, smooth lognormal top /
+sinusoidal-channel bottom, five-spot wells).
+
+One step = one request on the device-resident model: build the multibasis
+prolongations from scratch (restricted smoothing to tol 1e-3, at most 100
+sweeps, Galerkin operators, coarse inverses), solve from zero for source q1,
+re-solve for a changed source q2 (a new injector), add a dynamic stage from
+the increment x2 - x1, solve for q3, and compute fluxes.  Every solve runs to
+||b - A x|| <= 1e-6 ||b|| (checked on the true FP64 residual).  Value = 3 *
+active cells * steps / wall time (inputs already in HBM; model setup, i.e.
+validation, assembly and integer partition tables, is timed apart as setup_ms).
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine cells solved/s to 1e-6 rel. residual (FP64 plain vs mixed+served); p50/p99"
+HBM_PEAK_GBS = 8000.0
+DIMS = (60, 220, 85)
+STAGES = [(10, 10, 5), (6, 22, 17)]
+RTOL = 1e-6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kernel", default="sweep", help="kernel class for the roofline object")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def workload(dims=DIMS, seed=0):
+    """Model plus the three sources of a request (injector only; injector split
+    with a new column; the new column rescaled)."""
+    import numpy as np
+
+    from workloads import make_config1, rng_for
+
+    prob = make_config1(dims=dims, seed=seed)
+    nx, ny, nz = prob.dims
+    rng = rng_for(4, seed)
+    q1 = prob.source.copy()
+    inj = prob.wells["injector"]
+    cx, cy = int(rng.integers(nx // 4, 3 * nx // 4)), int(rng.integers(ny // 4, 3 * ny // 4))
+    col = np.array([cx + nx * (cy + ny * k) for k in range(nz)])
+    col = col[prob.active[col]]
+    q2 = q1 * 0.5
+    q2[col] += 0.5 / col.size
+    q3 = q2.copy()
+    q3[col] *= rng.uniform(0.5, 1.5)
+    return prob, [q1, q2, q3]
+
+
+# algorithmic bytes per active cell for one launch of each kernel class
+def bytes_per_cell(kernel, ns, mixed):
+    sp = 4 if mixed else 8
+    return {
+        "sweep": 2 * ns * sp + 3 * sp + 8,   # read P, write P, three face T, diagonal
+        "residual": 56,                      # x, b, r, three face T, diagonal
+        "smooth": 100,                       # both colours of red-black ILU(0)
+        "matvec": 48,
+    }[kernel]
+
+
+def gpu_leg(args, precision):
+    import numpy as np
+    import torch
+
+    from paper_2001_01624_amd import capi
+
+    prob, sources = workload()
+    parts = [{"kind": "cartesian", "coarse_dims": cd} for cd in STAGES]
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=30, precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = capi.Solver(prob, parts, opt)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    q = [torch.as_tensor(s).cuda() for s in sources]
+    N = prob.n_cells
+    x1 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    x3 = torch.zeros_like(x1)
+    info = {}
+
+    def step():
+        rec = {}
+        t = time.perf_counter()
+        g.clear_dynamic_basis()
+        sweeps = []
+        for k in range(len(STAGES)):
+            sw, _ = g.update_basis(stage=k, max_sweeps=100, tol=1e-3)
+            sweeps.append(sw)
+        x1.zero_()
+        it1, r1, c1 = g.solve(x1, source=q[0], rtol=RTOL, max_iters=3000)
+        x2.copy_(x1)
+        it2, r2, c2 = g.solve(x2, source=q[1], rtol=RTOL, max_iters=3000)
+        d = x2 - x1
+        nd = g.add_dynamic_basis([d])
+        x3.copy_(x2)
+        it3, r3, c3 = g.solve(x3, source=q[2], rtol=RTOL, max_iters=3000)
+        g.fluxes(x3)
+        torch.cuda.synchronize()
+        rec["ms"] = 1e3 * (time.perf_counter() - t)
+        rec["iters"] = [it1, it2, it3]
+        rec["relres"] = [r1, r2, r3]
+        rec["status"] = [c1, c2, c3]
+        rec["sweeps"] = sweeps
+        rec["dyn_blocks"] = nd
+        return rec
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    g.profile_begin(args.kernel, 200000)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = g.profile_end()
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    ms = sorted(rec["ms"] for rec in recs)
+    n_act = prob.n_active
+    cells = 3 * n_act * args.steps
+    ns = 8
+    bpc = bytes_per_cell(args.kernel, ns, precision == "mixed") if args.kernel in ("sweep", "residual", "smooth",
+                                                                                  "matvec") else None
+    roof = None
+    if bpc is not None and launches > 0:
+        per_launch = bpc * n_act
+        avg_s = kern_ms / launches / 1e3
+        ach = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_record(args.kernel, precision),
+                "kernel": args.kernel, "launches": launches, "avg_launch_us": round(1e6 * avg_s, 2),
+                "algorithmic_bytes_per_launch": per_launch}
+    out = {
+        "value": cells / wall,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "p50_ms": ms[len(ms) // 2],
+        "p99_ms": ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))],
+        "setup_ms": setup_ms,
+        "iters": [rec["iters"] for rec in recs][-1],
+        "sweeps": recs[-1]["sweeps"],
+        "dyn_blocks": recs[-1]["dyn_blocks"],
+        "relres": max(max(rec["relres"]) for rec in recs),
+        "all_converged": all(s == 0 for rec in recs for s in rec["status"]),
+        "roofline": roof,
+        "cells": n_act,
+    }
+    g.close()
+    return out
+
+
+def traffic_record(kernel, precision):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2001_01624_amd", "csrc", rec.get("source", "k_basis.hip"))
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if h != rec.get("sha256"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_leg():
+    """The oracle, as it stands, on a bounded sample of the same request
+    (same recipe and block shapes at 30 x 110 x 21 cells): basis, three
+    solves, dynamic stage, fluxes.  Single thread."""
+    import oracle as O
+
+    prob, sources = workload(dims=(30, 110, 21))
+    parts = [{"kind": "cartesian", "coarse_dims": (5, 5, 1)}, {"kind": "cartesian", "coarse_dims": (3, 11, 4)}]
+    t0 = time.perf_counter()
+    o = O.Oracle(prob, parts, smoother="ilu0_rb")
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.update_basis(100, 1e-3)
+    x1, i1, r1, s1 = o.solve_gmres(source=sources[0], rtol=RTOL, restart=30, max_iters=3000)
+    x2, i2, r2, s2 = o.solve_gmres(source=sources[1], x0=x1, rtol=RTOL, restart=30, max_iters=3000)
+    o.add_dynamic_basis([x2 - x1])
+    x3, i3, r3, s3 = o.solve_gmres(source=sources[2], x0=x2, rtol=RTOL, restart=30, max_iters=3000)
+    o.fluxes(x3)
+    t = time.perf_counter() - t0
+    print(json.dumps({"value": 3 * prob.n_active / t, "seconds": t, "setup_s": setup, "cells": prob.n_active,
+                      "iters": [i1, i2, i3]}))
+
+
+def run_cpu_baseline():
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg"], capture_output=True, text=True,
+                       env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": rec["value"], "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"same request recipe at 30x110x21 ({rec['cells']} cells, blocks 6x22x21 and ~10x10x5), "
+                      f"basis + 3 GMRES solves + dynamic stage + fluxes, {rec['seconds']:.1f} s on 1 thread of "
+                      f"{cpu} ({os.cpu_count()} host threads); oracle setup {rec['setup_s']:.1f} s excluded",
+            "iters": rec["iters"]}
+
+
+def main():
+    args = parse()
+    if args.cpu_leg:
+        cpu_leg()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
+              f"in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X", file=sys.stderr)
+        sys.exit(1)
+    f64 = gpu_leg(args, "fp64")
+    mixed = None if args.no_mixed else gpu_leg(args, "mixed")
+    cpu = None if args.no_cpu_baseline else run_cpu_baseline()
+    line = {
+        "metric": METRIC,
+        "value": f64["value"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "layered lognormal+channel five-spot 60x220x85 (20x10x2 cells); general stages "
+                               "10x10x5 and 6x22x17 coarse blocks; MsRSB tol 1e-3 <= 100 sweeps; red-black ILU(0); "
+                               "GMRES(30) with the multistage cycle; 3 solves per request (+1 dynamic stage)",
+                   "cells": f64["cells"], "solves_per_step": 3, "rtol": RTOL},
+        "p50_ms": f64["p50_ms"],
+        "p99_ms": f64["p99_ms"],
+        "setup_ms": f64["setup_ms"],
+        "iters": f64["iters"],
+        "sweeps": f64["sweeps"],
+        "dyn_blocks": f64["dyn_blocks"],
+        "max_relres": f64["relres"],
+        "all_converged": f64["all_converged"],
+        "roofline": f64["roofline"],
+        "cpu_baseline": cpu,
+    }
+    if mixed is not None:
+        line["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"], "p50_ms": mixed["p50_ms"],
+                         "p99_ms": mixed["p99_ms"], "iters": mixed["iters"], "sweeps": mixed["sweeps"],
+                         "max_relres": mixed["relres"], "all_converged": mixed["all_converged"],
+                         "roofline": mixed["roofline"], "dtype": "f32 sweeps/smoother, bf16 basis, f64 residual"}
+    line["host"] = platform.node()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

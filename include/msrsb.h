@@ -232,6 +232,28 @@ int msrsb_export_stage(msrsb_ctx *ctx, int stage, int32_t *h_block, int32_t *h_s
 int msrsb_validate_grid(const msrsb_grid *grid);
 int msrsb_axis_support(int n, int m, int32_t *lo, int32_t *nv, int32_t *slo, int32_t *shi);
 
+/*
+ * Launch timing (measurement support).  Between msrsb_profile_begin and
+ * msrsb_profile_end every launch of one kernel class is bracketed by HIP
+ * events on the context's stream (at most max_launches launches are
+ * recorded).  msrsb_profile_end synchronises the stream and returns the
+ * summed kernel time in milliseconds and the number of launches timed.
+ */
+enum {
+    MSRSB_K_SWEEP = 1,     /* one restricted-smoothing sweep over all cells */
+    MSRSB_K_RESIDUAL = 2,  /* r = b - A x */
+    MSRSB_K_SMOOTH = 3,    /* smoother correction (both colours for ILU(0)) */
+    MSRSB_K_RESTRICT = 4,  /* d = P^T r */
+    MSRSB_K_PROLONG = 5,   /* x += P p_c */
+    MSRSB_K_COARSE = 6,    /* p_c = A_c^{-1} d */
+    MSRSB_K_ORTHO = 7,     /* one Gram-Schmidt pass: dots + update */
+    MSRSB_K_MATVEC = 8,    /* y = A x */
+    MSRSB_K_RAP = 9,       /* Galerkin coarse operator of one stage */
+    MSRSB_K_INVERSE = 10   /* coarse inverse of one stage */
+};
+int msrsb_profile_begin(msrsb_ctx *ctx, int kernel_class, int max_launches);
+int msrsb_profile_end(msrsb_ctx *ctx, double *total_ms, int *launches);
+
 /* Change the stream used by later calls (hipStream_t). */
 int msrsb_set_stream(msrsb_ctx *ctx, void *hip_stream);
 

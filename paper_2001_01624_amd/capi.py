@@ -21,6 +21,8 @@ SMOOTH_JACOBI, SMOOTH_ILU0_RB = 0, 1
 FP64, MIXED = 0, 1
 RICHARDSON, GMRES = 0, 1
 OP_RESIDUAL, OP_SMOOTH, OP_PRECOND, OP_MATVEC = 0, 1, 2, 3
+K_CLASSES = {"sweep": 1, "residual": 2, "smooth": 3, "restrict": 4, "prolong": 5, "coarse": 6, "ortho": 7,
+             "matvec": 8, "rap": 9, "inverse": 10}
 _NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_SINGULAR", -5: "E_NOCONV", -6: "E_STATE"}
 
 
@@ -73,6 +75,8 @@ def _load():
         "msrsb_destroy": (None, [VP]),
         "msrsb_validate_grid": (I, [P(Grid)]),
         "msrsb_axis_support": (I, [I, I, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
+        "msrsb_profile_begin": (I, [VP, I, I]),
+        "msrsb_profile_end": (I, [VP, P(D), P(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -252,6 +256,17 @@ class Solver:
         bcf = torch.empty(max(self.n_bc, 1), dtype=torch.float64, device=p.device)
         _check(_lib.msrsb_fluxes(self.h, _dptr(p), _dptr(face), _dptr(bcf)))
         return face.view(3, self.N), bcf[: self.n_bc]
+
+    def profile_begin(self, kernel_class, max_launches=100000):
+        cls = K_CLASSES.get(kernel_class, kernel_class)
+        _check(_lib.msrsb_profile_begin(self.h, int(cls), int(max_launches)))
+
+    def profile_end(self):
+        """Returns (total kernel milliseconds, launches timed)."""
+        ms = C.c_double(0.0)
+        n = C.c_int(0)
+        _check(_lib.msrsb_profile_end(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def num_stages(self):
         return _lib.msrsb_num_stages(self.h)

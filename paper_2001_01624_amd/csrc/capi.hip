@@ -185,6 +185,18 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         s.tab_off[a][2] = (int)tab.size(); tab.insert(tab.end(), slo.begin(), slo.end());
         s.tab_off[a][3] = (int)tab.size(); tab.insert(tab.end(), shi.begin(), shi.end());
         s.tab_off[a][4] = (int)tab.size(); tab.insert(tab.end(), be.begin(), be.end());
+        // split[J]: first cell of block J whose lo is J (cells before it have lo = J-1)
+        std::vector<int32_t> split(cd.m[a]);
+        for (int J = 0; J < cd.m[a]; ++J) {
+            int sp = be[J + 1];
+            for (int i = be[J]; i < be[J + 1]; ++i)
+                if (lo[i] == J) {
+                    sp = i;
+                    break;
+                }
+            split[J] = sp;
+        }
+        s.tab_off[a][5] = (int)tab.size(); tab.insert(tab.end(), split.begin(), split.end());
     }
     // blocks with active cells, compacted in Cartesian order; active cells per block
     const int M0 = cd.m[0] * cd.m[1] * cd.m[2];
@@ -224,6 +236,7 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         cd.slo[a] = s.d_tab + s.tab_off[a][2];
         cd.shi[a] = s.d_tab + s.tab_off[a][3];
         cd.be[a] = s.d_tab + s.tab_off[a][4];
+        cd.split[a] = s.d_tab + s.tab_off[a][5];
     }
     cd.cmap = s.d_tab + cmap_off;
     cd.present = s.d_tab + pres_off;
@@ -244,6 +257,8 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     s.dvec = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
     s.pc = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
     if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
+    s.rpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.M * 8 * s.ns);
+    if (!s.rpart) return MSRSB_E_NOMEM;
     return MSRSB_OK;
 }
 
@@ -296,13 +311,18 @@ static std::vector<Stage *> cycle_stages(Ctx &c) {
 }
 
 // One cycle of eq. multiscale-multibasis on (b, x).  If r_valid, c.r already
-// holds b - A x on entry.
-static void cycle(Ctx &c, const double *b, double *x, bool r_valid, const int *done) {
+// holds b - A x on entry; if x_zero, x is zero on entry (so b - A x = b and
+// the first smoother step reads b directly).
+static void cycle(Ctx &c, const double *b, double *x, bool r_valid, const int *done, bool x_zero = false) {
     auto st = cycle_stages(c);
     for (size_t k = 0; k < st.size(); ++k) {
         Stage &s = *st[k];
-        if (!(k == 0 && r_valid)) launch_residual(c, b, x, c.r, false, done);
-        launch_smooth(c, c.r, x, done);
+        if (k == 0 && x_zero) {
+            launch_smooth(c, b, x, done);
+        } else {
+            if (!(k == 0 && r_valid)) launch_residual(c, b, x, c.r, false, done);
+            launch_smooth(c, c.r, x, done);
+        }
         launch_residual(c, b, x, c.r, false, done);
         if (s.kind == 3) launch_dyn_restrict(c, s, c.r, done);
         else launch_restrict(c, s, c.r, done);
@@ -368,13 +388,23 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
                 const int *done = &c.status->done;
                 double *vj = c.V + (long)j * N;
                 zero_vec(c, c.z, done);
-                cycle(c, vj, c.z, false, done);
-                launch_matvec(c, c.z, w, false, done);
-                launch_multidot(c, c.V, j + 1, w, c.scal + 8, done);
-                launch_multiaxpy(c, c.V, j + 1, c.scal + 8, w, -1.0, false, done);
-                launch_multidot(c, c.V, j + 1, w, c.scal + 80, done);
-                launch_multiaxpy(c, c.V, j + 1, c.scal + 80, w, -1.0, true, done);
+                cycle(c, vj, c.z, false, done, true);
+                launch_matvec(c, c.z, w, true, done);
+                launch_norm_finish(c, c.scal + 2, done);
+                {
+                    ProfScope ps(c, MSRSB_K_ORTHO);
+                    launch_multidot(c, c.V, j + 1, w, c.scal + 8, done);
+                    launch_multiaxpy(c, c.V, j + 1, c.scal + 8, w, -1.0, true, done);
+                }
                 launch_norm_finish(c, c.scal, done);
+                launch_reorth_check(c, j + 1);
+                {
+                    const int *skip = &c.status->skip2;
+                    ProfScope ps(c, MSRSB_K_ORTHO);
+                    launch_multidot(c, c.V, j + 1, w, c.scal + 80, skip);
+                    launch_multiaxpy(c, c.V, j + 1, c.scal + 80, w, -1.0, true, skip);
+                    launch_norm_finish(c, c.scal, skip);
+                }
                 launch_gmres_step(c, j, rtol, max_iters, m);
                 launch_gmres_scale(c, w, c.V + (long)(j + 1) * N, j);
             }
@@ -389,7 +419,7 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
             zero_vec(c, c.u, nullptr);
             launch_multiaxpy(c, c.V, k, c.scal + 4608, c.u, 1.0, false, nullptr);
             zero_vec(c, c.z, nullptr);
-            cycle(c, c.u, c.z, false, nullptr);
+            cycle(c, c.u, c.z, false, nullptr, true);
             launch_axpy(c, x, c.z, nullptr);
         }
     }
@@ -763,7 +793,7 @@ int msrsb_apply(msrsb_ctx *c, int op, const double *d_in, double *d_out) {
             return MSRSB_E_STATE;
         }
         zero_vec(*c, d_out, nullptr);
-        cycle(*c, d_in, d_out, false, nullptr);
+        cycle(*c, d_in, d_out, false, nullptr, true);
         break;
     case MSRSB_OP_MATVEC: launch_matvec(*c, d_in, d_out, false, nullptr); break;
     default: set_error("unknown op %d", op); return MSRSB_E_INVAL;
@@ -881,6 +911,42 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
     return MSRSB_OK;
 }
 
+int msrsb_profile_begin(msrsb_ctx *c, int kernel_class, int max_launches) {
+    g_err.clear();
+    if (!c || kernel_class < 1 || kernel_class > 10 || max_launches < 1 || max_launches > 1000000) {
+        set_error("bad profile arguments");
+        return MSRSB_E_INVAL;
+    }
+    const int need = 2 * max_launches;
+    while ((int)c->prof_ev.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+        c->prof_ev.push_back(e);
+    }
+    c->prof_used = 0;
+    c->prof_class = kernel_class;
+    return MSRSB_OK;
+}
+
+int msrsb_profile_end(msrsb_ctx *c, double *total_ms, int *launches) {
+    g_err.clear();
+    if (!c) return MSRSB_E_INVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "profile sync");
+    double tot = 0.0;
+    for (int k = 0; k + 1 < c->prof_used; k += 2) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, c->prof_ev[k], c->prof_ev[k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = c->prof_used / 2;
+    c->prof_class = -1;
+    c->prof_used = 0;
+    return MSRSB_OK;
+}
+
 int msrsb_set_stream(msrsb_ctx *c, void *hip_stream) {
     if (!c) return MSRSB_E_INVAL;
     c->stream = (hipStream_t)hip_stream;
@@ -892,6 +958,7 @@ void msrsb_destroy(msrsb_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     for (void *p : c->allocs) hipFree(p);
+    for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
     if (c->h_status) hipHostFree(c->h_status);
     delete c;
 }

@@ -52,6 +52,18 @@ __device__ inline double block_max(double v, double *lds) {
     return s;
 }
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  xcd_block renumbers them so that XCD x runs one
+// contiguous range of logical blocks: stencil neighbours in the next row or
+// layer are then read through the same L2.  The grid must be a multiple of
+// kXcd (xcd_grid rounds up); logical ids past the real block count exit.
+constexpr int kXcd = 8;
+__device__ inline int xcd_block() {
+    const int per = gridDim.x / kXcd;
+    return (blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+}
+inline int xcd_grid(int nblocks) { return ((nblocks + kXcd - 1) / kXcd) * kXcd; }
+
 __device__ inline float bf16_to_float(uint16_t u) { return __uint_as_float(((uint32_t)u) << 16); }
 
 // Round-to-nearest-even FP32 -> BF16 (finite inputs).

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(CartDev cd, Fine g, const PT *
                                                   const int *done) {
     __shared__ double lds[kBlock / 64];
     if (*done) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     double chg = 0.0;
     if (i < g.N) {
         const long N = g.N;
@@ -176,7 +176,7 @@ template <typename PT>
 static void sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
                            unsigned long long *bits, int check_blocks) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    const dim3 grid(cdiv(c.N, kBlock)), blk(kBlock);
+    const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
     const PT om = (PT)c.opt.omega;
     const int *done = &c.status->done;
     switch (s.ns) {
@@ -232,6 +232,7 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
             const int kend = std::min(max_sweeps, k + chunk);
             for (; k < kend; ++k) {
                 const int in = (s.cur + k) & 1, out = in ^ 1;
+                ProfScope ps(c, MSRSB_K_SWEEP);
                 if (mixed)
                     sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out], c.maxbits + k,
                                           check_blocks);
@@ -272,41 +273,91 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
 
 // ------------------------------------------------- restriction / prolongation
 
-// d_j = sum over the support box of block j of P_ij r_i; one workgroup per
-// block, fixed-order tree sum (no atomics).
+// d = P^T r in two deterministic passes.
+// Pass 1 (k_restrict_tile): each coarse block B reads its own cells once.
+// Along every split axis the cells of B fall into two groups, g = -1 (cells
+// whose first support block is B-1, i.e. left of B's centre) and g = 0; inside
+// one of the (up to) 8 group boxes every cell has the same lo, so slot s
+// always maps to the same block and the products P_is r_i can be summed per
+// slot in registers.  part[(B*8 + group)*NS + s] = sum over the group box.
+// Pass 2 (k_restrict_gather): d_J adds, in a fixed order, the partials of the
+// group boxes whose slot s points at J: per axis (B, g, s) with B + g + s = J.
 template <int NS, typename PS>
-__global__ __launch_bounds__(kBlock) void k_restrict(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                     const double *__restrict__ r, double *__restrict__ d,
-                                                     const int *done) {
-    __shared__ double lds[kBlock / 64];
+__global__ __launch_bounds__(512) void k_restrict_tile(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                       const double *__restrict__ r, double *__restrict__ part,
+                                                       const int *done) {
     if (done && *done) return;
     const int j = blockIdx.x;
+    const int o = threadIdx.x >> 6, lane = threadIdx.x & 63;  // one wavefront per group box
     const int cid = cd.present[j];
-    int J[3] = {cid % cd.m[0], (cid / cd.m[0]) % cd.m[1], cid / (cd.m[0] * cd.m[1])};
-    int b0[3], sz[3];
+    const int J[3] = {cid % cd.m[0], (cid / cd.m[0]) % cd.m[1], cid / (cd.m[0] * cd.m[1])};
+    int b0[3], nb[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        b0[a] = cd.slo[a][J[a]];
-        sz[a] = cd.shi[a][J[a]] - b0[a] + 1;
-    }
-    const int vol = sz[0] * sz[1] * sz[2];
-    double acc = 0.0;
-    for (int t = threadIdx.x; t < vol; t += blockDim.x) {
-        const int cx = b0[0] + t % sz[0];
-        const int rem = t / sz[0];
-        const int cy = b0[1] + rem % sz[1];
-        const int cz = b0[2] + rem / sz[1];
-        const int i = cx + g.nx * (cy + g.ny * cz);
-        if (g.diag[i] > 0.0) {
-            int s = 0;
-            if (cd.bit[0] >= 0) s |= (J[0] - cd.lo[0][cx]) << cd.bit[0];
-            if (cd.bit[1] >= 0) s |= (J[1] - cd.lo[1][cy]) << cd.bit[1];
-            if (cd.bit[2] >= 0) s |= (J[2] - cd.lo[2][cz]) << cd.bit[2];
-            acc += ld_basis(P, (long)s * g.N + i) * r[i];
+        const int sp = cd.split[a][J[a]];
+        if ((o >> a) & 1) {  // group 0
+            b0[a] = sp;
+            nb[a] = cd.be[a][J[a] + 1] - sp;
+        } else {             // group -1
+            b0[a] = cd.be[a][J[a]];
+            nb[a] = sp - b0[a];
         }
     }
-    const double sum = block_sum(acc, lds);
-    if (threadIdx.x == 0) d[j] = sum;
+    const int vol = (nb[0] > 0 && nb[1] > 0 && nb[2] > 0) ? nb[0] * nb[1] * nb[2] : 0;
+    double acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int t = lane; t < vol; t += 64) {
+        const int cx = b0[0] + t % nb[0], rem = t / nb[0];
+        const int cy = b0[1] + rem % nb[1], cz = b0[2] + rem / nb[1];
+        const long i = cx + (long)g.nx * (cy + (long)g.ny * cz);
+        const double ri = r[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] += ld_basis(P, (long)s * g.N + i) * ri;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double v = wave_sum(acc[s]);
+        if (lane == 0) part[((long)j * 8 + o) * NS + s] = v;
+    }
+}
+
+// One wavefront per block J; lane q takes combination q of the per-axis
+// (B, g, s) triples; the wave sum has a fixed shape.
+template <int NS>
+__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, int M, const double *__restrict__ part,
+                                                         double *__restrict__ d, const int *done) {
+    if (done && *done) return;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int q = threadIdx.x & 63;
+    if (j >= M) return;
+    const int cid = cd.present[j];
+    const int J[3] = {cid % cd.m[0], (cid / cd.m[0]) % cd.m[1], cid / (cd.m[0] * cd.m[1])};
+    const int cb[4] = {1, 0, 0, -1}, cg[4] = {-1, -1, 0, 0}, cs[4] = {0, 1, 0, 1};
+    double v = 0.0;
+    int rem = q, B[3], o = 0, s = 0;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (cd.bit[a] < 0) {
+            B[a] = J[a];
+            o |= 1 << a;  // one block along the axis: all cells are in group 0
+            continue;
+        }
+        const int c = rem & 3;
+        rem >>= 2;
+        B[a] = J[a] + cb[c];
+        if (B[a] < 0 || B[a] >= cd.m[a]) ok = false;
+        o |= (cg[c] + 1) << a;
+        s |= cs[c] << cd.bit[a];
+    }
+    if (rem != 0) ok = false;  // lanes beyond 4^(split axes)
+    if (ok) {
+        const int jb = cd.cmap[B[0] + cd.m[0] * (B[1] + cd.m[1] * B[2])];
+        if (jb >= 0) v = part[((long)jb * 8 + o) * NS + s];
+    }
+    v = wave_sum(v);
+    if (q == 0) d[j] = v;
 }
 
 // x_i += sum_s P_is p_c[block(i,s)]
@@ -315,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(CartDev cd, Fine g, const PS
                                                     const double *__restrict__ pc, double *__restrict__ x,
                                                     const int *done) {
     if (done && *done) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= g.N || !(g.diag[i] > 0.0)) return;
     int c[3], lo[3], nv[3];
     cell_coords(g, i, c);
@@ -338,15 +389,27 @@ template <typename PS>
 static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *x, bool restrict_, const int *done) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     if (restrict_) {
-        const dim3 grid(s.M), blk(kBlock);
+        const dim3 grid(s.M), blk(512), fgrid(cdiv(s.M, 4)), fblk(256);
         switch (s.ns) {
-        case 1: hipLaunchKernelGGL((k_restrict<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.dvec, done); break;
-        case 2: hipLaunchKernelGGL((k_restrict<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.dvec, done); break;
-        case 4: hipLaunchKernelGGL((k_restrict<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.dvec, done); break;
-        default: hipLaunchKernelGGL((k_restrict<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.dvec, done); break;
+        case 1:
+            hipLaunchKernelGGL((k_restrict_tile<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<1>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_restrict_tile<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<2>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_restrict_tile<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<4>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            break;
+        default:
+            hipLaunchKernelGGL((k_restrict_tile<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<8>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            break;
         }
     } else {
-        const dim3 grid(cdiv(c.N, kBlock)), blk(kBlock);
+        const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
         switch (s.ns) {
         case 1: hipLaunchKernelGGL((k_prolong<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
         case 2: hipLaunchKernelGGL((k_prolong<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
@@ -357,11 +420,13 @@ static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *
 }
 
 void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done) {
+    ProfScope ps(c, MSRSB_K_RESTRICT);
     if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, r, nullptr, true, done);
     else rp_dispatch<double>(c, s, s.P64[s.cur], r, nullptr, true, done);
 }
 
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done) {
+    ProfScope ps(c, MSRSB_K_PROLONG);
     if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, nullptr, x, false, done);
     else rp_dispatch<double>(c, s, s.P64[s.cur], nullptr, x, false, done);
 }
@@ -573,6 +638,7 @@ static void rap_dispatch(Ctx &c, Stage &s, const PS *P) {
 }
 
 void launch_rap(Ctx &c, Stage &s) {
+    ProfScope ps(c, MSRSB_K_RAP);
     hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
     if (c.opt.precision == MSRSB_MIXED) rap_dispatch<uint16_t>(c, s, s.Pbf);
     else rap_dispatch<double>(c, s, s.P64[s.cur]);

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double *__restrict__ A, int M
 }
 
 void launch_coarse_inverse(Ctx &c, Stage &s) {
+    ProfScope ps(c, MSRSB_K_INVERSE);
     const int nt = s.Mp / T_;
     double *A = s.Ainv;
     hipMemcpyAsync(A, s.Ac, sizeof(double) * (size_t)s.Mp * s.Mp, hipMemcpyDeviceToDevice, c.stream);
@@ -126,6 +127,7 @@ __global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, int 
 }
 
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done) {
+    ProfScope ps(c, MSRSB_K_COARSE);
     hipLaunchKernelGGL(k_gemv, dim3(cdiv(s.M, 4)), dim3(256), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec, s.pc, done);
 }
 

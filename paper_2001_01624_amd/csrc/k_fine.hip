@@ -22,7 +22,7 @@ static Fine fine_of(const Ctx &c) {
     return g;
 }
 
-static int red_grid(int N) { return std::min(kRedBlocks, cdiv(N, kBlock)); }
+static int red_grid(int N) { return xcd_grid(std::min(kRedBlocks, cdiv(N, kBlock))); }
 
 // (A x)_i for an active cell with diagonal d.
 __device__ inline double ax_row(const Fine &g, const double *__restrict__ x, int i, double d) {
@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+    const int lb = xcd_block();
+    for (int i = lb * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
         const double d = g.diag[i];
         double ri = 0.0;
         if (d > 0.0) ri = b[i] - ax_row(g, x, i, d);
@@ -118,11 +119,12 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
     }
     if (NORM) {
         const double s = block_sum(acc, lds);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[lb] = s;
     }
 }
 
 void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done) {
+    ProfScope ps(c, MSRSB_K_RESIDUAL);
     Fine g = fine_of(c);
     const int grid = red_grid(c.N);
     if (norm)
@@ -137,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Fine g, const double *__restr
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+    const int lb = xcd_block();
+    for (int i = lb * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
         const double d = g.diag[i];
         const double v = d > 0.0 ? ax_row(g, x, i, d) : 0.0;
         y[i] = v;
@@ -145,11 +148,12 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Fine g, const double *__restr
     }
     if (NORM) {
         const double s = block_sum(acc, lds);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[lb] = s;
     }
 }
 
 void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done) {
+    ProfScope ps(c, MSRSB_K_MATVEC);
     Fine g = fine_of(c);
     const int grid = red_grid(c.N);
     if (norm)
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restri
                                                       double *__restrict__ e, double *__restrict__ x,
                                                       const int *done) {
     if (done && *done) return;
-    const int i = colour_cell(g, 1, blockIdx.x * blockDim.x + threadIdx.x);
+    const int i = colour_cell(g, 1, xcd_block() * blockDim.x + threadIdx.x);
     if (i < 0) return;
     const TT dt = dtil[i];
     if (!(dt > (TT)0)) return;
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
                                                     const double *__restrict__ r, const double *__restrict__ e,
                                                     double *__restrict__ x, const int *done) {
     if (done && *done) return;
-    const int i = colour_cell(g, 0, blockIdx.x * blockDim.x + threadIdx.x);
+    const int i = colour_cell(g, 0, xcd_block() * blockDim.x + threadIdx.x);
     if (i < 0) return;
     const TT d = diag[i];
     if (!(d > (TT)0)) return;
@@ -231,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
 }
 
 void launch_smooth(Ctx &c, const double *r, double *x, const int *done) {
+    ProfScope ps(c, MSRSB_K_SMOOTH);
     Fine g = fine_of(c);
     const bool mixed = c.opt.precision == MSRSB_MIXED;
     if (c.opt.smoother == MSRSB_SMOOTH_JACOBI) {
@@ -243,7 +248,7 @@ void launch_smooth(Ctx &c, const double *r, double *x, const int *done) {
         return;
     }
     const int half = ((c.nx + 1) / 2) * c.ny * c.nz;
-    const dim3 grid(cdiv(half, kBlock));
+    const dim3 grid(xcd_grid(cdiv(half, kBlock)));
     if (mixed) {
         hipLaunchKernelGGL(k_ilu_black<float>, grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32,
                            c.dtil32, r, c.e, x, done);
@@ -323,17 +328,37 @@ void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf) {
 // Classical Gram-Schmidt in two passes (CGS2): h = V^T w, w -= V h, twice.
 // Dots use a fixed grid and a fixed-order final sum.
 
+// partial[j][block] = sum over the block's cells of V_j w, eight vectors per
+// pass over w (register accumulators, one combined reduction per pass).
 __global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__restrict__ V, int k,
                                                      const double *__restrict__ w, double *__restrict__ partial,
                                                      const int *done) {
-    __shared__ double lds[kBlock / 64];
+    __shared__ double red[8][kBlock / 64];
     if (done && *done) return;
-    for (int j = 0; j < k; ++j) {
-        const double *v = V + (long)j * N;
-        double acc = 0.0;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) acc += v[i] * w[i];
-        const double s = block_sum(acc, lds);
-        if (threadIdx.x == 0) partial[(long)j * gridDim.x + blockIdx.x] = s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        const int nb = min(8, k - j0);
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nb) acc[q] += V[(long)(j0 + q) * N + i] * wi;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red[q][wv] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            double t = 0.0;
+            for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[threadIdx.x][m];
+            partial[(long)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -491,6 +516,18 @@ __global__ void k_axpy(int N, double *__restrict__ x, const double *__restrict__
 
 void launch_axpy(Ctx &c, double *x, const double *z, const int *done) {
     hipLaunchKernelGGL(k_axpy, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, x, z, done);
+}
+
+// Second Gram-Schmidt pass only when the first removed most of w
+// (||w_after|| < 0.7 ||w_before||, the Daniel-Gragg-Kaufman-Stewart test);
+// scal[2] = ||w_before||^2, scal[0] = ||w_after||^2.  Clears h2 either way.
+__global__ void k_reorth_check(Status *st, double *scal, int k) {
+    for (int i = 0; i < k; ++i) scal[S_H2 + i] = 0.0;
+    st->skip2 = (st->done || !(scal[0] < 0.49 * scal[2])) ? 1 : 0;
+}
+
+void launch_reorth_check(Ctx &c, int k) {
+    hipLaunchKernelGGL(k_reorth_check, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, k);
 }
 
 // exported for the solver driver

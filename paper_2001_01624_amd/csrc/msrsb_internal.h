@@ -35,6 +35,7 @@ struct CartDev {
     int ns;                       // slots per cell = 2^(#axes with m_d > 1)
     const int32_t *lo[3], *nv[3], *slo[3], *shi[3];
     const int32_t *be[3];         // block start per axis (m+1 entries)
+    const int32_t *split[3];      // per block: first cell whose first support block is the block itself
     const int32_t *cmap;          // Cartesian block -> compact id (-1 dropped)
     const int32_t *present;       // compact id -> Cartesian block
 };
@@ -48,7 +49,7 @@ struct Stage {
     int32_t *d_tab = nullptr;     // one allocation holding every table
     std::vector<int32_t> h_present;
     std::vector<int32_t> h_tab;   // host copy of the tables (export, checks)
-    int tab_off[3][5] = {};       // offsets of lo/nv/slo/shi/be per axis in h_tab
+    int tab_off[3][6] = {};       // offsets of lo/nv/slo/shi/be/split per axis in h_tab
     int32_t *gbase = nullptr;     // [m0*m1*m2+1] active cells before each Cartesian block
     // basis values, slot-major [ns*N]
     double *P64[2] = {nullptr, nullptr};
@@ -65,6 +66,8 @@ struct Stage {
     // coarse operator and its inverse (Mp x Mp, row-major), coarse vectors
     double *Ac = nullptr, *Ainv = nullptr;
     double *dvec = nullptr, *pc = nullptr;
+    // restriction partial sums per (block, group box, slot)
+    double *rpart = nullptr;
 };
 
 struct Status {                   // device-side solver status (one struct per context)
@@ -72,6 +75,7 @@ struct Status {                   // device-side solver status (one struct per c
     int iters;                    // iterations completed
     int flag;                     // error bits (1: singular pivot, 2: row sum <= 0)
     int jcur;                     // GMRES: inner index of the next Arnoldi step
+    int skip2;                    // GMRES: 1 = second Gram-Schmidt pass not needed (or done)
     double relres;
     double bnorm;
     double change_bits_dummy;
@@ -79,6 +83,10 @@ struct Status {                   // device-side solver status (one struct per c
 
 struct Ctx {
     hipStream_t stream = nullptr;
+    // launch timing of one kernel class (msrsb_profile_begin/end)
+    int prof_class = -1;
+    std::vector<hipEvent_t> prof_ev;  // pairs: start, stop
+    int prof_used = 0;
     int device = 0;
     msrsb_options opt{};
     int nx = 0, ny = 0, nz = 0, N = 0, n_active = 0;
@@ -113,6 +121,22 @@ struct Ctx {
     std::vector<void *> allocs;   // every device allocation (freed at destroy)
 };
 
+// Brackets the launches of one kernel class with HIP events when that class
+// is being timed.
+struct ProfScope {
+    Ctx &c;
+    bool on;
+    ProfScope(Ctx &cc, int cls) : c(cc), on(cc.prof_class == cls && cc.prof_used + 2 <= (int)cc.prof_ev.size()) {
+        if (on) (void)hipEventRecord(c.prof_ev[c.prof_used], c.stream);
+    }
+    ~ProfScope() {
+        if (on) {
+            (void)hipEventRecord(c.prof_ev[c.prof_used + 1], c.stream);
+            c.prof_used += 2;
+        }
+    }
+};
+
 // ---- error helpers (capi.hip) ----
 void set_error(const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
@@ -140,6 +164,7 @@ void launch_gmres_step(Ctx &c, int j, double rtol, int max_iters, int restart);
 void launch_gmres_scale(Ctx &c, const double *w, double *v, int j);
 void launch_gmres_solve_small(Ctx &c, int restart);
 void launch_axpy(Ctx &c, double *x, const double *z, const int *done);
+void launch_reorth_check(Ctx &c, int k);
 
 // ---- basis kernels (k_basis.hip) ----
 int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *sweeps, double *change);
