@@ -197,6 +197,12 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
             split[J] = sp;
         }
         s.tab_off[a][5] = (int)tab.size(); tab.insert(tab.end(), split.begin(), split.end());
+        std::vector<int32_t> pack(n[a]);
+        for (int i = 0; i < n[a]; ++i) {
+            const int dm = i > 0 ? lo[i] - lo[i - 1] : 0, dp = i + 1 < n[a] ? lo[i + 1] - lo[i] : 0;
+            pack[i] = lo[i] | ((nv[i] == 2) << 20) | (dm << 21) | (dp << 22);
+        }
+        s.tab_off[a][6] = (int)tab.size(); tab.insert(tab.end(), pack.begin(), pack.end());
     }
     // blocks with active cells, compacted in Cartesian order; active cells per block
     const int M0 = cd.m[0] * cd.m[1] * cd.m[2];
@@ -237,6 +243,7 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         cd.shi[a] = s.d_tab + s.tab_off[a][3];
         cd.be[a] = s.d_tab + s.tab_off[a][4];
         cd.split[a] = s.d_tab + s.tab_off[a][5];
+        cd.pack[a] = s.d_tab + s.tab_off[a][6];
     }
     cd.cmap = s.d_tab + cmap_off;
     cd.present = s.d_tab + pres_off;
@@ -257,7 +264,11 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     s.dvec = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
     s.pc = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
     if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
-    s.rpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.M * 8 * s.ns);
+    if (c.nx > 64 * 4) {
+        set_error("rows longer than 256 cells are not supported by the restriction kernel");
+        return MSRSB_E_INVAL;
+    }
+    s.rpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)c.nz * cd.m[1] * cd.m[0] * s.ns);
     if (!s.rpart) return MSRSB_E_NOMEM;
     return MSRSB_OK;
 }
@@ -389,24 +400,7 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
                 double *vj = c.V + (long)j * N;
                 zero_vec(c, c.z, done);
                 cycle(c, vj, c.z, false, done, true);
-                launch_matvec(c, c.z, w, true, done);
-                launch_norm_finish(c, c.scal + 2, done);
-                {
-                    ProfScope ps(c, MSRSB_K_ORTHO);
-                    launch_multidot(c, c.V, j + 1, w, c.scal + 8, done);
-                    launch_multiaxpy(c, c.V, j + 1, c.scal + 8, w, -1.0, true, done);
-                }
-                launch_norm_finish(c, c.scal, done);
-                launch_reorth_check(c, j + 1);
-                {
-                    const int *skip = &c.status->skip2;
-                    ProfScope ps(c, MSRSB_K_ORTHO);
-                    launch_multidot(c, c.V, j + 1, w, c.scal + 80, skip);
-                    launch_multiaxpy(c, c.V, j + 1, c.scal + 80, w, -1.0, true, skip);
-                    launch_norm_finish(c, c.scal, skip);
-                }
-                launch_gmres_step(c, j, rtol, max_iters, m);
-                launch_gmres_scale(c, w, c.V + (long)(j + 1) * N, j);
+                launch_arnoldi(c, c.z, w, j, rtol, max_iters, m);
             }
             if ((rc = read_status(c))) return rc;
             if (c.h_status->done) break;
@@ -527,7 +521,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     const size_t N = c.N;
     size_t b = N * 8 * 3 + N * 4 * 3 + N * 8 * 6 + N * 4 * 2;  // T, T32, diag/b/src/bcdiag/bcrhs/dtil, f32 copies
     b += N * 8 * 5;                                          // work vectors
-    b += (size_t)kRedBlocks * (kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
+    b += (size_t)kRedBlocks * (2 * kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
     if (o.outer == MSRSB_GMRES) b += (size_t)(o.restart + 1) * N * 8;
     b += (size_t)g->n_bc * 24;
     long cb = 0;
@@ -608,7 +602,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     c->tmp = (double *)alloc(8 * (size_t)N);
     c->z = (double *)alloc(8 * (size_t)N);
     c->u = (double *)alloc(8 * (size_t)N);
-    c->partial = (double *)alloc(8 * (size_t)kRedBlocks * (kMaxRestart + 2));
+    c->partial = (double *)alloc(8 * (size_t)kRedBlocks * (2 * kMaxRestart + 2));
     c->scal = (double *)alloc(8 * 8192);
     c->status = (Status *)alloc(sizeof(Status));
     c->maxbits = (unsigned long long *)alloc(8 * 65536);

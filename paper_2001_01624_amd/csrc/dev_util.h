@@ -64,6 +64,19 @@ __device__ inline int xcd_block() {
 }
 inline int xcd_grid(int nblocks) { return ((nblocks + kXcd - 1) / kXcd) * kXcd; }
 
+// Traversal order of the stencil kernels: thread t visits the cell with x
+// fastest, then z, then y.  Memory stays x-y-z; only the visiting order
+// changes, so that the largest neighbour reuse distance is one x-z slice
+// (nx*nz cells) rather than one x-y layer.  Returns -1 past the end.
+__device__ inline int xzy_cell(int t, int nx, int ny, int nz) {
+    const int nxz = nx * nz;
+    const int y = t / nxz;
+    if (y >= ny) return -1;
+    const int r = t - y * nxz;
+    const int z = r / nx, x = r - z * nx;
+    return x + nx * (y + ny * z);
+}
+
 __device__ inline float bf16_to_float(uint16_t u) { return __uint_as_float(((uint32_t)u) << 16); }
 
 // Round-to-nearest-even FP32 -> BF16 (finite inputs).

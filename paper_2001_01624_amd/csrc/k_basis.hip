@@ -70,6 +70,12 @@ __global__ void k_basis_init(CartDev cd, Fine g, PT *__restrict__ P) {
 // with A_b the zero-row-sum part of A (face transmissibilities only, so
 // (A_b P)_is = sum_l T_il (P_is - P_l,s)) and D_b its diagonal.  The largest
 // entry change goes to maxbits (bit pattern of a non-negative double).
+//
+// Neighbour l of cell i along a split axis holds block lo_i + b (slot bit b)
+// in its slot bit b + (lo_i - lo_l), where lo_i - lo_l is 0 or +-1; a shifted
+// bit outside {0,1} means the block is not in l's support (value 0).  Slots
+// with bit b >= nv_l hold exact zeros, so no other test is needed.  The
+// per-axis table word packs lo, nv and the two neighbour shifts.
 template <int NS, typename PT>
 __global__ __launch_bounds__(kBlock) void k_sweep(CartDev cd, Fine g, const PT *__restrict__ tx,
                                                   const PT *__restrict__ ty, const PT *__restrict__ tz,
@@ -78,26 +84,34 @@ __global__ __launch_bounds__(kBlock) void k_sweep(CartDev cd, Fine g, const PT *
                                                   const int *done) {
     __shared__ double lds[kBlock / 64];
     if (*done) return;
-    const int i = xcd_block() * blockDim.x + threadIdx.x;
+    const int i = xzy_cell(xcd_block() * blockDim.x + threadIdx.x, g.nx, g.ny, g.nz);
     double chg = 0.0;
-    if (i < g.N) {
+    if (i >= 0) {
         const long N = g.N;
         if (!(g.diag[i] > 0.0)) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) Pout[s * N + i] = (PT)0;
         } else {
-            int c[3], lo[3], nv[3];
+            int c[3], lo[3], nv2[3], dmin[3], dpl[3];
             cell_coords(g, i, c);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                lo[a] = cd.lo[a][c[a]];
-                nv[a] = cd.nv[a][c[a]];
+                const int w = cd.pack[a][c[a]];
+                lo[a] = w & 0xFFFFF;
+                nv2[a] = (w >> 20) & 1;
+                dmin[a] = (w >> 21) & 1;  // lo[c] - lo[c-1]
+                dpl[a] = (w >> 22) & 1;   // lo[c+1] - lo[c]
             }
-            bool ok[NS];
             PT p[NS], acc[NS];
+            bool ok[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                ok[s] = slot_ok(cd, nv, s) && (!check_blocks || slot_block(cd, lo, s) >= 0);
+                bool v = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (cd.bit[a] >= 0 && ((s >> cd.bit[a]) & 1) > nv2[a]) v = false;
+                if (check_blocks && v && slot_block(cd, lo, s) < 0) v = false;
+                ok[s] = v;
                 p[s] = Pin[s * N + i];
                 acc[s] = (PT)0;
             }
@@ -120,39 +134,39 @@ __global__ __launch_bounds__(kBlock) void k_sweep(CartDev cd, Fine g, const PT *
                 }
                 if (T == (PT)0) continue;
                 db += T;
-                const int cl = c[a] + (up ? 1 : -1);
-                const int delta = lo[a] - cd.lo[a][cl];
-                const int nvl = cd.nv[a][cl];
                 const int bit = cd.bit[a];
+                if (bit < 0) {
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (!ok[s]) continue;
-                    int s2 = s;
-                    if (bit >= 0) {
-                        const int sd2 = ((s >> bit) & 1) + delta;
-                        if (sd2 < 0 || sd2 >= nvl) continue;
-                        s2 = (s & ~(1 << bit)) | (sd2 << bit);
+                    for (int s = 0; s < NS; ++s) acc[s] += T * Pin[s * N + l];
+                } else {
+                    const int d = up ? -dpl[a] : dmin[a];  // lo_i - lo_l
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        const int sd2 = ((s >> bit) & 1) + d;
+                        const int s2 = (s & ~(1 << bit)) | ((sd2 & 1) << bit);
+                        const PT v = Pin[s2 * N + l];
+                        acc[s] += ((unsigned)sd2 <= 1u) ? T * v : (PT)0;
                     }
-                    acc[s] += T * Pin[s2 * N + l];
                 }
             }
+            const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
             PT pn[NS];
             PT rs = (PT)0;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                PT v = (PT)0;
-                if (ok[s]) v = db > (PT)0 ? p[s] - omega * ((db * p[s] - acc[s]) / db) : p[s];
-                pn[s] = v;
-                rs += v;
+                const PT v = db > (PT)0 ? p[s] - omega * (p[s] - acc[s] * idb) : p[s];
+                pn[s] = ok[s] ? v : (PT)0;
+                rs += pn[s];
             }
             if (!(rs > (PT)0)) {
                 atomicOr(flag, 2);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) Pout[s * N + i] = p[s];
             } else {
+                const PT irs = (PT)1 / rs;
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const PT v = pn[s] / rs;
+                    const PT v = pn[s] * irs;
                     chg = fmax(chg, fabs((double)v - (double)p[s]));
                     Pout[s * N + i] = v;
                 }
@@ -274,90 +288,108 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
 // ------------------------------------------------- restriction / prolongation
 
 // d = P^T r in two deterministic passes.
-// Pass 1 (k_restrict_tile): each coarse block B reads its own cells once.
-// Along every split axis the cells of B fall into two groups, g = -1 (cells
-// whose first support block is B-1, i.e. left of B's centre) and g = 0; inside
-// one of the (up to) 8 group boxes every cell has the same lo, so slot s
-// always maps to the same block and the products P_is r_i can be summed per
-// slot in registers.  part[(B*8 + group)*NS + s] = sum over the group box.
-// Pass 2 (k_restrict_gather): d_J adds, in a fixed order, the partials of the
-// group boxes whose slot s points at J: per axis (B, g, s) with B + g + s = J.
+// Cells whose first support block along every axis is the same (lo = L: the
+// "dual box" between block centres L and L+1) share their eight slot->block
+// maps, so P_is r_i can be summed per slot over a dual box and attributed
+// afterwards.
+// Pass 1 (k_restrict_rows): one wavefront per (dual interval Ly along y,
+// layer z) walks the rows y of that interval; lane x keeps per-slot sums for
+// its own column (its dual interval along x is fixed), so rows are read
+// coalesced and every P entry once.  Lanes of one dual x-interval are then
+// added in lane order:  part[((z*my + Ly)*mx + Lx)*NS + s].
+// Pass 2 (k_restrict_gather): d_J = sum over s, and over the layers z of the
+// dual interval J_z - s_z, of part[z, J_y - s_y, J_x - s_x, s] (fixed order).
+constexpr int kRowChunks = 4;  // rows up to 64*kRowChunks cells
+
+constexpr int kRowWaves = 4;
+
 template <int NS, typename PS>
-__global__ __launch_bounds__(512) void k_restrict_tile(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                       const double *__restrict__ r, double *__restrict__ part,
-                                                       const int *done) {
+__global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                                  const double *__restrict__ r,
+                                                                  double *__restrict__ part, const int *done) {
+    extern __shared__ double red[];  // [kRowWaves][nx][NS]
     if (done && *done) return;
-    const int j = blockIdx.x;
-    const int o = threadIdx.x >> 6, lane = threadIdx.x & 63;  // one wavefront per group box
-    const int cid = cd.present[j];
-    const int J[3] = {cid % cd.m[0], (cid / cd.m[0]) % cd.m[1], cid / (cd.m[0] * cd.m[1])};
-    int b0[3], nb[3];
+    const int Ly = blockIdx.x, z = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int mx = cd.m[0], my = cd.m[1];
+    int y0 = 0, y1 = g.ny;
+    if (cd.bit[1] >= 0) {
+        y0 = Ly == 0 ? 0 : cd.split[1][Ly];
+        y1 = Ly + 1 < my ? cd.split[1][Ly + 1] : g.ny;
+    }
+    const int nch = (g.nx + 63) >> 6;
+    double acc[kRowChunks][NS];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int sp = cd.split[a][J[a]];
-        if ((o >> a) & 1) {  // group 0
-            b0[a] = sp;
-            nb[a] = cd.be[a][J[a] + 1] - sp;
-        } else {             // group -1
-            b0[a] = cd.be[a][J[a]];
-            nb[a] = sp - b0[a];
+    for (int k = 0; k < kRowChunks; ++k)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
+    for (int y = y0 + wv; y < y1; y += kRowWaves) {
+        const long row = (long)g.nx * (y + (long)g.ny * z);
+#pragma unroll
+        for (int k = 0; k < kRowChunks; ++k) {
+            const int x = lane + 64 * k;
+            if (k < nch && x < g.nx) {
+                const long i = row + x;
+                const double ri = r[i];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc[k][s] += ld_basis(P, (long)s * g.N + i) * ri;
+            }
         }
     }
-    const int vol = (nb[0] > 0 && nb[1] > 0 && nb[2] > 0) ? nb[0] * nb[1] * nb[2] : 0;
-    double acc[NS];
+    double *mine = red + (long)wv * g.nx * NS;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-    for (int t = lane; t < vol; t += 64) {
-        const int cx = b0[0] + t % nb[0], rem = t / nb[0];
-        const int cy = b0[1] + rem % nb[1], cz = b0[2] + rem / nb[1];
-        const long i = cx + (long)g.nx * (cy + (long)g.ny * cz);
-        const double ri = r[i];
+    for (int k = 0; k < kRowChunks; ++k) {
+        const int x = lane + 64 * k;
+        if (k < nch && x < g.nx)
 #pragma unroll
-        for (int s = 0; s < NS; ++s) acc[s] += ld_basis(P, (long)s * g.N + i) * ri;
+            for (int s = 0; s < NS; ++s) mine[x * NS + s] = acc[k][s];
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const double v = wave_sum(acc[s]);
-        if (lane == 0) part[((long)j * 8 + o) * NS + s] = v;
+    __syncthreads();
+    // thread (Lx, s) adds waves, then columns of dual x-interval Lx, in order
+    for (int t = threadIdx.x; t < mx * NS; t += blockDim.x) {
+        const int Lx = t / NS, s = t % NS;
+        int x0 = 0, x1 = g.nx;
+        if (cd.bit[0] >= 0) {
+            x0 = Lx == 0 ? 0 : cd.split[0][Lx];
+            x1 = Lx + 1 < mx ? cd.split[0][Lx + 1] : g.nx;
+        }
+        double tot = 0.0;
+        for (int x = x0; x < x1; ++x)
+            for (int w = 0; w < kRowWaves; ++w) tot += red[((long)w * g.nx + x) * NS + s];
+        part[(((long)z * my + Ly) * mx + Lx) * NS + s] = tot;
     }
 }
 
-// One wavefront per block J; lane q takes combination q of the per-axis
-// (B, g, s) triples; the wave sum has a fixed shape.
 template <int NS>
-__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, int M, const double *__restrict__ part,
+__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
                                                          double *__restrict__ d, const int *done) {
     if (done && *done) return;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int q = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     if (j >= M) return;
+    const int mx = cd.m[0], my = cd.m[1], mz = cd.m[2];
     const int cid = cd.present[j];
-    const int J[3] = {cid % cd.m[0], (cid / cd.m[0]) % cd.m[1], cid / (cd.m[0] * cd.m[1])};
-    const int cb[4] = {1, 0, 0, -1}, cg[4] = {-1, -1, 0, 0}, cs[4] = {0, 1, 0, 1};
+    const int J[3] = {cid % mx, (cid / mx) % my, cid / (mx * my)};
+    // work items: (slot s, layer z of the dual interval J_z - s_z)
     double v = 0.0;
-    int rem = q, B[3], o = 0, s = 0;
-    bool ok = true;
+    for (int s = 0; s < NS; ++s) {
+        int L[3];
+        bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (cd.bit[a] < 0) {
-            B[a] = J[a];
-            o |= 1 << a;  // one block along the axis: all cells are in group 0
-            continue;
+        for (int a = 0; a < 3; ++a) {
+            L[a] = J[a] - (cd.bit[a] >= 0 ? (s >> cd.bit[a]) & 1 : 0);
+            if (L[a] < 0) ok = false;
         }
-        const int c = rem & 3;
-        rem >>= 2;
-        B[a] = J[a] + cb[c];
-        if (B[a] < 0 || B[a] >= cd.m[a]) ok = false;
-        o |= (cg[c] + 1) << a;
-        s |= cs[c] << cd.bit[a];
-    }
-    if (rem != 0) ok = false;  // lanes beyond 4^(split axes)
-    if (ok) {
-        const int jb = cd.cmap[B[0] + cd.m[0] * (B[1] + cd.m[1] * B[2])];
-        if (jb >= 0) v = part[((long)jb * 8 + o) * NS + s];
+        if (!ok) continue;
+        int z0 = 0, z1 = g.nz;
+        if (cd.bit[2] >= 0) {
+            z0 = L[2] == 0 ? 0 : cd.split[2][L[2]];
+            z1 = L[2] + 1 < mz ? cd.split[2][L[2] + 1] : g.nz;
+        }
+        for (int z = z0 + lane; z < z1; z += 64) v += part[(((long)z * my + L[1]) * mx + L[0]) * NS + s];
     }
     v = wave_sum(v);
-    if (q == 0) d[j] = v;
+    if (lane == 0) d[j] = v;
 }
 
 // x_i += sum_s P_is p_c[block(i,s)]
@@ -366,8 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(CartDev cd, Fine g, const PS
                                                     const double *__restrict__ pc, double *__restrict__ x,
                                                     const int *done) {
     if (done && *done) return;
-    const int i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= g.N || !(g.diag[i] > 0.0)) return;
+    const int i = xzy_cell(xcd_block() * blockDim.x + threadIdx.x, g.nx, g.ny, g.nz);
+    if (i < 0 || !(g.diag[i] > 0.0)) return;
     int c[3], lo[3], nv[3];
     cell_coords(g, i, c);
 #pragma unroll
@@ -389,23 +421,24 @@ template <typename PS>
 static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *x, bool restrict_, const int *done) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     if (restrict_) {
-        const dim3 grid(s.M), blk(512), fgrid(cdiv(s.M, 4)), fblk(256);
+        const dim3 grid(s.cart.m[1], c.nz), blk(64 * kRowWaves), fgrid(cdiv(s.M, 4)), fblk(256);
+        const size_t lds = sizeof(double) * kRowWaves * (size_t)c.nx * s.ns;
         switch (s.ns) {
         case 1:
-            hipLaunchKernelGGL((k_restrict_tile<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<1>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            hipLaunchKernelGGL((k_restrict_rows<1, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<1>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
             break;
         case 2:
-            hipLaunchKernelGGL((k_restrict_tile<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<2>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            hipLaunchKernelGGL((k_restrict_rows<2, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<2>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
             break;
         case 4:
-            hipLaunchKernelGGL((k_restrict_tile<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<4>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            hipLaunchKernelGGL((k_restrict_rows<4, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<4>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
             break;
         default:
-            hipLaunchKernelGGL((k_restrict_tile<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<8>), fgrid, fblk, 0, c.stream, s.cart, s.M, s.rpart, s.dvec, done);
+            hipLaunchKernelGGL((k_restrict_rows<8, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<8>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
             break;
         }
     } else {

@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
     if (done && *done) return;
     double acc = 0.0;
     const int lb = xcd_block();
-    for (int i = lb * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+    for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += gridDim.x * blockDim.x) {
+        const int i = xzy_cell(t, g.nx, g.ny, g.nz);
         const double d = g.diag[i];
         double ri = 0.0;
         if (d > 0.0) ri = b[i] - ax_row(g, x, i, d);
@@ -140,7 +141,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Fine g, const double *__restr
     if (done && *done) return;
     double acc = 0.0;
     const int lb = xcd_block();
-    for (int i = lb * blockDim.x + threadIdx.x; i < g.N; i += gridDim.x * blockDim.x) {
+    for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += gridDim.x * blockDim.x) {
+        const int i = xzy_cell(t, g.nx, g.ny, g.nz);
         const double d = g.diag[i];
         const double v = d > 0.0 ? ax_row(g, x, i, d) : 0.0;
         y[i] = v;
@@ -174,15 +176,16 @@ __global__ void k_jacobi(int N, const TT *__restrict__ diag, TT omega, const dou
 }
 
 // Cell of colour `col` handled by thread t: rows (y,z) hold ceil(nx/2) slots.
+// (rows visited z fastest, then y: see xzy_cell)
 __device__ inline int colour_cell(const Fine &g, int col, int t) {
     const int hx = (g.nx + 1) >> 1;
     const int row = t / hx;
     if (row >= g.ny * g.nz) return -1;
     const int k = t - row * hx;
-    const int iy = row % g.ny, iz = row / g.ny;
+    const int iz = row % g.nz, iy = row / g.nz;
     const int ix = 2 * k + ((col + iy + iz) & 1);
     if (ix >= g.nx) return -1;
-    return ix + g.nx * row;
+    return ix + g.nx * (iy + g.ny * iz);
 }
 
 // Forward sweep of (D~ + L) w = r restricted to black cells, which in
@@ -528,6 +531,246 @@ __global__ void k_reorth_check(Status *st, double *scal, int k) {
 
 void launch_reorth_check(Ctx &c, int k) {
     hipLaunchKernelGGL(k_reorth_check, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, k);
+}
+
+// ---- fused Arnoldi step (w = A z, two Gram-Schmidt passes, norm) ----------
+// Partials are laid out partial[q*grid + block] for dot q and
+// partial[nd*grid + block] for the squared norm; the finish kernels add them
+// in block order, one wavefront per quantity.
+
+// w = A z; partial dots V_q^T w (q < k) and ||w||^2.
+__global__ __launch_bounds__(kBlock) void k_mvdot(Fine g, const double *__restrict__ z, double *__restrict__ w,
+                                                  const double *__restrict__ V, int k, double *__restrict__ partial,
+                                                  const int *done) {
+    __shared__ double red[9][kBlock / 64];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, G = gridDim.x;
+    double nrm = 0.0;
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        const int nb = min(8, k - j0);
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += G * blockDim.x) {
+            double wi;
+            if (j0 == 0) {
+                const double d = g.diag[i];
+                wi = d > 0.0 ? ax_row(g, z, i, d) : 0.0;
+                w[i] = wi;
+                nrm += wi * wi;
+            } else {
+                wi = w[i];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nb) acc[q] += V[(long)(j0 + q) * g.N + i] * wi;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red[q][wv] = v;
+        }
+        const double vn = wave_sum(nrm);
+        if (lane == 0) red[8][wv] = vn;
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            double t = 0.0;
+            for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[threadIdx.x][m];
+            partial[(long)(j0 + threadIdx.x) * G + blockIdx.x] = t;
+        }
+        if (j0 == 0 && threadIdx.x == 8) {
+            double t = 0.0;
+            for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[8][m];
+            partial[(long)kMaxRestart * 2 * G + blockIdx.x] = t;  // norm slot
+        }
+        __syncthreads();
+    }
+}
+
+// Whether a second Gram-Schmidt pass is due, from ||w - V h||^2 =
+// ||w||^2 - ||h||^2 (V orthonormal): iff that is < 0.49 ||w||^2 (the DGKS
+// test ||w'|| < 0.7 ||w||).  Every kernel that needs the decision evaluates
+// this same expression on the same scalars.
+__device__ inline bool second_pass(const double *scal, int k) {
+    double hh = 0.0;
+    for (int q = 0; q < k; ++q) hh += scal[S_H1 + q] * scal[S_H1 + q];
+    return scal[2] - hh < 0.49 * scal[2];
+}
+
+// One wavefront per quantity: out[q] = sum of dot partials q (q < nd), *nout
+// = sum of the norm partials (q == nd); fixed order.  mode 2 (after the first
+// update): when no second pass is due the dots are not summed and out
+// (h2) is cleared instead.
+__global__ __launch_bounds__(64) void k_finish_dots(const double *__restrict__ partial, int G, int nd,
+                                                    double *__restrict__ out, double *nout, const Status *st,
+                                                    const double *scal, int mode) {
+    if (st->done) return;
+    const int q = blockIdx.x, lane = threadIdx.x;
+    if (mode == 2 && q < nd && !second_pass(scal, nd)) {
+        if (lane == 0) out[q] = 0.0;
+        return;
+    }
+    const long base = q < nd ? (long)q * G : (long)kMaxRestart * 2 * G;
+    double t = 0.0;
+    for (int b = lane; b < G; b += 64) t += partial[base + b];
+    t = wave_sum(t);
+    if (lane == 0) {
+        if (q < nd) out[q] = t;
+        else *nout = t;
+    }
+}
+
+// w -= V h1; if a second pass follows, partial dots V_q^T w; always ||w||^2.
+__global__ __launch_bounds__(kBlock) void k_axpy_dot(int N, const double *__restrict__ V, int k,
+                                                     const double *__restrict__ h, double *__restrict__ w,
+                                                     double *__restrict__ partial, const Status *st,
+                                                     const double *scal) {
+    __shared__ double hs[kMaxRestart + 1];
+    __shared__ double red[9][kBlock / 64];
+    if (st->done) return;
+    const bool dots = second_pass(scal, k);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, G = gridDim.x;
+    for (int q = threadIdx.x; q < k; q += blockDim.x) hs[q] = h[q];
+    __syncthreads();
+    double nrm = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += G * blockDim.x) {
+        double sacc = 0.0;
+        for (int q = 0; q < k; ++q) sacc += hs[q] * V[(long)q * N + i];
+        const double v = w[i] - sacc;
+        w[i] = v;
+        nrm += v * v;
+    }
+    {
+        const double vn = wave_sum(nrm);
+        if (lane == 0) red[8][wv] = vn;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[8][m];
+            partial[(long)kMaxRestart * 2 * G + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+    if (!dots) return;
+    for (int j0 = 0; j0 < k; j0 += 8) {
+        const int nb = min(8, k - j0);
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += G * blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nb) acc[q] += V[(long)(j0 + q) * N + i] * wi;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red[q][wv] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            double t = 0.0;
+            for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[threadIdx.x][m];
+            partial[(long)(j0 + threadIdx.x) * G + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Second pass: w -= V h2 and ||w||^2 partials (only when a second pass is due).
+__global__ __launch_bounds__(kBlock) void k_axpy_norm(int N, const double *__restrict__ V, int k,
+                                                      const double *__restrict__ h, double *__restrict__ w,
+                                                      double *__restrict__ partial, const Status *st,
+                                                      const double *scal) {
+    __shared__ double hs[kMaxRestart + 1];
+    __shared__ double lds[kBlock / 64];
+    if (st->done || !second_pass(scal, k)) return;
+    const int G = gridDim.x;
+    for (int q = threadIdx.x; q < k; q += blockDim.x) hs[q] = h[q];
+    __syncthreads();
+    double nrm = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += G * blockDim.x) {
+        double sacc = 0.0;
+        for (int q = 0; q < k; ++q) sacc += hs[q] * V[(long)q * N + i];
+        const double v = w[i] - sacc;
+        w[i] = v;
+        nrm += v * v;
+    }
+    const double t = block_sum(nrm, lds);
+    if (threadIdx.x == 0) partial[(long)kMaxRestart * 2 * G + blockIdx.x] = t;
+}
+
+// Norm of the orthogonalised w (second pass if any) then Arnoldi step j:
+// H(:,j) = h1 + h2, H(j+1,j) = ||w||, Givens rotations, residual estimate.
+__global__ __launch_bounds__(64) void k_gmres_step2(Status *st, double *scal, const double *__restrict__ partial,
+                                                    int G, int j, double rtol, int max_iters, int restart) {
+    if (st->done) return;
+    double hn2;
+    if (second_pass(scal, j + 1)) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < G; b += 64) t += partial[(long)kMaxRestart * 2 * G + b];
+        hn2 = wave_sum(t);
+    } else {
+        hn2 = scal[3];
+    }
+    if (threadIdx.x != 0) return;
+    double *H = scal + S_H;
+    double *gv = scal + S_G;
+    double *cs = scal + S_CS;
+    double *sn = scal + S_SN;
+    const int ld = kMaxRestart + 1;
+    for (int i = 0; i <= j; ++i) H[i + ld * j] = scal[S_H1 + i] + scal[S_H2 + i];
+    const double hn = sqrt(hn2);
+    H[j + 1 + ld * j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i + ld * j], b = H[i + 1 + ld * j];
+        H[i + ld * j] = cs[i] * a + sn[i] * b;
+        H[i + 1 + ld * j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = H[j + ld * j], b = H[j + 1 + ld * j];
+    const double rr = hypot(a, b);
+    const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? b / rr : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    H[j + ld * j] = rr;
+    H[j + 1 + ld * j] = 0.0;
+    gv[j + 1] = -sj * gv[j];
+    gv[j] = cj * gv[j];
+    st->iters += 1;
+    st->jcur = j + 1;
+    const double rel = fabs(gv[j + 1]) / st->bnorm;
+    st->relres = rel;
+    scal[S_INV] = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (rel <= rtol || st->iters >= max_iters || j + 1 >= restart || hn == 0.0 || !(rel == rel)) st->done = 1;
+}
+
+void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart) {
+    Fine g = fine_of(c);
+    const int G = red_grid(c.N);
+    const int *done = &c.status->done;
+    {
+        ProfScope ps(c, MSRSB_K_MATVEC);
+        hipLaunchKernelGGL(k_mvdot, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, j + 1, c.partial, done);
+    }
+    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(64), 0, c.stream, c.partial, G, j + 1, c.scal + S_H1,
+                       c.scal + 2, (const Status *)c.status, (const double *)c.scal, 1);
+    {
+        ProfScope ps(c, MSRSB_K_ORTHO);
+        hipLaunchKernelGGL(k_axpy_dot, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, j + 1, c.scal + S_H1, w,
+                           c.partial, (const Status *)c.status, (const double *)c.scal);
+    }
+    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(64), 0, c.stream, c.partial, G, j + 1, c.scal + S_H2,
+                       c.scal + 3, (const Status *)c.status, (const double *)c.scal, 2);
+    {
+        ProfScope ps(c, MSRSB_K_ORTHO);
+        hipLaunchKernelGGL(k_axpy_norm, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, j + 1, c.scal + S_H2, w,
+                           c.partial, (const Status *)c.status, (const double *)c.scal);
+    }
+    hipLaunchKernelGGL(k_gmres_step2, dim3(1), dim3(64), 0, c.stream, c.status, c.scal, c.partial, G, j, rtol,
+                       max_iters, restart);
+    hipLaunchKernelGGL(k_scale, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, w,
+                       c.V + (long)(j + 1) * c.N, c.scal + S_INV, done);
 }
 
 // exported for the solver driver

@@ -36,6 +36,7 @@ struct CartDev {
     const int32_t *lo[3], *nv[3], *slo[3], *shi[3];
     const int32_t *be[3];         // block start per axis (m+1 entries)
     const int32_t *split[3];      // per block: first cell whose first support block is the block itself
+    const int32_t *pack[3];       // per cell: lo | (nv==2)<<20 | (lo[c]-lo[c-1])<<21 | (lo[c+1]-lo[c])<<22
     const int32_t *cmap;          // Cartesian block -> compact id (-1 dropped)
     const int32_t *present;       // compact id -> Cartesian block
 };
@@ -49,7 +50,7 @@ struct Stage {
     int32_t *d_tab = nullptr;     // one allocation holding every table
     std::vector<int32_t> h_present;
     std::vector<int32_t> h_tab;   // host copy of the tables (export, checks)
-    int tab_off[3][6] = {};       // offsets of lo/nv/slo/shi/be/split per axis in h_tab
+    int tab_off[3][7] = {};       // offsets of lo/nv/slo/shi/be/split/pack per axis in h_tab
     int32_t *gbase = nullptr;     // [m0*m1*m2+1] active cells before each Cartesian block
     // basis values, slot-major [ns*N]
     double *P64[2] = {nullptr, nullptr};
@@ -106,7 +107,7 @@ struct Ctx {
     double *bc_trans = nullptr, *bc_value = nullptr;
     // work vectors [N]
     double *r = nullptr, *e = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr;
-    double *partial = nullptr;    // [kRedBlocks * (kMaxRestart + 2)]
+    double *partial = nullptr;    // [kRedBlocks * (2 * kMaxRestart + 2)]
     double *cbuf = nullptr;       // coarse inverse column panel [max Mp * kTile]
     long cbuf_n = 0;
     double *scal = nullptr;       // small device scalars / GMRES Hessenberg state
@@ -165,6 +166,7 @@ void launch_gmres_scale(Ctx &c, const double *w, double *v, int j);
 void launch_gmres_solve_small(Ctx &c, int restart);
 void launch_axpy(Ctx &c, double *x, const double *z, const int *done);
 void launch_reorth_check(Ctx &c, int k);
+void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart);
 
 // ---- basis kernels (k_basis.hip) ----
 int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *sweeps, double *change);
