@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kernel", default="sweep", help="kernel class for the roofline object")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -180,6 +182,31 @@ def gpu_leg(args, precision):
     return out
 
 
+def serve_leg(args):
+    """The same seeded Poisson stream (200 requests/s; 10 % layered
+    60x220x85 models with two general stages, 90 % ensemble members
+    32..128 x 32..128 x 8..16 with one 8x8x4 stage; 1-5 solves each) served
+    two ways: FP64, one request at a time; mixed precision with four
+    concurrent slots (continuous batching, HBM-footprint admission)."""
+    from paper_2001_01624_amd import capi
+    from paper_2001_01624_amd.serve import Server
+    from workloads.requests import poisson_stream
+
+    Server(slots=1).run(poisson_stream(2, 200.0, seed=99), realtime=False)  # load kernels
+    out = {}
+    for name, slots, prec in (("fp64_plain", 1, "fp64"), ("mixed_served", 4, "mixed")):
+        reqs = poisson_stream(args.serve_requests, 200.0, seed=0)
+        opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=prec)
+        st = Server(slots=slots, options=opt, rtol=RTOL).run(reqs, realtime=True)
+        out[name] = {"cells_per_s": st["cells_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                     "solves": st["solves"], "requests": st["completed"], "makespan_s": st["makespan_s"],
+                     "all_converged": st["all_converged"], "max_relres": st["max_relres"], "slots": slots}
+    out["speedup"] = out["mixed_served"]["cells_per_s"] / out["fp64_plain"]["cells_per_s"]
+    out["stream"] = (f"{args.serve_requests} requests, Poisson 200/s, 10% layered 60x220x85 (2 stages), 90% "
+                     f"ensemble members (1 stage 8x8x4), 1-5 solves each, rtol {RTOL}")
+    return out
+
+
 def traffic_record(kernel, precision):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source; else None."""
@@ -257,6 +284,7 @@ def main():
         sys.exit(1)
     f64 = gpu_leg(args, "fp64")
     mixed = None if args.no_mixed else gpu_leg(args, "mixed")
+    served = None if args.no_serve else serve_leg(args)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline()
     line = {
         "metric": METRIC,
@@ -291,6 +319,8 @@ def main():
                          "p99_ms": mixed["p99_ms"], "iters": mixed["iters"], "sweeps": mixed["sweeps"],
                          "max_relres": mixed["relres"], "all_converged": mixed["all_converged"],
                          "roofline": mixed["roofline"], "dtype": "f32 sweeps/smoother, bf16 basis, f64 residual"}
+    if served is not None:
+        line["served"] = served
     line["host"] = platform.node()
     print(json.dumps(line))
 
