@@ -273,6 +273,155 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     return MSRSB_OK;
 }
 
+// Fault-cut stage: the pieces of every block of the (rectilinear) parent
+// stage that stay connected without crossing a fault face, numbered by
+// (parent block, smallest cell); the support of a piece is what a breadth-
+// first search from it reaches inside the parent block's support box
+// without crossing a fault face.  Integer work on the host.
+static int build_fault_stage(Ctx &c, const msrsb_partition &p, int index, Stage &s, const double *T3[3]) {
+    if (p.parent < 0 || p.parent >= index || c.stages[p.parent].kind != 0) {
+        set_error("FAULT_CUT partition %d: parent must be an earlier CARTESIAN partition", index);
+        return MSRSB_E_INVAL;
+    }
+    const Stage &par = c.stages[p.parent];
+    const int N = c.N, nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
+    const int step[3] = {1, nx, nxy};
+    const int32_t *pt = par.h_tab.data();
+    const int cmap_off = (int)(par.cart.cmap - par.d_tab);
+    auto pblk = [&](int i) -> int {
+        if (!c.h_active[i]) return -1;
+        const int cc[3] = {i % nx, (i / nx) % ny, i / nxy};
+        int J[3];
+        for (int a = 0; a < 3; ++a) J[a] = (int)(((long)cc[a] * par.cart.m[a]) / par.cart.n[a]);
+        return pt[cmap_off + J[0] + par.cart.m[0] * (J[1] + par.cart.m[1] * J[2])];
+    };
+    std::vector<int32_t> pb(N);
+    for (int i = 0; i < N; ++i) pb[i] = pblk(i);
+    auto open = [&](int i, int a) {
+        return T3[a][i] != 0.0 && !(c.h_fault.size() && c.h_fault[(size_t)a * N + i]);
+    };
+    DSU d(N);
+    for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < N; ++i)
+            if (open(i, a) && pb[i] == pb[i + step[a]]) d.unite(i, i + step[a]);
+    // pieces ordered by (parent block, smallest cell): the DSU root is the smallest cell
+    std::vector<std::pair<int64_t, int>> keys;
+    std::vector<int> root_id(N, -1);
+    for (int i = 0; i < N; ++i)
+        if (c.h_active[i] && d.find(i) == i) keys.push_back({(int64_t)pb[i] * N + i, i});
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 0; k < keys.size(); ++k) root_id[keys[k].second] = (int)k;
+    const int M = (int)keys.size();
+    s.h_xpblock.assign(N, -1);
+    std::vector<std::vector<int>> members(M);
+    for (int i = 0; i < N; ++i)
+        if (c.h_active[i]) {
+            const int j = root_id[d.find(i)];
+            s.h_xpblock[i] = j;
+            members[j].push_back(i);
+        }
+    // supports: BFS inside the parent's support box over open faces
+    std::vector<std::vector<int>> slots(N);
+    std::vector<int> stamp(N, -1), frontier, next;
+    for (int j = 0; j < M; ++j) {
+        const int J = pb[members[j][0]];
+        const int cid = par.h_present[J];
+        const int Jc[3] = {cid % par.cart.m[0], (cid / par.cart.m[0]) % par.cart.m[1],
+                           cid / (par.cart.m[0] * par.cart.m[1])};
+        int lo3[3], hi3[3];
+        for (int a = 0; a < 3; ++a) {
+            lo3[a] = pt[par.tab_off[a][2] + Jc[a]];
+            hi3[a] = pt[par.tab_off[a][3] + Jc[a]];
+        }
+        auto inbox = [&](int i) {
+            const int cc[3] = {i % nx, (i / nx) % ny, i / nxy};
+            for (int a = 0; a < 3; ++a)
+                if (cc[a] < lo3[a] || cc[a] > hi3[a]) return false;
+            return c.h_active[i] != 0;
+        };
+        frontier = members[j];
+        for (int i : frontier) stamp[i] = j;
+        std::vector<int> reached = frontier;
+        while (!frontier.empty()) {
+            next.clear();
+            for (int i : frontier)
+                for (int a = 0; a < 3; ++a) {
+                    if (open(i, a)) {
+                        const int l = i + step[a];
+                        if (stamp[l] != j && inbox(l)) {
+                            stamp[l] = j;
+                            next.push_back(l);
+                        }
+                    }
+                    if (i >= step[a] && open(i - step[a], a)) {
+                        const int l = i - step[a];
+                        if (stamp[l] != j && inbox(l)) {
+                            stamp[l] = j;
+                            next.push_back(l);
+                        }
+                    }
+                }
+            reached.insert(reached.end(), next.begin(), next.end());
+            frontier.swap(next);
+        }
+        for (int i : reached) slots[i].push_back(j);  // j ascending: lists stay sorted
+    }
+    int ns = 1;
+    for (int i = 0; i < N; ++i) ns = std::max(ns, (int)slots[i].size());
+    if (ns > kMaxXSlots) {
+        set_error("fault-cut stage needs %d slots per cell (limit %d)", ns, kMaxXSlots);
+        return MSRSB_E_INVAL;
+    }
+    s.kind = 2;
+    s.parent = p.parent;
+    s.ns = ns;
+    s.M = M;
+    s.Mp = cdiv(M, kTile) * kTile;
+    s.h_xsb.assign((size_t)ns * N, -1);
+    std::vector<int32_t> cnt(M + 1, 0);
+    for (int i = 0; i < N; ++i)
+        for (size_t t = 0; t < slots[i].size(); ++t) {
+            s.h_xsb[t * N + i] = slots[i][t];
+            cnt[slots[i][t] + 1]++;
+        }
+    for (int j = 0; j < M; ++j) cnt[j + 1] += cnt[j];
+    std::vector<int32_t> cell(cnt[M]), pos(cnt.begin(), cnt.end() - 1);
+    std::vector<uint8_t> slot(cnt[M]);
+    for (int i = 0; i < N; ++i)
+        for (size_t t = 0; t < slots[i].size(); ++t) {
+            const int j = slots[i][t];
+            cell[pos[j]] = i;
+            slot[pos[j]] = (uint8_t)t;
+            pos[j]++;
+        }
+    auto upi = [&](int32_t *&dst, const std::vector<int32_t> &h) -> bool {
+        dst = (int32_t *)ctx_alloc(c, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
+        return dst && hipMemcpy(dst, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!upi(s.xsb, s.h_xsb) || !upi(s.xpblock, s.h_xpblock) || !upi(s.xptr, cnt) || !upi(s.xcell, cell))
+        return MSRSB_E_NOMEM;
+    s.xslot = (uint8_t *)ctx_alloc(c, std::max<size_t>(slot.size(), 1));
+    if (!s.xslot || hipMemcpy(s.xslot, slot.data(), slot.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return MSRSB_E_NOMEM;
+    const size_t nsN = (size_t)ns * N;
+    if (c.opt.precision == MSRSB_MIXED) {
+        s.P32[0] = (float *)ctx_alloc(c, sizeof(float) * nsN);
+        s.P32[1] = (float *)ctx_alloc(c, sizeof(float) * nsN);
+        s.Pbf = (uint16_t *)ctx_alloc(c, sizeof(uint16_t) * nsN);
+        if (!s.P32[0] || !s.P32[1] || !s.Pbf) return MSRSB_E_NOMEM;
+    } else {
+        s.P64[0] = (double *)ctx_alloc(c, sizeof(double) * nsN);
+        s.P64[1] = (double *)ctx_alloc(c, sizeof(double) * nsN);
+        if (!s.P64[0] || !s.P64[1]) return MSRSB_E_NOMEM;
+    }
+    s.Ac = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    s.Ainv = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    s.dvec = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
+    s.pc = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
+    if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
+    return MSRSB_OK;
+}
+
 static size_t cart_bytes(const Ctx &c, const msrsb_partition &p) {
     int nbits = 0;
     long M = 1;
@@ -476,8 +625,15 @@ static int check_parts(const msrsb_grid *g, int n_part, const msrsb_partition *p
         return MSRSB_E_INVAL;
     }
     for (int k = 0; k < n_part; ++k) {
+        if (parts[k].kind == MSRSB_PART_FAULT_CUT) {
+            if (parts[k].parent < 0 || parts[k].parent >= k || parts[parts[k].parent].kind != MSRSB_PART_CARTESIAN) {
+                set_error("partition %d: FAULT_CUT needs an earlier CARTESIAN parent", k);
+                return MSRSB_E_INVAL;
+            }
+            continue;
+        }
         if (parts[k].kind != MSRSB_PART_CARTESIAN) {
-            set_error("partition %d: only CARTESIAN partitions are supported by this build", k);
+            set_error("partition %d: unknown kind %d", k, parts[k].kind);
             return MSRSB_E_INVAL;
         }
         const int n[3] = {g->nx, g->ny, g->nz};
@@ -526,8 +682,11 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     b += (size_t)g->n_bc * 24;
     long cb = 0;
     for (int k = 0; k < n_part; ++k) {
-        b += cart_bytes(c, parts[k]);
-        long M = (long)parts[k].coarse_dims[0] * parts[k].coarse_dims[1] * parts[k].coarse_dims[2];
+        const msrsb_partition &pk = parts[k].kind == MSRSB_PART_FAULT_CUT ? parts[parts[k].parent] : parts[k];
+        b += cart_bytes(c, pk);
+        if (parts[k].kind == MSRSB_PART_FAULT_CUT) b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
+        long M = (long)pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
+        if (parts[k].kind == MSRSB_PART_FAULT_CUT) M *= 2;
         cb = std::max(cb, (long)cdiv(M, kTile) * kTile);
     }
     cb = std::max(cb, (long)cdiv(o.max_dyn_blocks, kTile) * kTile);
@@ -555,6 +714,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     (void)hipGetDevice(&c->device);
     c->nx = g->nx; c->ny = g->ny; c->nz = g->nz;
     const int N = c->N = g->nx * g->ny * g->nz;
+    if (g->fault) c->h_fault.assign(g->fault, g->fault + (size_t)3 * N);
     c->h_active.assign(N, 1);
     if (g->active)
         for (int i = 0; i < N; ++i) c->h_active[i] = g->active[i] ? 1 : 0;
@@ -626,8 +786,11 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     }
     c->stages.resize(n_part);
     long cb = cdiv(o.max_dyn_blocks, kTile) * kTile;
+    const double *T3[3] = {g->tx, g->ty, g->tz};
     for (int k = 0; k < n_part; ++k) {
-        if ((rc = build_cart_stage(*c, parts[k], c->stages[k]))) return fail(rc);
+        if (parts[k].kind == MSRSB_PART_FAULT_CUT) rc = build_fault_stage(*c, parts[k], k, c->stages[k], T3);
+        else rc = build_cart_stage(*c, parts[k], c->stages[k]);
+        if (rc) return fail(rc);
         cb = std::max(cb, (long)c->stages[k].Mp);
     }
     c->cbuf = (double *)alloc(8 * (size_t)cb * kTile);
@@ -849,7 +1012,20 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
     }
     const int N = c->N;
     hipError_t e = hipSuccess;
-    if (s->kind == 3) {
+    if (s->kind == 2) {
+        if (h_block) memcpy(h_block, s->h_xpblock.data(), 4 * (size_t)N);
+        if (h_slot_block) memcpy(h_slot_block, s->h_xsb.data(), 4 * (size_t)s->ns * N);
+        if (h_vals) {
+            double *dv = (double *)ctx_alloc(*c, 8 * (size_t)s->ns * N);
+            if (!dv) return MSRSB_E_NOMEM;
+            launch_export_cart(*c, *s, dv);
+            e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess) e = hipMemcpy(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost);
+            hipFree(dv);
+            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
+            if (e != hipSuccess) return hip_fail(e, "export");
+        }
+    } else if (s->kind == 3) {
         std::vector<int32_t> blk(N);
         e = hipMemcpy(blk.data(), s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "export");

@@ -230,7 +230,8 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
     const bool mixed = c.opt.precision == MSRSB_MIXED;
     const int check_blocks = (int)s.h_present.size() != s.cart.m[0] * s.cart.m[1] * s.cart.m[2];
     if (!warm) {
-        if (mixed) init_dispatch<float>(c, s, s.P32[0]);
+        if (s.kind == 2) launch_xinit(c, s);
+        else if (mixed) init_dispatch<float>(c, s, s.P32[0]);
         else init_dispatch<double>(c, s, s.P64[0]);
         s.cur = 0;
     }
@@ -247,7 +248,9 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
             for (; k < kend; ++k) {
                 const int in = (s.cur + k) & 1, out = in ^ 1;
                 ProfScope ps(c, MSRSB_K_SWEEP);
-                if (mixed)
+                if (s.kind == 2)
+                    launch_xsweep(c, s, in, out, c.maxbits + k);
+                else if (mixed)
                     sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out], c.maxbits + k,
                                           check_blocks);
                 else
@@ -454,12 +457,20 @@ static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *
 
 void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done) {
     ProfScope ps(c, MSRSB_K_RESTRICT);
+    if (s.kind == 2) {
+        launch_xrestrict(c, s, r, done);
+        return;
+    }
     if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, r, nullptr, true, done);
     else rp_dispatch<double>(c, s, s.P64[s.cur], r, nullptr, true, done);
 }
 
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done) {
     ProfScope ps(c, MSRSB_K_PROLONG);
+    if (s.kind == 2) {
+        launch_xprolong(c, s, x, done);
+        return;
+    }
     if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, nullptr, x, false, done);
     else rp_dispatch<double>(c, s, s.P64[s.cur], nullptr, x, false, done);
 }
@@ -672,6 +683,10 @@ static void rap_dispatch(Ctx &c, Stage &s, const PS *P) {
 
 void launch_rap(Ctx &c, Stage &s) {
     ProfScope ps(c, MSRSB_K_RAP);
+    if (s.kind == 2) {
+        launch_xrap(c, s);
+        return;
+    }
     hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
     if (c.opt.precision == MSRSB_MIXED) rap_dispatch<uint16_t>(c, s, s.Pbf);
     else rap_dispatch<double>(c, s, s.P64[s.cur]);

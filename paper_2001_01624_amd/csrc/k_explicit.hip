@@ -1,0 +1,319 @@
+// Stages with explicit slots: static partitions whose blocks and supports
+// are not boxes (the fault-cut stage: pieces of the general blocks separated
+// by faults, paper section "Multiscale methods", partition type "Static").
+//
+// Layout: slot-major tables sb[s*N + i] = block held by slot s of cell i
+// (ascending, -1 past the cell's last slot) and basis values P[s*N + i];
+// per-block support lists (CSR over cells in ascending order, with the slot
+// index of the block in that cell) for restriction and the Galerkin rows.
+#include "dev_util.h"
+#include "msrsb_internal.h"
+
+namespace msrsb {
+
+template <typename PT>
+__global__ void k_xinit(int N, int ns, const int32_t *__restrict__ sb, const int32_t *__restrict__ pblock,
+                        PT *__restrict__ P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int own = pblock[i];
+    for (int s = 0; s < ns; ++s) P[(long)s * N + i] = (own >= 0 && sb[(long)s * N + i] == own) ? (PT)1 : (PT)0;
+}
+
+// One restricted-smoothing sweep (same definition as the rectilinear one):
+// the neighbour's value of block j is found by comparing slot lists.
+template <int NSX, typename PT>
+__global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t *__restrict__ sb,
+                                                   const PT *__restrict__ tx, const PT *__restrict__ ty,
+                                                   const PT *__restrict__ tz, const PT *__restrict__ Pin,
+                                                   PT *__restrict__ Pout, PT omega, unsigned long long *maxbits,
+                                                   int *flag, const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (*done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double chg = 0.0;
+    if (i < g.N) {
+        const long N = g.N;
+        int bi[NSX];
+        PT p[NSX], acc[NSX];
+#pragma unroll
+        for (int s = 0; s < NSX; ++s) {
+            bi[s] = s < ns ? sb[s * N + i] : -1;
+            p[s] = s < ns ? Pin[s * N + i] : (PT)0;
+            acc[s] = (PT)0;
+        }
+        if (!(g.diag[i] > 0.0)) {
+            for (int s = 0; s < ns; ++s) Pout[s * N + i] = (PT)0;
+        } else {
+            PT db = (PT)0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int a = q >> 1;
+                const bool up = q & 1;
+                const int step = a == 0 ? 1 : (a == 1 ? g.nx : g.nxy);
+                const PT *Ta = a == 0 ? tx : (a == 1 ? ty : tz);
+                int l;
+                PT T;
+                if (up) {
+                    T = Ta[i];
+                    l = i + step;
+                } else {
+                    if (i < step) continue;
+                    l = i - step;
+                    T = Ta[l];
+                }
+                if (T == (PT)0) continue;
+                db += T;
+                for (int t = 0; t < ns; ++t) {
+                    const int bl = sb[t * N + l];
+                    if (bl < 0) break;
+                    const PT v = Pin[t * N + l];
+#pragma unroll
+                    for (int s = 0; s < NSX; ++s)
+                        if (bi[s] == bl) acc[s] += T * v;
+                }
+            }
+            const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
+            PT pn[NSX];
+            PT rs = (PT)0;
+#pragma unroll
+            for (int s = 0; s < NSX; ++s) {
+                PT v = (PT)0;
+                if (bi[s] >= 0) v = db > (PT)0 ? p[s] - omega * (p[s] - acc[s] * idb) : p[s];
+                pn[s] = v;
+                rs += v;
+            }
+            if (!(rs > (PT)0)) {
+                atomicOr(flag, 2);
+                for (int s = 0; s < ns; ++s) Pout[s * N + i] = Pin[s * N + i];
+            } else {
+                const PT irs = (PT)1 / rs;
+#pragma unroll
+                for (int s = 0; s < NSX; ++s) {
+                    if (s >= ns) break;
+                    const PT v = pn[s] * irs;
+                    chg = fmax(chg, fabs((double)v - (double)p[s]));
+                    Pout[s * N + i] = v;
+                }
+            }
+        }
+    }
+    const double m = block_max(chg, lds);
+    if (threadIdx.x == 0 && m > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+}
+
+template <typename PT>
+static void xsweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
+                            unsigned long long *bits) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    const dim3 grid(cdiv(c.N, kBlock)), blk(kBlock);
+    const PT om = (PT)c.opt.omega;
+    const int *done = &c.status->done;
+    if (s.ns <= 8)
+        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, bits,
+                           c.flag, done);
+    else if (s.ns <= 16)
+        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, bits,
+                           c.flag, done);
+    else
+        hipLaunchKernelGGL((k_xsweep<kMaxXSlots, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out,
+                           om, bits, c.flag, done);
+}
+
+void launch_xinit(Ctx &c, Stage &s) {
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_xinit<float>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, s.ns, s.xsb,
+                           s.xpblock, s.P32[0]);
+    else
+        hipLaunchKernelGGL(k_xinit<double>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, s.ns, s.xsb,
+                           s.xpblock, s.P64[0]);
+}
+
+void launch_xsweep(Ctx &c, Stage &s, int in, int out, unsigned long long *bits) {
+    if (c.opt.precision == MSRSB_MIXED)
+        xsweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out], bits);
+    else
+        xsweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out], bits);
+}
+
+// d_j = sum over the support list of block j of P_ij r_i (one workgroup per
+// block, fixed-order sum).
+template <typename PS>
+__global__ __launch_bounds__(kBlock) void k_xrestrict(int N, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ cell,
+                                                      const uint8_t *__restrict__ slot, const PS *__restrict__ P,
+                                                      const double *__restrict__ r, double *__restrict__ d,
+                                                      const int *done) {
+    __shared__ double lds[kBlock / 64];
+    if (done && *done) return;
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int k = ptr[j] + threadIdx.x; k < ptr[j + 1]; k += blockDim.x) {
+        const int i = cell[k];
+        acc += ld_basis(P, (long)slot[k] * N + i) * r[i];
+    }
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) d[j] = s;
+}
+
+template <typename PS>
+__global__ __launch_bounds__(kBlock) void k_xprolong(int N, int ns, const int32_t *__restrict__ sb,
+                                                     const PS *__restrict__ P, const double *__restrict__ pc,
+                                                     double *__restrict__ x, const int *done) {
+    if (done && *done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const int b = sb[(long)s * N + i];
+        if (b < 0) break;
+        acc += ld_basis(P, (long)s * N + i) * pc[b];
+    }
+    x[i] += acc;
+}
+
+void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done) {
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_xrestrict<uint16_t>, dim3(s.M), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcell, s.xslot,
+                           s.Pbf, r, s.dvec, done);
+    else
+        hipLaunchKernelGGL(k_xrestrict<double>, dim3(s.M), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcell, s.xslot,
+                           s.P64[s.cur], r, s.dvec, done);
+}
+
+void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done) {
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_xprolong<uint16_t>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, s.ns, s.xsb,
+                           s.Pbf, s.pc, x, done);
+    else
+        hipLaunchKernelGGL(k_xprolong<double>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, s.ns, s.xsb,
+                           s.P64[s.cur], s.pc, x, done);
+}
+
+// Row j of A_c = P^T A P from the face form (see the rectilinear kernel):
+// one wavefront walks the support list of block j; every face (a, b) with
+// P_aj - P_bj != 0 is taken once (from a, and from b only when a is not in
+// the support), and its contributions T g_j g_k are summed per column k by
+// fixed-shape wave reductions committed in a fixed order.
+template <typename PS>
+__global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__restrict__ sb,
+                                             const int32_t *__restrict__ ptr, const int32_t *__restrict__ cell,
+                                             const uint8_t *__restrict__ slot, const PS *__restrict__ P,
+                                             const double *__restrict__ bcdiag, double *__restrict__ Ac, int Mp) {
+    const int j = blockIdx.x, lane = threadIdx.x;
+    const long N = g.N;
+    double *row = Ac + (long)j * Mp;
+    const int k0 = ptr[j], k1 = ptr[j + 1];
+    for (int base = k0; base < k1; base += 64) {
+        const int k = base + lane;
+        const bool live = k < k1;
+        const int a = live ? cell[k] : 0;
+        const double Paj = live ? ld_basis(P, (long)slot[k] * N + a) : 0.0;
+        // boundary term: bc_a P_aj P_ak over a's slots
+        {
+            const double bc = live ? bcdiag[a] : 0.0;
+            for (int t = 0; t < ns; ++t) {
+                int kb = -1;
+                double v = 0.0;
+                if (live && bc > 0.0) {
+                    kb = sb[(long)t * N + a];
+                    if (kb >= 0) v = bc * Paj * ld_basis(P, (long)t * N + a);
+                }
+                unsigned long long pending = __ballot(kb >= 0);
+                while (pending) {
+                    const int leader = __ffsll((long long)pending) - 1;
+                    const int kk = __shfl(kb, leader, 64);
+                    const unsigned long long same = __ballot(kb == kk);
+                    const double sum = wave_sum(kb == kk ? v : 0.0);
+                    if (lane == 0) row[kk] += sum;
+                    pending &= ~same;
+                }
+            }
+        }
+        for (int q = 0; q < 6; ++q) {
+            const int ax = q >> 1;
+            const bool up = q & 1;
+            const int step = ax == 0 ? 1 : (ax == 1 ? g.nx : g.nxy);
+            const double *Ta = ax == 0 ? g.tx : (ax == 1 ? g.ty : g.tz);
+            int b = -1;
+            double T = 0.0;
+            if (live) {
+                if (up) {
+                    T = Ta[a];
+                    b = a + step;
+                } else if (a >= step) {
+                    b = a - step;
+                    T = Ta[b];
+                }
+            }
+            // value of block j at b, and whether b lies in the support
+            double Pbj = 0.0;
+            bool bin = false;
+            if (T != 0.0) {
+                for (int t = 0; t < ns; ++t) {
+                    const int bl = sb[(long)t * N + b];
+                    if (bl < 0) break;
+                    if (bl == j) {
+                        Pbj = ld_basis(P, (long)t * N + b);
+                        bin = true;
+                    }
+                }
+            }
+            // each face once: from a, unless b is also in the support and b < a
+            const bool take = T != 0.0 && !(bin && b < a);
+            const double gj = take ? Paj - Pbj : 0.0;
+            const bool act = take && gj != 0.0;
+            // columns: blocks of a (with b's value of the same block), then blocks only of b
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int t = 0; t < ns; ++t) {
+                    int kb = -1;
+                    double v = 0.0;
+                    if (act) {
+                        const int src = pass == 0 ? a : b, oth = pass == 0 ? b : a;
+                        kb = sb[(long)t * N + src];
+                        if (kb >= 0) {
+                            const double ps = ld_basis(P, (long)t * N + src);
+                            double po = 0.0;
+                            bool shared = false;
+                            for (int u = 0; u < ns; ++u) {
+                                const int bo = sb[(long)u * N + oth];
+                                if (bo < 0) break;
+                                if (bo == kb) {
+                                    po = ld_basis(P, (long)u * N + oth);
+                                    shared = true;
+                                }
+                            }
+                            if (pass == 1 && shared) kb = -1;  // already taken with a's slots
+                            else v = T * gj * (pass == 0 ? ps - po : -ps);
+                        }
+                    }
+                    unsigned long long pending = __ballot(kb >= 0);
+                    while (pending) {
+                        const int leader = __ffsll((long long)pending) - 1;
+                        const int kk = __shfl(kb, leader, 64);
+                        const unsigned long long same = __ballot(kb == kk);
+                        const double sum = wave_sum(kb == kk ? v : 0.0);
+                        if (lane == 0) row[kk] += sum;
+                        pending &= ~same;
+                    }
+                }
+            }
+        }
+    }
+}
+
+void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
+
+void launch_xrap(Ctx &c, Stage &s) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_xrap<uint16_t>, dim3(s.M), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xcell,
+                           s.xslot, s.Pbf, c.bcdiag, s.Ac, s.Mp);
+    else
+        hipLaunchKernelGGL(k_xrap<double>, dim3(s.M), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xcell,
+                           s.xslot, s.P64[s.cur], c.bcdiag, s.Ac, s.Mp);
+    launch_symmetrize(c, s.Ac, s.M, s.Mp);
+}
+
+}  // namespace msrsb

@@ -16,6 +16,7 @@ constexpr int kBlock = 256;        // threads per workgroup of the streaming ker
 constexpr int kRedBlocks = 2048;   // fixed grid of the norm/dot kernels (deterministic order)
 constexpr int kTile = 32;          // coarse inverse tile / panel width
 constexpr int kMaxRestart = 64;
+constexpr int kMaxXSlots = 32;   // slots per cell of an explicit (fault-cut) stage
 
 // Geometry of the fine box as the kernels see it.
 struct Fine {
@@ -42,7 +43,7 @@ struct CartDev {
 };
 
 struct Stage {
-    int kind = 0;                 // 0 general (Cartesian), 3 dynamic
+    int kind = 0;                 // 0 general (Cartesian), 2 fault cut (explicit slots), 3 dynamic
     int M = 0, Mp = 0;            // blocks; padded to a multiple of kTile
     int ns = 1;                   // slots per cell
     // Cartesian tables
@@ -69,6 +70,12 @@ struct Stage {
     double *dvec = nullptr, *pc = nullptr;
     // restriction partial sums per (block, group box, slot)
     double *rpart = nullptr;
+    // explicit-slot stage (fault cut): slot tables, piece of each cell,
+    // per-block support lists (cells ascending, with the block's slot there)
+    int parent = -1;
+    int32_t *xsb = nullptr, *xpblock = nullptr, *xptr = nullptr, *xcell = nullptr;
+    uint8_t *xslot = nullptr;
+    std::vector<int32_t> h_xsb, h_xpblock;
 };
 
 struct Status {                   // device-side solver status (one struct per context)
@@ -93,6 +100,7 @@ struct Ctx {
     int nx = 0, ny = 0, nz = 0, N = 0, n_active = 0;
     // host copies needed later (dynamic stages, export)
     std::vector<uint8_t> h_active;
+    std::vector<uint8_t> h_fault;   // [3N] or empty
     std::vector<int32_t> h_bc_cell;
     std::vector<double> h_bc_trans, h_bc_value;
     int n_bc = 0;
@@ -178,6 +186,13 @@ void launch_export_cart(Ctx &c, Stage &s, double *d_vals);
 // ---- coarse kernels (k_coarse.hip) ----
 void launch_coarse_inverse(Ctx &c, Stage &s);
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done);
+
+// ---- explicit-slot stage kernels (k_explicit.hip) ----
+void launch_xinit(Ctx &c, Stage &s);
+void launch_xsweep(Ctx &c, Stage &s, int in, int out, unsigned long long *bits);
+void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done);
+void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done);
+void launch_xrap(Ctx &c, Stage &s);
 
 // ---- dynamic basis kernels (k_dyn.hip) ----
 int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count);

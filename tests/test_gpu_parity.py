@@ -311,3 +311,66 @@ def test_deterministic_repeat(capi):
     g.update_basis(max_sweeps=40, tol=1e-3)
     g.solve(b, rtol=1e-8, max_iters=500)
     assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------- fault cut ----
+
+FAULT_PARTS = [{"kind": "cartesian", "coarse_dims": (3, 3, 2)}, {"kind": "fault_cut", "parent": 0}]
+
+
+def build_fault(capi, smoother="jacobi", outer="richardson", precision="fp64", dims=(18, 30, 12), seed=2):
+    prob = make_config2(dims=dims, seed=seed)
+    say(f"fault-cut case dims={dims} seed={seed} faults={int(prob.fault.sum())} smoother={smoother}")
+    opt = capi.default_options(smoother=smoother, outer=outer, precision=precision)
+    g = capi.Solver(prob, FAULT_PARTS, opt)
+    o = O.Oracle(prob, FAULT_PARTS, smoother=smoother)
+    return prob, g, o
+
+
+def test_fault_cut_structure(capi):
+    prob, g, o = build_fault(capi)
+    M, kind, ns = g.stage_info(1)
+    st = o.stages[1]
+    assert kind == 2 and M == st.M and M > o.stages[0].M
+    e = g.export_stage(1, values=False, coarse=False)
+    assert np.array_equal(e["block"], np.where(prob.active, st.block, -1))
+    sb = e["slot_block"]
+    pairs = {(i, int(b)) for s in range(ns) for i, b in zip(np.nonzero(sb[s] >= 0)[0].tolist(),
+                                                           sb[s][sb[s] >= 0].tolist())}
+    assert pairs == oracle_support_slots(o, 1)
+    # slot lists ascending, padded with -1
+    for s in range(1, ns):
+        both = (sb[s] >= 0)
+        assert np.all(sb[s - 1][both] < sb[s][both]) and np.all(sb[s - 1][~both | (sb[s - 1] >= 0)] >= -1)
+
+
+@pytest.mark.parametrize("sweeps", [0, 1, 6, 25])
+def test_fault_cut_basis_and_coarse(capi, sweeps):
+    prob, g, o = build_fault(capi)
+    g.update_basis(max_sweeps=sweeps, tol=0.0)
+    o.update_basis(max_sweeps=sweeps, tol=0.0)
+    for k in (0, 1):
+        assert np.abs(g.dense_basis(k) - o.export_basis(k)).max() <= 1e-12
+        assert relerr(g.export_stage(k)["Ac"], o.stages[k].Ac) <= 1e-12
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+def test_fault_cut_cycles(capi, smoother):
+    prob, g, o = build_fault(capi, smoother=smoother)
+    g.update_basis(max_sweeps=20, tol=0.0)
+    o.update_basis(max_sweeps=20, tol=0.0)
+    p = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(p, rtol=0.0, max_iters=6)
+    xo, cyc, relo, st = o.solve(rtol=0.0, max_cycles=6)
+    assert it == cyc == 6 and relerr(host(p), xo) <= 1e-9
+
+
+def test_fault_cut_gmres_converges(capi):
+    prob, g, o = build_fault(capi, smoother="ilu0_rb", outer="gmres", dims=(24, 40, 14), seed=3)
+    g.update_basis(max_sweeps=60, tol=1e-3)
+    p = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(p, rtol=1e-10, max_iters=1000)
+    assert rc == capi.OK
+    x = host(p)
+    assert np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b) <= 1.0001e-10
+    assert relerr(x, o.direct_solve()) <= 1e-7
