@@ -374,3 +374,61 @@ def test_fault_cut_gmres_converges(capi):
     x = host(p)
     assert np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b) <= 1.0001e-10
     assert relerr(x, o.direct_solve()) <= 1e-7
+
+
+# ------------------------------------------------------- mixed precision ----
+# Stated per-result bounds against the FP64 oracle: basis entries within
+# 2^-8 |P| + 2e-5 (BF16 rounding of the stored basis, 2^-9 relative, plus the
+# drift of FP32 sweeps); coarse operators within 1e-2 relative to their
+# largest entry; solves reach the same FP64 relative residual.
+
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
+def test_mixed_basis_within_bound(capi, name):
+    prob, g, o = build(capi, name, precision="mixed")
+    g.update_basis(max_sweeps=20, tol=0.0)
+    o.update_basis(max_sweeps=20, tol=0.0)
+    P = g.dense_basis(0)
+    Po = o.export_basis(0)
+    err = np.abs(P - Po)
+    say(f"mixed basis max error {err.max():.2e}")
+    assert np.all(err <= 2.0 ** -8 * np.abs(Po) + 2e-5)
+    # stored values are exact BF16 numbers
+    v = P[P != 0].astype(np.float32).view(np.uint32)
+    assert np.all(v & 0xFFFF == 0)
+    Ac = g.export_stage(0)["Ac"]
+    assert np.abs(Ac - Ac.T).max() == 0.0
+    assert relerr(Ac, o.stages[0].Ac) <= 1e-2
+
+
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
+def test_mixed_solve_meets_fp64_tolerance(capi, name):
+    prob, g, o = build(capi, name, smoother="ilu0_rb", outer="gmres", precision="mixed")
+    g.update_basis(max_sweeps=60, tol=1e-3)
+    p = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(p, rtol=1e-6, max_iters=2000)
+    assert rc == capi.OK
+    x = host(p)
+    true = np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b)
+    xd = o.direct_solve()
+    say(f"mixed {name}: {it} its, relres {true:.2e}, solution error {relerr(x, xd):.2e}")
+    assert true <= 1.0001e-6
+    f64 = capi.Solver(prob, [{"kind": "cartesian", "coarse_dims": CASES[name][1]}],
+                      capi.default_options(smoother="ilu0_rb", outer="gmres"))
+    f64.update_basis(max_sweeps=60, tol=1e-3)
+    q = dev(np.zeros(prob.n_cells))
+    it64, _, _ = f64.solve(q, rtol=1e-6, max_iters=2000)
+    # equal accuracy: both within 1e-6 of the FP64 residual; mixed needs at most a few more iterations
+    assert it <= it64 + max(3, it64 // 5)
+
+
+def test_mixed_fault_cut(capi):
+    prob, g, o = build_fault(capi, smoother="ilu0_rb", outer="gmres", precision="mixed")
+    g.update_basis(max_sweeps=15, tol=0.0)
+    o.update_basis(max_sweeps=15, tol=0.0)
+    for k in (0, 1):
+        err = np.abs(g.dense_basis(k) - o.export_basis(k))
+        assert np.all(err <= 2.0 ** -8 * np.abs(o.export_basis(k)) + 2e-5)
+    p = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(p, rtol=1e-6, max_iters=2000)
+    assert rc == capi.OK
+    assert np.linalg.norm(o.residual(host(p))) / np.linalg.norm(o.b) <= 1.0001e-6
