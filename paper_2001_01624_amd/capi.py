@@ -53,6 +53,11 @@ class Options(C.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime (same soname as the system one).  Load
+    # it first so that the library binds to that runtime: one runtime per
+    # process, and torch's streams and allocations are valid handles here.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2001_01624_amd.build.build()")
     lib = C.CDLL(LIB_PATH)
