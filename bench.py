@@ -214,7 +214,7 @@ def traffic_record(kernel, precision):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2001_01624_amd", "csrc", rec.get("source", "k_basis.hip"))
+    src = os.path.join(ROOT, "paper_2001_01624_amd", "csrc", rec.get("source", "k_sweep.hip"))
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if h != rec.get("sha256"):
         return None

@@ -269,7 +269,8 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         return MSRSB_E_INVAL;
     }
     s.rpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)c.nz * cd.m[1] * cd.m[0] * s.ns);
-    if (!s.rpart) return MSRSB_E_NOMEM;
+    s.rap_part = (double *)ctx_alloc(c, sizeof(double) * rap_part_doubles(s.ns, cd.m[0] * cd.m[1] * cd.m[2]));
+    if (!s.rpart || !s.rap_part) return MSRSB_E_NOMEM;
     return MSRSB_OK;
 }
 
@@ -433,6 +434,8 @@ static size_t cart_bytes(const Ctx &c, const msrsb_partition &p) {
     const size_t nsN = ((size_t)1 << nbits) * c.N;
     size_t b = (c.opt.precision == MSRSB_MIXED) ? nsN * 10 : nsN * 16;
     b += 16 * (size_t)Mp * Mp + 16 * Mp + 4 * (size_t)(c.nx + c.ny + c.nz) * 5 + 12 * (size_t)M;
+    b += sizeof(double) * ((size_t)c.nz * p.coarse_dims[1] * p.coarse_dims[0] << nbits);  // restriction partials
+    b += sizeof(double) * rap_part_doubles(1 << nbits, (int)M);                          // Galerkin partials
     return b;
 }
 

@@ -24,15 +24,38 @@ static Fine fine_of(const Ctx &c) {
 
 static int red_grid(int N) { return xcd_grid(std::min(kRedBlocks, cdiv(N, kBlock))); }
 
-// (A x)_i for an active cell with diagonal d.
+// The six faces of cell i in the order -x, +x, -y, +y, -z, +z: neighbour
+// index (clamped to i outside the grid) and transmissibility (0 there).  All
+// loads depend on i alone, so a kernel can issue every load before its first
+// use.
+template <typename TT>
+__device__ inline void cell_faces(const Fine &g, int i, const TT *__restrict__ tx, const TT *__restrict__ ty,
+                                  const TT *__restrict__ tz, int l[6], TT t[6]) {
+    const int step[3] = {1, g.nx, g.nxy};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const TT *Ta = a == 0 ? tx : (a == 1 ? ty : tz);
+        const bool dn = i >= step[a], up = i + step[a] < g.N;
+        l[2 * a] = dn ? i - step[a] : i;
+        l[2 * a + 1] = up ? i + step[a] : i;
+        const TT td = Ta[l[2 * a]], tu = Ta[i];
+        t[2 * a] = dn ? td : (TT)0;
+        t[2 * a + 1] = up ? tu : (TT)0;
+    }
+}
+
+// (A x)_i for an active cell with diagonal d; the off-diagonal terms are
+// subtracted in face order (faces outside the grid have t = 0).
 __device__ inline double ax_row(const Fine &g, const double *__restrict__ x, int i, double d) {
-    double s = d * x[i];
-    if (i >= 1) s -= g.tx[i - 1] * x[i - 1];
-    if (i + 1 < g.N) s -= g.tx[i] * x[i + 1];
-    if (i >= g.nx) s -= g.ty[i - g.nx] * x[i - g.nx];
-    if (i + g.nx < g.N) s -= g.ty[i] * x[i + g.nx];
-    if (i >= g.nxy) s -= g.tz[i - g.nxy] * x[i - g.nxy];
-    if (i + g.nxy < g.N) s -= g.tz[i] * x[i + g.nxy];
+    int l[6];
+    double t[6], xl[6];
+    cell_faces(g, i, g.tx, g.ty, g.tz, l, t);
+    const double xi = x[i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) xl[q] = x[l[q]];
+    double s = d * xi;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s -= t[q] * xl[q];
     return s;
 }
 
@@ -112,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
     const int lb = xcd_block();
     for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += gridDim.x * blockDim.x) {
         const int i = xzy_cell(t, g.nx, g.ny, g.nz);
-        const double d = g.diag[i];
-        double ri = 0.0;
-        if (d > 0.0) ri = b[i] - ax_row(g, x, i, d);
+        const double d = g.diag[i], bi = b[i];
+        const double ax = ax_row(g, x, i, d);
+        const double ri = d > 0.0 ? bi - ax : 0.0;
         r[i] = ri;
         acc += ri * ri;
     }
@@ -144,7 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_matvec(Fine g, const double *__restr
     for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += gridDim.x * blockDim.x) {
         const int i = xzy_cell(t, g.nx, g.ny, g.nz);
         const double d = g.diag[i];
-        const double v = d > 0.0 ? ax_row(g, x, i, d) : 0.0;
+        const double ax = ax_row(g, x, i, d);
+        const double v = d > 0.0 ? ax : 0.0;
         y[i] = v;
         acc += v * v;
     }
@@ -188,9 +212,13 @@ __device__ inline int colour_cell(const Fine &g, int col, int t) {
     return ix + g.nx * (iy + g.ny * iz);
 }
 
-// Forward sweep of (D~ + L) w = r restricted to black cells, which in
-// red-black order is also their final value e_b = w_b:
-//   e_b = (r_b + sum_j T_bj r_j / a_jj) / d~_b          (j red neighbours)
+// Red-black ILU(0) applied to r: with red cells first, L and U couple red to
+// black only, so the forward pass leaves red rows unchanged and the backward
+// pass is two colour sweeps.
+//   black: e_b = (r_b + sum_{red l} T_bl r_l / a_ll) / dtil_b,
+//   red:   e_r = (r_r + sum_{black l} T_rl e_l) / a_rr,
+// x += e on each colour.  Faces with T = 0 (boundary, inactive neighbour)
+// leave the sum untouched; cells with a non-positive pivot are skipped.
 template <typename TT>
 __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
                                                       const TT *__restrict__ tz, const TT *__restrict__ diag,
@@ -200,22 +228,25 @@ __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restri
     if (done && *done) return;
     const int i = colour_cell(g, 1, xcd_block() * blockDim.x + threadIdx.x);
     if (i < 0) return;
+    int l[6];
+    TT t[6], rl[6], dl[6];
+    cell_faces(g, i, tx, ty, tz, l, t);
     const TT dt = dtil[i];
-    if (!(dt > (TT)0)) return;
     TT s = (TT)r[i];
-    TT t;
-    if (i >= 1 && (t = tx[i - 1]) != (TT)0) s += t * (TT)r[i - 1] / diag[i - 1];
-    if ((t = tx[i]) != (TT)0) s += t * (TT)r[i + 1] / diag[i + 1];
-    if (i >= g.nx && (t = ty[i - g.nx]) != (TT)0) s += t * (TT)r[i - g.nx] / diag[i - g.nx];
-    if ((t = ty[i]) != (TT)0) s += t * (TT)r[i + g.nx] / diag[i + g.nx];
-    if (i >= g.nxy && (t = tz[i - g.nxy]) != (TT)0) s += t * (TT)r[i - g.nxy] / diag[i - g.nxy];
-    if ((t = tz[i]) != (TT)0) s += t * (TT)r[i + g.nxy] / diag[i + g.nxy];
+    const double xo = x[i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        rl[q] = (TT)r[l[q]];
+        dl[q] = diag[l[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s = t[q] != (TT)0 ? s + t[q] * rl[q] / dl[q] : s;
+    const bool on = dt > (TT)0;
     const TT v = s / dt;
-    e[i] = (double)v;
-    x[i] += (double)v;
+    e[i] = on ? (double)v : 0.0;
+    x[i] = on ? xo + (double)v : xo;
 }
 
-// Backward sweep for red cells: e_r = (r_r + sum_j T_rj e_j) / a_rr.
 template <typename TT>
 __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
                                                     const TT *__restrict__ tz, const TT *__restrict__ diag,
@@ -224,17 +255,17 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
     if (done && *done) return;
     const int i = colour_cell(g, 0, xcd_block() * blockDim.x + threadIdx.x);
     if (i < 0) return;
+    int l[6];
+    TT t[6], el[6];
+    cell_faces(g, i, tx, ty, tz, l, t);
     const TT d = diag[i];
-    if (!(d > (TT)0)) return;
     TT s = (TT)r[i];
-    TT t;
-    if (i >= 1 && (t = tx[i - 1]) != (TT)0) s += t * (TT)e[i - 1];
-    if ((t = tx[i]) != (TT)0) s += t * (TT)e[i + 1];
-    if (i >= g.nx && (t = ty[i - g.nx]) != (TT)0) s += t * (TT)e[i - g.nx];
-    if ((t = ty[i]) != (TT)0) s += t * (TT)e[i + g.nx];
-    if (i >= g.nxy && (t = tz[i - g.nxy]) != (TT)0) s += t * (TT)e[i - g.nxy];
-    if ((t = tz[i]) != (TT)0) s += t * (TT)e[i + g.nxy];
-    x[i] += (double)(s / d);
+    const double xo = x[i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) el[q] = (TT)e[l[q]];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s = t[q] != (TT)0 ? s + t[q] * el[q] : s;
+    x[i] = d > (TT)0 ? xo + (double)(s / d) : xo;
 }
 
 void launch_smooth(Ctx &c, const double *r, double *x, const int *done) {
@@ -555,7 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_mvdot(Fine g, const double *__restri
             double wi;
             if (j0 == 0) {
                 const double d = g.diag[i];
-                wi = d > 0.0 ? ax_row(g, z, i, d) : 0.0;
+                const double ax = ax_row(g, z, i, d);
+                wi = d > 0.0 ? ax : 0.0;
                 w[i] = wi;
                 nrm += wi * wi;
             } else {

@@ -1,0 +1,564 @@
+// Rectilinear-stage transfer operators: restriction d = P^T r, prolongation
+// x += P p_c and the Galerkin product A_c = P^T A P (the reduced pressure
+// system with R = P^T).  Basis layout as in the sweeps: slot-major P[s*N + i]
+// with implicit slots (at most two consecutive blocks per axis).
+#include <algorithm>
+
+#include "cart_util.h"
+#include "dev_util.h"
+#include "msrsb_internal.h"
+
+namespace msrsb {
+
+
+// ------------------------------------------------- restriction / prolongation
+
+// d = P^T r in two deterministic passes.
+// Cells whose first support block along every axis is the same (lo = L: the
+// "dual box" between block centres L and L+1) share their eight slot->block
+// maps, so P_is r_i can be summed per slot over a dual box and attributed
+// afterwards.
+// Pass 1 (k_restrict_rows): one wavefront per (dual interval Ly along y,
+// layer z) walks the rows y of that interval; lane x keeps per-slot sums for
+// its own column (its dual interval along x is fixed), so rows are read
+// coalesced and every P entry once.  Lanes of one dual x-interval are then
+// added in lane order:  part[((z*my + Ly)*mx + Lx)*NS + s].
+// Pass 2 (k_restrict_gather): d_J = sum over s, and over the layers z of the
+// dual interval J_z - s_z, of part[z, J_y - s_y, J_x - s_x, s] (fixed order).
+constexpr int kRowChunks = 4;  // rows up to 64*kRowChunks cells
+
+constexpr int kRowWaves = 4;
+constexpr int kRowUnroll = 3;
+
+template <int NS, typename PS>
+__global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                                  const double *__restrict__ r,
+                                                                  double *__restrict__ part, const int *done) {
+    extern __shared__ double red[];  // [kRowWaves][nx][NS]
+    if (done && *done) return;
+    const int Ly = blockIdx.x, z = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int mx = cd.m[0], my = cd.m[1];
+    int y0 = 0, y1 = g.ny;
+    if (cd.bit[1] >= 0) {
+        y0 = Ly == 0 ? 0 : cd.split[1][Ly];
+        y1 = Ly + 1 < my ? cd.split[1][Ly + 1] : g.ny;
+    }
+    const int nch = (g.nx + 63) >> 6;
+    double acc[kRowChunks][NS];
+#pragma unroll
+    for (int k = 0; k < kRowChunks; ++k)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
+    // kRowUnroll rows per pass, all loads of a pass issued before the first
+    // use; rows past the interval load row y0 and add nothing.  Rows are
+    // still added in increasing y, so the sums do not depend on the unroll.
+    for (int yb = y0 + wv; yb < y1; yb += kRowWaves * kRowUnroll) {
+#pragma unroll
+        for (int k = 0; k < kRowChunks; ++k) {
+            const int x = lane + 64 * k;
+            if (k < nch && x < g.nx) {
+                double ri[kRowUnroll], pv[kRowUnroll][NS];
+                bool in[kRowUnroll];
+#pragma unroll
+                for (int u = 0; u < kRowUnroll; ++u) {
+                    const int y = yb + u * kRowWaves;
+                    in[u] = y < y1;
+                    const long i = (long)g.nx * ((in[u] ? y : y0) + (long)g.ny * z) + x;
+                    ri[u] = r[i];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) pv[u][s] = ld_basis(P, (long)s * g.N + i);
+                }
+#pragma unroll
+                for (int u = 0; u < kRowUnroll; ++u)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) acc[k][s] = in[u] ? acc[k][s] + pv[u][s] * ri[u] : acc[k][s];
+            }
+        }
+    }
+    double *mine = red + (long)wv * g.nx * NS;
+#pragma unroll
+    for (int k = 0; k < kRowChunks; ++k) {
+        const int x = lane + 64 * k;
+        if (k < nch && x < g.nx)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) mine[x * NS + s] = acc[k][s];
+    }
+    __syncthreads();
+    // thread (Lx, s) adds waves, then columns of dual x-interval Lx, in order
+    for (int t = threadIdx.x; t < mx * NS; t += blockDim.x) {
+        const int Lx = t / NS, s = t % NS;
+        int x0 = 0, x1 = g.nx;
+        if (cd.bit[0] >= 0) {
+            x0 = Lx == 0 ? 0 : cd.split[0][Lx];
+            x1 = Lx + 1 < mx ? cd.split[0][Lx + 1] : g.nx;
+        }
+        double tot = 0.0;
+        for (int x = x0; x < x1; ++x)
+            for (int w = 0; w < kRowWaves; ++w) tot += red[((long)w * g.nx + x) * NS + s];
+        part[(((long)z * my + Ly) * mx + Lx) * NS + s] = tot;
+    }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
+                                                         double *__restrict__ d, const int *done) {
+    if (done && *done) return;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= M) return;
+    const int mx = cd.m[0], my = cd.m[1], mz = cd.m[2];
+    const int cid = cd.present[j];
+    const int J[3] = {cid % mx, (cid / mx) % my, cid / (mx * my)};
+    // work items: (slot s, layer z of the dual interval J_z - s_z)
+    double v = 0.0;
+    for (int s = 0; s < NS; ++s) {
+        int L[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            L[a] = J[a] - (cd.bit[a] >= 0 ? (s >> cd.bit[a]) & 1 : 0);
+            if (L[a] < 0) ok = false;
+        }
+        if (!ok) continue;
+        int z0 = 0, z1 = g.nz;
+        if (cd.bit[2] >= 0) {
+            z0 = L[2] == 0 ? 0 : cd.split[2][L[2]];
+            z1 = L[2] + 1 < mz ? cd.split[2][L[2] + 1] : g.nz;
+        }
+        for (int z = z0 + lane; z < z1; z += 64) v += part[(((long)z * my + L[1]) * mx + L[0]) * NS + s];
+    }
+    v = wave_sum(v);
+    if (lane == 0) d[j] = v;
+}
+
+// x_i += sum_s P_is p_c[block(i,s)]
+template <int NS, typename PS>
+__global__ __launch_bounds__(kBlock) void k_prolong(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                    const double *__restrict__ pc, double *__restrict__ x,
+                                                    const int *done) {
+    // x_i += sum_s P_is pc[block(i, s)].  Every load is issued on an address
+    // that depends on i and the small tables only; slots outside the support
+    // or on a dropped block add nothing.
+    if (done && *done) return;
+    const int i = xzy_cell(xcd_block() * blockDim.x + threadIdx.x, g.nx, g.ny, g.nz);
+    if (i < 0) return;
+    int c[3], lo[3], nv[3];
+    cell_coords(g, i, c);
+    const double dg = g.diag[i];
+    const double xo = x[i];
+    double pv[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pv[s] = ld_basis(P, (long)s * g.N + i);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int w = cd.bit[a] >= 0 ? cd.pack[a][c[a]] : 0;
+        lo[a] = w & 0xFFFFF;
+        nv[a] = 1 + ((w >> 20) & 1);
+    }
+    int blk[NS];
+    double pcv[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        blk[s] = slot_ok(cd, nv, s) ? slot_block(cd, lo, s) : -1;
+        pcv[s] = pc[blk[s] >= 0 ? blk[s] : 0];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc = blk[s] >= 0 ? acc + pv[s] * pcv[s] : acc;
+    x[i] = dg > 0.0 ? xo + acc : xo;
+}
+
+template <typename PS>
+static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *x, bool restrict_, const int *done) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    if (restrict_) {
+        const dim3 grid(s.cart.m[1], c.nz), blk(64 * kRowWaves), fgrid(cdiv(s.M, 4)), fblk(256);
+        const size_t lds = sizeof(double) * kRowWaves * (size_t)c.nx * s.ns;
+        switch (s.ns) {
+        case 1:
+            hipLaunchKernelGGL((k_restrict_rows<1, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<1>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_restrict_rows<2, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<2>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_restrict_rows<4, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<4>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
+            break;
+        default:
+            hipLaunchKernelGGL((k_restrict_rows<8, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
+            hipLaunchKernelGGL((k_restrict_gather<8>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
+            break;
+        }
+    } else {
+        const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
+        switch (s.ns) {
+        case 1: hipLaunchKernelGGL((k_prolong<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+        case 2: hipLaunchKernelGGL((k_prolong<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+        case 4: hipLaunchKernelGGL((k_prolong<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+        default: hipLaunchKernelGGL((k_prolong<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+        }
+    }
+}
+
+void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done) {
+    ProfScope ps(c, MSRSB_K_RESTRICT);
+    if (s.kind == 2) {
+        launch_xrestrict(c, s, r, done);
+        return;
+    }
+    if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, r, nullptr, true, done);
+    else rp_dispatch<double>(c, s, s.P64[s.cur], r, nullptr, true, done);
+}
+
+void launch_prolong(Ctx &c, Stage &s, double *x, const int *done) {
+    ProfScope ps(c, MSRSB_K_PROLONG);
+    if (s.kind == 2) {
+        launch_xprolong(c, s, x, done);
+        return;
+    }
+    if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, nullptr, x, false, done);
+    else rp_dispatch<double>(c, s, s.P64[s.cur], nullptr, x, false, done);
+}
+
+// ------------------------------------------------------------ Galerkin ----
+// A_c = P^T A P with A = D - T (D the diagonal including boundary terms, T
+// the face transmissibilities), summed per dual box: the cells L whose first
+// support block is L along every axis share the slot -> block map
+// block(s) = L + bits(s).  With P_i the slot vector of cell i,
+//   A_c = sum_L [ S_L  on blocks (L+s, L+t) ]
+//       + sum_L sum_a [ X_La on (L+s, L+e_a+t) and its transpose ],
+//   S_L   = sum_{i in L} P_i Q_i^T,  Q_i = D_i P_i - sum_{l ~ i, l in L} T_il P_l,
+//   X_La  = - sum_{i in L, l = i + e_a in L + e_a} T_il P_i P_l^T.
+// S_L is symmetric; only its upper triangle is formed.  Pass 1
+// (k_rap_box) reads the basis once, one workgroup per dual box, and reduces
+// each quantity over the workgroup in a fixed order; pass 2 (k_rap_gather)
+// adds the contributions of every coarse entry in a fixed order, one thread
+// per entry (j, k) with k >= j, which writes both (j, k) and (k, j).
+constexpr int kRapThreads = 256;
+
+template <int NS>
+struct RapLayout {
+    static constexpr int nsym = NS * (NS + 1) / 2;
+    static constexpr int spad = nsym <= 1 ? 1 : (nsym <= 4 ? 4 : (nsym <= 16 ? 16 : 64));
+    static constexpr int stride = spad + 3 * NS * NS;  // [S][X_x][X_y][X_z]
+    __host__ __device__ static constexpr int sym(int s, int t) { return s * NS - s * (s - 1) / 2 + (t - s); }
+};
+
+// Sum of V values (V a power of two <= 64) over the wavefront, by halving
+// exchanges: afterwards every lane holds the total of value lane >> (6 - log2 V).
+// Lane pairs add the same two operands, so the result does not depend on
+// the lane that computes it.
+template <int V>
+__device__ inline double wave_transpose_sum(double (&v)[V], int lane) {
+#pragma unroll
+    for (int step = 0; step < 6; ++step) {
+        const int o = 32 >> step;
+        const int c = V >> step;
+        if (c >= 2) {
+            // lanes with bit o clear keep the lower half, the others the
+            // upper half; both halves are exchanged and the kept one summed
+            // (a select on sums, not on array slots, keeps v in registers)
+            const bool up = lane & o;
+#pragma unroll
+            for (int k = 0; k < (c >> 1); ++k) {
+                const double lo = v[k], hi = v[k + (c >> 1)];
+                const double rlo = __shfl_xor(lo, o, 64), rhi = __shfl_xor(hi, o, 64);
+                v[k] = up ? hi + rhi : lo + rlo;
+            }
+        } else {
+            v[0] += __shfl_xor(v[0], o, 64);
+        }
+    }
+    return v[0];
+}
+
+// Workgroup total of V per-thread values, written to out[0..nout): waves in
+// order, each wave by wave_transpose_sum.
+template <int V>
+__device__ inline void group_sum_store(double (&v)[V], int nout, double *red, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double t = wave_transpose_sum<V>(v, lane);
+    if ((lane & ((64 / V) - 1)) == 0) red[wv * V + lane / (64 / V)] = t;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nout; q += blockDim.x) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w * V + q];
+        out[q] = sum;
+    }
+    __syncthreads();
+}
+
+__device__ inline void box_range(const CartDev &cd, int a, int L, int &lo, int &hi) {
+    if (cd.bit[a] < 0) {
+        lo = 0;
+        hi = cd.n[a];
+        return;
+    }
+    lo = L == 0 ? 0 : cd.split[a][L];
+    hi = L + 1 < cd.m[a] ? cd.split[a][L + 1] : cd.n[a];
+}
+
+template <int AM, typename PS>
+__global__ __launch_bounds__(kRapThreads) void k_rap_box(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                         double *__restrict__ part, int nbox) {
+    constexpr int NS = 1 << __builtin_popcount(AM);
+    using Lay = RapLayout<NS>;
+    __shared__ double red[(kRapThreads / 64) * 64];
+    const int box = xcd_block();
+    if (box >= nbox) return;
+    const int Lc[3] = {box % cd.m[0], (box / cd.m[0]) % cd.m[1], box / (cd.m[0] * cd.m[1])};
+    int lo[3], hi[3], ext[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        box_range(cd, a, Lc[a], lo[a], hi[a]);
+        ext[a] = hi[a] - lo[a];
+    }
+    const int N = g.N;
+    const int step[3] = {1, g.nx, g.nxy};
+    double *out = part + (long)box * Lay::stride;
+
+    // S_L: upper triangle of sum_i P_i Q_i^T
+    {
+        double acc[Lay::spad];
+#pragma unroll
+        for (int q = 0; q < Lay::spad; ++q) acc[q] = 0.0;
+        const int vol = ext[0] * ext[1] * ext[2];
+        for (int t = threadIdx.x; t < vol; t += blockDim.x) {
+            const int c[3] = {lo[0] + t % ext[0], lo[1] + (t / ext[0]) % ext[1], lo[2] + t / (ext[0] * ext[1])};
+            const int i = c[0] + g.nx * (c[1] + g.ny * c[2]);
+            const double d = g.diag[i];
+            double p[NS], nb[6][NS], T[6];
+            bool in[6];
+            int l[6];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) p[s] = ld_basis(P, (long)s * N + i);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
+                in[2 * a] = c[a] - 1 >= lo[a];
+                in[2 * a + 1] = c[a] + 1 < hi[a];
+                l[2 * a] = in[2 * a] ? i - step[a] : i;
+                l[2 * a + 1] = in[2 * a + 1] ? i + step[a] : i;
+                const double td = Ta[l[2 * a]], tu = Ta[i];
+                T[2 * a] = in[2 * a] ? td : 0.0;
+                T[2 * a + 1] = in[2 * a + 1] ? tu : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) nb[q][s] = ld_basis(P, (long)s * N + l[q]);
+            double Q[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                double v = d * p[s];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) v -= T[q] * nb[q][s];
+                Q[s] = v;
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int u = s; u < NS; ++u) acc[Lay::sym(s, u)] += p[s] * Q[u];
+        }
+        group_sum_store<Lay::spad>(acc, Lay::spad, red, out);
+    }
+    // X_La over the faces leaving the box along +a
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!((AM >> a) & 1)) continue;
+        double acc[NS * NS];
+#pragma unroll
+        for (int q = 0; q < NS * NS; ++q) acc[q] = 0.0;
+        const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+        const bool has_next = hi[a] < cd.n[a];
+        const int cnt = has_next ? ext[b1] * ext[b2] : 0;
+        const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            int c[3];
+            c[a] = hi[a] - 1;
+            c[b1] = lo[b1] + t % ext[b1];
+            c[b2] = lo[b2] + t / ext[b1];
+            const int i = c[0] + g.nx * (c[1] + g.ny * c[2]);
+            const int l = i + step[a];
+            const double T = Ta[i];
+            double p[NS], q[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                p[s] = ld_basis(P, (long)s * N + i);
+                q[s] = ld_basis(P, (long)s * N + l);
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double tp = -T * p[s];
+#pragma unroll
+                for (int u = 0; u < NS; ++u) acc[s * NS + u] += tp * q[u];
+            }
+        }
+        group_sum_store<NS * NS>(acc, NS * NS, red, out + Lay::spad + a * NS * NS);
+    }
+}
+
+template <int AM>
+__global__ __launch_bounds__(128) void k_rap_gather(CartDev cd, const double *__restrict__ part,
+                                                    double *__restrict__ Ac, int M, int Mp) {
+    constexpr int NS = 1 << __builtin_popcount(AM);
+    constexpr int NB = __builtin_popcount(AM);
+    constexpr int NOFF = NB == 0 ? 1 : (NB == 1 ? 5 : (NB == 2 ? 25 : 125));
+    using Lay = RapLayout<NS>;
+    const int j = blockIdx.x, o = threadIdx.x;
+    if (j >= M || o >= NOFF) return;
+    const int m[3] = {cd.m[0], cd.m[1], cd.m[2]};
+    const int cid = cd.present[j];
+    const int J[3] = {cid % m[0], (cid / m[0]) % m[1], cid / (m[0] * m[1])};
+    int K[3];
+    {
+        int rem = o;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if ((AM >> a) & 1) {
+                K[a] = J[a] + rem % 5 - 2;
+                rem /= 5;
+            } else {
+                K[a] = 0;
+            }
+            if (K[a] < 0 || K[a] >= m[a]) return;
+        }
+    }
+    const int kc = cd.cmap[K[0] + m[0] * (K[1] + m[1] * K[2])];
+    if (kc < j) return;  // dropped block, or the entry of the row kc
+    auto bitoff = [](int s, int a) { return ((AM >> a) & 1) ? (s >> __builtin_popcount(AM & ((1 << a) - 1))) & 1 : 0; };
+    auto slot_of = [](const int u[3]) {
+        int s = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if ((AM >> a) & 1) s |= u[a] << __builtin_popcount(AM & ((1 << a) - 1));
+        return s;
+    };
+    double sum = 0.0;
+    // S terms: L = J - off(s), K - L in {0,1}^3
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int L[3], u[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            L[a] = J[a] - bitoff(s, a);
+            u[a] = K[a] - L[a];
+            if (L[a] < 0 || u[a] < 0 || u[a] > 1) ok = false;
+        }
+        if (!ok) continue;
+        const int t = slot_of(u);
+        const long bx = L[0] + (long)m[0] * (L[1] + (long)m[1] * L[2]);
+        sum += part[bx * Lay::stride + (s <= t ? Lay::sym(s, t) : Lay::sym(t, s))];
+    }
+    // X terms: (L + off(s), L + e_a + off(t)) and the transposed position
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!((AM >> a) & 1)) continue;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int *R = side == 0 ? J : K;  // holds L + off(s)
+                const int *C = side == 0 ? K : J;  // holds L + e_a + off(t)
+                int L[3], u[3];
+                bool ok = true;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    L[b] = R[b] - bitoff(s, b);
+                    u[b] = C[b] - L[b] - (b == a ? 1 : 0);
+                    if (L[b] < 0 || u[b] < 0 || u[b] > 1) ok = false;
+                }
+                if (!ok || L[a] + 1 >= m[a]) continue;
+                const int t = slot_of(u);
+                const long bx = L[0] + (long)m[0] * (L[1] + (long)m[1] * L[2]);
+                sum += part[bx * Lay::stride + Lay::spad + a * NS * NS + s * NS + t];
+            }
+        }
+    }
+    Ac[(long)j * Mp + kc] = sum;
+    Ac[(long)kc * Mp + j] = sum;
+}
+
+__global__ void k_pad_identity(double *A, int M, int Mp) {
+    const int k = M + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < Mp) A[(long)k * Mp + k] = 1.0;
+}
+
+// A := (A + A^T)/2 on the leading M x M part (rows are built independently).
+__global__ void k_symmetrize(double *A, int M, int Mp) {
+    const int i = blockIdx.y * 16 + threadIdx.y;
+    const int j = blockIdx.x * 16 + threadIdx.x;
+    if (i >= M || j >= M || j <= i) return;
+    const double v = 0.5 * (A[(long)i * Mp + j] + A[(long)j * Mp + i]);
+    A[(long)i * Mp + j] = v;
+    A[(long)j * Mp + i] = v;
+}
+
+void launch_symmetrize(Ctx &c, double *A, int M, int Mp) {
+    hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(M, 16), cdiv(M, 16)), dim3(16, 16), 0, c.stream, A, M, Mp);
+    if (Mp > M) hipLaunchKernelGGL(k_pad_identity, dim3(cdiv(Mp - M, 64)), dim3(64), 0, c.stream, A, M, Mp);
+}
+
+template <typename PS>
+static void rap_dispatch(Ctx &c, Stage &s, const PS *P) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    const CartDev &cd = s.cart;
+    const int nbox = cd.m[0] * cd.m[1] * cd.m[2];
+    int am = 0;
+    for (int a = 0; a < 3; ++a)
+        if (cd.bit[a] >= 0) am |= 1 << a;
+    const dim3 grid(xcd_grid(nbox)), blk(kRapThreads), ggrid(s.M), gblk(128);
+#define MSRSB_RAP(AM)                                                                                           \
+    case AM:                                                                                                    \
+        hipLaunchKernelGGL((k_rap_box<AM, PS>), grid, blk, 0, c.stream, cd, g, P, s.rap_part, nbox);           \
+        hipLaunchKernelGGL((k_rap_gather<AM>), ggrid, gblk, 0, c.stream, cd, s.rap_part, s.Ac, s.M, s.Mp);    \
+        break;
+    switch (am) {
+        MSRSB_RAP(0) MSRSB_RAP(1) MSRSB_RAP(2) MSRSB_RAP(3)
+        MSRSB_RAP(4) MSRSB_RAP(5) MSRSB_RAP(6) MSRSB_RAP(7)
+    }
+#undef MSRSB_RAP
+    if (s.Mp > s.M)
+        hipLaunchKernelGGL(k_pad_identity, dim3(cdiv(s.Mp - s.M, 64)), dim3(64), 0, c.stream, s.Ac, s.M, s.Mp);
+}
+
+size_t rap_part_doubles(int ns, int nbox) {
+    switch (ns) {
+    case 1: return (size_t)RapLayout<1>::stride * nbox;
+    case 2: return (size_t)RapLayout<2>::stride * nbox;
+    case 4: return (size_t)RapLayout<4>::stride * nbox;
+    default: return (size_t)RapLayout<8>::stride * nbox;
+    }
+}
+
+void launch_rap(Ctx &c, Stage &s) {
+    ProfScope ps(c, MSRSB_K_RAP);
+    if (s.kind == 2) {
+        launch_xrap(c, s);
+        return;
+    }
+    hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
+    if (c.opt.precision == MSRSB_MIXED) rap_dispatch<uint16_t>(c, s, s.Pbf);
+    else rap_dispatch<double>(c, s, s.P64[s.cur]);
+}
+
+__global__ void k_export_vals(long n, const uint16_t *__restrict__ in, double *__restrict__ out) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = (double)bf16_to_float(in[k]);
+}
+
+// Current basis values of a rectilinear stage as FP64 (device buffer).
+void launch_export_cart(Ctx &c, Stage &s, double *d_vals) {
+    const long n = (long)s.ns * c.N;
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_export_vals, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, s.Pbf, d_vals);
+    else
+        hipMemcpyAsync(d_vals, s.P64[s.cur], sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream);
+}
+
+}  // namespace msrsb

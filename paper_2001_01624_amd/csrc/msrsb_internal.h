@@ -68,8 +68,10 @@ struct Stage {
     // coarse operator and its inverse (Mp x Mp, row-major), coarse vectors
     double *Ac = nullptr, *Ainv = nullptr;
     double *dvec = nullptr, *pc = nullptr;
-    // restriction partial sums per (block, group box, slot)
+    // restriction partial sums per (layer, dual interval, slot); Galerkin
+    // partial sums per dual box
     double *rpart = nullptr;
+    double *rap_part = nullptr;
     // explicit-slot stage (fault cut): slot tables, piece of each cell,
     // per-block support lists (cells ascending, with the block's slot there)
     int parent = -1;
@@ -162,6 +164,7 @@ void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
 void launch_check(Ctx &c, double rtol, int max_iters, int count);
 void launch_gmres_begin(Ctx &c, double rtol, int max_iters);
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
+size_t rap_part_doubles(int ns, int nbox);
 void *ctx_alloc(Ctx &c, size_t bytes);
 void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf);
 // GMRES helpers
@@ -176,7 +179,7 @@ void launch_axpy(Ctx &c, double *x, const double *z, const int *done);
 void launch_reorth_check(Ctx &c, int k);
 void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart);
 
-// ---- basis kernels (k_basis.hip) ----
+// ---- basis kernels (k_sweep.hip, k_transfer.hip) ----
 int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *sweeps, double *change);
 void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done);
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done);
