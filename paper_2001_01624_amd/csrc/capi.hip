@@ -204,6 +204,22 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         }
         s.tab_off[a][6] = (int)tab.size(); tab.insert(tab.end(), pack.begin(), pack.end());
     }
+    // x-axis flags as 64-bit masks per run of 64 cells (bit j: cell 64 t + j):
+    // [nv == 2, lo[c] - lo[c-1], lo[c+1] - lo[c]], read by scalar loads
+    if (tab.size() & 1) tab.push_back(0);
+    const int xmask_off = (int)tab.size();
+    {
+        const int nxt = cdiv(c.nx, 64);
+        const int32_t *px = tab.data() + s.tab_off[0][6];
+        std::vector<uint64_t> xm(3 * (size_t)nxt, 0);
+        for (int i = 0; i < c.nx; ++i)
+            for (int f = 0; f < 3; ++f)
+                if ((px[i] >> (20 + f)) & 1) xm[3 * (i / 64) + f] |= 1ull << (i % 64);
+        for (uint64_t v : xm) {
+            tab.push_back((int32_t)(uint32_t)(v & 0xFFFFFFFFu));
+            tab.push_back((int32_t)(uint32_t)(v >> 32));
+        }
+    }
     // blocks with active cells, compacted in Cartesian order; active cells per block
     const int M0 = cd.m[0] * cd.m[1] * cd.m[2];
     std::vector<int64_t> cnt(M0, 0);
@@ -245,6 +261,7 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         cd.split[a] = s.d_tab + s.tab_off[a][5];
         cd.pack[a] = s.d_tab + s.tab_off[a][6];
     }
+    cd.xmask = (const uint64_t *)(s.d_tab + xmask_off);
     cd.cmap = s.d_tab + cmap_off;
     cd.present = s.d_tab + pres_off;
     s.gbase = s.d_tab + gbase_off;
@@ -765,7 +782,10 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     c->tmp = (double *)alloc(8 * (size_t)N);
     c->z = (double *)alloc(8 * (size_t)N);
     c->u = (double *)alloc(8 * (size_t)N);
-    c->partial = (double *)alloc(8 * (size_t)kRedBlocks * (2 * kMaxRestart + 2));
+    // reduction partials: dot/norm kernels, and one maximum per sweep workgroup
+    const size_t npart = std::max((size_t)kRedBlocks * (2 * kMaxRestart + 2),
+                                  (size_t)cdiv(g->nx, 64) * cdiv((long)g->ny * g->nz, 4));
+    c->partial = (double *)alloc(8 * npart);
     c->scal = (double *)alloc(8 * 8192);
     c->status = (Status *)alloc(sizeof(Status));
     c->maxbits = (unsigned long long *)alloc(8 * 65536);

@@ -38,6 +38,7 @@ struct CartDev {
     const int32_t *be[3];         // block start per axis (m+1 entries)
     const int32_t *split[3];      // per block: first cell whose first support block is the block itself
     const int32_t *pack[3];       // per cell: lo | (nv==2)<<20 | (lo[c]-lo[c-1])<<21 | (lo[c+1]-lo[c])<<22
+    const uint64_t *xmask;        // per run of 64 x cells: bits 20, 21, 22 of pack[0] as three masks
     const int32_t *cmap;          // Cartesian block -> compact id (-1 dropped)
     const int32_t *present;       // compact id -> Cartesian block
 };
