@@ -50,13 +50,15 @@ __global__ void k_basis_init(CartDev cd, Fine g, PT *__restrict__ P) {
 // in l's support (value 0).  So the values cell i needs from l are l's own
 // NS slots, permuted (bit flipped where lo differs) and masked.
 //
-// Work layout: a wavefront owns a run of 64 cells along x of one row (y, z);
-// rows are visited z fastest, so the z neighbours of a row are the rows of
-// the adjacent wavefronts.  Within a wavefront y and z (and so the y and z
-// neighbour shifts) are uniform.  Loads go through buffer resources with
-// the slot offset in a scalar register, so a neighbour's NS slots cost one
-// vector address.  All loads of a cell are issued before the first use;
-// faces outside the grid have T = 0 and their loads are clamped to the cell.
+// Work layout (z march): a wavefront owns a run of 64 cells along x at one
+// row y and walks the layers z0..z1-1 of its chunk.  It keeps the slots of
+// layers z-1, z, z+1 of its run in registers (the z neighbours), takes the
+// x neighbours from the adjacent lanes, and the rows y-1 and y+1 from the
+// neighbouring wavefronts of its workgroup through LDS (the first and last
+// row of the workgroup load the row beyond from memory, with the uniform
+// slot permutation in the scalar load offsets).  Loads go through buffer
+// resources with the slot offset in a scalar register.  Faces outside the
+// grid have T = 0 and their loads are clamped to the cell.
 // Faces are added in the order -x, +x, -y, +y, -z, +z.
 template <int AM>
 __device__ constexpr int am_bit(int a) {
@@ -94,7 +96,8 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
                                                            const PT *__restrict__ ty, const PT *__restrict__ tz,
                                                            const PT *__restrict__ Pin, PT *__restrict__ Pout,
                                                            PT omega, double *__restrict__ part, int *flag,
-                                                           int check_blocks, const int *done, int nxt, int nblk,
+                                                           int check_blocks, const int *done, int nxt, int ngy,
+                                                           int nzc, int zc, int nblk,
                                                            const unsigned long long *__restrict__ xmask,
                                                            const int *__restrict__ packy,
                                                            const int *__restrict__ packz) {
@@ -105,143 +108,197 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
     const int b = xcd_block();
     if (b >= nblk) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy, N = g.N;
+    const int NSZ = N * SZ;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int xt = b % nxt;
-    const int row = (b / nxt) * kSweepRows + wv;  // row = z + nz * y
-    const bool row_ok = row < ny * nz;
-    const int rc = row_ok ? row : ny * nz - 1;
-    const int y = rc / nz, z = rc - y * nz;
+    // block id: z chunk fastest, then row group, then x tile
+    const int zk = b % nzc, r2 = b / nzc;
+    const int yg = r2 % ngy, xt = r2 / ngy;
+    const int y = yg * kSweepRows + wv;
+    const bool row_ok = y < ny;
+    const int yc = min(y, ny - 1);
     const int x = xt * 64 + lane;
     const bool own = row_ok && x < nx;
     const int xc = min(x, nx - 1);
-    const int i = xc + nx * y + nxy * z;
+    const int z0 = zk * zc, z1 = min(nz, z0 + zc);
 
     const __amdgpu_buffer_rsrc_t rP = rsrc(Pin, (long)NS * N * SZ), rO = rsrc(Pout, (long)NS * N * SZ);
     const __amdgpu_buffer_rsrc_t rX = rsrc(tx, (long)N * SZ), rY = rsrc(ty, (long)N * SZ), rZ = rsrc(tz, (long)N * SZ);
-    // neighbour cells (clamped to i outside the grid) in face order
-    const bool fin[6] = {xc > 0, xc + 1 < nx, y > 0, y + 1 < ny, z > 0, z + 1 < nz};
-    const int l[6] = {fin[0] ? i - 1 : i, fin[1] ? i + 1 : i, fin[2] ? i - nx : i,
-                      fin[3] ? i + nx : i, fin[4] ? i - nxy : i, fin[5] ? i + nxy : i};
-    // table words without the lo field (bits 20-22); y and z are uniform
+    const __amdgpu_buffer_rsrc_t rD = rsrc(g.diag, (long)N * 8);
+    // table words without the lo field (bits 20-22): x per lane, y per row
     int wx = 0;
     if (AM & 1) {
         const unsigned long long *mk = xmask + 3 * xt;
 #pragma unroll
         for (int f = 0; f < 3; ++f) wx |= (int)((mk[f] >> lane) & 1) << (20 + f);
     }
-    const int wy = (AM & 2) ? packy[y] : 0;
-    const int wz = (AM & 4) ? packz[z] : 0;
-    const int w[3] = {wx, wy, wz};
-    // Face q along a split axis with its shift bit set (lo of the neighbour
-    // differs): on a down face slot s reads the neighbour's slot s|m and the
-    // slots with bit m are empty; on an up face slot s reads slot s&~m and
-    // the slots without bit m are empty.  The permutation goes into the load
-    // offsets (scalar for y and z, where the shift is uniform; per lane for
-    // x) and the empty slots are weighted by Tz = 0 instead of T.
-    bool sh[6];
+    const int wy = (AM & 2) ? packy[yc] : 0;
+    constexpr int mX = (AM & 1) ? 1 << am_bit<AM>(0) : 0;
+    constexpr int mY = (AM & 2) ? 1 << am_bit<AM>(1) : 0;
+    constexpr int mZ = (AM & 4) ? 1 << am_bit<AM>(2) : 0;
+    const bool shx0 = (AM & 1) && ((wx >> 21) & 1), shx1 = (AM & 1) && ((wx >> 22) & 1);
+    const bool shy0 = (AM & 2) && ((wy >> 21) & 1), shy1 = (AM & 2) && ((wy >> 22) & 1);
+    const bool fxm = xc > 0, fxp = xc + 1 < nx, fym = yc > 0, fyp = yc + 1 < ny;
+    // y neighbours: permuted slot offsets, uniform over the wavefront
+    int sym_[NS], syp_[NS], soym[NS], soyp[NS];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) sh[q] = ((AM >> (q >> 1)) & 1) && ((w[q >> 1] >> ((q & 1) ? 22 : 21)) & 1);
-    const int NSZ = N * SZ;
-    PT p[NS], nb[6][NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) p[s] = bload<PT>(rP, i * SZ, s * NSZ);
-    const PT t0 = bload<PT>(rX, l[0] * SZ, 0), t1 = bload<PT>(rX, i * SZ, 0);
-    const PT t2 = bload<PT>(rY, l[2] * SZ, 0), t3 = bload<PT>(rY, i * SZ, 0);
-    const PT t4 = bload<PT>(rZ, l[4] * SZ, 0), t5 = bload<PT>(rZ, i * SZ, 0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int a = q >> 1;
-        const bool up = q & 1;
-        if (!((AM >> a) & 1)) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) nb[q][s] = bload<PT>(rP, l[q] * SZ, s * NSZ);
-            continue;
-        }
-        const int m = 1 << am_bit<AM>(a);
-        if (a == 0) {
-            // per-lane shift.  Down face: the moved slots s read s + m, the
-            // vector offset gains m planes when shifted.  Up face: the moved
-            // slots read s - m, put in the scalar offset, and the vector offset
-            // gains the m planes back when not shifted (a vector offset stays
-            // non-negative: the buffer range check applies to it alone).
-            const int vo = l[q] * SZ, vs = vo + ((sh[q] != up) ? m * NSZ : 0);
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const bool moved = up ? (s & m) : !(s & m);
-                nb[q][s] = bload<PT>(rP, moved ? vs : vo, (moved && up ? s - m : s) * NSZ);
-            }
-        } else {
-            const bool shu = __builtin_amdgcn_readfirstlane(sh[q]);
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int s2 = shu ? (up ? (s & ~m) : (s | m)) : s;
-                nb[q][s] = bload<PT>(rP, l[q] * SZ, s2 * NSZ);
-            }
-        }
+    for (int s = 0; s < NS; ++s) {
+        sym_[s] = shy0 ? (s | mY) : s;
+        syp_[s] = shy1 ? (s & ~mY) : s;
+        soym[s] = sym_[s] * NSZ;
+        soyp[s] = syp_[s] * NSZ;
     }
-    const double dg = g.diag[i];
-    // keep every load above this point: one memory round trip per wavefront
-    __builtin_amdgcn_sched_barrier(0);
-    const PT T[6] = {fin[0] ? t0 : (PT)0, fin[1] ? t1 : (PT)0, fin[2] ? t2 : (PT)0,
-                     fin[3] ? t3 : (PT)0, fin[4] ? t4 : (PT)0, fin[5] ? t5 : (PT)0};
+    const int base = xc + nx * yc;
+    int i = base + nxy * z0;
+    PT Pm[NS], Pc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        Pc[s] = bload<PT>(rP, i * SZ, s * NSZ);
+        Pm[s] = bload<PT>(rP, (z0 > 0 ? i - nxy : i) * SZ, s * NSZ);
+    }
+    const PT tzm0 = bload<PT>(rZ, (z0 > 0 ? i - nxy : i) * SZ, 0);
+    PT tzm = z0 > 0 ? tzm0 : (PT)0;
+    double chg = 0.0;
 
-    PT acc[NS];
+    // rows y-1 and y+1 of the current layer: from the neighbouring
+    // wavefronts through LDS (double buffered, one barrier per layer); the
+    // first and last row of the workgroup load the row beyond from memory
+    __shared__ PT rowbuf[2][kSweepRows][NS][64];
+    const bool ym_mem = wv == 0, yp_mem = wv == kSweepRows - 1;
+    for (int z = z0; z < z1; ++z, i += nxy) {
+        const bool fzp = z + 1 < nz;
+        const int lym = fym ? i - nx : i, lyp = fyp ? i + nx : i;
+        const int buf = (z - z0) & 1;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = (PT)0;
-    PT db = (PT)0;
+        for (int s = 0; s < NS; ++s) rowbuf[buf][wv][s][lane] = Pc[s];
+        PT Pn[NS], Ym[NS], Yp[NS];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int a = q >> 1;
-        const bool up = q & 1;
-        const PT Tq = T[q];
-        const PT Tz = sh[q] ? (PT)0 : Tq;
-        db += Tq;
+        for (int s = 0; s < NS; ++s) Pn[s] = bload<PT>(rP, (fzp ? i + nxy : i) * SZ, s * NSZ);
+        if (ym_mem) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) Ym[s] = bload<PT>(rP, lym * SZ, soym[s]);
+        }
+        if (yp_mem) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) Yp[s] = bload<PT>(rP, lyp * SZ, soyp[s]);
+        }
+        const PT txc = bload<PT>(rX, i * SZ, 0), tym = bload<PT>(rY, lym * SZ, 0);
+        const PT tyc = bload<PT>(rY, i * SZ, 0), tzc = bload<PT>(rZ, i * SZ, 0);
+        const double dg = bload<double>(rD, i * 8, 0);
+        const int wz = (AM & 4) ? packz[z] : 0;
+        const bool shz0 = (AM & 4) && ((wz >> 21) & 1), shz1 = (AM & 4) && ((wz >> 22) & 1);
+        __syncthreads();
+        if (!ym_mem) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) Ym[s] = rowbuf[buf][wv - 1][sym_[s]][lane];
+        }
+        if (!yp_mem) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) Yp[s] = rowbuf[buf][wv + 1][syp_[s]][lane];
+        }
+
+        // x neighbours from the adjacent lanes; lanes at a tile edge fetch
+        // across it
+        PT xm[NS], xp[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const bool empty = ((AM >> a) & 1) && (up ? !(s & (1 << am_bit<AM>(a))) : (s & (1 << am_bit<AM>(a))));
-            acc[s] += (empty ? Tz : Tq) * nb[q][s];
+            xm[s] = __shfl_up(Pc[s], 1, 64);
+            xp[s] = __shfl_down(Pc[s], 1, 64);
         }
-    }
-    // Inactive cells store zeros; a row whose new sum is not positive keeps
-    // its old values and raises flag bit 2.
-    const bool active = dg > 0.0;
-    bool ok[NS];
+        PT txm = __shfl_up(txc, 1, 64);
+        if (nxt > 1) {
+            if (lane == 0 && fxm) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        bool v = true;
+                for (int s = 0; s < NS; ++s) xm[s] = bload<PT>(rP, (i - 1) * SZ, s * NSZ);
+                txm = bload<PT>(rX, (i - 1) * SZ, 0);
+            }
+            if (lane == 63 && fxp) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (((AM >> a) & 1) && (s & (1 << am_bit<AM>(a))) && !((w[a] >> 20) & 1)) v = false;
-        ok[s] = v;
-    }
-    if (check_blocks && active) {
-        const int lo[3] = {(AM & 1) ? cd.pack[0][xc] & 0xFFFFF : 0, wy & 0xFFFFF, wz & 0xFFFFF};
+                for (int s = 0; s < NS; ++s) xp[s] = bload<PT>(rP, (i + 1) * SZ, s * NSZ);
+            }
+        }
+        // Neighbour slot permutation along split axes (see above): a down
+        // face with the shift reads slot s|m for the slots without bit m, an
+        // up face reads slot s&~m for the slots with bit m; the other slots
+        // are empty and weighted by zero.
+        PT nb[6][NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (ok[s] && slot_block(cd, lo, s) < 0) ok[s] = false;
-    }
-    const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
-    PT pn[NS];
-    PT rs = (PT)0;
+        for (int s = 0; s < NS; ++s) {
+            nb[0][s] = (mX && !(s & mX) && shx0) ? xm[s | mX] : xm[s];
+            nb[1][s] = (mX && (s & mX) && shx1) ? xp[s & ~mX] : xp[s];
+            nb[2][s] = Ym[s];
+            nb[3][s] = Yp[s];
+            nb[4][s] = (mZ && !(s & mZ) && shz0) ? Pm[s | mZ] : Pm[s];
+            nb[5][s] = (mZ && (s & mZ) && shz1) ? Pn[s & ~mZ] : Pn[s];
+        }
+        const bool sh[6] = {shx0, shx1, shy0, shy1, shz0, shz1};
+        const PT T[6] = {fxm ? txm : (PT)0, txc, fym ? tym : (PT)0, fyp ? tyc : (PT)0, tzm, fzp ? tzc : (PT)0};
+
+        PT acc[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const PT v = db > (PT)0 ? p[s] - omega * (p[s] - acc[s] * idb) : p[s];
-        pn[s] = ok[s] ? v : (PT)0;
-        rs += pn[s];
-    }
-    const bool bad = own && active && !(rs > (PT)0);
-    if (bad) atomicOr(flag, 2);
-    const PT irs = (PT)1 / rs;
-    double chg = 0.0;
+        for (int s = 0; s < NS; ++s) acc[s] = (PT)0;
+        PT db = (PT)0;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const PT v = pn[s] * irs;
-        const PT o = active ? (bad ? p[s] : v) : (PT)0;
-        chg = fmax(chg, fabs((double)v - (double)p[s]));
-        if (own) bstore<PT>(o, rO, i * SZ, s * N * SZ);
+        for (int q = 0; q < 6; ++q) {
+            const int a = q >> 1;
+            const bool up = q & 1;
+            const PT Tq = T[q];
+            const PT Tz = sh[q] ? (PT)0 : Tq;
+            db += Tq;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const bool empty = ((AM >> a) & 1) && (up ? !(s & (1 << am_bit<AM>(a))) : (s & (1 << am_bit<AM>(a))));
+                acc[s] += (empty ? Tz : Tq) * nb[q][s];
+            }
+        }
+        // Inactive cells store zeros; a row whose new sum is not positive
+        // keeps its old values and raises flag bit 2.
+        const bool active = dg > 0.0;
+        const int w[3] = {wx, wy, wz};
+        bool ok[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            bool v = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (((AM >> a) & 1) && (s & (1 << am_bit<AM>(a))) && !((w[a] >> 20) & 1)) v = false;
+            ok[s] = v;
+        }
+        if (check_blocks && active) {
+            const int lo[3] = {(AM & 1) ? cd.pack[0][xc] & 0xFFFFF : 0, wy & 0xFFFFF, wz & 0xFFFFF};
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (ok[s] && slot_block(cd, lo, s) < 0) ok[s] = false;
+        }
+        const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
+        PT pn[NS];
+        PT rs = (PT)0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const PT v = db > (PT)0 ? Pc[s] - omega * (Pc[s] - acc[s] * idb) : Pc[s];
+            pn[s] = ok[s] ? v : (PT)0;
+            rs += pn[s];
+        }
+        const bool bad = own && active && !(rs > (PT)0);
+        if (bad) atomicOr(flag, 2);
+        const PT irs = (PT)1 / rs;
+        double c = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const PT v = pn[s] * irs;
+            const PT o = active ? (bad ? Pc[s] : v) : (PT)0;
+            c = fmax(c, fabs((double)v - (double)Pc[s]));
+            if (own) bstore<PT>(o, rO, i * SZ, s * NSZ);
+        }
+        chg = (own && active && !bad) ? fmax(chg, c) : chg;
+        // slide the window
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            Pm[s] = Pc[s];
+            Pc[s] = Pn[s];
+        }
+        tzm = tzc;
     }
-    chg = (own && active && !bad) ? chg : 0.0;
     const double mx = block_max(chg, lds);
     if (threadIdx.x == 0) part[b] = mx;
 }
@@ -270,8 +327,13 @@ template <typename PT>
 static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
                           int check_blocks) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    const int nxt = cdiv(c.nx, 64);
-    const int nblk = nxt * cdiv((long)c.ny * c.nz, kSweepRows);
+    // z chunks sized for about 4096 wavefronts
+    const int nxt = cdiv(c.nx, 64), ngy = cdiv(c.ny, kSweepRows);
+    const int rows = nxt * ngy * kSweepRows;
+    int nzc = std::min(c.nz, std::max(1, cdiv(4096, rows)));
+    const int zc = cdiv(c.nz, nzc);
+    nzc = cdiv(c.nz, zc);
+    const int nblk = nzc * ngy * nxt;
     const dim3 grid(xcd_grid(nblk)), blk(64 * kSweepRows);
     const PT om = (PT)c.opt.omega;
     const int *done = &c.status->done;
@@ -281,8 +343,8 @@ static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT
 #define MSRSB_SWEEP(AM)                                                                                         \
     case AM:                                                                                                    \
         hipLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, s.cart, g, tx, ty, tz, in, out, om,       \
-                           c.partial, c.flag, check_blocks, done, nxt, nblk, (const unsigned long long *)s.cart.xmask,\
-                           s.cart.pack[1], s.cart.pack[2]);                                                     \
+                           c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,                      \
+                           (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);           \
         break;
     switch (am) {
         MSRSB_SWEEP(0) MSRSB_SWEEP(1) MSRSB_SWEEP(2) MSRSB_SWEEP(3)
