@@ -215,6 +215,8 @@ def traffic_record(kernel, precision):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2001_01624_amd", "csrc", rec.get("source", "k_sweep.hip"))
+    if not os.path.exists(src):
+        return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if h != rec.get("sha256"):
         return None

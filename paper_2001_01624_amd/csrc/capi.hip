@@ -783,8 +783,9 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     c->z = (double *)alloc(8 * (size_t)N);
     c->u = (double *)alloc(8 * (size_t)N);
     // reduction partials: dot/norm kernels, and one maximum per sweep workgroup
-    const size_t npart = std::max((size_t)kRedBlocks * (2 * kMaxRestart + 2),
-                                  (size_t)cdiv(g->nx, 64) * cdiv((long)g->ny * g->nz, 4));
+    const size_t npart = std::max({(size_t)kRedBlocks * (2 * kMaxRestart + 2),
+                                   (size_t)cdiv(g->nx, 64) * cdiv((long)g->ny * g->nz, 4),
+                                   (size_t)cdiv(N, kBlock)});
     c->partial = (double *)alloc(8 * npart);
     c->scal = (double *)alloc(8 * 8192);
     c->status = (Status *)alloc(sizeof(Status));

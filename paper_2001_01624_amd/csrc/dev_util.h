@@ -38,6 +38,15 @@ __device__ inline double block_sum(double v, double *lds) {
     return s;
 }
 
+// Sum of p[0..n) by one workgroup in a fixed order: thread t adds
+// p[t], p[t + blockDim], ... (loads unrolled), then block_sum.
+__device__ inline double sum_partials(const double *__restrict__ p, int n, double *lds) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[k];
+    return block_sum(s, lds);
+}
+
 __device__ inline double block_max(double v, double *lds) {
     v = wave_max(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -89,6 +98,67 @@ __device__ inline uint16_t float_to_bf16(float f) {
 template <typename T> __device__ inline double ld_basis(const T *p, long idx) { return (double)p[idx]; }
 template <> __device__ inline double ld_basis<uint16_t>(const uint16_t *p, long idx) {
     return (double)bf16_to_float(p[idx]);
+}
+
+// Sum of V values (V a power of two <= 64) over the wavefront, by halving
+// exchanges: afterwards every lane holds the total of value lane >> (6 - log2 V).
+// Lane pairs add the same two operands, so the result does not depend on
+// the lane that computes it.
+template <int V>
+__device__ inline double wave_transpose_sum(double (&v)[V], int lane) {
+#pragma unroll
+    for (int step = 0; step < 6; ++step) {
+        const int o = 32 >> step;
+        const int c = V >> step;
+        if (c >= 2) {
+            // lanes with bit o clear keep the lower half, the others the
+            // upper half; both halves are exchanged and the kept one summed
+            // (a select on sums, not on array slots, keeps v in registers)
+            const bool up = lane & o;
+#pragma unroll
+            for (int k = 0; k < (c >> 1); ++k) {
+                const double lo = v[k], hi = v[k + (c >> 1)];
+                const double rlo = __shfl_xor(lo, o, 64), rhi = __shfl_xor(hi, o, 64);
+                v[k] = up ? hi + rhi : lo + rlo;
+            }
+        } else {
+            v[0] += __shfl_xor(v[0], o, 64);
+        }
+    }
+    return v[0];
+}
+
+// Workgroup total of V per-thread values, written to out[0..nout): waves in
+// order, each wave by wave_transpose_sum.
+template <int V>
+__device__ inline void group_sum_store(double (&v)[V], int nout, double *red, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double t = wave_transpose_sum<V>(v, lane);
+    if ((lane & ((64 / V) - 1)) == 0) red[wv * V + lane / (64 / V)] = t;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nout; q += blockDim.x) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w * V + q];
+        out[q] = sum;
+    }
+    __syncthreads();
+}
+
+// Workgroup totals of V per-thread values left in red[nw*V + q] (nw = number
+// of wavefronts; red holds (nw + 1) * V doubles): waves in order, each wave
+// by wave_transpose_sum.  Ends with a barrier.
+template <int V>
+__device__ inline void group_sum_lds(double (&v)[V], double *red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    const double t = wave_transpose_sum<V>(v, lane);
+    if ((lane & ((64 / V) - 1)) == 0) red[wv * V + lane / (64 / V)] = t;
+    __syncthreads();
+    if ((int)threadIdx.x < V) {
+        double sum = 0.0;
+        for (int w = 0; w < nw; ++w) sum += red[w * V + threadIdx.x];
+        red[nw * V + threadIdx.x] = sum;
+    }
+    __syncthreads();
 }
 
 }  // namespace msrsb

@@ -26,7 +26,7 @@ template <int NSX, typename PT>
 __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t *__restrict__ sb,
                                                    const PT *__restrict__ tx, const PT *__restrict__ ty,
                                                    const PT *__restrict__ tz, const PT *__restrict__ Pin,
-                                                   PT *__restrict__ Pout, PT omega, unsigned long long *maxbits,
+                                                   PT *__restrict__ Pout, PT omega, double *__restrict__ part,
                                                    int *flag, const int *done) {
     __shared__ double lds[kBlock / 64];
     if (*done) return;
@@ -99,25 +99,27 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t
         }
     }
     const double m = block_max(chg, lds);
-    if (threadIdx.x == 0 && m > 0.0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(m));
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 
+// Returns the number of per-workgroup maxima written to c.partial.
 template <typename PT>
-static void xsweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
-                            unsigned long long *bits) {
+static int xsweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     const dim3 grid(cdiv(c.N, kBlock)), blk(kBlock);
     const PT om = (PT)c.opt.omega;
     const int *done = &c.status->done;
+    double *part = c.partial;
     if (s.ns <= 8)
-        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, bits,
+        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, part,
                            c.flag, done);
     else if (s.ns <= 16)
-        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, bits,
+        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, part,
                            c.flag, done);
     else
         hipLaunchKernelGGL((k_xsweep<kMaxXSlots, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out,
-                           om, bits, c.flag, done);
+                           om, part, c.flag, done);
+    return (int)grid.x;
 }
 
 void launch_xinit(Ctx &c, Stage &s) {
@@ -129,11 +131,10 @@ void launch_xinit(Ctx &c, Stage &s) {
                            s.xpblock, s.P64[0]);
 }
 
-void launch_xsweep(Ctx &c, Stage &s, int in, int out, unsigned long long *bits) {
+int launch_xsweep(Ctx &c, Stage &s, int in, int out) {
     if (c.opt.precision == MSRSB_MIXED)
-        xsweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out], bits);
-    else
-        xsweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out], bits);
+        return xsweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out]);
+    return xsweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out]);
 }
 
 // d_j = sum over the support list of block j of P_ij r_i (one workgroup per

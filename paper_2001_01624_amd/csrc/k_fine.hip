@@ -310,9 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_finish(const double *__restrict
                                                         const int *done) {
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < np; k += blockDim.x) s += partial[k];
-    s = block_sum(s, lds);
+    const double s = sum_partials(partial, np, lds);
     if (threadIdx.x == 0) *out = s;
 }
 
@@ -401,9 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot_finish(const double *__rest
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     const int j = blockIdx.x;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < np; k += blockDim.x) s += partial[(long)j * np + k];
-    s = block_sum(s, lds);
+    const double s = sum_partials(partial + (long)j * np, np, lds);
     if (threadIdx.x == 0) h[j] = s;
 }
 
@@ -619,6 +615,67 @@ __global__ __launch_bounds__(kBlock) void k_mvdot(Fine g, const double *__restri
     }
 }
 
+// Register-resident forms for k < KM basis vectors: every element of V is
+// read once per kernel.  A thread keeps the KM - 1 dot accumulators (and
+// the squared norm in the last slot); loads past k are clamped to vector
+// k - 1 and weighted by zero, so no load sits behind a branch.  Totals per
+// workgroup by group_sum_lds (fixed order).
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_mvdot_r(Fine g, const double *__restrict__ z, double *__restrict__ w,
+                                                    const double *__restrict__ V, int k,
+                                                    double *__restrict__ partial, const int *done) {
+    __shared__ double red[(kBlock / 64 + 1) * KM];
+    if (done && *done) return;
+    const int G = gridDim.x;
+    double acc[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += G * blockDim.x) {
+        double vq[KM - 1];
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) vq[q] = V[(long)min(q, k - 1) * g.N + i];
+        // faces as in cell_faces, with the zeroing applied after the loads
+        const int step[3] = {1, g.nx, g.nxy};
+        bool in[6];
+        int l[6];
+        double traw[6], xl[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
+            in[2 * a] = i >= step[a];
+            in[2 * a + 1] = i + step[a] < g.N;
+            l[2 * a] = in[2 * a] ? i - step[a] : i;
+            l[2 * a + 1] = in[2 * a + 1] ? i + step[a] : i;
+            traw[2 * a] = Ta[l[2 * a]];
+            traw[2 * a + 1] = Ta[i];
+        }
+        const double d = g.diag[i], xi = z[i];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) xl[q] = z[l[q]];
+        __builtin_amdgcn_sched_barrier(0);  // all loads of the element first
+        double ax = d * xi;                 // (A z)_i, as ax_row
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ax -= (in[q] ? traw[q] : 0.0) * xl[q];
+        const double wi = d > 0.0 ? ax : 0.0;
+        w[i] = wi;
+        acc[KM - 1] += wi * wi;
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) acc[q] += vq[q] * (q < k ? wi : 0.0);
+    }
+    group_sum_lds<KM>(acc, red);
+    const int nw = blockDim.x >> 6;
+    if ((int)threadIdx.x < k) partial[(long)threadIdx.x * G + blockIdx.x] = red[nw * KM + threadIdx.x];
+    if (threadIdx.x == KM - 1) partial[(long)kMaxRestart * 2 * G + blockIdx.x] = red[nw * KM + KM - 1];
+}
+
+// w -= V h (first pass), ||w||^2, and when the second pass is due the dots
+// V^T w of the updated w, from the same loads of V.
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_axpy_dot_r(int N, const double *__restrict__ V, int k,
+                                                       const double *__restrict__ h, double *__restrict__ w,
+                                                       double *__restrict__ partial, const Status *st,
+                                                       const double *scal);
+
 // Whether a second Gram-Schmidt pass is due, from ||w - V h||^2 =
 // ||w||^2 - ||h||^2 (V orthonormal): iff that is < 0.49 ||w||^2 (the DGKS
 // test ||w'|| < 0.7 ||w||).  Every kernel that needs the decision evaluates
@@ -633,26 +690,65 @@ __device__ inline bool second_pass(const double *scal, int k) {
 // = sum of the norm partials (q == nd); fixed order.  mode 2 (after the first
 // update): when no second pass is due the dots are not summed and out
 // (h2) is cleared instead.
-__global__ __launch_bounds__(64) void k_finish_dots(const double *__restrict__ partial, int G, int nd,
-                                                    double *__restrict__ out, double *nout, const Status *st,
-                                                    const double *scal, int mode) {
+__global__ __launch_bounds__(kBlock) void k_finish_dots(const double *__restrict__ partial, int G, int nd,
+                                                       double *__restrict__ out, double *nout, const Status *st,
+                                                       const double *scal, int mode) {
+    __shared__ double lds[kBlock / 64];
     if (st->done) return;
-    const int q = blockIdx.x, lane = threadIdx.x;
+    const int q = blockIdx.x;
     if (mode == 2 && q < nd && !second_pass(scal, nd)) {
-        if (lane == 0) out[q] = 0.0;
+        if (threadIdx.x == 0) out[q] = 0.0;
         return;
     }
     const long base = q < nd ? (long)q * G : (long)kMaxRestart * 2 * G;
-    double t = 0.0;
-    for (int b = lane; b < G; b += 64) t += partial[base + b];
-    t = wave_sum(t);
-    if (lane == 0) {
+    const double t = sum_partials(partial + base, G, lds);
+    if (threadIdx.x == 0) {
         if (q < nd) out[q] = t;
         else *nout = t;
     }
 }
 
 // w -= V h1; if a second pass follows, partial dots V_q^T w; always ||w||^2.
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_axpy_dot_r(int N, const double *__restrict__ V, int k,
+                                                       const double *__restrict__ h, double *__restrict__ w,
+                                                       double *__restrict__ partial, const Status *st,
+                                                       const double *scal) {
+    __shared__ double red[(kBlock / 64 + 1) * KM];
+    if (st->done) return;
+    const bool dots = second_pass(scal, k);
+    const int G = gridDim.x;
+    double hq[KM - 1];
+#pragma unroll
+    for (int q = 0; q < KM - 1; ++q) {
+        const double hv = h[min(q, k - 1)];
+        hq[q] = q < k ? hv : 0.0;
+    }
+    double acc[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += G * blockDim.x) {
+        double vq[KM - 1];
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) vq[q] = V[(long)min(q, k - 1) * N + i];
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q)
+            if (q < k) sacc += hq[q] * vq[q];
+        const double v = w[i] - sacc;
+        w[i] = v;
+        acc[KM - 1] += v * v;
+        if (dots) {
+#pragma unroll
+            for (int q = 0; q < KM - 1; ++q) acc[q] += vq[q] * (q < k ? v : 0.0);
+        }
+    }
+    group_sum_lds<KM>(acc, red);
+    const int nw = blockDim.x >> 6;
+    if (dots && (int)threadIdx.x < k) partial[(long)threadIdx.x * G + blockIdx.x] = red[nw * KM + threadIdx.x];
+    if (threadIdx.x == KM - 1) partial[(long)kMaxRestart * 2 * G + blockIdx.x] = red[nw * KM + KM - 1];
+}
+
 __global__ __launch_bounds__(kBlock) void k_axpy_dot(int N, const double *__restrict__ V, int k,
                                                      const double *__restrict__ h, double *__restrict__ w,
                                                      double *__restrict__ partial, const Status *st,
@@ -735,32 +831,35 @@ __global__ __launch_bounds__(kBlock) void k_axpy_norm(int N, const double *__res
 
 // Norm of the orthogonalised w (second pass if any) then Arnoldi step j:
 // H(:,j) = h1 + h2, H(j+1,j) = ||w||, Givens rotations, residual estimate.
-__global__ __launch_bounds__(64) void k_gmres_step2(Status *st, double *scal, const double *__restrict__ partial,
-                                                    int G, int j, double rtol, int max_iters, int restart) {
+__global__ __launch_bounds__(kBlock) void k_gmres_step2(Status *st, double *scal, const double *__restrict__ partial,
+                                                       int G, int j, double rtol, int max_iters, int restart) {
+    __shared__ double lds[kBlock / 64];
     if (st->done) return;
     double hn2;
-    if (second_pass(scal, j + 1)) {
-        double t = 0.0;
-        for (int b = threadIdx.x; b < G; b += 64) t += partial[(long)kMaxRestart * 2 * G + b];
-        hn2 = wave_sum(t);
-    } else {
-        hn2 = scal[3];
-    }
-    if (threadIdx.x != 0) return;
+    if (second_pass(scal, j + 1)) hn2 = sum_partials(partial + (long)kMaxRestart * 2 * G, G, lds);
+    else hn2 = scal[3];
+    // the new Hessenberg column and the previous rotations, staged in LDS
+    __shared__ double col[kMaxRestart + 1], rc[kMaxRestart], rs[kMaxRestart];
     double *H = scal + S_H;
     double *gv = scal + S_G;
     double *cs = scal + S_CS;
     double *sn = scal + S_SN;
     const int ld = kMaxRestart + 1;
-    for (int i = 0; i <= j; ++i) H[i + ld * j] = scal[S_H1 + i] + scal[S_H2 + i];
     const double hn = sqrt(hn2);
-    H[j + 1 + ld * j] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a = H[i + ld * j], b = H[i + 1 + ld * j];
-        H[i + ld * j] = cs[i] * a + sn[i] * b;
-        H[i + 1 + ld * j] = -sn[i] * a + cs[i] * b;
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = i <= j ? scal[S_H1 + i] + scal[S_H2 + i] : hn;
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        rc[i] = cs[i];
+        rs[i] = sn[i];
     }
-    const double a = H[j + ld * j], b = H[j + 1 + ld * j];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double a_i = col[0];
+    for (int i = 0; i < j; ++i) {
+        const double b = col[i + 1];
+        H[i + ld * j] = rc[i] * a_i + rs[i] * b;
+        a_i = -rs[i] * a_i + rc[i] * b;
+    }
+    const double a = a_i, b = hn;
     const double rr = hypot(a, b);
     const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? b / rr : 0.0;
     cs[j] = cj;
@@ -781,25 +880,42 @@ void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int 
     Fine g = fine_of(c);
     const int G = red_grid(c.N);
     const int *done = &c.status->done;
+    const int k = j + 1;
     {
         ProfScope ps(c, MSRSB_K_MATVEC);
-        hipLaunchKernelGGL(k_mvdot, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, j + 1, c.partial, done);
+        if (k <= 7)
+            hipLaunchKernelGGL(k_mvdot_r<8>, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, k, c.partial, done);
+        else if (k <= 15)
+            hipLaunchKernelGGL(k_mvdot_r<16>, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, k, c.partial, done);
+        else if (k <= 31)
+            hipLaunchKernelGGL(k_mvdot_r<32>, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, k, c.partial, done);
+        else
+            hipLaunchKernelGGL(k_mvdot, dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, k, c.partial, done);
     }
-    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(64), 0, c.stream, c.partial, G, j + 1, c.scal + S_H1,
+    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(kBlock), 0, c.stream, c.partial, G, j + 1, c.scal + S_H1,
                        c.scal + 2, (const Status *)c.status, (const double *)c.scal, 1);
     {
         ProfScope ps(c, MSRSB_K_ORTHO);
-        hipLaunchKernelGGL(k_axpy_dot, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, j + 1, c.scal + S_H1, w,
-                           c.partial, (const Status *)c.status, (const double *)c.scal);
+        const double *h1 = c.scal + S_H1;
+        const Status *st = c.status;
+        const double *sc = c.scal;
+        if (k <= 7)
+            hipLaunchKernelGGL(k_axpy_dot_r<8>, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, k, h1, w, c.partial, st, sc);
+        else if (k <= 15)
+            hipLaunchKernelGGL(k_axpy_dot_r<16>, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, k, h1, w, c.partial, st, sc);
+        else if (k <= 31)
+            hipLaunchKernelGGL(k_axpy_dot_r<32>, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, k, h1, w, c.partial, st, sc);
+        else
+            hipLaunchKernelGGL(k_axpy_dot, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, k, h1, w, c.partial, st, sc);
     }
-    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(64), 0, c.stream, c.partial, G, j + 1, c.scal + S_H2,
+    hipLaunchKernelGGL(k_finish_dots, dim3(j + 2), dim3(kBlock), 0, c.stream, c.partial, G, j + 1, c.scal + S_H2,
                        c.scal + 3, (const Status *)c.status, (const double *)c.scal, 2);
     {
         ProfScope ps(c, MSRSB_K_ORTHO);
         hipLaunchKernelGGL(k_axpy_norm, dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, j + 1, c.scal + S_H2, w,
                            c.partial, (const Status *)c.status, (const double *)c.scal);
     }
-    hipLaunchKernelGGL(k_gmres_step2, dim3(1), dim3(64), 0, c.stream, c.status, c.scal, c.partial, G, j, rtol,
+    hipLaunchKernelGGL(k_gmres_step2, dim3(1), dim3(kBlock), 0, c.stream, c.status, c.scal, c.partial, G, j, rtol,
                        max_iters, restart);
     hipLaunchKernelGGL(k_scale, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, w,
                        c.V + (long)(j + 1) * c.N, c.scal + S_INV, done);

@@ -311,6 +311,7 @@ __global__ __launch_bounds__(256) void k_sweep_check(Status *st, unsigned long l
     __shared__ double lds[4];
     if (st->done) return;
     double m = 0.0;
+#pragma unroll 8
     for (int t = threadIdx.x; t < npart; t += blockDim.x) m = fmax(m, part[t]);
     m = block_max(m, lds);
     if (threadIdx.x == 0) {
@@ -404,7 +405,7 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
                 {
                     ProfScope ps(c, MSRSB_K_SWEEP);
                     if (s.kind == 2)
-                        launch_xsweep(c, s, in, out, c.maxbits + k);
+                        npart = launch_xsweep(c, s, in, out);
                     else if (mixed)
                         npart = sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out],
                                                       check_blocks);

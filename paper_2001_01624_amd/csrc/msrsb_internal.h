@@ -193,7 +193,7 @@ void launch_coarse_solve(Ctx &c, Stage &s, const int *done);
 
 // ---- explicit-slot stage kernels (k_explicit.hip) ----
 void launch_xinit(Ctx &c, Stage &s);
-void launch_xsweep(Ctx &c, Stage &s, int in, int out, unsigned long long *bits);
+int launch_xsweep(Ctx &c, Stage &s, int in, int out);
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done);
 void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done);
 void launch_xrap(Ctx &c, Stage &s);
