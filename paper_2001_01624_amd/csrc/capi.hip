@@ -710,7 +710,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
         cb = std::max(cb, (long)cdiv(M, kTile) * kTile);
     }
     cb = std::max(cb, (long)cdiv(o.max_dyn_blocks, kTile) * kTile);
-    b += (size_t)cb * kTile * 8;
+    b += (size_t)(cb + 2 * kTile) * kTile * 8;
     return b;
 }
 
@@ -817,7 +817,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         if (rc) return fail(rc);
         cb = std::max(cb, (long)c->stages[k].Mp);
     }
-    c->cbuf = (double *)alloc(8 * (size_t)cb * kTile);
+    c->cbuf = (double *)alloc(8 * (size_t)(cb + 2 * kTile) * kTile);  // + two diagonal-block inverses
     c->cbuf_n = cb;
     if (!c->cbuf) return fail(MSRSB_E_NOMEM);
     hipMemsetAsync(c->tmp, 0, 8 * (size_t)N, c->stream);
@@ -903,7 +903,7 @@ int msrsb_add_dynamic_basis(msrsb_ctx *c, int n_incr, const double *const *d_dp,
         if (n_dyn_blocks) n_dyn_blocks[k] = count;
         if (count == 0) continue;
         if (s.Mp > c->cbuf_n) {
-            c->cbuf = (double *)ctx_alloc(*c, 8 * (size_t)s.Mp * kTile);
+            c->cbuf = (double *)ctx_alloc(*c, 8 * (size_t)(s.Mp + 2 * kTile) * kTile);
             if (!c->cbuf) return MSRSB_E_NOMEM;
             c->cbuf_n = s.Mp;
         }

@@ -5,96 +5,280 @@
 // pivots in order turns A_c into A_c^{-1} in place.  Each pivot of the sweep
 // is a diagonal entry of a Schur complement of A_c (the square of the
 // corresponding Cholesky diagonal), so a non-positive pivot means A_c is
-// not SPD and is reported.  The sweep is blocked by kTile columns:
-//   1. D = A[K,K] is inverted in LDS (one workgroup),
-//   2. row panel A[K,J] <- D^{-1} A[K,J] and a copy C of the column panel,
-//   3. A[I,J] -= C[I] A[K,J];  A[I,K] <- -C[I] D^{-1};  A[K,K] <- D^{-1}.
+// not SPD and is reported.  The sweep is blocked by T = kTile columns; for
+// pivot block K with D = A[K,K]:
+//   A[K,J] <- D^{-1} A[K,J]                      (row panel, J != K)
+//   A[I,J] <- A[I,J] - A[I,K] (D^{-1} A[K,J])     (I != K, J != K)
+//   A[I,K] <- -A[I,K] D^{-1},  A[K,K] <- D^{-1}.
+// D^{-1} of the next pivot block is formed by the workgroup that updates
+// that block, inside the update of the current step, so only the first
+// block inversion is on its own on the critical path.
 // Each cycle then applies the inverse by a GEMV (one wavefront per row).
 #include "dev_util.h"
 #include "msrsb_internal.h"
 
 namespace msrsb {
 
-constexpr int T_ = kTile;
+constexpr int T_ = kTile;     // 64
+constexpr int kGJThreads = 256;
+constexpr int kLd = T_ + 1;   // LDS row pitch (bank spread)
 
-__global__ __launch_bounds__(256) void k_gj_diag(double *__restrict__ A, int Mp, int k0, double *__restrict__ Dinv,
-                                                 int *flag) {
-    __shared__ double D[T_][T_ + 1];
-    __shared__ double col[T_];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < T_ * T_; e += blockDim.x) D[e / T_][e % T_] = A[(long)(k0 + e / T_) * Mp + k0 + e % T_];
-    __syncthreads();
-    for (int k = 0; k < T_; ++k) {
-        const double p = D[k][k];
-        if (tid == 0 && !(p > 0.0)) atomicOr(flag, 1);
-        const double ip = p > 0.0 ? 1.0 / p : 0.0;
-        if (tid < T_) col[tid] = D[tid][k];
-        __syncthreads();
-        if (tid < T_ && tid != k) D[k][tid] *= ip;
-        __syncthreads();
-        for (int e = tid; e < T_ * T_; e += blockDim.x) {
-            const int i = e / T_, j = e % T_;
-            if (i != k && j != k) D[i][j] -= col[i] * D[k][j];
+// In-place inversion of the T x T (64) block M in LDS by one workgroup of
+// 256 threads: Gauss-Jordan blocked by 16 pivots.  For sub-block s (rows and
+// columns o..o+15, o = 16 s):
+//   1. D = M[s,s] is inverted element-wise by one wavefront (pivot row and
+//      column by lane shuffles, no workgroup barrier per pivot);
+//   2. W[s,:] = D^{-1} M[s,:] off the block, W[s,s] = D^{-1}; Cb = M[:,s];
+//   3. M[i,j] <- M[i,j] - Cb[i,:] W[:,j] for rows i off the block (with 0 in
+//      place of M[i,j] on the block columns), M[s,:] <- W[s,:].
+// W is 16 x kLd and Cb 64 x 17 doubles of LDS scratch.
+__device__ inline void gj_invert_lds(double (*M)[kLd], double (*W)[kLd], double (*Cb)[17], int *flag) {
+    const int t = threadIdx.x;
+#pragma unroll 1
+    for (int sb = 0; sb < T_ / 16; ++sb) {
+        const int o = 16 * sb;
+        // 1. element-wise inverse of the 16 x 16 diagonal sub-block by the
+        //    first wavefront: lane l owns row l/4, columns 4(l%4)..+3, and
+        //    takes the pivot row and column from the owning lanes by shuffles
+        if (t < 64) {
+            const int r = t >> 2, cg = t & 3;
+            double x[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) x[b] = M[o + r][o + 4 * cg + b];
+#pragma unroll 4
+            for (int k = 0; k < 16; ++k) {  // k & 3 is fixed within the unrolled body
+                const double p = __shfl(x[k & 3], 4 * k + (k >> 2), 64);
+                if (t == 0 && !(p > 0.0)) atomicOr(flag, 1);
+                const double ip = p > 0.0 ? 1.0 / p : 0.0;
+                const double dik = __shfl(x[k & 3], 4 * r + (k >> 2), 64);
+                double rowk[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) rowk[b] = __shfl(x[b], 4 * k + cg, 64);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int c = 4 * cg + b;
+                    const double rk = rowk[b] * ip;
+                    double nx = c == k ? -dik * ip : x[b] - dik * rk;
+                    if (r == k) nx = c == k ? ip : rk;
+                    x[b] = nx;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) M[o + r][o + 4 * cg + b] = x[b];
         }
         __syncthreads();
-        if (tid < T_) {
-            if (tid != k) D[tid][k] = -col[tid] * ip;
-            else D[k][k] = ip;
+        // 2. row panel W = D^{-1} M[s,:] (W[s,s] = D^{-1}), column copy Cb
+        {
+            const int r = t >> 4, j4 = (t & 15) * 4;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int q = 0; q < 16; ++q) {
+                const double d = M[o + r][o + q];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[b] += d * M[o + q][j4 + b];
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = j4 + b;
+                W[r][j] = (j >= o && j < o + 16) ? M[o + r][j] : acc[b];
+            }
+            for (int e = t; e < T_ * 16; e += blockDim.x) Cb[e >> 4][e & 15] = M[e >> 4][o + (e & 15)];
+            __syncthreads();
         }
-        __syncthreads();
+        // 3. rows off the block: 3 rows x 4 columns per thread
+        {
+            const int g = t >> 4, j4 = (t & 15) * 4;
+            double acc[3][4];
+            int ri[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int rr = 3 * g + a;  // 0..47
+                ri[a] = rr < o ? rr : rr + 16;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int j = j4 + b;
+                    acc[a][b] = (j >= o && j < o + 16) ? 0.0 : M[ri[a]][j];
+                }
+            }
+#pragma unroll 4
+            for (int q = 0; q < 16; ++q) {
+                double w[4], cv[3];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) w[b] = W[q][j4 + b];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) cv[a] = Cb[ri[a]][q];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] -= cv[a] * w[b];
+            }
+            __syncthreads();  // every read of M's old block column done
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) M[ri[a]][j4 + b] = acc[a][b];
+            for (int e = t; e < 16 * T_; e += blockDim.x) M[o + (e >> 6)][e & 63] = W[e >> 6][e & 63];
+            __syncthreads();
+        }
     }
-    for (int e = tid; e < T_ * T_; e += blockDim.x) Dinv[e] = D[e / T_][e % T_];
 }
 
-// Workgroup t: row panel tile (columns of tile t) and column-panel copy (rows of tile t).
-__global__ __launch_bounds__(256) void k_gj_panel(double *__restrict__ A, int Mp, int K, const double *__restrict__ Dinv,
-                                                  double *__restrict__ C) {
-    __shared__ double Ds[T_][T_ + 1];
-    __shared__ double Bs[T_][T_ + 1];
-    const int t = blockIdx.x, tid = threadIdx.x;
+// acc = X * Y for T x T tiles staged in LDS (X row-major [T][kLd], Y
+// row-major [T][kLd]); thread t computes rows 4 (t / 16) + (0..3), columns
+// 4 (t % 16) + (0..3), summing k = 0..T-1 in order.
+__device__ inline void tile_mm(const double (*X)[kLd], const double (*Y)[kLd], double (&acc)[4][4]) {
+    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < T_; ++k) {
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = X[ti + a][k];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = Y[k][tj + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+    }
+}
+
+// T x T tile from global (leading dimension ld) into LDS: all 16 loads of a
+// thread first, then the stores (256 threads).
+__device__ inline void load_tile(double (*S)[kLd], const double *__restrict__ src, long ld) {
+    double r[T_ * T_ / kGJThreads];
+#pragma unroll
+    for (int q = 0; q < T_ * T_ / kGJThreads; ++q) {
+        const int e = threadIdx.x + kGJThreads * q;
+        r[q] = src[(long)(e / T_) * ld + e % T_];
+    }
+#pragma unroll
+    for (int q = 0; q < T_ * T_ / kGJThreads; ++q) {
+        const int e = threadIdx.x + kGJThreads * q;
+        S[e / T_][e % T_] = r[q];
+    }
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_diag(const double *__restrict__ A, int Mp, int k0,
+                                                        double *__restrict__ Dinv, int *flag) {
+    __shared__ double Ms[T_][kLd], Ws[16][kLd], Cb[T_][17];
+    load_tile(Ms, A + (long)k0 * Mp + k0, Mp);
+    __syncthreads();
+    gj_invert_lds(Ms, Ws, Cb, flag);
+    for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dinv[e] = Ms[e / T_][e % T_];
+}
+
+// Workgroup t: row panel A[K,t] <- D^{-1} A[K,t] and a copy C[t] = A[t,K]
+// of the column panel (taken before the update).
+__global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A, int Mp, int K,
+                                                         const double *__restrict__ Dinv, double *__restrict__ C) {
+    __shared__ double Ds[T_][kLd], Bs[T_][kLd];
+    const int t = blockIdx.x;
     if (t == K) return;
     const int k0 = K * T_, c0 = t * T_;
-    for (int e = tid; e < T_ * T_; e += blockDim.x) {
-        const int i = e / T_, j = e % T_;
-        Ds[i][j] = Dinv[e];
-        Bs[i][j] = A[(long)(k0 + i) * Mp + c0 + j];
-        C[(long)(c0 + i) * T_ + j] = A[(long)(c0 + i) * Mp + k0 + j];
+    load_tile(Ds, Dinv, T_);
+    load_tile(Bs, A + (long)k0 * Mp + c0, Mp);
+    {
+        double r[T_ * T_ / kGJThreads];
+#pragma unroll
+        for (int q = 0; q < T_ * T_ / kGJThreads; ++q) {
+            const int e = threadIdx.x + kGJThreads * q;
+            r[q] = A[(long)(c0 + e / T_) * Mp + k0 + e % T_];
+        }
+#pragma unroll
+        for (int q = 0; q < T_ * T_ / kGJThreads; ++q) {
+            const int e = threadIdx.x + kGJThreads * q;
+            C[(long)(c0 + e / T_) * T_ + e % T_] = r[q];
+        }
     }
     __syncthreads();
-    for (int e = tid; e < T_ * T_; e += blockDim.x) {
-        const int i = e / T_, j = e % T_;
-        double s = 0.0;
-#pragma unroll 8
-        for (int m = 0; m < T_; ++m) s += Ds[i][m] * Bs[m][j];
-        A[(long)(k0 + i) * Mp + c0 + j] = s;
-    }
+    double acc[4][4];
+    tile_mm(Ds, Bs, acc);
+    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) A[(long)(k0 + ti + a) * Mp + c0 + tj + b] = acc[a][b];
 }
 
-__global__ __launch_bounds__(256) void k_gj_update(double *__restrict__ A, int Mp, int K, const double *__restrict__ Dinv,
-                                                   const double *__restrict__ C) {
-    __shared__ double Cs[T_][T_ + 1];
-    __shared__ double Bs[T_][T_ + 1];
-    const int I = blockIdx.y, J = blockIdx.x, tid = threadIdx.x;
+// Trailing update of step K over all tiles (I, J).  Workgroup 0 takes tile
+// (K+1, K+1) and, after its update, inverts it into Dnext.
+__global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A, int Mp, int K, int nt,
+                                                          const double *__restrict__ Dinv,
+                                                          const double *__restrict__ C, double *__restrict__ Dnext,
+                                                          int *flag) {
+    __shared__ double Cs[T_][kLd], Bs[T_][kLd];
+    // tile of this workgroup: 0 -> (K+1, K+1) (when it exists), then the rest
+    const int L = K + 1 < nt ? K + 1 : -1;
+    int b = blockIdx.x, I, J;
+    if (L >= 0) {
+        if (b == 0) {
+            I = J = L;
+        } else {
+            const int lin = b - 1 + (b - 1 >= L * nt + L ? 1 : 0);  // skip (L, L)
+            I = lin / nt;
+            J = lin % nt;
+        }
+    } else {
+        I = b / nt;
+        J = b % nt;
+    }
     const int r0 = I * T_, c0 = J * T_, k0 = K * T_;
     if (I == K) {
-        if (J == K)
-            for (int e = tid; e < T_ * T_; e += blockDim.x) A[(long)(k0 + e / T_) * Mp + k0 + e % T_] = Dinv[e];
+        if (J == K) {
+            double r[T_ * T_ / kGJThreads];
+#pragma unroll
+            for (int q = 0; q < T_ * T_ / kGJThreads; ++q) r[q] = Dinv[threadIdx.x + kGJThreads * q];
+#pragma unroll
+            for (int q = 0; q < T_ * T_ / kGJThreads; ++q) {
+                const int e = threadIdx.x + kGJThreads * q;
+                A[(long)(k0 + e / T_) * Mp + k0 + e % T_] = r[q];
+            }
+        }
         return;
     }
-    for (int e = tid; e < T_ * T_; e += blockDim.x) {
-        const int i = e / T_, j = e % T_;
-        Cs[i][j] = C[(long)(r0 + i) * T_ + j];
-        Bs[i][j] = (J == K) ? Dinv[e] : A[(long)(k0 + i) * Mp + c0 + j];
+    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+    double old[4][4];
+    if (J != K) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) old[a][bb] = A[(long)(r0 + ti + a) * Mp + c0 + tj + bb];
     }
+    load_tile(Cs, C + (long)r0 * T_, T_);
+    if (J == K) load_tile(Bs, Dinv, T_);
+    else load_tile(Bs, A + (long)k0 * Mp + c0, Mp);
     __syncthreads();
-    for (int e = tid; e < T_ * T_; e += blockDim.x) {
-        const int i = e / T_, j = e % T_;
-        double s = 0.0;
-#pragma unroll 8
-        for (int m = 0; m < T_; ++m) s += Cs[i][m] * Bs[m][j];
-        double *dst = &A[(long)(r0 + i) * Mp + c0 + j];
-        if (J == K) *dst = -s;
-        else *dst -= s;
+    double acc[4][4];
+    tile_mm(Cs, Bs, acc);
+    if (J == K) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) A[(long)(r0 + ti + a) * Mp + c0 + tj + bb] = -acc[a][bb];
+        return;
+    }
+    double nv[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            nv[a][bb] = old[a][bb] - acc[a][bb];
+            if (I != L || J != L) A[(long)(r0 + ti + a) * Mp + c0 + tj + bb] = nv[a][bb];
+        }
+    if (I == L && J == L) {
+        // the next pivot block: stage the updated tile and invert it
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) Cs[ti + a][tj + bb] = nv[a][bb];
+        __syncthreads();
+        gj_invert_lds(Cs, Bs, reinterpret_cast<double (*)[17]>(&Bs[16][0]), flag);
+        for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dnext[e] = Cs[e / T_][e % T_];
     }
 }
 
@@ -103,12 +287,14 @@ void launch_coarse_inverse(Ctx &c, Stage &s) {
     const int nt = s.Mp / T_;
     double *A = s.Ainv;
     hipMemcpyAsync(A, s.Ac, sizeof(double) * (size_t)s.Mp * s.Mp, hipMemcpyDeviceToDevice, c.stream);
-    double *Dinv = c.scal + 6000;            // kTile^2 doubles
-    double *C = c.cbuf;                       // Mp * kTile doubles
+    double *C = c.cbuf;                                       // Mp * kTile doubles
+    double *Dbuf[2] = {c.cbuf + (size_t)c.cbuf_n * T_, c.cbuf + (size_t)(c.cbuf_n + T_) * T_};
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(kGJThreads), 0, c.stream, A, s.Mp, 0, Dbuf[0], c.flag);
     for (int K = 0; K < nt; ++K) {
-        hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, c.stream, A, s.Mp, K * T_, Dinv, c.flag);
-        hipLaunchKernelGGL(k_gj_panel, dim3(nt), dim3(256), 0, c.stream, A, s.Mp, K, Dinv, C);
-        hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(256), 0, c.stream, A, s.Mp, K, Dinv, C);
+        double *D = Dbuf[K & 1], *Dn = Dbuf[(K + 1) & 1];
+        hipLaunchKernelGGL(k_gj_panel, dim3(nt), dim3(kGJThreads), 0, c.stream, A, s.Mp, K, D, C);
+        hipLaunchKernelGGL(k_gj_update, dim3(nt * nt), dim3(kGJThreads), 0, c.stream, A, s.Mp, K, nt, D, C, Dn,
+                           c.flag);
     }
 }
 

@@ -14,7 +14,7 @@ namespace msrsb {
 
 constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
 constexpr int kRedBlocks = 2048;   // fixed grid of the norm/dot kernels (deterministic order)
-constexpr int kTile = 32;          // coarse inverse tile / panel width
+constexpr int kTile = 64;          // coarse inverse tile / panel width
 constexpr int kMaxRestart = 64;
 constexpr int kMaxXSlots = 32;   // slots per cell of an explicit (fault-cut) stage
 
@@ -119,7 +119,7 @@ struct Ctx {
     // work vectors [N]
     double *r = nullptr, *e = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr;
     double *partial = nullptr;    // [kRedBlocks * (2 * kMaxRestart + 2)]
-    double *cbuf = nullptr;       // coarse inverse column panel [max Mp * kTile]
+    double *cbuf = nullptr;       // coarse inverse column panel [cbuf_n * kTile], then 2 kTile^2 block inverses
     long cbuf_n = 0;
     double *scal = nullptr;       // small device scalars / GMRES Hessenberg state
     Status *status = nullptr;     // device
