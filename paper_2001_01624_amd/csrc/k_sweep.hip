@@ -8,6 +8,8 @@
 // support (beyond nv, an inactive cell, a dropped block) holds exactly 0.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "cart_util.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -341,11 +343,13 @@ static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT
     int am = 0;
     for (int a = 0; a < 3; ++a)
         if (s.cart.bit[a] >= 0) am |= 1 << a;
+    hipEvent_t e0, e1;  // timed by the dispatch when sweeps are profiled
+    prof_pair(c, MSRSB_K_SWEEP, &e0, &e1);
 #define MSRSB_SWEEP(AM)                                                                                         \
     case AM:                                                                                                    \
-        hipLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, s.cart, g, tx, ty, tz, in, out, om,       \
-                           c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,                      \
-                           (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);           \
+        hipExtLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, e0, e1, 0, s.cart, g, tx, ty, tz, in,  \
+                              out, om, c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,          \
+                              (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);        \
         break;
     switch (am) {
         MSRSB_SWEEP(0) MSRSB_SWEEP(1) MSRSB_SWEEP(2) MSRSB_SWEEP(3)
@@ -402,11 +406,11 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
             for (; k < kend; ++k) {
                 const int in = (s.cur + k) & 1, out = in ^ 1;
                 int npart = 0;
-                {
+                if (s.kind == 2) {
                     ProfScope ps(c, MSRSB_K_SWEEP);
-                    if (s.kind == 2)
-                        npart = launch_xsweep(c, s, in, out);
-                    else if (mixed)
+                    npart = launch_xsweep(c, s, in, out);
+                } else {
+                    if (mixed)
                         npart = sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out],
                                                       check_blocks);
                     else

@@ -135,6 +135,18 @@ struct Ctx {
 
 // Brackets the launches of one kernel class with HIP events when that class
 // is being timed.
+// For launches timed by the dispatch itself (hipExtLaunchKernelGGL): the
+// next event pair of class cls, or null events when that class is not being
+// profiled.
+inline void prof_pair(Ctx &c, int cls, hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (c.prof_class == cls && c.prof_used + 2 <= (int)c.prof_ev.size()) {
+        *e0 = c.prof_ev[c.prof_used];
+        *e1 = c.prof_ev[c.prof_used + 1];
+        c.prof_used += 2;
+    }
+}
+
 struct ProfScope {
     Ctx &c;
     bool on;
