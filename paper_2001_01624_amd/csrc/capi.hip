@@ -285,6 +285,16 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
         set_error("rows longer than 256 cells are not supported by the restriction kernel");
         return MSRSB_E_INVAL;
     }
+    {
+        // widest dual z-interval: cells of one layer range sharing lo (split to split)
+        const int32_t *sp = s.h_tab.data() + s.tab_off[2][5];
+        s.zwide = 0;
+        for (int L = 0; L < cd.m[2]; ++L) {
+            const int z0 = (cd.m[2] > 1 && L > 0) ? sp[L] : 0;
+            const int z1 = (cd.m[2] > 1 && L + 1 < cd.m[2]) ? sp[L + 1] : c.nz;
+            s.zwide = std::max(s.zwide, z1 - z0);
+        }
+    }
     s.rpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)c.nz * cd.m[1] * cd.m[0] * s.ns);
     s.rap_part = (double *)ctx_alloc(c, sizeof(double) * rap_part_doubles(s.ns, cd.m[0] * cd.m[1] * cd.m[2]));
     if (!s.rpart || !s.rap_part) return MSRSB_E_NOMEM;
@@ -491,21 +501,25 @@ static std::vector<Stage *> cycle_stages(Ctx &c) {
 }
 
 // One cycle of eq. multiscale-multibasis on (b, x).  If r_valid, c.r already
-// holds b - A x on entry; if x_zero, x is zero on entry (so b - A x = b and
-// the first smoother step reads b directly).
+// holds b - A x on entry; if x_zero, the cycle starts from x = 0 (x need not
+// be initialised: the first smoother step assigns x = S b).
 static void cycle(Ctx &c, const double *b, double *x, bool r_valid, const int *done, bool x_zero = false) {
     auto st = cycle_stages(c);
     for (size_t k = 0; k < st.size(); ++k) {
         Stage &s = *st[k];
         if (k == 0 && x_zero) {
-            launch_smooth(c, b, x, done);
+            launch_smooth(c, b, x, done, true);
         } else {
             if (!(k == 0 && r_valid)) launch_residual(c, b, x, c.r, false, done);
             launch_smooth(c, c.r, x, done);
         }
-        launch_residual(c, b, x, c.r, false, done);
-        if (s.kind == 3) launch_dyn_restrict(c, s, c.r, done);
-        else launch_restrict(c, s, c.r, done);
+        if (s.kind == 0) {
+            launch_residual_restrict(c, s, b, x, done);
+        } else {
+            launch_residual(c, b, x, c.r, false, done);
+            if (s.kind == 3) launch_dyn_restrict(c, s, c.r, done);
+            else launch_restrict(c, s, c.r, done);
+        }
         launch_coarse_solve(c, s, done);
         if (s.kind == 3) launch_dyn_prolong(c, s, x, done);
         else launch_prolong(c, s, x, done);
@@ -567,7 +581,6 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
             for (; j < jend; ++j) {
                 const int *done = &c.status->done;
                 double *vj = c.V + (long)j * N;
-                zero_vec(c, c.z, done);
                 cycle(c, vj, c.z, false, done, true);
                 launch_arnoldi(c, c.z, w, j, rtol, max_iters, m);
             }
@@ -581,7 +594,6 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
             launch_gmres_solve_small(c, m);
             zero_vec(c, c.u, nullptr);
             launch_multiaxpy(c, c.V, k, c.scal + 4608, c.u, 1.0, false, nullptr);
-            zero_vec(c, c.z, nullptr);
             cycle(c, c.u, c.z, false, nullptr, true);
             launch_axpy(c, x, c.z, nullptr);
         }
@@ -964,16 +976,12 @@ int msrsb_apply(msrsb_ctx *c, int op, const double *d_in, double *d_out) {
     }
     switch (op) {
     case MSRSB_OP_RESIDUAL: launch_residual(*c, c->b, d_in, d_out, false, nullptr); break;
-    case MSRSB_OP_SMOOTH:
-        zero_vec(*c, d_out, nullptr);
-        launch_smooth(*c, d_in, d_out, nullptr);
-        break;
+    case MSRSB_OP_SMOOTH: launch_smooth(*c, d_in, d_out, nullptr, true); break;
     case MSRSB_OP_PRECOND:
         if (!ready(c)) {
             set_error("precondition before update_basis");
             return MSRSB_E_STATE;
         }
-        zero_vec(*c, d_out, nullptr);
         cycle(*c, d_in, d_out, false, nullptr, true);
         break;
     case MSRSB_OP_MATVEC: launch_matvec(*c, d_in, d_out, false, nullptr); break;

@@ -12,6 +12,7 @@
 
 #include "dev_util.h"
 #include "msrsb_internal.h"
+#include "stencil.h"
 
 namespace msrsb {
 
@@ -24,40 +25,6 @@ static Fine fine_of(const Ctx &c) {
 
 static int red_grid(int N) { return xcd_grid(std::min(kRedBlocks, cdiv(N, kBlock))); }
 
-// The six faces of cell i in the order -x, +x, -y, +y, -z, +z: neighbour
-// index (clamped to i outside the grid) and transmissibility (0 there).  All
-// loads depend on i alone, so a kernel can issue every load before its first
-// use.
-template <typename TT>
-__device__ inline void cell_faces(const Fine &g, int i, const TT *__restrict__ tx, const TT *__restrict__ ty,
-                                  const TT *__restrict__ tz, int l[6], TT t[6]) {
-    const int step[3] = {1, g.nx, g.nxy};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const TT *Ta = a == 0 ? tx : (a == 1 ? ty : tz);
-        const bool dn = i >= step[a], up = i + step[a] < g.N;
-        l[2 * a] = dn ? i - step[a] : i;
-        l[2 * a + 1] = up ? i + step[a] : i;
-        const TT td = Ta[l[2 * a]], tu = Ta[i];
-        t[2 * a] = dn ? td : (TT)0;
-        t[2 * a + 1] = up ? tu : (TT)0;
-    }
-}
-
-// (A x)_i for an active cell with diagonal d; the off-diagonal terms are
-// subtracted in face order (faces outside the grid have t = 0).
-__device__ inline double ax_row(const Fine &g, const double *__restrict__ x, int i, double d) {
-    int l[6];
-    double t[6], xl[6];
-    cell_faces(g, i, g.tx, g.ty, g.tz, l, t);
-    const double xi = x[i];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) xl[q] = x[l[q]];
-    double s = d * xi;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) s -= t[q] * xl[q];
-    return s;
-}
 
 __global__ void k_assemble(Fine g, const double *__restrict__ bcdiag, const double *__restrict__ bcrhs,
                            const double *__restrict__ src, double *__restrict__ diag, double *__restrict__ b) {
@@ -189,14 +156,15 @@ void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *don
 }
 
 // Damped Jacobi: x += omega_s r / a_ii.
-template <typename TT>
+template <typename TT, bool ASSIGN>
 __global__ void k_jacobi(int N, const TT *__restrict__ diag, TT omega, const double *__restrict__ r,
                          double *__restrict__ x, const int *done) {
     if (done && *done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const TT d = diag[i];
-    if (d > (TT)0) x[i] += (double)(omega * (TT)r[i] / d);
+    if (ASSIGN) x[i] = d > (TT)0 ? (double)(omega * (TT)r[i] / d) : 0.0;
+    else if (d > (TT)0) x[i] += (double)(omega * (TT)r[i] / d);
 }
 
 // Cell of colour `col` handled by thread t: rows (y,z) hold ceil(nx/2) slots.
@@ -219,7 +187,7 @@ __device__ inline int colour_cell(const Fine &g, int col, int t) {
 //   red:   e_r = (r_r + sum_{black l} T_rl e_l) / a_rr,
 // x += e on each colour.  Faces with T = 0 (boundary, inactive neighbour)
 // leave the sum untouched; cells with a non-positive pivot are skipped.
-template <typename TT>
+template <typename TT, bool ASSIGN>
 __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
                                                       const TT *__restrict__ tz, const TT *__restrict__ diag,
                                                       const TT *__restrict__ dtil, const double *__restrict__ r,
@@ -233,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restri
     cell_faces(g, i, tx, ty, tz, l, t);
     const TT dt = dtil[i];
     TT s = (TT)r[i];
-    const double xo = x[i];
+    const double xo = ASSIGN ? 0.0 : x[i];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         rl[q] = (TT)r[l[q]];
@@ -244,10 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restri
     const bool on = dt > (TT)0;
     const TT v = s / dt;
     e[i] = on ? (double)v : 0.0;
-    x[i] = on ? xo + (double)v : xo;
+    x[i] = on ? (ASSIGN ? (double)v : xo + (double)v) : xo;
 }
 
-template <typename TT>
+template <typename TT, bool ASSIGN>
 __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict__ tx, const TT *__restrict__ ty,
                                                     const TT *__restrict__ tz, const TT *__restrict__ diag,
                                                     const double *__restrict__ r, const double *__restrict__ e,
@@ -260,40 +228,47 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
     cell_faces(g, i, tx, ty, tz, l, t);
     const TT d = diag[i];
     TT s = (TT)r[i];
-    const double xo = x[i];
+    const double xo = ASSIGN ? 0.0 : x[i];
 #pragma unroll
     for (int q = 0; q < 6; ++q) el[q] = (TT)e[l[q]];
 #pragma unroll
     for (int q = 0; q < 6; ++q) s = t[q] != (TT)0 ? s + t[q] * el[q] : s;
-    x[i] = d > (TT)0 ? xo + (double)(s / d) : xo;
+    x[i] = d > (TT)0 ? (ASSIGN ? (double)(s / d) : xo + (double)(s / d)) : xo;
 }
 
-void launch_smooth(Ctx &c, const double *r, double *x, const int *done) {
-    ProfScope ps(c, MSRSB_K_SMOOTH);
+template <bool ASSIGN>
+static void smooth_dispatch(Ctx &c, const double *r, double *x, const int *done) {
     Fine g = fine_of(c);
     const bool mixed = c.opt.precision == MSRSB_MIXED;
     if (c.opt.smoother == MSRSB_SMOOTH_JACOBI) {
         if (mixed)
-            hipLaunchKernelGGL(k_jacobi<float>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag32,
-                               (float)c.opt.omega_s, r, x, done);
+            hipLaunchKernelGGL((k_jacobi<float, ASSIGN>), dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N,
+                               c.diag32, (float)c.opt.omega_s, r, x, done);
         else
-            hipLaunchKernelGGL(k_jacobi<double>, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag,
-                               c.opt.omega_s, r, x, done);
+            hipLaunchKernelGGL((k_jacobi<double, ASSIGN>), dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N,
+                               c.diag, c.opt.omega_s, r, x, done);
         return;
     }
     const int half = ((c.nx + 1) / 2) * c.ny * c.nz;
     const dim3 grid(xcd_grid(cdiv(half, kBlock)));
     if (mixed) {
-        hipLaunchKernelGGL(k_ilu_black<float>, grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32,
-                           c.dtil32, r, c.e, x, done);
-        hipLaunchKernelGGL(k_ilu_red<float>, grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32, r,
-                           c.e, x, done);
+        hipLaunchKernelGGL((k_ilu_black<float, ASSIGN>), grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32,
+                           c.diag32, c.dtil32, r, c.e, x, done);
+        hipLaunchKernelGGL((k_ilu_red<float, ASSIGN>), grid, dim3(kBlock), 0, c.stream, g, c.tx32, c.ty32, c.tz32,
+                           c.diag32, r, c.e, x, done);
     } else {
-        hipLaunchKernelGGL(k_ilu_black<double>, grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz, c.diag, c.dtil,
+        hipLaunchKernelGGL((k_ilu_black<double, ASSIGN>), grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz,
+                           c.diag, c.dtil, r, c.e, x, done);
+        hipLaunchKernelGGL((k_ilu_red<double, ASSIGN>), grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz, c.diag,
                            r, c.e, x, done);
-        hipLaunchKernelGGL(k_ilu_red<double>, grid, dim3(kBlock), 0, c.stream, g, c.tx, c.ty, c.tz, c.diag, r, c.e,
-                           x, done);
     }
+}
+
+// x += S r, or x = S r (assign: x need not be initialised; inactive cells get 0).
+void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool assign) {
+    ProfScope ps(c, MSRSB_K_SMOOTH);
+    if (assign) smooth_dispatch<true>(c, r, x, done);
+    else smooth_dispatch<false>(c, r, x, done);
 }
 
 __global__ void k_zero_inactive(int N, const double *__restrict__ diag, double *__restrict__ x) {

@@ -7,6 +7,7 @@
 #include "cart_util.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
+#include "stencil.h"
 
 namespace msrsb {
 
@@ -30,9 +31,12 @@ constexpr int kRowChunks = 4;  // rows up to 64*kRowChunks cells
 constexpr int kRowWaves = 4;
 constexpr int kRowUnroll = 3;
 
-template <int NS, typename PS>
+// RES: r is not read but formed per cell as b - A x, with the operations of
+// the residual kernel (so the restricted vector is the same bit for bit).
+template <int NS, typename PS, int NCH, bool RES>
 __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                                  const double *__restrict__ r,
+                                                                  const double *__restrict__ rb,
+                                                                  const double *__restrict__ x,
                                                                   double *__restrict__ part, const int *done) {
     extern __shared__ double red[];  // [kRowWaves][nx][NS]
     if (done && *done) return;
@@ -44,10 +48,9 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
         y0 = Ly == 0 ? 0 : cd.split[1][Ly];
         y1 = Ly + 1 < my ? cd.split[1][Ly + 1] : g.ny;
     }
-    const int nch = (g.nx + 63) >> 6;
-    double acc[kRowChunks][NS];
+    double acc[NCH][NS];
 #pragma unroll
-    for (int k = 0; k < kRowChunks; ++k)
+    for (int k = 0; k < NCH; ++k)
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
     // kRowUnroll rows per pass, all loads of a pass issued before the first
@@ -55,19 +58,49 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
     // still added in increasing y, so the sums do not depend on the unroll.
     for (int yb = y0 + wv; yb < y1; yb += kRowWaves * kRowUnroll) {
 #pragma unroll
-        for (int k = 0; k < kRowChunks; ++k) {
-            const int x = lane + 64 * k;
-            if (k < nch && x < g.nx) {
+        for (int k = 0; k < NCH; ++k) {
+            const int xx = lane + 64 * k;
+            if (xx < g.nx) {
                 double ri[kRowUnroll], pv[kRowUnroll][NS];
-                bool in[kRowUnroll];
+                double xi[kRowUnroll], xl[kRowUnroll][6], traw[kRowUnroll][6], dg[kRowUnroll], bi[kRowUnroll];
+                bool in[kRowUnroll], fin[kRowUnroll][6];
 #pragma unroll
                 for (int u = 0; u < kRowUnroll; ++u) {
                     const int y = yb + u * kRowWaves;
                     in[u] = y < y1;
-                    const long i = (long)g.nx * ((in[u] ? y : y0) + (long)g.ny * z) + x;
-                    ri[u] = r[i];
+                    const int i = g.nx * ((in[u] ? y : y0) + g.ny * z) + xx;
 #pragma unroll
                     for (int s = 0; s < NS; ++s) pv[u][s] = ld_basis(P, (long)s * g.N + i);
+                    if (RES) {
+                        // faces as in cell_faces, the zeroing applied after the loads
+                        const int step[3] = {1, g.nx, g.nxy};
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
+                            fin[u][2 * a] = i >= step[a];
+                            fin[u][2 * a + 1] = i + step[a] < g.N;
+                            const int ld = fin[u][2 * a] ? i - step[a] : i, lu = fin[u][2 * a + 1] ? i + step[a] : i;
+                            traw[u][2 * a] = Ta[ld];
+                            traw[u][2 * a + 1] = Ta[i];
+                            xl[u][2 * a] = x[ld];
+                            xl[u][2 * a + 1] = x[lu];
+                        }
+                        xi[u] = x[i];
+                        dg[u] = g.diag[i];
+                        bi[u] = rb[i];
+                    } else {
+                        ri[u] = rb[i];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (RES) {
+#pragma unroll
+                    for (int u = 0; u < kRowUnroll; ++u) {
+                        double ax = dg[u] * xi[u];  // (A x)_i as ax_row
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) ax -= (fin[u][q] ? traw[u][q] : 0.0) * xl[u][q];
+                        ri[u] = dg[u] > 0.0 ? bi[u] - ax : 0.0;
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kRowUnroll; ++u)
@@ -78,11 +111,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
     }
     double *mine = red + (long)wv * g.nx * NS;
 #pragma unroll
-    for (int k = 0; k < kRowChunks; ++k) {
-        const int x = lane + 64 * k;
-        if (k < nch && x < g.nx)
+    for (int k = 0; k < NCH; ++k) {
+        const int xx = lane + 64 * k;
+        if (xx < g.nx)
 #pragma unroll
-            for (int s = 0; s < NS; ++s) mine[x * NS + s] = acc[k][s];
+            for (int s = 0; s < NS; ++s) mine[xx * NS + s] = acc[k][s];
     }
     __syncthreads();
     // thread (Lx, s) adds waves, then columns of dual x-interval Lx, in order
@@ -94,13 +127,15 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
             x1 = Lx + 1 < mx ? cd.split[0][Lx + 1] : g.nx;
         }
         double tot = 0.0;
-        for (int x = x0; x < x1; ++x)
-            for (int w = 0; w < kRowWaves; ++w) tot += red[((long)w * g.nx + x) * NS + s];
+        for (int xx = x0; xx < x1; ++xx)
+            for (int w = 0; w < kRowWaves; ++w) tot += red[((long)w * g.nx + xx) * NS + s];
         part[(((long)z * my + Ly) * mx + Lx) * NS + s] = tot;
     }
 }
 
-template <int NS>
+// NARROW: every dual z-interval has at most 64 layers, so each lane adds at
+// most one layer per slot and all loads of a wavefront are independent.
+template <int NS, bool NARROW>
 __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
                                                          double *__restrict__ d, const int *done) {
     if (done && *done) return;
@@ -112,6 +147,7 @@ __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int
     const int J[3] = {cid % mx, (cid / mx) % my, cid / (mx * my)};
     // work items: (slot s, layer z of the dual interval J_z - s_z)
     double v = 0.0;
+#pragma unroll
     for (int s = 0; s < NS; ++s) {
         int L[3];
         bool ok = true;
@@ -120,13 +156,21 @@ __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int
             L[a] = J[a] - (cd.bit[a] >= 0 ? (s >> cd.bit[a]) & 1 : 0);
             if (L[a] < 0) ok = false;
         }
-        if (!ok) continue;
         int z0 = 0, z1 = g.nz;
-        if (cd.bit[2] >= 0) {
+        if (cd.bit[2] >= 0 && ok) {
             z0 = L[2] == 0 ? 0 : cd.split[2][L[2]];
             z1 = L[2] + 1 < mz ? cd.split[2][L[2] + 1] : g.nz;
         }
-        for (int z = z0 + lane; z < z1; z += 64) v += part[(((long)z * my + L[1]) * mx + L[0]) * NS + s];
+        if (NARROW) {
+            const int z = z0 + lane;
+            const bool in = ok && z < z1;
+            const long at = in ? (((long)z * my + L[1]) * mx + L[0]) * NS + s : 0;
+            const double pv = part[at];
+            v += in ? pv : 0.0;
+        } else {
+            if (!ok) continue;
+            for (int z = z0 + lane; z < z1; z += 64) v += part[(((long)z * my + L[1]) * mx + L[0]) * NS + s];
+        }
     }
     v = wave_sum(v);
     if (lane == 0) d[j] = v;
@@ -169,38 +213,43 @@ __global__ __launch_bounds__(kBlock) void k_prolong(CartDev cd, Fine g, const PS
     x[i] = dg > 0.0 ? xo + acc : xo;
 }
 
-template <typename PS>
-static void rp_dispatch(Ctx &c, Stage &s, const PS *P, const double *r, double *x, bool restrict_, const int *done) {
+template <typename PS, bool RES>
+static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, const double *x, const int *done) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    if (restrict_) {
-        const dim3 grid(s.cart.m[1], c.nz), blk(64 * kRowWaves), fgrid(cdiv(s.M, 4)), fblk(256);
-        const size_t lds = sizeof(double) * kRowWaves * (size_t)c.nx * s.ns;
-        switch (s.ns) {
-        case 1:
-            hipLaunchKernelGGL((k_restrict_rows<1, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<1>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_restrict_rows<2, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<2>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_restrict_rows<4, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<4>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
-            break;
-        default:
-            hipLaunchKernelGGL((k_restrict_rows<8, PS>), grid, blk, lds, c.stream, s.cart, g, P, r, s.rpart, done);
-            hipLaunchKernelGGL((k_restrict_gather<8>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done);
-            break;
-        }
-    } else {
-        const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
-        switch (s.ns) {
-        case 1: hipLaunchKernelGGL((k_prolong<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-        case 2: hipLaunchKernelGGL((k_prolong<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-        case 4: hipLaunchKernelGGL((k_prolong<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-        default: hipLaunchKernelGGL((k_prolong<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-        }
+    const dim3 grid(s.cart.m[1], c.nz), blk(64 * kRowWaves), fgrid(cdiv(s.M, 4)), fblk(256);
+    const size_t lds = sizeof(double) * kRowWaves * (size_t)c.nx * s.ns;
+    const int nch = cdiv(c.nx, 64);
+#define MSRSB_RROWS(NS, NCH) \
+    hipLaunchKernelGGL((k_restrict_rows<NS, PS, NCH, RES>), grid, blk, lds, c.stream, s.cart, g, P, rb, x, s.rpart, done)
+#define MSRSB_RNS(NS)                                                                                        \
+    {                                                                                                        \
+        if (nch == 1) MSRSB_RROWS(NS, 1);                                                                    \
+        else if (nch == 2) MSRSB_RROWS(NS, 2);                                                               \
+        else MSRSB_RROWS(NS, 4);                                                                             \
+        if (s.zwide <= 64)                                                                                   \
+            hipLaunchKernelGGL((k_restrict_gather<NS, true>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_restrict_gather<NS, false>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done); \
+    }
+    switch (s.ns) {
+    case 1: MSRSB_RNS(1) break;
+    case 2: MSRSB_RNS(2) break;
+    case 4: MSRSB_RNS(4) break;
+    default: MSRSB_RNS(8) break;
+    }
+#undef MSRSB_RNS
+#undef MSRSB_RROWS
+}
+
+template <typename PS>
+static void prolong_dispatch(Ctx &c, Stage &s, const PS *P, double *x, const int *done) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
+    switch (s.ns) {
+    case 1: hipLaunchKernelGGL((k_prolong<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+    case 2: hipLaunchKernelGGL((k_prolong<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+    case 4: hipLaunchKernelGGL((k_prolong<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+    default: hipLaunchKernelGGL((k_prolong<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
     }
 }
 
@@ -210,8 +259,15 @@ void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done) {
         launch_xrestrict(c, s, r, done);
         return;
     }
-    if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, r, nullptr, true, done);
-    else rp_dispatch<double>(c, s, s.P64[s.cur], r, nullptr, true, done);
+    if (c.opt.precision == MSRSB_MIXED) restrict_dispatch<uint16_t, false>(c, s, s.Pbf, r, nullptr, done);
+    else restrict_dispatch<double, false>(c, s, s.P64[s.cur], r, nullptr, done);
+}
+
+// d = P^T (b - A x) without storing the residual (rectilinear stages).
+void launch_residual_restrict(Ctx &c, Stage &s, const double *b, const double *x, const int *done) {
+    ProfScope ps(c, MSRSB_K_RESTRICT);
+    if (c.opt.precision == MSRSB_MIXED) restrict_dispatch<uint16_t, true>(c, s, s.Pbf, b, x, done);
+    else restrict_dispatch<double, true>(c, s, s.P64[s.cur], b, x, done);
 }
 
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done) {
@@ -220,8 +276,8 @@ void launch_prolong(Ctx &c, Stage &s, double *x, const int *done) {
         launch_xprolong(c, s, x, done);
         return;
     }
-    if (c.opt.precision == MSRSB_MIXED) rp_dispatch<uint16_t>(c, s, s.Pbf, nullptr, x, false, done);
-    else rp_dispatch<double>(c, s, s.P64[s.cur], nullptr, x, false, done);
+    if (c.opt.precision == MSRSB_MIXED) prolong_dispatch<uint16_t>(c, s, s.Pbf, x, done);
+    else prolong_dispatch<double>(c, s, s.P64[s.cur], x, done);
 }
 
 // ------------------------------------------------------------ Galerkin ----

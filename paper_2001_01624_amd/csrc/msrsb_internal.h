@@ -73,6 +73,7 @@ struct Stage {
     // partial sums per dual box
     double *rpart = nullptr;
     double *rap_part = nullptr;
+    int zwide = 0;                // widest dual z-interval (layers)
     // explicit-slot stage (fault cut): slot tables, piece of each cell,
     // per-block support lists (cells ascending, with the block's slot there)
     int parent = -1;
@@ -171,7 +172,7 @@ void launch_source_update(Ctx &c, const double *d_source);
 void launch_ilu_factor(Ctx &c);
 void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done);
 void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done);
-void launch_smooth(Ctx &c, const double *r, double *x, const int *done);
+void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool assign = false);
 void launch_zero_inactive(Ctx &c, double *x);
 void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
 void launch_check(Ctx &c, double rtol, int max_iters, int count);
@@ -195,6 +196,7 @@ void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int 
 // ---- basis kernels (k_sweep.hip, k_transfer.hip) ----
 int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *sweeps, double *change);
 void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done);
+void launch_residual_restrict(Ctx &c, Stage &s, const double *b, const double *x, const int *done);
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done);
 void launch_rap(Ctx &c, Stage &s);
 void launch_export_cart(Ctx &c, Stage &s, double *d_vals);
