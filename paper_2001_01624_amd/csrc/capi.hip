@@ -565,28 +565,42 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
     const int m = std::max(1, std::min(c.opt.restart, kMaxRestart));
     const long N = c.N;
     double *w = c.tmp;
+    const bool dcgs = m <= kDcgsMax;
     int rc;
     for (;;) {
-        // restart: true residual of the current iterate
-        launch_residual(c, b, x, c.r, true, nullptr);
+        // restart: true residual of the current iterate (DCGS2: into V(0),
+        // which holds u_0 = r; the cycle overwrites c.r)
+        launch_residual(c, b, x, dcgs ? c.V : c.r, true, nullptr);
         launch_norm_finish(c, c.scal, nullptr);
         launch_gmres_begin(c, rtol, max_iters);
         if ((rc = read_status(c))) return rc;
         if (c.h_status->done) break;
-        launch_gmres_start(c, c.r, c.V, m);
+        if (!dcgs) launch_gmres_start(c, c.r, c.V, m);
         int j = 0;
         int chunk = 4;
         while (j < m) {
             const int jend = std::min(m, j + chunk);
             for (; j < jend; ++j) {
                 const int *done = &c.status->done;
-                double *vj = c.V + (long)j * N;
-                cycle(c, vj, c.z, false, done, true);
-                launch_arnoldi(c, c.z, w, j, rtol, max_iters, m);
+                if (dcgs) {
+                    // column j from u_j = V(j) (u_0 = r); q_j and u_{j+1} land in V
+                    const double *uj = c.V + (long)j * N;
+                    cycle(c, uj, c.z, false, done, true);
+                    launch_dgmres_step(c, c.z, w, uj, j, rtol, max_iters, false);
+                } else {
+                    double *vj = c.V + (long)j * N;
+                    cycle(c, vj, c.z, false, done, true);
+                    launch_arnoldi(c, c.z, w, j, rtol, max_iters, m);
+                }
             }
             if ((rc = read_status(c))) return rc;
             if (c.h_status->done) break;
             chunk = std::min(chunk * 2, 16);
+        }
+        if (dcgs && j == m && !c.h_status->done) {
+            // finalise the last column from u_m
+            launch_dgmres_step(c, nullptr, w, c.V + (long)m * N, m, rtol, max_iters, true);
+            if ((rc = read_status(c))) return rc;
         }
         // x += M^{-1} V y
         const int k = c.h_status->jcur;
@@ -799,7 +813,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
                                    (size_t)cdiv(g->nx, 64) * cdiv((long)g->ny * g->nz, 4),
                                    (size_t)cdiv(N, kBlock)});
     c->partial = (double *)alloc(8 * npart);
-    c->scal = (double *)alloc(8 * 8192);
+    c->scal = (double *)alloc(8 * 16384);
     c->status = (Status *)alloc(sizeof(Status));
     c->maxbits = (unsigned long long *)alloc(8 * 65536);
     c->flag = (int *)alloc(sizeof(int));

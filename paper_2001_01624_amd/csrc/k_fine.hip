@@ -851,6 +851,277 @@ __global__ __launch_bounds__(kBlock) void k_gmres_step2(Status *st, double *scal
     if (rel <= rtol || st->iters >= max_iters || j + 1 >= restart || hn == 0.0 || !(rel == rel)) st->done = 1;
 }
 
+// ---- GMRES with delayed reorthogonalisation (DCGS2) -------------------------
+// Column j is formed from u_j, the once-orthogonalised candidate for q_j
+// (u_0 = r).  Pass A: w = A M^{-1} u_j (z given) and the dots s = Q^T u_j,
+// alpha = u_j.u_j, t = Q^T w, beta = u_j.w.  The step kernel finalises
+// column j-1 (H(:,j-1) += s, H(j,j-1) = rho = sqrt(alpha - s.s), Givens,
+// residual estimate) and forms column j in the small space:
+//   g = H(0..j, 0..j-1) s,  h = ([t; (beta - s.t)/rho] - g) / rho,
+// since A M^{-1} q_j = (w - Q_{j+1} g)/rho.  Pass B writes
+//   q_j = (u_j - Q s)/rho  and  u_{j+1} = w/rho - Q_{j+1} (g/rho + h).
+// Q = V(0..j-1) is read once per pass.  Scalars: totals of pass A at S_DA,
+// unrotated Hessenberg at S_HU, update coefficients at S_DC, 1/rho at S_RHO.
+constexpr int S_HU = 8192, S_DA = 12500, S_DC = 12700, S_RHO = 12800;
+
+template <int KM, bool MV>
+__global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__restrict__ z, double *__restrict__ w,
+                                                    const double *__restrict__ Q, const double *__restrict__ u,
+                                                    int j, double *__restrict__ partial, const int *done) {
+    __shared__ double red[(kBlock / 64 + 1) * KM];
+    if (done && *done) return;
+    const int G = gridDim.x;
+    double as[KM], at[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        as[q] = 0.0;
+        at[q] = 0.0;
+    }
+    const int jc = j > 0 ? j - 1 : 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += G * blockDim.x) {
+        double vq[KM - 1];
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) vq[q] = Q[(long)min(q, jc) * g.N + i];  // slots q >= j unused
+        const double ui = u[i];
+        const int step[3] = {1, g.nx, g.nxy};
+        bool in[6];
+        double traw[6], xl[6], d = 0.0, xi = 0.0;
+        if (MV) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
+                in[2 * a] = i >= step[a];
+                in[2 * a + 1] = i + step[a] < g.N;
+                const int ld = in[2 * a] ? i - step[a] : i, lu = in[2 * a + 1] ? i + step[a] : i;
+                traw[2 * a] = Ta[ld];
+                traw[2 * a + 1] = Ta[i];
+                xl[2 * a] = z[ld];
+                xl[2 * a + 1] = z[lu];
+            }
+            d = g.diag[i];
+            xi = z[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // all loads of the element first
+        as[KM - 1] += ui * ui;
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) as[q] += vq[q] * (q < j ? ui : 0.0);
+        if (MV) {
+            double ax = d * xi;  // (A z)_i, as ax_row
+#pragma unroll
+            for (int q = 0; q < 6; ++q) ax -= (in[q] ? traw[q] : 0.0) * xl[q];
+            const double wi = d > 0.0 ? ax : 0.0;
+            w[i] = wi;
+            at[KM - 1] += ui * wi;
+#pragma unroll
+            for (int q = 0; q < KM - 1; ++q) at[q] += vq[q] * (q < j ? wi : 0.0);
+        }
+    }
+    const int nw = blockDim.x >> 6;
+    group_sum_lds<KM>(as, red);
+    if ((int)threadIdx.x < j) partial[(long)threadIdx.x * G + blockIdx.x] = red[nw * KM + threadIdx.x];
+    if (threadIdx.x == KM - 1) partial[(long)j * G + blockIdx.x] = red[nw * KM + KM - 1];
+    if (MV) {
+        group_sum_lds<KM>(at, red);
+        if ((int)threadIdx.x < j) partial[(long)(j + 1 + threadIdx.x) * G + blockIdx.x] = red[nw * KM + threadIdx.x];
+        if (threadIdx.x == KM - 1) partial[(long)(2 * j + 1) * G + blockIdx.x] = red[nw * KM + KM - 1];
+    }
+}
+
+// out[q] = sum over blocks of partial[q*G + b], one workgroup per quantity.
+__global__ __launch_bounds__(kBlock) void k_finish_n(const double *__restrict__ partial, int G,
+                                                     double *__restrict__ out, const Status *st) {
+    __shared__ double lds[kBlock / 64];
+    if (st->done) return;
+    const double t = sum_partials(partial + (long)blockIdx.x * G, G, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// Finalise column j-1 and (unless final) prepare column j.  The pass-A
+// totals and the needed part of the unrotated Hessenberg matrix are staged
+// in LDS; sums run in index order.
+__global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int j, double rtol, int max_iters,
+                                                  int final_) {
+    constexpr int HL = kDcgsMax + 2;  // rows of the staged Hessenberg block
+    __shared__ double Hs[HL][HL];     // Hs[l][i] = Hu(l, i)
+    __shared__ double rcs[kDcgsMax + 1], rsn[kDcgsMax + 1], gv[kDcgsMax + 2];
+    __shared__ double A[2 * kDcgsMax + 4];  // s[0..j), alpha, t[0..j), beta
+    __shared__ double sh[3];
+    __shared__ int stop;
+    if (st->done) return;
+    const int tid = threadIdx.x;
+    const int ld = kMaxRestart + 1;
+    double *Hu = scal + S_HU;
+    double *H = scal + S_H;
+    double *gg = scal + S_G;
+    double *cs = scal + S_CS;
+    double *sn = scal + S_SN;
+    const int na = final_ ? j + 1 : 2 * j + 2;
+    for (int i = tid; i < na; i += blockDim.x) A[i] = scal[S_DA + i];
+    // columns 0..j-1, rows 0..j (upper Hessenberg: rows up to i + 1)
+    for (int e = tid; e < j * (j + 1); e += blockDim.x) {
+        const int i = e / (j + 1), l = e % (j + 1);
+        Hs[l][i] = l <= i + 1 ? Hu[l + ld * i] : 0.0;
+    }
+    for (int i = tid; i + 1 < j; i += blockDim.x) {
+        rcs[i] = cs[i];
+        rsn[i] = sn[i];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        // s.s and s.t: lane sums in index order, then the fixed wave tree
+        double ss = 0.0, sdt = 0.0;
+        for (int i = tid; i < j; i += 64) {
+            ss += A[i] * A[i];
+            if (!final_) sdt += A[i] * A[j + 1 + i];
+        }
+        ss = wave_sum(ss);
+        sdt = wave_sum(sdt);
+        if (tid == 0) {
+            const double r2 = A[j] - ss;
+            sh[0] = r2 > 0.0 ? sqrt(r2) : 0.0;
+            sh[1] = sdt;
+            stop = 0;
+        }
+    }
+    __syncthreads();
+    const double rho = sh[0];
+    if (j > 0) {
+        // finalise column j-1 of the Arnoldi matrix and of its rotated copy
+        const int c = j - 1;
+        for (int i = tid; i <= j; i += blockDim.x) {
+            const double v = i < j ? Hs[i][c] + A[i] : rho;
+            Hs[i][c] = v;
+            Hu[i + ld * c] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a_i = Hs[0][c];
+            for (int i = 0; i < c; ++i) {
+                const double b = Hs[i + 1][c];
+                H[i + ld * c] = rcs[i] * a_i + rsn[i] * b;
+                a_i = -rsn[i] * a_i + rcs[i] * b;
+            }
+            const double a = a_i, b = Hs[c + 1][c];
+            const double rr = hypot(a, b);
+            const double cj = rr > 0.0 ? a / rr : 1.0, sj = rr > 0.0 ? b / rr : 0.0;
+            cs[c] = cj;
+            sn[c] = sj;
+            H[c + ld * c] = rr;
+            H[c + 1 + ld * c] = 0.0;
+            gg[c + 1] = -sj * gg[c];
+            gg[c] = cj * gg[c];
+            st->iters += 1;
+            st->jcur = j;
+            const double rel = fabs(gg[c + 1]) / st->bnorm;
+            st->relres = rel;
+            if (rel <= rtol || st->iters >= max_iters || !(rho > 0.0) || !(rel == rel) || final_) {
+                st->done = 1;
+                stop = 1;
+            }
+        }
+        __syncthreads();
+        if (stop) return;
+    } else {
+        if (tid == 0) {
+            gg[0] = rho;  // ||r|| as used by q_0 = r / rho
+            if (!(rho > 0.0)) {
+                st->done = 1;
+                stop = 1;
+            }
+        }
+        __syncthreads();
+        if (stop) return;
+    }
+    // column j: g = H(0..j, 0..j-1) s (upper Hessenberg)
+    for (int l = tid; l <= j; l += blockDim.x) {
+        double v = 0.0;
+        for (int i = (l > 0 ? l - 1 : 0); i < j; ++i) v += Hs[l][i] * A[i];
+        gv[l] = v;
+    }
+    __syncthreads();
+    const double irho = 1.0 / rho;
+    const double beta = A[2 * j + 1], sdt = sh[1];
+    for (int l = tid; l <= j; l += blockDim.x) {
+        const double proj = l < j ? A[j + 1 + l] : (beta - sdt) * irho;
+        const double h = (proj - gv[l]) * irho;
+        Hu[l + ld * j] = h;
+        scal[S_DC + l] = gv[l] * irho + h;
+    }
+    if (tid == 0) scal[S_RHO] = irho;
+}
+
+// q_j = (u_j - Q s) / rho into qout, u_{j+1} = w / rho - Q c(0..j-1) - c_j q_j
+// into unext (qout may alias u).
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const double *__restrict__ Q, const double *u,
+                                                    const double *__restrict__ w, int j, double *qout,
+                                                    double *__restrict__ unext, const double *__restrict__ scal,
+                                                    const Status *st) {
+    if (st->done) return;
+    const int jc = j > 0 ? j - 1 : 0;
+    double sq[KM - 1], cq[KM - 1];
+#pragma unroll
+    for (int q = 0; q < KM - 1; ++q) {
+        const double sv = scal[S_DA + min(q, jc)], cv = scal[S_DC + min(q, jc)];
+        sq[q] = q < j ? sv : 0.0;
+        cq[q] = q < j ? cv : 0.0;
+    }
+    const double cj = scal[S_DC + j], irho = scal[S_RHO];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double vq[KM - 1];
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) {
+            const double v = Q[(long)min(q, jc) * N + i];
+            vq[q] = q < j ? v : 0.0;  // unused slots may hold anything (V(0) before its first write)
+        }
+        const double ui = u[i], wi = w[i];
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < KM - 1; ++q) {
+            a += sq[q] * vq[q];
+            b += cq[q] * vq[q];
+        }
+        const double qj = (ui - a) * irho;
+        qout[i] = qj;
+        unext[i] = wi * irho - (b + cj * qj);
+    }
+}
+
+template <int KM>
+static void dgmres_step_k(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
+                          bool final_) {
+    Fine g = fine_of(c);
+    const int G = red_grid(c.N);
+    const int *done = &c.status->done;
+    const Status *st = c.status;
+    {
+        ProfScope ps(c, final_ ? MSRSB_K_ORTHO : MSRSB_K_MATVEC);
+        if (final_)
+            hipLaunchKernelGGL((k_dpass_a<KM, false>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, u, j,
+                               c.partial, done);
+        else
+            hipLaunchKernelGGL((k_dpass_a<KM, true>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, u, j,
+                               c.partial, done);
+    }
+    hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, G,
+                       c.scal + S_DA, st);
+    hipLaunchKernelGGL(k_dstep, dim3(1), dim3(kBlock), 0, c.stream, c.status, c.scal, j, rtol, max_iters,
+                       final_ ? 1 : 0);
+    if (final_) return;
+    ProfScope ps(c, MSRSB_K_ORTHO);
+    double *qout = c.V + (long)j * c.N, *unext = c.V + (long)(j + 1) * c.N;
+    hipLaunchKernelGGL((k_dpass_b<KM>), dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, u, w, j, qout, unext, c.scal,
+                       st);
+}
+
+// One DCGS2 Arnoldi step for column j (final: only finalise column j - 1).
+void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
+                        bool final_) {
+    if (j <= 7) dgmres_step_k<8>(c, z, w, u, j, rtol, max_iters, final_);
+    else if (j <= 15) dgmres_step_k<16>(c, z, w, u, j, rtol, max_iters, final_);
+    else dgmres_step_k<32>(c, z, w, u, j, rtol, max_iters, final_);
+}
+
 void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart) {
     Fine g = fine_of(c);
     const int G = red_grid(c.N);

@@ -173,6 +173,9 @@ void launch_ilu_factor(Ctx &c);
 void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done);
 void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done);
 void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool assign = false);
+void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
+                        bool final_);
+constexpr int kDcgsMax = 31;  // largest restart served by the DCGS2 kernels
 void launch_zero_inactive(Ctx &c, double *x);
 void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
 void launch_check(Ctx &c, double rtol, int max_iters, int count);
