@@ -236,6 +236,118 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
     x[i] = d > (TT)0 ? (ASSIGN ? (double)(s / d) : xo + (double)(s / d)) : xo;
 }
 
+// Both colours of the red-black ILU(0) application in one pass (rows of at
+// most 62 cells).  A wavefront owns one row y with one halo lane on each side
+// (lane l is x = l - 1); a workgroup holds kIluInner rows plus the row above
+// and below, whose black corrections it computes for its own red cells.  The
+// workgroup walks the layers of its z chunk: step L forms the black
+// corrections of layer L (from r and a of layers L-1..L+1) and the red
+// corrections of layer L-1 (from the black ones of layers L-2..L), keeping the
+// per-layer values in registers, taking x neighbours from adjacent lanes and
+// y neighbours of the black corrections through LDS (three layer buffers,
+// one barrier per step).  Operations per cell and face order are those of
+// k_ilu_black / k_ilu_red; x is read and written once.
+constexpr int kIluInner = 6, kIluRows = kIluInner + 2;
+
+template <typename TT, bool ASSIGN>
+__global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__restrict__ tx,
+                                                           const TT *__restrict__ ty, const TT *__restrict__ tz,
+                                                           const TT *__restrict__ diag, const TT *__restrict__ dtil,
+                                                           const double *__restrict__ r, double *__restrict__ x,
+                                                           int ngy, int nzc, int zc, int nblk, const int *done) {
+    __shared__ TT eb[3][kIluRows][64];
+    if (done && *done) return;
+    const int b = xcd_block();
+    if (b >= nblk) return;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int zk = b % nzc, yg = b / nzc;
+    const int xr = lane - 1, y = yg * kIluInner - 1 + wv;
+    const bool xin = xr >= 0 && xr < nx, yin = y >= 0 && y < ny;
+    const bool inner = wv >= 1 && wv <= kIluInner && yin;
+    const int xc = min(max(xr, 0), nx - 1), yc = min(max(y, 0), ny - 1);
+    // faces of the (clamped) cell: rows and lanes outside the grid take the
+    // neighbours of the cell they load, so every index stays inside the grid
+    const bool fxm = xc > 0 && xr > 0, fym = yc > 0, fyp = yc + 1 < ny;
+    const int z0 = zk * zc, z1 = min(nz, z0 + zc);
+    const int col = xc + nx * yc;
+    const int dym = fym ? nx : 0, dyp = fyp ? nx : 0;
+    auto at = [&](int L) { return col + nxy * min(max(L, 0), nz - 1); };
+
+    const int Ls = max(z0 - 1, 0), Le = z1;  // black layers Ls..min(z1, nz-1); red layers z0..z1-1
+    // rolling own-column values (layer L-1, L, L+1) and the previous layer's faces
+    TT rm = Ls > 0 ? (TT)r[at(Ls - 1)] : (TT)0, r0 = (TT)r[at(Ls)];
+    TT dm = Ls > 0 ? diag[at(Ls - 1)] : (TT)0, d0 = diag[at(Ls)];
+    TT tzm = Ls > 0 ? tz[at(Ls - 1)] : (TT)0, tzm2 = (TT)0;
+    TT txp = (TT)0, typ = (TT)0, tymp = (TT)0, rprev = (TT)0, dprev = (TT)0;
+    TT em = (TT)0, em2 = (TT)0;
+    for (int L = Ls; L <= Le; ++L) {
+        const bool hasb = L < nz;  // layer L exists (the step L = nz only forms red of nz - 1)
+        const int i = at(L);
+        // loads of layer L (own faces, y neighbours) and L + 1 (own column)
+        const TT rp = (TT)r[at(L + 1)], dp = diag[at(L + 1)];
+        const TT tx0 = tx[i], ty0 = ty[i], tym0 = ty[i - dym], tz0 = tz[i], dt0 = dtil[i];
+        const TT rym = (TT)r[i - dym], ryp = (TT)r[i + dyp], dym_ = diag[i - dym], dyp_ = diag[i + dyp];
+        const int lo = at(L - 1);
+        const double xo = (ASSIGN || L - 1 < z0) ? 0.0 : x[lo];
+        // black corrections of layer L (faces -x, +x, -y, +y, -z, +z)
+        TT e0 = (TT)0;
+        {
+            const TT rxm = __shfl_up(r0, 1, 64), rxp = __shfl_down(r0, 1, 64);
+            const TT dxm = __shfl_up(d0, 1, 64), dxp = __shfl_down(d0, 1, 64);
+            const TT txm = __shfl_up(tx0, 1, 64);
+            const TT t[6] = {fxm ? txm : (TT)0, tx0, fym ? tym0 : (TT)0, fyp ? ty0 : (TT)0,
+                             L > 0 ? tzm : (TT)0, L + 1 < nz ? tz0 : (TT)0};
+            const TT rl[6] = {rxm, rxp, rym, ryp, rm, rp};
+            const TT dl[6] = {dxm, dxp, dym_, dyp_, dm, dp};
+            TT sb = r0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sb = t[q] != (TT)0 ? sb + t[q] * rl[q] / dl[q] : sb;
+            const bool black = ((xr + y + L) & 1) == 1;
+            const bool on = hasb && black && dt0 > (TT)0;
+            const TT v = sb / dt0;
+            e0 = on ? v : (TT)0;
+        }
+        eb[L % 3][wv][lane] = e0;
+        __syncthreads();
+        // red corrections of layer L - 1, and the stores of layer L - 1
+        const int Lr = L - 1;
+        if (Lr >= z0 && Lr < z1) {
+            const TT exm = __shfl_up(em, 1, 64), exp_ = __shfl_down(em, 1, 64);
+            const TT eym = eb[Lr % 3][wv > 0 ? wv - 1 : 0][lane], eyp = eb[Lr % 3][wv + 1 < kIluRows ? wv + 1 : wv][lane];
+            const TT txm = __shfl_up(txp, 1, 64);
+            const TT t[6] = {fxm ? txm : (TT)0, txp, fym ? tymp : (TT)0, fyp ? typ : (TT)0,
+                             Lr > 0 ? tzm2 : (TT)0, Lr + 1 < nz ? tzm : (TT)0};
+            const TT el[6] = {exm, exp_, eym, eyp, em2, e0};
+            TT sr = rprev;
+            const bool red = ((xr + y + Lr) & 1) == 0;
+            if (red) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) sr = t[q] != (TT)0 ? sr + t[q] * el[q] : sr;
+            }
+            double xn;
+            if (red) xn = dprev > (TT)0 ? (ASSIGN ? (double)(sr / dprev) : xo + (double)(sr / dprev)) : xo;
+            else xn = ASSIGN ? (double)em : xo + (double)em;  // em = 0 where the pivot is not positive
+            if (inner && xin) x[lo] = xn;
+        }
+        // slide: layer L becomes the previous one
+        em2 = em;
+        em = e0;
+        tzm2 = tzm;
+        tzm = tz0;
+        txp = tx0;
+        typ = ty0;
+        tymp = tym0;
+        rprev = r0;
+        dprev = d0;
+        rm = r0;
+        dm = d0;
+        r0 = rp;
+        d0 = dp;
+    }
+}
+
 template <bool ASSIGN>
 static void smooth_dispatch(Ctx &c, const double *r, double *x, const int *done) {
     Fine g = fine_of(c);
@@ -247,6 +359,21 @@ static void smooth_dispatch(Ctx &c, const double *r, double *x, const int *done)
         else
             hipLaunchKernelGGL((k_jacobi<double, ASSIGN>), dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N,
                                c.diag, c.opt.omega_s, r, x, done);
+        return;
+    }
+    if (c.nx <= 62) {
+        const int ngy = cdiv(c.ny, kIluInner);
+        int nzc = std::min(c.nz, std::max(1, cdiv(4096, ngy * kIluRows)));
+        const int zc = cdiv(c.nz, nzc);
+        nzc = cdiv(c.nz, zc);
+        const int nblk = nzc * ngy;
+        const dim3 grid(xcd_grid(nblk)), blk(64 * kIluRows);
+        if (mixed)
+            hipLaunchKernelGGL((k_ilu_zm<float, ASSIGN>), grid, blk, 0, c.stream, g, c.tx32, c.ty32, c.tz32, c.diag32,
+                               c.dtil32, r, x, ngy, nzc, zc, nblk, done);
+        else
+            hipLaunchKernelGGL((k_ilu_zm<double, ASSIGN>), grid, blk, 0, c.stream, g, c.tx, c.ty, c.tz, c.diag,
+                               c.dtil, r, x, ngy, nzc, zc, nblk, done);
         return;
     }
     const int half = ((c.nx + 1) / 2) * c.ny * c.nz;
