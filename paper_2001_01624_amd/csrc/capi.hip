@@ -279,10 +279,17 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     s.Ac = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
     s.Ainv = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
     s.dvec = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
-    s.pc = (double *)ctx_alloc(c, sizeof(double) * s.Mp);
+    const size_t npc = std::max((size_t)s.Mp, (size_t)cd.m[0] * cd.m[1] * cd.m[2]);
+    s.pc = (double *)ctx_alloc(c, sizeof(double) * npc);
     if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
+    if (hipMemset(s.pc, 0, sizeof(double) * npc) != hipSuccess) return hip_fail(hipGetLastError(), "clear p_c");
+    s.pc_map = cd.present;
     if (c.nx > 64 * 4) {
         set_error("rows longer than 256 cells are not supported by the restriction kernel");
+        return MSRSB_E_INVAL;
+    }
+    if (cd.m[2] > 1024) {
+        set_error("more than 1024 coarse blocks along z are not supported by the restriction kernel");
         return MSRSB_E_INVAL;
     }
     {
@@ -561,6 +568,10 @@ static int solve_richardson(Ctx &c, const double *b, double *x, double rtol, int
     return MSRSB_OK;
 }
 
+// Mixed precision keeps the GMRES basis in FP32 on the DCGS2 path (dots,
+// Hessenberg and candidate vectors stay FP64; the restart residual is FP64).
+static bool fp32_basis(const msrsb_options &o) { return o.precision == MSRSB_MIXED && o.restart <= kDcgsMax; }
+
 static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_iters) {
     const int m = std::max(1, std::min(c.opt.restart, kMaxRestart));
     const long N = c.N;
@@ -584,7 +595,7 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
                 const int *done = &c.status->done;
                 if (dcgs) {
                     // column j from u_j = V(j) (u_0 = r); q_j and u_{j+1} land in V
-                    const double *uj = c.V + (long)j * N;
+                    const double *uj = c.V + (c.Vf ? (long)(j & 1) : (long)j) * N;
                     cycle(c, uj, c.z, false, done, true);
                     launch_dgmres_step(c, c.z, w, uj, j, rtol, max_iters, false);
                 } else {
@@ -599,7 +610,7 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
         }
         if (dcgs && j == m && !c.h_status->done) {
             // finalise the last column from u_m
-            launch_dgmres_step(c, nullptr, w, c.V + (long)m * N, m, rtol, max_iters, true);
+            launch_dgmres_step(c, nullptr, w, c.V + (c.Vf ? (long)(m & 1) : (long)m) * N, m, rtol, max_iters, true);
             if ((rc = read_status(c))) return rc;
         }
         // x += M^{-1} V y
@@ -607,7 +618,8 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
         if (k > 0) {
             launch_gmres_solve_small(c, m);
             zero_vec(c, c.u, nullptr);
-            launch_multiaxpy(c, c.V, k, c.scal + 4608, c.u, 1.0, false, nullptr);
+            if (c.Vf) launch_multiaxpy(c, c.Vf, k, c.scal + 4608, c.u, 1.0, false, nullptr);
+            else launch_multiaxpy(c, c.V, k, c.scal + 4608, c.u, 1.0, false, nullptr);
             cycle(c, c.u, c.z, false, nullptr, true);
             launch_axpy(c, x, c.z, nullptr);
         }
@@ -724,7 +736,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     size_t b = N * 8 * 3 + N * 4 * 3 + N * 8 * 6 + N * 4 * 2;  // T, T32, diag/b/src/bcdiag/bcrhs/dtil, f32 copies
     b += N * 8 * 5;                                          // work vectors
     b += (size_t)kRedBlocks * (2 * kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
-    if (o.outer == MSRSB_GMRES) b += (size_t)(o.restart + 1) * N * 8;
+    if (o.outer == MSRSB_GMRES) b += fp32_basis(o) ? N * 8 * 2 + (size_t)o.restart * N * 4 : (size_t)(o.restart + 1) * N * 8;
     b += (size_t)g->n_bc * 24;
     long cb = 0;
     for (int k = 0; k < n_part; ++k) {
@@ -831,8 +843,15 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         hipMemcpy(c->bc_value, g->bc_value, 8 * (size_t)g->n_bc, hipMemcpyHostToDevice);
     }
     if (o.outer == MSRSB_GMRES) {
-        c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
-        if (!c->V) return fail(MSRSB_E_NOMEM);
+        if (fp32_basis(o)) {
+            c->V = (double *)alloc(8 * 2 * (size_t)N);
+            c->Vf = (float *)alloc(4 * (size_t)o.restart * N);
+            if (!c->V || !c->Vf) return fail(MSRSB_E_NOMEM);
+            if (hipMemset(c->Vf, 0, 4 * (size_t)o.restart * N) != hipSuccess) return fail(MSRSB_E_DEVICE);
+        } else {
+            c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
+            if (!c->V) return fail(MSRSB_E_NOMEM);
+        }
     }
     c->stages.resize(n_part);
     long cb = cdiv(o.max_dyn_blocks, kTile) * kTile;

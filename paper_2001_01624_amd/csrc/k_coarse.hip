@@ -300,12 +300,14 @@ void launch_coarse_inverse(Ctx &c, Stage &s) {
 
 // p_c = A_c^{-1} d: one wavefront per row (four rows per workgroup), d
 // staged in LDS when it fits; each lane adds its strided entries in order
-// (loads unrolled), then a fixed-order wave sum.
+// (loads unrolled), then a fixed-order wave sum.  Row j is stored at
+// y[map[j]] when a map is given.
 constexpr int kGemvLds = 16384;  // doubles of d held in LDS
 
 template <bool LDS>
 __global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, int M, int Mp, const double *__restrict__ d,
-                                              double *__restrict__ y, const int *done) {
+                                              double *__restrict__ y, const int32_t *__restrict__ map,
+                                              const int *done) {
     extern __shared__ double ds[];
     if (done && *done) return;
     if (LDS) {
@@ -320,17 +322,17 @@ __global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, int 
 #pragma unroll 8
     for (int k = lane; k < M; k += 64) s += a[k] * (LDS ? ds[k] : d[k]);
     s = wave_sum(s);
-    if (lane == 0) y[row] = s;
+    if (lane == 0) y[map ? map[row] : row] = s;
 }
 
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done) {
     ProfScope ps(c, MSRSB_K_COARSE);
     if (s.M <= kGemvLds)
         hipLaunchKernelGGL(k_gemv<true>, dim3(cdiv(s.M, 4)), dim3(256), sizeof(double) * (size_t)s.M, c.stream,
-                           s.Ainv, s.M, s.Mp, s.dvec, s.pc, done);
+                           s.Ainv, s.M, s.Mp, s.dvec, s.pc, s.pc_map, done);
     else
         hipLaunchKernelGGL(k_gemv<false>, dim3(cdiv(s.M, 4)), dim3(256), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec,
-                           s.pc, done);
+                           s.pc, s.pc_map, done);
 }
 
 }  // namespace msrsb

@@ -519,8 +519,8 @@ void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_
     hipLaunchKernelGGL(k_multidot_finish, dim3(k), dim3(kBlock), 0, c.stream, c.partial, grid, h_out, done);
 }
 
-template <bool NORM>
-__global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const double *__restrict__ V, int k,
+template <bool NORM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const VT *__restrict__ V, int k,
                                                       const double *__restrict__ h, double sign,
                                                       double *__restrict__ w, double *__restrict__ partial,
                                                       const int *done) {
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const double *__res
     double acc = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int j = 0; j < k; ++j) s += hs[j] * V[(long)j * N + i];
+        for (int j = 0; j < k; ++j) s += hs[j] * (double)V[(long)j * N + i];
         const double v = w[i] + sign * s;
         w[i] = v;
         acc += v * v;
@@ -543,15 +543,26 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const double *__res
     }
 }
 
-void launch_multiaxpy(Ctx &c, const double *V, int k, const double *h, double *w, double sign, bool norm,
-                      const int *done) {
+template <typename VT>
+static void multiaxpy_t(Ctx &c, const VT *V, int k, const double *h, double *w, double sign, bool norm,
+                        const int *done) {
     const int grid = red_grid(c.N);
     if (norm)
-        hipLaunchKernelGGL(k_multiaxpy<true>, dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
+        hipLaunchKernelGGL((k_multiaxpy<true, VT>), dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
                            c.partial, done);
     else
-        hipLaunchKernelGGL(k_multiaxpy<false>, dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
+        hipLaunchKernelGGL((k_multiaxpy<false, VT>), dim3(grid), dim3(kBlock), 0, c.stream, c.N, V, k, h, sign, w,
                            c.partial, done);
+}
+
+void launch_multiaxpy(Ctx &c, const double *V, int k, const double *h, double *w, double sign, bool norm,
+                      const int *done) {
+    multiaxpy_t<double>(c, V, k, h, w, sign, norm, done);
+}
+
+void launch_multiaxpy(Ctx &c, const float *V, int k, const double *h, double *w, double sign, bool norm,
+                      const int *done) {
+    multiaxpy_t<float>(c, V, k, h, w, sign, norm, done);
 }
 
 // Start of a restart cycle: beta = ||r|| (scal[0] holds ||r||^2), v0 = r/beta,
@@ -991,9 +1002,9 @@ __global__ __launch_bounds__(kBlock) void k_gmres_step2(Status *st, double *scal
 // unrotated Hessenberg at S_HU, update coefficients at S_DC, 1/rho at S_RHO.
 constexpr int S_HU = 8192, S_DA = 12500, S_DC = 12700, S_RHO = 12800;
 
-template <int KM, bool MV>
+template <int KM, bool MV, typename VT>
 __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__restrict__ z, double *__restrict__ w,
-                                                    const double *__restrict__ Q, const double *__restrict__ u,
+                                                    const VT *__restrict__ Q, const double *__restrict__ u,
                                                     int j, double *__restrict__ partial, const int *done) {
     __shared__ double red[(kBlock / 64 + 1) * KM];
     if (done && *done) return;
@@ -1008,7 +1019,7 @@ __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__rest
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += G * blockDim.x) {
         double vq[KM - 1];
 #pragma unroll
-        for (int q = 0; q < KM - 1; ++q) vq[q] = Q[(long)min(q, jc) * g.N + i];  // slots q >= j unused
+        for (int q = 0; q < KM - 1; ++q) vq[q] = (double)Q[(long)min(q, jc) * g.N + i];  // slots q >= j unused
         const double ui = u[i];
         const int step[3] = {1, g.nx, g.nxy};
         bool in[6];
@@ -1178,10 +1189,11 @@ __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int 
 }
 
 // q_j = (u_j - Q s) / rho into qout, u_{j+1} = w / rho - Q c(0..j-1) - c_j q_j
-// into unext (qout may alias u).
-template <int KM>
-__global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const double *__restrict__ Q, const double *u,
-                                                    const double *__restrict__ w, int j, double *qout,
+// into unext (qout may alias u).  q_j enters u_{j+1} as stored (rounded to
+// VT), so u_{j+1} is formed against the basis that is kept.
+template <int KM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict__ Q, const double *u,
+                                                    const double *__restrict__ w, int j, VT *qout,
                                                     double *__restrict__ unext, const double *__restrict__ scal,
                                                     const Status *st) {
     if (st->done) return;
@@ -1198,7 +1210,7 @@ __global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const double *__restr
         double vq[KM - 1];
 #pragma unroll
         for (int q = 0; q < KM - 1; ++q) {
-            const double v = Q[(long)min(q, jc) * N + i];
+            const double v = (double)Q[(long)min(q, jc) * N + i];
             vq[q] = q < j ? v : 0.0;  // unused slots may hold anything (V(0) before its first write)
         }
         const double ui = u[i], wi = w[i];
@@ -1208,15 +1220,15 @@ __global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const double *__restr
             a += sq[q] * vq[q];
             b += cq[q] * vq[q];
         }
-        const double qj = (ui - a) * irho;
-        qout[i] = qj;
-        unext[i] = wi * irho - (b + cj * qj);
+        const VT qs = (VT)((ui - a) * irho);
+        qout[i] = qs;
+        unext[i] = wi * irho - (b + cj * (double)qs);
     }
 }
 
-template <int KM>
-static void dgmres_step_k(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
-                          bool final_) {
+template <int KM, typename VT>
+static void dgmres_step_k(Ctx &c, const VT *Q, VT *qout, double *unext, const double *z, double *w, const double *u,
+                          int j, double rtol, int max_iters, bool final_) {
     Fine g = fine_of(c);
     const int G = red_grid(c.N);
     const int *done = &c.status->done;
@@ -1224,10 +1236,10 @@ static void dgmres_step_k(Ctx &c, const double *z, double *w, const double *u, i
     {
         ProfScope ps(c, final_ ? MSRSB_K_ORTHO : MSRSB_K_MATVEC);
         if (final_)
-            hipLaunchKernelGGL((k_dpass_a<KM, false>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, u, j,
+            hipLaunchKernelGGL((k_dpass_a<KM, false, VT>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
                                c.partial, done);
         else
-            hipLaunchKernelGGL((k_dpass_a<KM, true>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, c.V, u, j,
+            hipLaunchKernelGGL((k_dpass_a<KM, true, VT>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
                                c.partial, done);
     }
     hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, G,
@@ -1236,17 +1248,29 @@ static void dgmres_step_k(Ctx &c, const double *z, double *w, const double *u, i
                        final_ ? 1 : 0);
     if (final_) return;
     ProfScope ps(c, MSRSB_K_ORTHO);
-    double *qout = c.V + (long)j * c.N, *unext = c.V + (long)(j + 1) * c.N;
-    hipLaunchKernelGGL((k_dpass_b<KM>), dim3(G), dim3(kBlock), 0, c.stream, c.N, c.V, u, w, j, qout, unext, c.scal,
+    hipLaunchKernelGGL((k_dpass_b<KM, VT>), dim3(G), dim3(kBlock), 0, c.stream, c.N, Q, u, w, j, qout, unext, c.scal,
                        st);
 }
 
+template <typename VT>
+static void dgmres_step_t(Ctx &c, const VT *Q, VT *qout, double *unext, const double *z, double *w, const double *u,
+                          int j, double rtol, int max_iters, bool final_) {
+    if (j <= 7) dgmres_step_k<8, VT>(c, Q, qout, unext, z, w, u, j, rtol, max_iters, final_);
+    else if (j <= 15) dgmres_step_k<16, VT>(c, Q, qout, unext, z, w, u, j, rtol, max_iters, final_);
+    else dgmres_step_k<32, VT>(c, Q, qout, unext, z, w, u, j, rtol, max_iters, final_);
+}
+
 // One DCGS2 Arnoldi step for column j (final: only finalise column j - 1).
+// FP64 basis: q_j overwrites u_j in V(j) and u_{j+1} goes to V(j + 1).  FP32
+// basis (Vf set): q_j goes to Vf(j) and the candidates alternate between V(0)
+// and V(1).
 void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
                         bool final_) {
-    if (j <= 7) dgmres_step_k<8>(c, z, w, u, j, rtol, max_iters, final_);
-    else if (j <= 15) dgmres_step_k<16>(c, z, w, u, j, rtol, max_iters, final_);
-    else dgmres_step_k<32>(c, z, w, u, j, rtol, max_iters, final_);
+    const long N = c.N;
+    if (c.Vf)
+        dgmres_step_t<float>(c, c.Vf, c.Vf + j * N, c.V + ((j + 1) & 1) * N, z, w, u, j, rtol, max_iters, final_);
+    else
+        dgmres_step_t<double>(c, c.V, c.V + j * N, c.V + (j + 1) * N, z, w, u, j, rtol, max_iters, final_);
 }
 
 void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart) {

@@ -26,47 +26,50 @@ namespace msrsb {
 // added in lane order:  part[((z*my + Ly)*mx + Lx)*NS + s].
 // Pass 2 (k_restrict_gather): d_J = sum over s, and over the layers z of the
 // dual interval J_z - s_z, of part[z, J_y - s_y, J_x - s_x, s] (fixed order).
-constexpr int kRowChunks = 4;  // rows up to 64*kRowChunks cells
-
-constexpr int kRowWaves = 4;
-constexpr int kRowUnroll = 3;
-
 // RES: r is not read but formed per cell as b - A x, with the operations of
 // the residual kernel (so the restricted vector is the same bit for bit).
-template <int NS, typename PS, int NCH, bool RES>
-__global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                                  const double *__restrict__ rb,
-                                                                  const double *__restrict__ x,
-                                                                  double *__restrict__ part, const int *done) {
-    extern __shared__ double red[];  // [kRowWaves][nx][NS]
+// W wavefronts per workgroup, U rows per wavefront in flight.  One workgroup
+// per (dual y-interval Ly, layer z), numbered with z fastest and spread over
+// the XCDs in contiguous ranges, so the layers above and below are read
+// through the same L2.  Rows of at most 64 cells (NCH = 1) take the x
+// neighbours from the adjacent lanes.
+template <int NS, typename PS, int NCH, bool RES, int W, int U>
+__global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                          const double *__restrict__ rb,
+                                                          const double *__restrict__ x, double *__restrict__ part,
+                                                          const int *done) {
+    extern __shared__ double red[];  // [W][nx][NS]
     if (done && *done) return;
-    const int Ly = blockIdx.x, z = blockIdx.y;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int mx = cd.m[0], my = cd.m[1];
+    const int t = xcd_block();
+    if (t >= my * g.nz) return;
+    const int Ly = t / g.nz, z = t - Ly * g.nz;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int y0 = 0, y1 = g.ny;
     if (cd.bit[1] >= 0) {
         y0 = Ly == 0 ? 0 : cd.split[1][Ly];
         y1 = Ly + 1 < my ? cd.split[1][Ly + 1] : g.ny;
     }
+    constexpr bool SHX = RES && NCH == 1;  // x neighbours by lane exchange
     double acc[NCH][NS];
 #pragma unroll
     for (int k = 0; k < NCH; ++k)
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
-    // kRowUnroll rows per pass, all loads of a pass issued before the first
-    // use; rows past the interval load row y0 and add nothing.  Rows are
-    // still added in increasing y, so the sums do not depend on the unroll.
-    for (int yb = y0 + wv; yb < y1; yb += kRowWaves * kRowUnroll) {
+    // U rows per pass, all loads of a pass issued before the first use; rows
+    // past the interval load row y0 and add nothing.  Each wavefront adds its
+    // rows in increasing y, so the sums do not depend on U (they do on W).
+    for (int yb = y0 + wv; yb < y1; yb += W * U) {
 #pragma unroll
         for (int k = 0; k < NCH; ++k) {
             const int xx = lane + 64 * k;
             if (xx < g.nx) {
-                double ri[kRowUnroll], pv[kRowUnroll][NS];
-                double xi[kRowUnroll], xl[kRowUnroll][6], traw[kRowUnroll][6], dg[kRowUnroll], bi[kRowUnroll];
-                bool in[kRowUnroll], fin[kRowUnroll][6];
+                double ri[U], pv[U][NS];
+                double xi[U], xl[U][6], traw[U][6], dg[U], bi[U];
+                bool in[U], fin[U][6];
 #pragma unroll
-                for (int u = 0; u < kRowUnroll; ++u) {
-                    const int y = yb + u * kRowWaves;
+                for (int u = 0; u < U; ++u) {
+                    const int y = yb + u * W;
                     in[u] = y < y1;
                     const int i = g.nx * ((in[u] ? y : y0) + g.ny * z) + xx;
 #pragma unroll
@@ -75,16 +78,18 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
                         // faces as in cell_faces, the zeroing applied after the loads
                         const int step[3] = {1, g.nx, g.nxy};
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
+                        for (int a = SHX ? 1 : 0; a < 3; ++a) {
                             const double *Ta = a == 0 ? g.tx : (a == 1 ? g.ty : g.tz);
                             fin[u][2 * a] = i >= step[a];
                             fin[u][2 * a + 1] = i + step[a] < g.N;
                             const int ld = fin[u][2 * a] ? i - step[a] : i, lu = fin[u][2 * a + 1] ? i + step[a] : i;
                             traw[u][2 * a] = Ta[ld];
-                            traw[u][2 * a + 1] = Ta[i];
                             xl[u][2 * a] = x[ld];
                             xl[u][2 * a + 1] = x[lu];
                         }
+                        traw[u][1] = g.tx[i];
+                        traw[u][3] = g.ty[i];
+                        traw[u][5] = g.tz[i];
                         xi[u] = x[i];
                         dg[u] = g.diag[i];
                         bi[u] = rb[i];
@@ -93,9 +98,23 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
+                if (SHX) {
+                    // tx of the cell before is the previous lane's own tx (0 on
+                    // the first column, where the face does not exist); the end
+                    // lanes use their own x, multiplied by a zero coefficient
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const double tl = __shfl_up(traw[u][1], 1, 64), xm = __shfl_up(xi[u], 1, 64);
+                        const double xp = __shfl_down(xi[u], 1, 64);
+                        fin[u][0] = fin[u][1] = true;
+                        traw[u][0] = xx > 0 ? tl : 0.0;
+                        xl[u][0] = xx > 0 ? xm : xi[u];
+                        xl[u][1] = xx + 1 < g.nx ? xp : xi[u];
+                    }
+                }
                 if (RES) {
 #pragma unroll
-                    for (int u = 0; u < kRowUnroll; ++u) {
+                    for (int u = 0; u < U; ++u) {
                         double ax = dg[u] * xi[u];  // (A x)_i as ax_row
 #pragma unroll
                         for (int q = 0; q < 6; ++q) ax -= (fin[u][q] ? traw[u][q] : 0.0) * xl[u][q];
@@ -103,7 +122,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kRowUnroll; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int s = 0; s < NS; ++s) acc[k][s] = in[u] ? acc[k][s] + pv[u][s] * ri[u] : acc[k][s];
             }
@@ -119,8 +138,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
     }
     __syncthreads();
     // thread (Lx, s) adds waves, then columns of dual x-interval Lx, in order
-    for (int t = threadIdx.x; t < mx * NS; t += blockDim.x) {
-        const int Lx = t / NS, s = t % NS;
+    for (int e = threadIdx.x; e < mx * NS; e += blockDim.x) {
+        const int Lx = e / NS, s = e % NS;
         int x0 = 0, x1 = g.nx;
         if (cd.bit[0] >= 0) {
             x0 = Lx == 0 ? 0 : cd.split[0][Lx];
@@ -128,104 +147,143 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_restrict_rows(CartDev cd, Fi
         }
         double tot = 0.0;
         for (int xx = x0; xx < x1; ++xx)
-            for (int w = 0; w < kRowWaves; ++w) tot += red[((long)w * g.nx + xx) * NS + s];
+            for (int w = 0; w < W; ++w) tot += red[((long)w * g.nx + xx) * NS + s];
         part[(((long)z * my + Ly) * mx + Lx) * NS + s] = tot;
     }
 }
 
 // NARROW: every dual z-interval has at most 64 layers, so each lane adds at
-// most one layer per slot and all loads of a wavefront are independent.
+// most one layer per slot.  The z split table is staged in LDS, so the only
+// global round trips are the block id and one partial per slot; the partials
+// are loaded unconditionally (clamped index) and masked by a factor 0 or 1.
+constexpr int kGatherSplitLds = 1024;  // dual z-intervals held in LDS
+
 template <int NS, bool NARROW>
 __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
                                                          double *__restrict__ d, const int *done) {
+    __shared__ int spz[kGatherSplitLds];
     if (done && *done) return;
+    const int mx = cd.m[0], my = cd.m[1], mz = cd.m[2];
+    for (int t = threadIdx.x; t < mz; t += blockDim.x) spz[t] = cd.split[2][t];
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int cid = cd.present[min(j, M - 1)];
+    __syncthreads();
     if (j >= M) return;
-    const int mx = cd.m[0], my = cd.m[1], mz = cd.m[2];
-    const int cid = cd.present[j];
     const int J[3] = {cid % mx, (cid / mx) % my, cid / (mx * my)};
     // work items: (slot s, layer z of the dual interval J_z - s_z)
-    double v = 0.0;
+    int L[NS][3], z0[NS], z1[NS];
+    bool ok[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        int L[3];
-        bool ok = true;
+        ok[s] = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            L[a] = J[a] - (cd.bit[a] >= 0 ? (s >> cd.bit[a]) & 1 : 0);
-            if (L[a] < 0) ok = false;
+            L[s][a] = J[a] - (cd.bit[a] >= 0 ? (s >> cd.bit[a]) & 1 : 0);
+            ok[s] = ok[s] && L[s][a] >= 0;
         }
-        int z0 = 0, z1 = g.nz;
-        if (cd.bit[2] >= 0 && ok) {
-            z0 = L[2] == 0 ? 0 : cd.split[2][L[2]];
-            z1 = L[2] + 1 < mz ? cd.split[2][L[2] + 1] : g.nz;
+        const int l2 = max(L[s][2], 0);
+        const bool zs = cd.bit[2] >= 0 && ok[s];
+        z0[s] = zs && l2 > 0 ? spz[l2] : 0;
+        z1[s] = zs && l2 + 1 < mz ? spz[l2 + 1] : g.nz;
+    }
+    double v = 0.0;
+    if (NARROW) {
+        double pv[NS], f[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int z = z0[s] + lane;
+            const bool in = ok[s] && z < z1[s];
+            const long at = in ? (((long)z * my + L[s][1]) * mx + L[s][0]) * NS + s : 0;
+            pv[s] = part[at];
+            f[s] = in ? 1.0 : 0.0;
         }
-        if (NARROW) {
-            const int z = z0 + lane;
-            const bool in = ok && z < z1;
-            const long at = in ? (((long)z * my + L[1]) * mx + L[0]) * NS + s : 0;
-            const double pv = part[at];
-            v += in ? pv : 0.0;
-        } else {
-            if (!ok) continue;
-            for (int z = z0 + lane; z < z1; z += 64) v += part[(((long)z * my + L[1]) * mx + L[0]) * NS + s];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v += pv[s] * f[s];
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (!ok[s]) continue;
+            for (int z = z0[s] + lane; z < z1[s]; z += 64) v += part[(((long)z * my + L[s][1]) * mx + L[s][0]) * NS + s];
         }
     }
     v = wave_sum(v);
     if (lane == 0) d[j] = v;
 }
 
-// x_i += sum_s P_is p_c[block(i,s)]
-template <int NS, typename PS>
-__global__ __launch_bounds__(kBlock) void k_prolong(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                    const double *__restrict__ pc, double *__restrict__ x,
-                                                    const int *done) {
-    // x_i += sum_s P_is pc[block(i, s)].  Every load is issued on an address
-    // that depends on i and the small tables only; slots outside the support
-    // or on a dropped block add nothing.
-    if (done && *done) return;
-    const int i = xzy_cell(xcd_block() * blockDim.x + threadIdx.x, g.nx, g.ny, g.nz);
-    if (i < 0) return;
-    int c[3], lo[3], nv[3];
-    cell_coords(g, i, c);
-    const double dg = g.diag[i];
-    const double xo = x[i];
-    double pv[NS];
+// x_i += sum_s P_is p_c[block(i, s)], one wavefront per grid row (y, z) with
+// lanes along x.  The y and z parts of the slot -> block map are uniform over
+// the row, and p_c is held per Cartesian block (zero on dropped blocks), so
+// the block of a slot is index arithmetic on the packed per-axis tables.
+// Inactive cells and slots outside the support hold zero basis values (the
+// sweeps store zeros there) and add nothing.  The skip flag is read after the
+// data loads are issued, so it costs no separate round trip.
+constexpr int kProWaves = 4;
+
+template <int NS, typename PS, int NCH>
+__global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                                 const double *__restrict__ pcc,
+                                                                 double *__restrict__ x, const int *done) {
+    const int row = xcd_block() * kProWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (row >= g.ny * g.nz) return;
+    const int lane = threadIdx.x & 63;
+    const int z = row / g.ny, y = row - z * g.ny;
+    const int wy = cd.bit[1] >= 0 ? cd.pack[1][y] : 0;
+    const int wz = cd.bit[2] >= 0 ? cd.pack[2][z] : 0;
+    const int mx = cd.m[0], mxy = cd.m[0] * cd.m[1];
+    const int byz = mx * (wy & 0xFFFFF) + mxy * (wz & 0xFFFFF);
+    const int ny2 = (wy >> 20) & 1, nz2 = (wz >> 20) & 1;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) pv[s] = ld_basis(P, (long)s * g.N + i);
+    for (int k = 0; k < NCH; ++k) {
+        const int xx = lane + 64 * k;
+        if (xx >= g.nx) continue;
+        const long i = (long)row * g.nx + xx;
+        // the table load first: the gathers wait for it, not for the basis
+        const int wx = cd.bit[0] >= 0 ? cd.pack[0][xx] : 0;
+        double pv[NS];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int w = cd.bit[a] >= 0 ? cd.pack[a][c[a]] : 0;
-        lo[a] = w & 0xFFFFF;
-        nv[a] = 1 + ((w >> 20) & 1);
+        for (int s = 0; s < NS; ++s) pv[s] = ld_basis(P, (long)s * g.N + i);
+        const double xo = x[i];
+        if (done && *done) return;
+        const int b0 = byz + (wx & 0xFFFFF), nx2 = (wx >> 20) & 1;
+        // every gather issued (clamped index) before the first use, and the
+        // slot mask applied to the basis value: no branch per slot
+        double pcv[NS];
+        bool ok[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int sx = cd.bit[0] >= 0 ? (s >> cd.bit[0]) & 1 : 0;
+            const int sy = cd.bit[1] >= 0 ? (s >> cd.bit[1]) & 1 : 0;
+            const int sz = cd.bit[2] >= 0 ? (s >> cd.bit[2]) & 1 : 0;
+            ok[s] = sx <= nx2 && sy <= ny2 && sz <= nz2;
+            pcv[s] = pcc[ok[s] ? b0 + sx + mx * sy + mxy * sz : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc += (ok[s] ? pv[s] : 0.0) * pcv[s];
+        x[i] = xo + acc;
     }
-    int blk[NS];
-    double pcv[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        blk[s] = slot_ok(cd, nv, s) ? slot_block(cd, lo, s) : -1;
-        pcv[s] = pc[blk[s] >= 0 ? blk[s] : 0];
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc = blk[s] >= 0 ? acc + pv[s] * pcv[s] : acc;
-    x[i] = dg > 0.0 ? xo + acc : xo;
 }
+
+// four wavefronts with three rows each in flight measured fastest on the
+// 60x220x85 model (8x2, 8x3, 16x1 and 16x2 were slower)
+constexpr int kRestrictWaves = 4, kRestrictUnroll = 3;
 
 template <typename PS, bool RES>
 static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, const double *x, const int *done) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    const dim3 grid(s.cart.m[1], c.nz), blk(64 * kRowWaves), fgrid(cdiv(s.M, 4)), fblk(256);
-    const size_t lds = sizeof(double) * kRowWaves * (size_t)c.nx * s.ns;
     const int nch = cdiv(c.nx, 64);
-#define MSRSB_RROWS(NS, NCH) \
-    hipLaunchKernelGGL((k_restrict_rows<NS, PS, NCH, RES>), grid, blk, lds, c.stream, s.cart, g, P, rb, x, s.rpart, done)
+    constexpr int W = kRestrictWaves;
+    const dim3 grid(xcd_grid(s.cart.m[1] * c.nz)), blk(64 * W), fgrid(cdiv(s.M, 4)), fblk(256);
+    const size_t lds = sizeof(double) * W * (size_t)c.nx * s.ns;
+#define MSRSB_RR(NS, NCH, W_, U_) \
+    hipLaunchKernelGGL((k_restrict_rows<NS, PS, NCH, RES, W_, U_>), grid, blk, lds, c.stream, s.cart, g, P, rb, x, s.rpart, done)
 #define MSRSB_RNS(NS)                                                                                        \
     {                                                                                                        \
-        if (nch == 1) MSRSB_RROWS(NS, 1);                                                                    \
-        else if (nch == 2) MSRSB_RROWS(NS, 2);                                                               \
-        else MSRSB_RROWS(NS, 4);                                                                             \
+        if (nch == 1) MSRSB_RR(NS, 1, W, kRestrictUnroll);                                                   \
+        else if (nch == 2) MSRSB_RR(NS, 2, W, kRestrictUnroll);                                              \
+        else MSRSB_RR(NS, 4, W, kRestrictUnroll);                                                            \
         if (s.zwide <= 64)                                                                                   \
             hipLaunchKernelGGL((k_restrict_gather<NS, true>), fgrid, fblk, 0, c.stream, s.cart, g, s.M, s.rpart, s.dvec, done); \
         else                                                                                                 \
@@ -238,19 +296,30 @@ static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, c
     default: MSRSB_RNS(8) break;
     }
 #undef MSRSB_RNS
-#undef MSRSB_RROWS
+#undef MSRSB_RR
 }
 
 template <typename PS>
 static void prolong_dispatch(Ctx &c, Stage &s, const PS *P, double *x, const int *done) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    const dim3 grid(xcd_grid(cdiv(c.N, kBlock))), blk(kBlock);
-    switch (s.ns) {
-    case 1: hipLaunchKernelGGL((k_prolong<1, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-    case 2: hipLaunchKernelGGL((k_prolong<2, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-    case 4: hipLaunchKernelGGL((k_prolong<4, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
-    default: hipLaunchKernelGGL((k_prolong<8, PS>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done); break;
+    const dim3 grid(xcd_grid(cdiv(c.ny * c.nz, kProWaves))), blk(64 * kProWaves);
+    const int nch = cdiv(c.nx, 64);
+#define MSRSB_PROWS(NS, NCH) \
+    hipLaunchKernelGGL((k_prolong_rows<NS, PS, NCH>), grid, blk, 0, c.stream, s.cart, g, P, s.pc, x, done)
+#define MSRSB_PNS(NS)                         \
+    {                                         \
+        if (nch == 1) MSRSB_PROWS(NS, 1);     \
+        else if (nch == 2) MSRSB_PROWS(NS, 2); \
+        else MSRSB_PROWS(NS, 4);              \
     }
+    switch (s.ns) {
+    case 1: MSRSB_PNS(1) break;
+    case 2: MSRSB_PNS(2) break;
+    case 4: MSRSB_PNS(4) break;
+    default: MSRSB_PNS(8) break;
+    }
+#undef MSRSB_PNS
+#undef MSRSB_PROWS
 }
 
 void launch_restrict(Ctx &c, Stage &s, const double *r, const int *done) {

@@ -69,6 +69,9 @@ struct Stage {
     // coarse operator and its inverse (Mp x Mp, row-major), coarse vectors
     double *Ac = nullptr, *Ainv = nullptr;
     double *dvec = nullptr, *pc = nullptr;
+    // rectilinear stages hold p_c per Cartesian block (zero on dropped
+    // blocks); the coarse solve writes entry j at pc_map[j]
+    const int32_t *pc_map = nullptr;
     // restriction partial sums per (layer, dual interval, slot); Galerkin
     // partial sums per dual box
     double *rpart = nullptr;
@@ -127,8 +130,11 @@ struct Ctx {
     Status *h_status = nullptr;   // pinned host mirror
     unsigned long long *maxbits = nullptr;  // device max |change| bit pattern
     int *flag = nullptr;          // device error flag
-    // GMRES Krylov basis [(restart+1) * N]
+    // GMRES Krylov basis [(restart+1) * N]; with an FP32 basis (Vf, mixed
+    // precision and the DCGS2 path) V holds only the two candidate vectors
+    // u_j [2 * N] and Vf the basis [restart * N]
     double *V = nullptr;
+    float *Vf = nullptr;
     std::vector<Stage> stages;    // general + static
     std::vector<Stage> dyn;       // dynamic, newest first
     std::vector<void *> allocs;   // every device allocation (freed at destroy)
@@ -187,6 +193,8 @@ void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf);
 // GMRES helpers
 void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_out, const int *done);
 void launch_multiaxpy(Ctx &c, const double *V, int k, const double *h, double *w, double sign, bool norm,
+                      const int *done);
+void launch_multiaxpy(Ctx &c, const float *V, int k, const double *h, double *w, double sign, bool norm,
                       const int *done);
 void launch_gmres_start(Ctx &c, const double *r, double *v0, int restart);
 void launch_gmres_step(Ctx &c, int j, double rtol, int max_iters, int restart);
