@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_black(Fine g, const TT *__restri
         dl[q] = diag[l[q]];
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) s = t[q] != (TT)0 ? s + t[q] * rl[q] / dl[q] : s;
+    for (int q = 0; q < 6; ++q) s = t[q] != (TT)0 ? s + t[q] * (rl[q] / dl[q]) : s;
     const bool on = dt > (TT)0;
     const TT v = s / dt;
     e[i] = on ? (double)v : 0.0;
@@ -241,13 +241,18 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
 // (lane l is x = l - 1); a workgroup holds kIluInner rows plus the row above
 // and below, whose black corrections it computes for its own red cells.  The
 // workgroup walks the layers of its z chunk: step L forms the black
-// corrections of layer L (from r and a of layers L-1..L+1) and the red
-// corrections of layer L-1 (from the black ones of layers L-2..L), keeping the
-// per-layer values in registers, taking x neighbours from adjacent lanes and
-// y neighbours of the black corrections through LDS (three layer buffers,
-// one barrier per step).  Operations per cell and face order are those of
-// k_ilu_black / k_ilu_red; x is read and written once.
-constexpr int kIluInner = 6, kIluRows = kIluInner + 2;
+// corrections of layer L (from r and the pivots of layers L-1..L+1) and the
+// red corrections of layer L-1 (from the black ones of layers L-2..L).  Each
+// cell's ratio w = r / a_ii is formed once and shared: x neighbours from
+// adjacent lanes, y neighbours through LDS (the outer neighbours of the two
+// halo rows from memory), z neighbours in registers.  The loads of layer L+1
+// (and of r, a_ii at L+2) are issued at the start of step L, one step ahead
+// of their use.  One barrier per step; x is read and written once.  The
+// arithmetic per cell and the face order are those of k_ilu_black /
+// k_ilu_red.
+// 14 inner rows (1024 threads) measured fastest on the 60x220x85 model (6
+// and 10 were slower): the halo rows cost 2/16 of the loads.
+constexpr int kIluInner = 14, kIluRows = kIluInner + 2;
 
 template <typename TT, bool ASSIGN>
 __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__restrict__ tx,
@@ -255,7 +260,8 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
                                                            const TT *__restrict__ diag, const TT *__restrict__ dtil,
                                                            const double *__restrict__ r, double *__restrict__ x,
                                                            int ngy, int nzc, int zc, int nblk, const int *done) {
-    __shared__ TT eb[3][kIluRows][64];
+    __shared__ TT eb[3][kIluRows][64];  // black corrections, by layer mod 3
+    __shared__ TT wb[2][kIluRows][64];  // w = r / a_ii, by layer mod 2
     if (done && *done) return;
     const int b = xcd_block();
     if (b >= nblk) return;
@@ -273,49 +279,62 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
     const int z0 = zk * zc, z1 = min(nz, z0 + zc);
     const int col = xc + nx * yc;
     const int dym = fym ? nx : 0, dyp = fyp ? nx : 0;
+    // the halo rows read their outer y neighbour from memory
+    const bool top = wv == 0, bot = wv == kIluRows - 1;
+    const int dout = top ? -dym : (bot ? dyp : 0);
+    const int wup = wv > 0 ? wv - 1 : 0, wdn = wv + 1 < kIluRows ? wv + 1 : wv;
     auto at = [&](int L) { return col + nxy * min(max(L, 0), nz - 1); };
 
     const int Ls = max(z0 - 1, 0), Le = z1;  // black layers Ls..min(z1, nz-1); red layers z0..z1-1
-    // rolling own-column values (layer L-1, L, L+1) and the previous layer's faces
-    TT rm = Ls > 0 ? (TT)r[at(Ls - 1)] : (TT)0, r0 = (TT)r[at(Ls)];
-    TT dm = Ls > 0 ? diag[at(Ls - 1)] : (TT)0, d0 = diag[at(Ls)];
+    // registers: own column at L-1, L (w, r, a_ii), raw r, a_ii at L+1; faces
+    // of layer L and L-1; the halo row's outer r, a_ii at L
+    TT r0 = (TT)r[at(Ls)], d0 = diag[at(Ls)];
+    TT w0 = r0 / d0;
+    TT wm = Ls > 0 ? (TT)r[at(Ls - 1)] / diag[at(Ls - 1)] : (TT)0;
+    TT rp = (TT)r[at(Ls + 1)], dp = diag[at(Ls + 1)];
+    TT tx0 = tx[at(Ls)], ty0 = ty[at(Ls)], tym0 = ty[at(Ls) - dym], tz0 = tz[at(Ls)], dt0 = dtil[at(Ls)];
+    TT ro = (TT)r[at(Ls) + dout], dq = diag[at(Ls) + dout];
     TT tzm = Ls > 0 ? tz[at(Ls - 1)] : (TT)0, tzm2 = (TT)0;
     TT txp = (TT)0, typ = (TT)0, tymp = (TT)0, rprev = (TT)0, dprev = (TT)0;
     TT em = (TT)0, em2 = (TT)0;
+    double xo = 0.0;
+    wb[Ls & 1][wv][lane] = w0;
+    __syncthreads();
     for (int L = Ls; L <= Le; ++L) {
         const bool hasb = L < nz;  // layer L exists (the step L = nz only forms red of nz - 1)
-        const int i = at(L);
-        // loads of layer L (own faces, y neighbours) and L + 1 (own column)
-        const TT rp = (TT)r[at(L + 1)], dp = diag[at(L + 1)];
-        const TT tx0 = tx[i], ty0 = ty[i], tym0 = ty[i - dym], tz0 = tz[i], dt0 = dtil[i];
-        const TT rym = (TT)r[i - dym], ryp = (TT)r[i + dyp], dym_ = diag[i - dym], dyp_ = diag[i + dyp];
-        const int lo = at(L - 1);
-        const double xo = (ASSIGN || L - 1 < z0) ? 0.0 : x[lo];
+        const int in1 = at(L + 1);
+        // loads for step L + 1
+        const TT rpn = (TT)r[at(L + 2)], dpn = diag[at(L + 2)];
+        const TT txn = tx[in1], tyn = ty[in1], tymn = ty[in1 - dym], tzn = tz[in1], dtn = dtil[in1];
+        const TT ron = (TT)r[in1 + dout], don = diag[in1 + dout];
+        const double xon = (ASSIGN || L < z0) ? 0.0 : x[at(L)];
         // black corrections of layer L (faces -x, +x, -y, +y, -z, +z)
+        const TT wp = rp / dp;
         TT e0 = (TT)0;
         {
-            const TT rxm = __shfl_up(r0, 1, 64), rxp = __shfl_down(r0, 1, 64);
-            const TT dxm = __shfl_up(d0, 1, 64), dxp = __shfl_down(d0, 1, 64);
+            const TT wxm = __shfl_up(w0, 1, 64), wxp = __shfl_down(w0, 1, 64);
             const TT txm = __shfl_up(tx0, 1, 64);
+            const TT wo = ro / dq;
+            const TT wym = top ? wo : wb[L & 1][wup][lane], wyp = bot ? wo : wb[L & 1][wdn][lane];
             const TT t[6] = {fxm ? txm : (TT)0, tx0, fym ? tym0 : (TT)0, fyp ? ty0 : (TT)0,
                              L > 0 ? tzm : (TT)0, L + 1 < nz ? tz0 : (TT)0};
-            const TT rl[6] = {rxm, rxp, rym, ryp, rm, rp};
-            const TT dl[6] = {dxm, dxp, dym_, dyp_, dm, dp};
+            const TT wl[6] = {wxm, wxp, wym, wyp, wm, wp};
             TT sb = r0;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) sb = t[q] != (TT)0 ? sb + t[q] * rl[q] / dl[q] : sb;
+            for (int q = 0; q < 6; ++q) sb = t[q] != (TT)0 ? sb + t[q] * wl[q] : sb;
             const bool black = ((xr + y + L) & 1) == 1;
             const bool on = hasb && black && dt0 > (TT)0;
             const TT v = sb / dt0;
             e0 = on ? v : (TT)0;
         }
         eb[L % 3][wv][lane] = e0;
+        wb[(L + 1) & 1][wv][lane] = wp;
         __syncthreads();
         // red corrections of layer L - 1, and the stores of layer L - 1
         const int Lr = L - 1;
         if (Lr >= z0 && Lr < z1) {
             const TT exm = __shfl_up(em, 1, 64), exp_ = __shfl_down(em, 1, 64);
-            const TT eym = eb[Lr % 3][wv > 0 ? wv - 1 : 0][lane], eyp = eb[Lr % 3][wv + 1 < kIluRows ? wv + 1 : wv][lane];
+            const TT eym = eb[Lr % 3][wup][lane], eyp = eb[Lr % 3][wdn][lane];
             const TT txm = __shfl_up(txp, 1, 64);
             const TT t[6] = {fxm ? txm : (TT)0, txp, fym ? tymp : (TT)0, fyp ? typ : (TT)0,
                              Lr > 0 ? tzm2 : (TT)0, Lr + 1 < nz ? tzm : (TT)0};
@@ -329,9 +348,9 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
             double xn;
             if (red) xn = dprev > (TT)0 ? (ASSIGN ? (double)(sr / dprev) : xo + (double)(sr / dprev)) : xo;
             else xn = ASSIGN ? (double)em : xo + (double)em;  // em = 0 where the pivot is not positive
-            if (inner && xin) x[lo] = xn;
+            if (inner && xin) x[at(Lr)] = xn;
         }
-        // slide: layer L becomes the previous one
+        // slide: layer L becomes the previous one, the prefetched layer the current
         em2 = em;
         em = e0;
         tzm2 = tzm;
@@ -341,10 +360,20 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
         tymp = tym0;
         rprev = r0;
         dprev = d0;
-        rm = r0;
-        dm = d0;
+        wm = w0;
+        w0 = wp;
         r0 = rp;
         d0 = dp;
+        rp = rpn;
+        dp = dpn;
+        tx0 = txn;
+        ty0 = tyn;
+        tym0 = tymn;
+        tz0 = tzn;
+        dt0 = dtn;
+        ro = ron;
+        dq = don;
+        xo = xon;
     }
 }
 
