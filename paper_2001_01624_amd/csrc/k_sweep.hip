@@ -67,7 +67,6 @@ __device__ constexpr int am_bit(int a) {
     return __builtin_popcount(AM & ((1 << a) - 1));
 }
 
-constexpr int kSweepRows = 4;  // rows (wavefronts) per workgroup
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -93,7 +92,16 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *p, long bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <int AM, typename PT>
+// Rows (wavefronts) per workgroup: the first and last row also load the row
+// beyond, so more rows mean fewer repeated loads but more LDS and registers
+// per workgroup.  Measured on the 60x220x85 model: FP32 is fastest with 8
+// rows, FP64 (two wavefronts per SIMD either way) with 4.
+template <typename PT>
+constexpr int sweep_rows() {
+    return sizeof(PT) == 8 ? 4 : 8;
+}
+
+template <int AM, typename PT, int kSweepRows = sweep_rows<PT>()>
 __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, const PT *__restrict__ tx,
                                                            const PT *__restrict__ ty, const PT *__restrict__ tz,
                                                            const PT *__restrict__ Pin, PT *__restrict__ Pout,
@@ -331,6 +339,7 @@ static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT
                           int check_blocks) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     // z chunks sized for about 4096 wavefronts
+    constexpr int kSweepRows = sweep_rows<PT>();
     const int nxt = cdiv(c.nx, 64), ngy = cdiv(c.ny, kSweepRows);
     const int rows = nxt * ngy * kSweepRows;
     int nzc = std::min(c.nz, std::max(1, cdiv(4096, rows)));
