@@ -298,41 +298,30 @@ void launch_coarse_inverse(Ctx &c, Stage &s) {
     }
 }
 
-// p_c = A_c^{-1} d: one wavefront per row (four rows per workgroup), d
-// staged in LDS when it fits; each lane adds its strided entries in order
-// (loads unrolled), then a fixed-order wave sum.  Row j is stored at
-// y[map[j]] when a map is given.
-constexpr int kGemvLds = 16384;  // doubles of d held in LDS
+// p_c = A_c^{-1} d: one workgroup per row.  Thread t adds the entries
+// t, t + 256, ... of the row in order (all loads of a thread issued together;
+// d is read through the caches), then a fixed-order workgroup sum.  Row j is
+// stored at y[map[j]] when a map is given.
+constexpr int kGemvThreads = 256;
 
-template <bool LDS>
-__global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, int M, int Mp, const double *__restrict__ d,
-                                              double *__restrict__ y, const int32_t *__restrict__ map,
-                                              const int *done) {
-    extern __shared__ double ds[];
+__global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict__ A, int M, int Mp,
+                                                       const double *__restrict__ d, double *__restrict__ y,
+                                                       const int32_t *__restrict__ map, const int *done) {
+    __shared__ double lds[kGemvThreads / 64];
     if (done && *done) return;
-    if (LDS) {
-        for (int k = threadIdx.x; k < M; k += blockDim.x) ds[k] = d[k];
-        __syncthreads();
-    }
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= M) return;
+    const int row = blockIdx.x;
     const double *a = A + (long)row * Mp;
     double s = 0.0;
-#pragma unroll 8
-    for (int k = lane; k < M; k += 64) s += a[k] * (LDS ? ds[k] : d[k]);
-    s = wave_sum(s);
-    if (lane == 0) y[map ? map[row] : row] = s;
+#pragma unroll 16
+    for (int k = threadIdx.x; k < M; k += kGemvThreads) s += a[k] * d[k];
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) y[map ? map[row] : row] = s;
 }
 
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done) {
     ProfScope ps(c, MSRSB_K_COARSE);
-    if (s.M <= kGemvLds)
-        hipLaunchKernelGGL(k_gemv<true>, dim3(cdiv(s.M, 4)), dim3(256), sizeof(double) * (size_t)s.M, c.stream,
-                           s.Ainv, s.M, s.Mp, s.dvec, s.pc, s.pc_map, done);
-    else
-        hipLaunchKernelGGL(k_gemv<false>, dim3(cdiv(s.M, 4)), dim3(256), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec,
-                           s.pc, s.pc_map, done);
+    hipLaunchKernelGGL(k_gemv, dim3(s.M), dim3(kGemvThreads), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec, s.pc, s.pc_map,
+                       done);
 }
 
 }  // namespace msrsb
