@@ -240,16 +240,18 @@ __global__ __launch_bounds__(kBlock) void k_ilu_red(Fine g, const TT *__restrict
 // most 62 cells).  A wavefront owns one row y with one halo lane on each side
 // (lane l is x = l - 1); a workgroup holds kIluInner rows plus the row above
 // and below, whose black corrections it computes for its own red cells.  The
-// workgroup walks the layers of its z chunk: step L forms the black
-// corrections of layer L (from r and the pivots of layers L-1..L+1) and the
-// red corrections of layer L-1 (from the black ones of layers L-2..L).  Each
-// cell's ratio w = r / a_ii is formed once and shared: x neighbours from
-// adjacent lanes, y neighbours through LDS (the outer neighbours of the two
-// halo rows from memory), z neighbours in registers.  The loads of layer L+1
-// (and of r, a_ii at L+2) are issued at the start of step L, one step ahead
-// of their use.  One barrier per step; x is read and written once.  The
-// arithmetic per cell and the face order are those of k_ilu_black /
-// k_ilu_red.
+// workgroup walks the layers of its z chunk, upward in even chunks and
+// downward in odd ones, so that two neighbouring chunks read the layers
+// around their common boundary at the same time (through the same L2).  Step
+// L forms the black corrections of layer L (from r and the pivots of layers
+// L-1..L+1) and the red corrections of the layer before it in the walk (from
+// the black ones around it).  Each cell's ratio w = r / a_ii is formed once
+// and shared: x neighbours from adjacent lanes, y neighbours through LDS (the
+// outer neighbours of the two halo rows from memory), z neighbours in
+// registers.  The loads of the next layer (and r, a_ii two layers ahead) are
+// issued one step ahead of their use.  One barrier per step; x is read and
+// written once.  The arithmetic per cell and the face order are those of
+// k_ilu_black / k_ilu_red.
 // 14 inner rows (1024 threads) measured fastest on the 60x220x85 model (6
 // and 10 were slower): the halo rows cost 2/16 of the loads.
 constexpr int kIluInner = 14, kIluRows = kIluInner + 2;
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
                                                            const TT *__restrict__ diag, const TT *__restrict__ dtil,
                                                            const double *__restrict__ r, double *__restrict__ x,
                                                            int ngy, int nzc, int zc, int nblk, const int *done) {
-    __shared__ TT eb[3][kIluRows][64];  // black corrections, by layer mod 3
-    __shared__ TT wb[2][kIluRows][64];  // w = r / a_ii, by layer mod 2
+    __shared__ TT eb[3][kIluRows][64];  // black corrections, by step mod 3
+    __shared__ TT wb[2][kIluRows][64];  // w = r / a_ii, by step mod 2
     if (done && *done) return;
     const int b = xcd_block();
     if (b >= nblk) return;
@@ -284,41 +286,60 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
     const int dout = top ? -dym : (bot ? dyp : 0);
     const int wup = wv > 0 ? wv - 1 : 0, wdn = wv + 1 < kIluRows ? wv + 1 : wv;
     auto at = [&](int L) { return col + nxy * min(max(L, 0), nz - 1); };
-
-    const int Ls = max(z0 - 1, 0), Le = z1;  // black layers Ls..min(z1, nz-1); red layers z0..z1-1
-    // registers: own column at L-1, L (w, r, a_ii), raw r, a_ii at L+1; faces
-    // of layer L and L-1; the halo row's outer r, a_ii at L
+    // walk: black layers from Ls to Le (a halo layer at each end that exists),
+    // red layers z0..z1-1; the last step only forms red
+    const int dir = (zk & 1) ? -1 : 1;
+    const int Ls = dir > 0 ? max(z0 - 1, 0) : min(z1, nz - 1);
+    const int nsteps = dir > 0 ? z1 - Ls + 1 : Ls - z0 + 2;
+    // tz of the face between layer L and L + dir (index of the lower layer)
+    auto fz = [&](int L) { return at(dir > 0 ? L : L - 1); };
+    // registers: own column at L - dir, L (w, r, a_ii), raw r, a_ii at L + dir;
+    // faces of layer L and of the previous layer; z faces ahead (fa), behind
+    // (fb) and behind the previous layer (fbb); the halo row's outer r, a_ii
     TT r0 = (TT)r[at(Ls)], d0 = diag[at(Ls)];
     TT w0 = r0 / d0;
-    TT wm = Ls > 0 ? (TT)r[at(Ls - 1)] / diag[at(Ls - 1)] : (TT)0;
-    TT rp = (TT)r[at(Ls + 1)], dp = diag[at(Ls + 1)];
-    TT tx0 = tx[at(Ls)], ty0 = ty[at(Ls)], tym0 = ty[at(Ls) - dym], tz0 = tz[at(Ls)], dt0 = dtil[at(Ls)];
-    TT ro = (TT)r[at(Ls) + dout], dq = diag[at(Ls) + dout];
-    TT tzm = Ls > 0 ? tz[at(Ls - 1)] : (TT)0, tzm2 = (TT)0;
+    const int Lb = Ls - dir;
+    const bool hasbeh = Lb >= 0 && Lb < nz;
+    TT wm = hasbeh ? (TT)r[at(Lb)] / diag[at(Lb)] : (TT)0;
+    TT rp = (TT)r[at(Ls + dir)], dp = diag[at(Ls + dir)];
+    TT tx0 = tx[at(Ls)], ty0 = ty[at(Ls)], tym0 = ty[at(Ls) - dym], dt0 = dtil[at(Ls)];
+    TT fa = tz[fz(Ls)], fb = hasbeh ? tz[fz(Lb)] : (TT)0, fbb = (TT)0;
+    TT ro = (TT)0, dq = (TT)1;
+    if (top || bot) {
+        ro = (TT)r[at(Ls) + dout];
+        dq = diag[at(Ls) + dout];
+    }
     TT txp = (TT)0, typ = (TT)0, tymp = (TT)0, rprev = (TT)0, dprev = (TT)0;
     TT em = (TT)0, em2 = (TT)0;
     double xo = 0.0;
-    wb[Ls & 1][wv][lane] = w0;
+    wb[0][wv][lane] = w0;
     __syncthreads();
-    for (int L = Ls; L <= Le; ++L) {
-        const bool hasb = L < nz;  // layer L exists (the step L = nz only forms red of nz - 1)
-        const int in1 = at(L + 1);
-        // loads for step L + 1
-        const TT rpn = (TT)r[at(L + 2)], dpn = diag[at(L + 2)];
-        const TT txn = tx[in1], tyn = ty[in1], tymn = ty[in1 - dym], tzn = tz[in1], dtn = dtil[in1];
-        const TT ron = (TT)r[in1 + dout], don = diag[in1 + dout];
-        const double xon = (ASSIGN || L < z0) ? 0.0 : x[at(L)];
+    for (int k = 0; k < nsteps; ++k) {
+        const int L = Ls + k * dir;
+        const bool hasb = L >= 0 && L < nz;  // the last step only forms red
+        const int in1 = at(L + dir);
+        // loads for the next step
+        const TT rpn = (TT)r[at(L + 2 * dir)], dpn = diag[at(L + 2 * dir)];
+        const TT txn = tx[in1], tyn = ty[in1], tymn = ty[in1 - dym], fan = tz[fz(L + dir)], dtn = dtil[in1];
+        TT ron = (TT)0, don = (TT)1;
+        if (top || bot) {  // wave-uniform: only the halo rows use the outer neighbour
+            ron = (TT)r[in1 + dout];
+            don = diag[in1 + dout];
+        }
+        const double xon = (ASSIGN || L < z0 || L >= z1) ? 0.0 : x[at(L)];
         // black corrections of layer L (faces -x, +x, -y, +y, -z, +z)
         const TT wp = rp / dp;
         TT e0 = (TT)0;
         {
             const TT wxm = __shfl_up(w0, 1, 64), wxp = __shfl_down(w0, 1, 64);
             const TT txm = __shfl_up(tx0, 1, 64);
-            const TT wo = ro / dq;
-            const TT wym = top ? wo : wb[L & 1][wup][lane], wyp = bot ? wo : wb[L & 1][wdn][lane];
+            const TT wo = (top || bot) ? ro / dq : (TT)0;
+            const TT wym = top ? wo : wb[k & 1][wup][lane], wyp = bot ? wo : wb[k & 1][wdn][lane];
+            const TT tzl = dir > 0 ? fb : fa, tzu = dir > 0 ? fa : fb;  // faces to L - 1, L + 1
+            const TT wzl = dir > 0 ? wm : wp, wzu = dir > 0 ? wp : wm;
             const TT t[6] = {fxm ? txm : (TT)0, tx0, fym ? tym0 : (TT)0, fyp ? ty0 : (TT)0,
-                             L > 0 ? tzm : (TT)0, L + 1 < nz ? tz0 : (TT)0};
-            const TT wl[6] = {wxm, wxp, wym, wyp, wm, wp};
+                             L > 0 ? tzl : (TT)0, L + 1 < nz ? tzu : (TT)0};
+            const TT wl[6] = {wxm, wxp, wym, wyp, wzl, wzu};
             TT sb = r0;
 #pragma unroll
             for (int q = 0; q < 6; ++q) sb = t[q] != (TT)0 ? sb + t[q] * wl[q] : sb;
@@ -327,18 +348,22 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
             const TT v = sb / dt0;
             e0 = on ? v : (TT)0;
         }
-        eb[L % 3][wv][lane] = e0;
-        wb[(L + 1) & 1][wv][lane] = wp;
+        eb[k % 3][wv][lane] = e0;
+        wb[(k + 1) & 1][wv][lane] = wp;
         __syncthreads();
-        // red corrections of layer L - 1, and the stores of layer L - 1
-        const int Lr = L - 1;
-        if (Lr >= z0 && Lr < z1) {
+        // red corrections of the previous layer Lr = L - dir, and its stores
+        const int Lr = L - dir;
+        if (k > 0 && Lr >= z0 && Lr < z1) {
+            const int kr = (k + 2) % 3;  // slot of step k - 1
             const TT exm = __shfl_up(em, 1, 64), exp_ = __shfl_down(em, 1, 64);
-            const TT eym = eb[Lr % 3][wup][lane], eyp = eb[Lr % 3][wdn][lane];
+            const TT eym = eb[kr][wup][lane], eyp = eb[kr][wdn][lane];
             const TT txm = __shfl_up(txp, 1, 64);
+            // faces of Lr: toward L is fb, away from L is fbb
+            const TT tzl = dir > 0 ? fbb : fb, tzu = dir > 0 ? fb : fbb;
             const TT t[6] = {fxm ? txm : (TT)0, txp, fym ? tymp : (TT)0, fyp ? typ : (TT)0,
-                             Lr > 0 ? tzm2 : (TT)0, Lr + 1 < nz ? tzm : (TT)0};
-            const TT el[6] = {exm, exp_, eym, eyp, em2, e0};
+                             Lr > 0 ? tzl : (TT)0, Lr + 1 < nz ? tzu : (TT)0};
+            const TT ezl = dir > 0 ? em2 : e0, ezu = dir > 0 ? e0 : em2;
+            const TT el[6] = {exm, exp_, eym, eyp, ezl, ezu};
             TT sr = rprev;
             const bool red = ((xr + y + Lr) & 1) == 0;
             if (red) {
@@ -353,8 +378,9 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
         // slide: layer L becomes the previous one, the prefetched layer the current
         em2 = em;
         em = e0;
-        tzm2 = tzm;
-        tzm = tz0;
+        fbb = fb;
+        fb = fa;
+        fa = fan;
         txp = tx0;
         typ = ty0;
         tymp = tym0;
@@ -369,7 +395,6 @@ __global__ __launch_bounds__(64 * kIluRows) void k_ilu_zm(Fine g, const TT *__re
         tx0 = txn;
         ty0 = tyn;
         tym0 = tymn;
-        tz0 = tzn;
         dt0 = dtn;
         ro = ron;
         dq = don;
