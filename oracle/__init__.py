@@ -17,6 +17,7 @@ from .msrsb import (  # noqa: F401
     jacobi_correction,
     ilu0_factor,
     ilu0_apply,
+    ilu0_rb_fill,
     red_black_order,
     natural_order,
     dynamic_partition,

@@ -400,6 +400,27 @@ def ilu0_factor(A, order):
     return L, U, np.asarray(order)
 
 
+def ilu0_rb_fill(A, cells, dims):
+    """The fill that red-black ILU(0) drops: for the order of
+    ``red_black_order`` (even i+j+k first), ``L U - A`` is zero except on the
+    black (odd) rows and columns, where it is the off-diagonal part of
+    ``A_br D_rr^-1 A_rb``.  No two cells of one colour share a face, so the
+    red rows are eliminated without fill and each black pivot keeps only the
+    diagonal of its Schur complement.  Returned in the original (active)
+    numbering; ``A + F`` is the matrix whose inverse the smoother applies."""
+    ix, iy, iz = _coords(dims)
+    black = ((ix + iy + iz)[cells] % 2) == 1
+    bi, ri = np.nonzero(black)[0], np.nonzero(~black)[0]
+    Acsr = A.tocsr()
+    d_r = Acsr.diagonal()[ri]
+    S = (Acsr[bi][:, ri] @ sp.diags(1.0 / d_r) @ Acsr[ri][:, bi]).tocsr()
+    S.setdiag(0.0)
+    S.eliminate_zeros()
+    S = S.tocoo()
+    n = A.shape[0]
+    return sp.csr_matrix((S.data, (bi[S.row], bi[S.col])), shape=(n, n))
+
+
 def ilu0_apply(fac, r):
     """``(L U)^{-1} r`` in the original numbering."""
     L, U, order = fac

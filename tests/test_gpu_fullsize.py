@@ -1,0 +1,208 @@
+"""GPU parity at full size.
+
+Two models of 60x220x85 cells: the layered five-spot model in the launch
+configuration the benchmark times (general stages 10x10x5 and 6x22x17,
+red-black ILU(0), GMRES(30), FP64), and the faulted model of the same size
+with 5 % inactive cells in mixed precision (a Cartesian and a fault-cut
+stage, dynamic stages from two pressure increments).
+
+At this size the oracle is cheap for the structure and for single steps, so
+those are compared entry by entry: partitions and supports (bit-exact), one
+restricted-smoothing sweep applied to the GPU's own basis after the
+benchmark's sweeps, the Galerkin product of that basis, the dynamic
+partitions and their coarse operators, face fluxes.  The rest is checked
+through properties that hold at any size: partition of unity and zero basis
+outside the support, the smoother's defining equation (A + F) e = r with F
+the fill that red-black ILU(0) drops, and the true FP64 residual of every
+solve under the oracle's TPFA operator, with mass balance of the fluxes.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import bench
+import oracle as O
+from oracle.msrsb import rhs_for
+from workloads import make_config2, pressure_increment_pair, rng_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def capi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_01624_amd import capi as c
+    return c
+
+
+@pytest.fixture(scope="module")
+def layered(capi):
+    prob, sources = bench.workload()
+    parts = [{"kind": "cartesian", "coarse_dims": cd} for cd in bench.STAGES]
+    say(f"full-size layered model {prob.dims}, stages {bench.STAGES}, FP64, ilu0_rb, GMRES(30)")
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=30, precision="fp64")
+    g = capi.Solver(prob, parts, opt)
+    o = O.Oracle(prob, parts, smoother="jacobi")  # partitions, supports, operator
+    return prob, sources, parts, g, o
+
+
+def basis_matrix(e, cells, N):
+    """n_active x M sparse basis (or support pattern when values are absent)
+    from an exported stage; checks that no slot of an inactive cell is set."""
+    loc = np.full(N, -1)
+    loc[cells] = np.arange(cells.size)
+    rows, cols, vals = [], [], []
+    for s in range(e["n_slots"]):
+        blk = e["slot_block"][s]
+        on = blk >= 0
+        r = loc[np.nonzero(on)[0]]
+        assert np.all(r >= 0), "slot set on an inactive cell"
+        rows.append(r)
+        cols.append(blk[on])
+        vals.append(e["values"][s][on] if "values" in e else np.ones(int(on.sum())))
+    r, c, v = (np.concatenate(a) for a in (rows, cols, vals))
+    return sp.csr_matrix((v, (r, c)), shape=(cells.size, e["M"]))
+
+
+def test_full_structure(capi, layered):
+    prob, _, parts, g, o = layered
+    for k, st in enumerate(o.stages):
+        e = g.export_stage(k, values=False, coarse=False)
+        say(f"stage {k}: M gpu {e['M']} oracle {st.M}")
+        assert e["M"] == st.M
+        assert np.array_equal(e["block"], st.block)
+        pat = basis_matrix(e, o.cells, prob.n_cells)
+        assert (pat != st.S).nnz == 0
+
+
+def test_full_sweeps_and_galerkin(capi, layered):
+    prob, _, parts, g, o = layered
+    for k, st in enumerate(o.stages):
+        sweeps, change = g.update_basis(k, 100, 1e-3)
+        e = g.export_stage(k, coarse=False)
+        P = basis_matrix(e, o.cells, prob.n_cells)
+        # exact zeros outside the support; partition of unity
+        assert np.all(e["values"][e["slot_block"] < 0] == 0.0)
+        rs = np.asarray(P.sum(axis=1)).ravel()
+        say(f"stage {k}: {sweeps} sweeps, last change {change:.2e}, max |rowsum - 1| {np.abs(rs - 1).max():.2e}")
+        assert np.abs(rs - 1.0).max() <= 1e-12
+        # one more sweep of the GPU's basis, on the GPU and by the oracle
+        g.update_basis(k, 1, 0.0, warm=True)
+        e2 = g.export_stage(k)
+        P2 = basis_matrix(e2, o.cells, prob.n_cells)
+        Po, _, _ = O.msrsb_basis(o.Ab, st.block[o.cells], st.S, tol=0.0, max_sweeps=1, P0=P)
+        err = abs(P2 - Po).max()
+        say(f"stage {k}: one sweep, max entry difference {err:.2e}")
+        assert err <= 1e-12
+        Aco = O.galerkin(P2, o.A)
+        assert np.abs(e2["Ac"] - e2["Ac"].T).max() == 0.0
+        assert relerr(e2["Ac"], Aco) <= 1e-12
+
+
+def test_full_smoother_equation(capi, layered):
+    prob, _, parts, g, o = layered
+    F = O.ilu0_rb_fill(o.A, o.cells, prob.dims)
+    r = np.zeros(prob.n_cells)
+    r[o.cells] = np.random.default_rng(5).standard_normal(o.cells.size)
+    e = host(g.apply(capi.OP_SMOOTH, dev(r)))[o.cells]
+    res = (o.A + F) @ e - r[o.cells]
+    scale = abs(o.A).max() * np.abs(e).max()
+    say(f"smoother: max |(A + F) e - r| / (|A| |e|) = {np.abs(res).max() / scale:.2e}")
+    assert np.abs(res).max() <= 1e-13 * scale
+
+
+def test_full_request(capi, layered):
+    """The benchmark's request: two solves, a dynamic stage from their
+    difference, a third solve; every solve meets 1e-6 on the true residual."""
+    prob, sources, parts, g, o = layered
+    g.update_basis(-1, 100, 1e-3)
+    xs = []
+    x = dev(np.zeros(prob.n_cells))
+    for k, q in enumerate(sources):
+        if k == 2:
+            dp = host(xs[1]) - host(xs[0])
+            counts = g.add_dynamic_basis([dev(dp)])
+            oc = o.add_dynamic_basis([dp])
+            assert counts == oc
+            ed = g.export_stage(len(parts))
+            assert ed["kind"] == 3 and np.array_equal(ed["block"], o.dyn[0].block)
+            assert relerr(ed["Ac"], o.dyn[0].Ac) <= 1e-12
+        x = x.clone()
+        it, rel, rc = g.solve(x, source=dev(q), rtol=1e-6, max_iters=3000)
+        assert rc == capi.OK
+        xh = host(x)
+        bq = rhs_for(prob, o.cells, q)
+        true = np.linalg.norm(bq - o.A @ xh[o.cells]) / np.linalg.norm(bq)
+        say(f"solve {k}: {it} iterations, reported {rel:.2e}, true {true:.2e}")
+        assert true <= 1.0001e-6
+        xs.append(x)
+    face, bcf = g.fluxes(xs[-1])
+    fo, bo = o.fluxes(host(xs[-1]))
+    assert relerr(host(face), fo) <= 1e-12 and relerr(host(bcf), bo) <= 1e-12
+    q = sources[-1]
+    assert abs(q.sum() - host(bcf).sum()) <= 1e-5 * np.abs(q).sum()
+
+
+def test_full_faulted_mixed(capi):
+    prob = make_config2()
+    parts = [{"kind": "cartesian", "coarse_dims": (10, 10, 5)}, {"kind": "fault_cut", "parent": 0}]
+    say(f"full-size faulted model {prob.dims}, {int(prob.active.sum())} active cells, mixed precision")
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=30, precision="mixed")
+    g = capi.Solver(prob, parts, opt)
+    o = O.Oracle(prob, parts, smoother="jacobi")
+    for k, st in enumerate(o.stages):
+        e = g.export_stage(k, values=False, coarse=False)
+        assert e["M"] == st.M and np.array_equal(e["block"], st.block)
+        assert (basis_matrix(e, o.cells, prob.n_cells) != st.S).nnz == 0
+    g.update_basis(-1, 100, 1e-3)
+    for k in range(len(parts)):
+        e = g.export_stage(k, coarse=False)
+        P = basis_matrix(e, o.cells, prob.n_cells)
+        assert np.all(e["values"][e["slot_block"] < 0] == 0.0)
+        # rounding each entry to BF16 (nearest, 8-bit significand) moves it by
+        # at most 2^-8 of itself; the FP32 rows sum to one within 1e-6
+        rs = np.asarray(P.sum(axis=1)).ravel()
+        ra = np.asarray(abs(P).sum(axis=1)).ravel()
+        say(f"stage {k}: BF16 basis, max |rowsum - 1| {np.abs(rs - 1).max():.2e}, max sum|P| {ra.max():.3f}")
+        assert np.all(np.abs(rs - 1.0) <= 2.0 ** -8 * ra + 1e-6)
+        v = P.data[P.data != 0].astype(np.float32).view(np.uint32)
+        assert np.all(v & 0xFFFF == 0)
+    x = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(x, rtol=1e-6, max_iters=3000)
+    assert rc == capi.OK
+    true = np.linalg.norm(o.residual(host(x))) / np.linalg.norm(o.b)
+    say(f"mixed solve: {it} iterations, true relres {true:.2e}")
+    assert true <= 1.0001e-6
+    dps = pressure_increment_pair(prob, rng_for(8, 1))
+    counts = g.add_dynamic_basis([dev(d) for d in dps])
+    oc = o.add_dynamic_basis(dps)
+    assert counts == oc
+    for k in range(len(o.dyn)):
+        ed = g.export_stage(len(parts) + k)
+        assert ed["kind"] == 3 and np.array_equal(ed["block"], o.dyn[k].block)
+        assert relerr(ed["Ac"], o.dyn[k].Ac) <= 1e-12
+    x2 = dev(np.zeros(prob.n_cells))
+    it2, rel2, rc2 = g.solve(x2, rtol=1e-6, max_iters=3000)
+    assert rc2 == capi.OK
+    true2 = np.linalg.norm(o.residual(host(x2))) / np.linalg.norm(o.b)
+    say(f"mixed solve with dynamic stages: {it2} iterations, true relres {true2:.2e}")
+    assert true2 <= 1.0001e-6

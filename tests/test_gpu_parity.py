@@ -378,7 +378,7 @@ def test_fault_cut_gmres_converges(capi):
 
 # ------------------------------------------------------- mixed precision ----
 # Stated per-result bounds against the FP64 oracle: basis entries within
-# 2^-8 |P| + 2e-5 (BF16 rounding of the stored basis, 2^-9 relative, plus the
+# 2^-8 |P| + 2e-5 (BF16 rounding of the stored basis, at most 2^-8 relative, plus the
 # drift of FP32 sweeps); coarse operators within 1e-2 relative to their
 # largest entry; solves reach the same FP64 relative residual.
 

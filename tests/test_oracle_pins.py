@@ -15,7 +15,7 @@ import scipy.sparse.linalg as spla
 
 import oracle as O
 from oracle.msrsb import support_1d, rhs_for
-from workloads import Problem, make_config0, make_config1, make_homogeneous, make_lognormal_box, rng_for
+from workloads import Problem, make_config0, make_config1, make_config2, make_homogeneous, make_lognormal_box, rng_for
 from workloads.grids import face_transmissibility, half_transmissibility
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -336,6 +336,29 @@ def test_ilu0_matches_matrix_on_its_pattern(order):
     LU = (L @ U).toarray()
     np.testing.assert_allclose(LU[B.row, B.col], B.data, rtol=1e-13, atol=1e-13)
     assert np.all(np.diag(U.toarray()) > 0)
+
+
+@pytest.mark.parametrize("case", ["box", "inactive"])
+def test_ilu0_rb_fill_is_lu_minus_a(case):
+    # Red-black ILU(0) differs from A exactly by the dropped black-black fill:
+    # the textbook factor (itself pinned by its defining property above) must
+    # satisfy L U - A = F entry by entry, so (A + F) e = r for e = ilu0_apply(r).
+    if case == "box":
+        prob = make_lognormal_box((7, 5, 4), rng_for(9, 6), sigma=1.5)
+    else:
+        prob = make_config2(dims=(8, 9, 5), seed=3)
+    A, b, _, cells = O.assemble(prob)
+    perm = O.red_black_order(cells, prob.dims)
+    L, U, p = O.ilu0_factor(A, perm)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(p.size)
+    LU = (L @ U).tocsr()[inv][:, inv]
+    F = O.ilu0_rb_fill(A, cells, prob.dims)
+    assert abs(LU - A - F).max() <= 1e-13 * abs(A).max()
+    assert F.nnz > 0
+    r = np.random.default_rng(2).standard_normal(A.shape[0])
+    e = O.ilu0_apply((L, U, p), r)
+    np.testing.assert_allclose((A + F) @ e, r, atol=1e-12 * np.abs(r).max())
 
 
 def test_red_black_order_colours():
