@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kernel", default="sweep", help="kernel class for the roofline object")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="profiling aid: run only the mixed-precision request and print its record")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -297,6 +299,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X", file=sys.stderr)
         sys.exit(1)
+    if args.mixed_only:
+        rec = gpu_leg(args, "mixed")
+        print(json.dumps({"leg": "mixed", "metric": METRIC, "value": rec["value"], "unit": "cells/s",
+                          "ms_per_step": rec["ms_per_step"], "iters": rec["iters"], "max_relres": rec["relres"],
+                          "roofline": rec["roofline"]}))
+        return
     f64 = gpu_leg(args, "fp64")
     mixed = None if args.no_mixed else gpu_leg(args, "mixed")
     served = None if args.no_serve else serve_leg(args)
