@@ -2,6 +2,7 @@
 // partitions (integer tables, built once on the host and uploaded), the
 // solver drivers and every extern "C" entry point of msrsb.h.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -29,15 +30,66 @@ int hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? MSRSB_E_NOMEM : MSRSB_E_DEVICE;
 }
 
+// Device memory comes from the device's stream-ordered pool, allocated and
+// freed in the order of the context's stream: contexts created and destroyed
+// while others run on their own streams never synchronise the device.  The
+// pool keeps freed memory for reuse (release threshold raised once per
+// device), so a served request does not return memory to the driver.
+static void keep_pool_memory(int device) {
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (std::find(done.begin(), done.end(), device) != done.end()) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done.push_back(device);
+}
+
 void *ctx_alloc(Ctx &c, size_t bytes) {
     void *p = nullptr;
     if (bytes == 0) bytes = 8;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        set_error("hipMalloc of %zu bytes failed", bytes);
+    keep_pool_memory(c.device);
+    if (hipMallocAsync(&p, bytes, c.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed", bytes);
         return nullptr;
     }
     c.allocs.push_back(p);
     return p;
+}
+
+// Host -> device copy on the context's stream (the caller keeps the host
+// buffer alive until the stream is synchronised).
+static bool upload(Ctx &c, void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream) == hipSuccess;
+}
+
+// Pinned status mirrors are recycled: freeing pinned memory can wait for the
+// whole device.
+static std::mutex g_pinned_mu;
+static std::vector<Status *> g_pinned_free;
+
+static Status *pinned_status() {
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            Status *p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    Status *p = nullptr;
+    if (hipHostMalloc((void **)&p, sizeof(Status), 0) != hipSuccess) return nullptr;
+    return p;
+}
+
+static void release_pinned_status(Status *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_pinned_free.push_back(p);
 }
 
 // ------------------------------------------------------------ validation ----
@@ -250,7 +302,7 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     s.h_tab = tab;
     s.d_tab = (int32_t *)ctx_alloc(c, sizeof(int32_t) * tab.size());
     if (!s.d_tab) return MSRSB_E_NOMEM;
-    if (hipMemcpy(s.d_tab, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (!upload(c, s.d_tab, s.h_tab.data(), sizeof(int32_t) * tab.size()))
         return hip_fail(hipGetLastError(), "upload tables");
     for (int a = 0; a < 3; ++a) {
         cd.lo[a] = s.d_tab + s.tab_off[a][0];
@@ -282,7 +334,8 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     const size_t npc = std::max((size_t)s.Mp, (size_t)cd.m[0] * cd.m[1] * cd.m[2]);
     s.pc = (double *)ctx_alloc(c, sizeof(double) * npc);
     if (!s.Ac || !s.Ainv || !s.dvec || !s.pc) return MSRSB_E_NOMEM;
-    if (hipMemset(s.pc, 0, sizeof(double) * npc) != hipSuccess) return hip_fail(hipGetLastError(), "clear p_c");
+    if (hipMemsetAsync(s.pc, 0, sizeof(double) * npc, c.stream) != hipSuccess)
+        return hip_fail(hipGetLastError(), "clear p_c");
     s.pc_map = cd.present;
     if (c.nx > 64 * 4) {
         set_error("rows longer than 256 cells are not supported by the restriction kernel");
@@ -431,13 +484,14 @@ static int build_fault_stage(Ctx &c, const msrsb_partition &p, int index, Stage 
         }
     auto upi = [&](int32_t *&dst, const std::vector<int32_t> &h) -> bool {
         dst = (int32_t *)ctx_alloc(c, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
-        return dst && hipMemcpy(dst, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice) == hipSuccess;
+        return dst && upload(c, dst, h.data(), sizeof(int32_t) * h.size());
     };
     if (!upi(s.xsb, s.h_xsb) || !upi(s.xpblock, s.h_xpblock) || !upi(s.xptr, cnt) || !upi(s.xcell, cell))
         return MSRSB_E_NOMEM;
     s.xslot = (uint8_t *)ctx_alloc(c, std::max<size_t>(slot.size(), 1));
-    if (!s.xslot || hipMemcpy(s.xslot, slot.data(), slot.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return MSRSB_E_NOMEM;
+    if (!s.xslot || !upload(c, s.xslot, slot.data(), slot.size())) return MSRSB_E_NOMEM;
+    // the host tables above are local: wait for their copies
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return hip_fail(hipGetLastError(), "upload fault tables");
     const size_t nsN = (size_t)ns * N;
     if (c.opt.precision == MSRSB_MIXED) {
         s.P32[0] = (float *)ctx_alloc(c, sizeof(float) * nsN);
@@ -798,12 +852,13 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     };
     auto up = [&](double *&dst, const double *h) -> bool {
         dst = (double *)ctx_alloc(*c, sizeof(double) * N);
-        return dst && hipMemcpy(dst, h, sizeof(double) * N, hipMemcpyHostToDevice) == hipSuccess;
+        return dst && upload(*c, dst, h, sizeof(double) * N);
     };
     auto up32 = [&](float *&dst, const double *h) -> bool {
         for (int i = 0; i < N; ++i) t32[i] = (float)h[i];
         dst = (float *)ctx_alloc(*c, sizeof(float) * N);
-        return dst && hipMemcpy(dst, t32.data(), sizeof(float) * N, hipMemcpyHostToDevice) == hipSuccess;
+        // t32 is reused for every array: wait for each copy
+        return dst && upload(*c, dst, t32.data(), sizeof(float) * N) && hipStreamSynchronize(c->stream) == hipSuccess;
     };
     if (!up(c->tx, g->tx) || !up(c->ty, g->ty) || !up(c->tz, g->tz) || !up(c->bcdiag, bcd.data()) ||
         !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !up32(c->tx32, g->tx) || !up32(c->ty32, g->ty) ||
@@ -832,22 +887,23 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     if (!c->diag || !c->b || !c->dtil || !c->dtil32 || !c->diag32 || !c->r || !c->e || !c->tmp || !c->z || !c->u ||
         !c->partial || !c->scal || !c->status || !c->maxbits || !c->flag)
         return fail(MSRSB_E_NOMEM);
-    if (hipHostMalloc((void **)&c->h_status, sizeof(Status), 0) != hipSuccess) return fail(MSRSB_E_NOMEM);
+    if (!(c->h_status = pinned_status())) return fail(MSRSB_E_NOMEM);
     if (g->n_bc > 0) {
         c->bc_cell = (int32_t *)alloc(4 * (size_t)g->n_bc);
         c->bc_trans = (double *)alloc(8 * (size_t)g->n_bc);
         c->bc_value = (double *)alloc(8 * (size_t)g->n_bc);
         if (!c->bc_cell || !c->bc_trans || !c->bc_value) return fail(MSRSB_E_NOMEM);
-        hipMemcpy(c->bc_cell, g->bc_cell, 4 * (size_t)g->n_bc, hipMemcpyHostToDevice);
-        hipMemcpy(c->bc_trans, g->bc_trans, 8 * (size_t)g->n_bc, hipMemcpyHostToDevice);
-        hipMemcpy(c->bc_value, g->bc_value, 8 * (size_t)g->n_bc, hipMemcpyHostToDevice);
+        upload(*c, c->bc_cell, g->bc_cell, 4 * (size_t)g->n_bc);
+        upload(*c, c->bc_trans, g->bc_trans, 8 * (size_t)g->n_bc);
+        upload(*c, c->bc_value, g->bc_value, 8 * (size_t)g->n_bc);
     }
     if (o.outer == MSRSB_GMRES) {
         if (fp32_basis(o)) {
             c->V = (double *)alloc(8 * 2 * (size_t)N);
             c->Vf = (float *)alloc(4 * (size_t)o.restart * N);
             if (!c->V || !c->Vf) return fail(MSRSB_E_NOMEM);
-            if (hipMemset(c->Vf, 0, 4 * (size_t)o.restart * N) != hipSuccess) return fail(MSRSB_E_DEVICE);
+            if (hipMemsetAsync(c->Vf, 0, 4 * (size_t)o.restart * N, c->stream) != hipSuccess)
+                return fail(MSRSB_E_DEVICE);
         } else {
             c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
             if (!c->V) return fail(MSRSB_E_NOMEM);
@@ -1085,14 +1141,16 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
             if (!dv) return MSRSB_E_NOMEM;
             launch_export_cart(*c, *s, dv);
             e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess) e = hipMemcpy(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost);
-            hipFree(dv);
+            if (e == hipSuccess) e = hipMemcpyAsync(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            hipFreeAsync(dv, c->stream);
             c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
             if (e != hipSuccess) return hip_fail(e, "export");
         }
     } else if (s->kind == 3) {
         std::vector<int32_t> blk(N);
-        e = hipMemcpy(blk.data(), s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(blk.data(), s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_fail(e, "export");
         if (h_block) memcpy(h_block, blk.data(), 4 * (size_t)N);
         if (h_slot_block) memcpy(h_slot_block, blk.data(), 4 * (size_t)N);
@@ -1130,8 +1188,9 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
             if (!dv) return MSRSB_E_NOMEM;
             launch_export_cart(*c, *s, dv);
             e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess) e = hipMemcpy(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost);
-            hipFree(dv);
+            if (e == hipSuccess) e = hipMemcpyAsync(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            hipFreeAsync(dv, c->stream);
             c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
             if (e != hipSuccess) return hip_fail(e, "export");
         }
@@ -1184,17 +1243,19 @@ int msrsb_profile_end(msrsb_ctx *c, double *total_ms, int *launches) {
 
 int msrsb_set_stream(msrsb_ctx *c, void *hip_stream) {
     if (!c) return MSRSB_E_INVAL;
+    // work and pool allocations of the old stream complete before the switch
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "set stream");
     c->stream = (hipStream_t)hip_stream;
     return MSRSB_OK;
 }
 
 void msrsb_destroy(msrsb_ctx *c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
-    for (void *p : c->allocs) hipFree(p);
+    hipStreamSynchronize(c->stream);
+    for (void *p : c->allocs) hipFreeAsync(p, c->stream);
     for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
-    if (c->h_status) hipHostFree(c->h_status);
+    release_pinned_status(c->h_status);
     delete c;
 }
 
