@@ -39,7 +39,7 @@ def request_footprint(req, options) -> int:
 
 
 class Server:
-    def __init__(self, slots=4, hbm_budget=64 << 30, options=None, rtol=1e-6, max_iters=3000, max_sweeps=100,
+    def __init__(self, slots=8, hbm_budget=64 << 30, options=None, rtol=1e-6, max_iters=3000, max_sweeps=100,
                  basis_tol=1e-3, keep_solutions=False, dynamic=True):
         import torch
 
