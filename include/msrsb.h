@@ -124,8 +124,11 @@ size_t msrsb_footprint_bytes(const msrsb_grid *grid, int n_part, const msrsb_par
 /*
  * Validate the grid, assemble A and b on the device (two-point operator, see
  * msrsb_grid), build every partition and support, and factor the smoother.
- * hip_stream: a hipStream_t (NULL = null stream).  On success *out owns all
- * device memory of the context.  Errors: E_INVAL (bad sizes, non-finite or
+ * hip_stream: a hipStream_t (NULL = null stream); every device operation of
+ * the context, its allocations included (stream-ordered, from the device's
+ * default memory pool), runs on that stream, and msrsb_setup returns after
+ * synchronising it alone.  On success *out owns all device memory of the
+ * context.  Errors: E_INVAL (bad sizes, non-finite or
  * negative T, a face touching an inactive cell or leaving the box, a BC on
  * an inactive cell), E_SINGULAR (an active connected component without any
  * bc connection), E_NOMEM, E_DEVICE.
@@ -254,10 +257,14 @@ enum {
 int msrsb_profile_begin(msrsb_ctx *ctx, int kernel_class, int max_launches);
 int msrsb_profile_end(msrsb_ctx *ctx, double *total_ms, int *launches);
 
-/* Change the stream used by later calls (hipStream_t). */
+/* Change the stream used by later calls (hipStream_t).  The current stream
+ * is synchronised first (its work and stream-ordered allocations complete).
+ * Errors: E_INVAL (NULL ctx), E_DEVICE. */
 int msrsb_set_stream(msrsb_ctx *ctx, void *hip_stream);
 
-/* Free all device memory of the context (NULL is ignored). */
+/* Synchronise the context's stream and return all its device memory to the
+ * device's memory pool, in the stream's order (no device-wide
+ * synchronisation; NULL is ignored). */
 void msrsb_destroy(msrsb_ctx *ctx);
 
 /* Message of the last failing call on this thread ("" if none). */
