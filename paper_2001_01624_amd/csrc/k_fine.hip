@@ -114,10 +114,48 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
     }
 }
 
+// r = b - A x with one wavefront per grid row (y, z) of at most 64 cells,
+// lanes along x: no index division, the x neighbours (and tx of the cell
+// before) from the adjacent lanes, every load issued before the skip flag is
+// read.  Faces follow cell_faces (boundary faces carry T = 0 in the data), so
+// a lane at a row end may take its own x with the zero coefficient: the
+// operations and their order are those of residual_cell, bit for bit.
+constexpr int kResRows = 4;  // rows (wavefronts) per workgroup
+
+__global__ __launch_bounds__(64 * kResRows) void k_residual_rows(Fine g, const double *__restrict__ b,
+                                                                 const double *__restrict__ x,
+                                                                 double *__restrict__ r, const int *done) {
+    const int row = xcd_block() * kResRows + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (row >= g.ny * g.nz) return;
+    const int lane = threadIdx.x & 63;
+    const int xx = min(lane, g.nx - 1);  // lanes past the row load its last cell and store nothing
+    const int i = row * g.nx + xx;
+    const bool dny = i >= g.nx, upy = i + g.nx < g.N, dnz = i >= g.nxy, upz = i + g.nxy < g.N;
+    const double d = g.diag[i], bi = b[i], xi = x[i];
+    const double txi = g.tx[i], tyi = g.ty[i], tzi = g.tz[i];
+    const double tym = g.ty[dny ? i - g.nx : i], tzm = g.tz[dnz ? i - g.nxy : i];
+    const double xym = x[dny ? i - g.nx : i], xyp = x[upy ? i + g.nx : i];
+    const double xzm = x[dnz ? i - g.nxy : i], xzp = x[upz ? i + g.nxy : i];
+    if (done && *done) return;
+    const double txm = __shfl_up(txi, 1, 64), xxm = __shfl_up(xi, 1, 64), xxp = __shfl_down(xi, 1, 64);
+    const double t[6] = {xx > 0 ? txm : 0.0, txi, dny ? tym : 0.0, upy ? tyi : 0.0, dnz ? tzm : 0.0,
+                         upz ? tzi : 0.0};
+    const double xl[6] = {xx > 0 ? xxm : xi, xx + 1 < g.nx ? xxp : xi, xym, xyp, xzm, xzp};
+    double s = d * xi;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s -= t[q] * xl[q];
+    if (lane < g.nx) r[i] = d > 0.0 ? bi - s : 0.0;
+}
+
 void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done) {
     ProfScope ps(c, MSRSB_K_RESIDUAL);
     Fine g = fine_of(c);
     const int grid = red_grid(c.N);
+    if (!norm && c.nx <= 64) {
+        hipLaunchKernelGGL(k_residual_rows, dim3(xcd_grid(cdiv(c.ny * c.nz, kResRows))), dim3(64 * kResRows), 0,
+                           c.stream, g, b, x, r, done);
+        return;
+    }
     if (norm)
         hipLaunchKernelGGL(k_residual<true>, dim3(grid), dim3(kBlock), 0, c.stream, g, b, x, r, c.partial, done);
     else
