@@ -45,6 +45,14 @@ CASES = {
     "layered": (lambda: make_config1(dims=(20, 36, 14), seed=1), (4, 3, 2)),
     "faulted_inactive": (lambda: make_config2(dims=(18, 30, 12), seed=2), (3, 3, 2)),
     "line1d": (lambda: make_lognormal_box((33, 1, 1), rng_for(7, 2), sigma=1.0), (5, 1, 1)),
+    # row lengths around the kernels' layout limits: 62 (widest fused ILU
+    # row), 64 (one full wavefront), 70 and 130 (two and three 64-cell runs
+    # per row: several x tiles in the sweep, chunked rows in the transfer
+    # kernels, the general residual and two-pass ILU)
+    "edge62": (lambda: make_lognormal_box((62, 7, 6), rng_for(7, 3), sigma=1.5, corr=(4, 2, 1)), (4, 2, 2)),
+    "edge64": (lambda: make_lognormal_box((64, 5, 4), rng_for(7, 4), sigma=1.5, corr=(4, 2, 1)), (5, 2, 1)),
+    "wide": (lambda: make_lognormal_box((70, 9, 5), rng_for(7, 5), sigma=1.5, corr=(3, 2, 1)), (5, 2, 2)),
+    "wider": (lambda: make_config2(dims=(130, 6, 4), seed=4), (9, 2, 2)),
 }
 
 
@@ -77,7 +85,7 @@ def test_residual_and_matvec(capi, name):
     assert np.all(r[~prob.active] == 0) and np.all(y[~prob.active] == 0)
 
 
-@pytest.mark.parametrize("name", ["cfg0", "ragged3d", "faulted_inactive"])
+@pytest.mark.parametrize("name", ["cfg0", "ragged3d", "faulted_inactive", "edge62", "edge64", "wide", "wider"])
 @pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
 def test_smoother(capi, name, smoother):
     prob, g, o = build(capi, name, smoother=smoother)
@@ -170,7 +178,7 @@ def test_richardson_converges_cfg0(capi, smoother):
     assert np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b) <= 1.0001e-10
 
 
-@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide"])
 def test_gmres_converges(capi, name):
     prob, g, o = build(capi, name, smoother="ilu0_rb", outer="gmres")
     g.update_basis(max_sweeps=60, tol=1e-3)
