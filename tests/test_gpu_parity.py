@@ -390,7 +390,7 @@ def test_fault_cut_gmres_converges(capi):
 # drift of FP32 sweeps); coarse operators within 1e-2 relative to their
 # largest entry; solves reach the same FP64 relative residual.
 
-@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide", "wider"])
 def test_mixed_basis_within_bound(capi, name):
     prob, g, o = build(capi, name, precision="mixed")
     g.update_basis(max_sweeps=20, tol=0.0)
@@ -408,7 +408,7 @@ def test_mixed_basis_within_bound(capi, name):
     assert relerr(Ac, o.stages[0].Ac) <= 1e-2
 
 
-@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide"])
 def test_mixed_solve_meets_fp64_tolerance(capi, name):
     prob, g, o = build(capi, name, smoother="ilu0_rb", outer="gmres", precision="mixed")
     g.update_basis(max_sweeps=60, tol=1e-3)
