@@ -2,7 +2,7 @@
 
 Two models of 60x220x85 cells: the layered five-spot model in the launch
 configuration the benchmark times (general stages 10x10x5 and 6x22x17,
-red-black ILU(0), GMRES(30), FP64), and the faulted model of the same size
+red-black ILU(0), GMRES(16), FP64), and the faulted model of the same size
 with 5 % inactive cells in mixed precision (a Cartesian and a fault-cut
 stage, dynamic stages from two pressure increments).
 
@@ -58,8 +58,8 @@ def capi():
 def layered(capi):
     prob, sources = bench.workload()
     parts = [{"kind": "cartesian", "coarse_dims": cd} for cd in bench.STAGES]
-    say(f"full-size layered model {prob.dims}, stages {bench.STAGES}, FP64, ilu0_rb, GMRES(30)")
-    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=30, precision="fp64")
+    say(f"full-size layered model {prob.dims}, stages {bench.STAGES}, FP64, ilu0_rb, GMRES({bench.RESTART})")
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=bench.RESTART, precision="fp64")
     g = capi.Solver(prob, parts, opt)
     o = O.Oracle(prob, parts, smoother="jacobi")  # partitions, supports, operator
     return prob, sources, parts, g, o
