@@ -266,9 +266,9 @@ __global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fin
     }
 }
 
-// four wavefronts with three rows each in flight measured fastest on the
-// 60x220x85 model (8x2, 8x3, 16x1 and 16x2 were slower)
-constexpr int kRestrictWaves = 4, kRestrictUnroll = 3;
+// four wavefronts with two rows each in flight measured fastest on the
+// 60x220x85 model (4x3, 4x4, 8x2, 8x3, 16x1 and 16x2 were slower)
+constexpr int kRestrictWaves = 4, kRestrictUnroll = 2;
 
 template <typename PS, bool RES>
 static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, const double *x, const int *done) {
