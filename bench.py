@@ -50,6 +50,8 @@ def parse():
                     help="profiling aid: run only the mixed-precision request and print its record")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble (also skipped by --no-serve)")
+    ap.add_argument("--ensemble-members", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -207,9 +209,40 @@ def serve_leg(args):
         out[name] = {"cells_per_s": st["cells_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                      "solves": st["solves"], "requests": st["completed"], "makespan_s": st["makespan_s"],
                      "all_converged": st["all_converged"], "max_relres": st["max_relres"], "slots": slots}
+    # maximum sustainable rate: the same stream with every request available at once
+    reqs = poisson_stream(args.serve_requests, 200.0, seed=0)
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision="mixed")
+    st = Server(slots=8, options=opt, rtol=RTOL).run(reqs, realtime=False)
+    out["mixed_served"]["max_rate_cells_per_s"] = st["cells_per_s"]
     out["speedup"] = out["mixed_served"]["cells_per_s"] / out["fp64_plain"]["cells_per_s"]
     out["stream"] = (f"{args.serve_requests} requests, Poisson 200/s, 10% layered 60x220x85 (2 stages), 90% "
                      f"ensemble members (1 stage 8x8x4), 1-5 solves each, rtol {RTOL}")
+    return out
+
+
+def ensemble_leg(args):
+    """Batched ensemble: members of 32..128 x 32..128 x 8..16 cells (one 8x8x4
+    stage) solved once each to 1e-6, all admitted at once on eight slots, in
+    FP64 and in mixed precision; per solve, the largest difference of the mixed
+    solution from the FP64 one relative to the FP64 solution's largest entry."""
+    import numpy as np
+
+    from paper_2001_01624_amd import capi
+    from paper_2001_01624_amd.serve import Server
+    from workloads.requests import ensemble_batch
+
+    out, sols = {}, {}
+    for prec in ("fp64", "mixed"):
+        reqs = ensemble_batch(args.ensemble_members, seed=0)
+        opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=prec)
+        st = Server(slots=8, options=opt, rtol=RTOL, keep_solutions=True, dynamic=False).run(reqs, realtime=False)
+        out[prec] = {"cells_per_s": st["cells_per_s"], "makespan_s": st["makespan_s"], "solves": st["solves"],
+                     "all_converged": st["all_converged"], "max_relres": st["max_relres"]}
+        sols[prec] = [r.solutions[0] for r in sorted(reqs, key=lambda r: r.rid)]
+    err = [float(np.abs(m - f).max() / np.abs(f).max()) for m, f in zip(sols["mixed"], sols["fp64"])]
+    out["mixed_vs_fp64_error"] = {"max": max(err), "median": float(np.median(err)),
+                                  "per_solve": [float(f"{e:.3e}") for e in err]}
+    out["members"] = args.ensemble_members
     return out
 
 
@@ -312,6 +345,7 @@ def main():
     f64 = gpu_leg(args, "fp64")
     mixed = None if args.no_mixed else gpu_leg(args, "mixed")
     served = None if args.no_serve else serve_leg(args)
+    ensemble = None if (args.no_serve or args.no_ensemble) else ensemble_leg(args)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline()
     line = {
         "metric": METRIC,
@@ -348,6 +382,8 @@ def main():
                          "roofline": mixed["roofline"], "dtype": "f32 sweeps/smoother, bf16 basis, f64 residual"}
     if served is not None:
         line["served"] = served
+    if ensemble is not None:
+        line["ensemble"] = ensemble
     line["host"] = platform.node()
     print(json.dumps(line))
 

@@ -86,3 +86,14 @@ def poisson_stream(n_requests, rate, p_large=0.1, large_pool=4, small_pool=16, s
         reqs.append(Request(r, t, prob, LARGE_PARTS if large else SMALL_PARTS, source_sequence(prob, rng, k),
                             "large" if large else "small"))
     return reqs
+
+
+def ensemble_batch(n_members, seed=0):
+    """A batch of ensemble members (correlation length, size and permeability
+    from the member's seed), all available at time 0, one solve each with the
+    member's own source."""
+    reqs = []
+    for m in range(n_members):
+        prob = make_config3_member(m + 1000 * seed)
+        reqs.append(Request(m, 0.0, prob, SMALL_PARTS, [np.asarray(prob.source, dtype=np.float64)], "member"))
+    return reqs
