@@ -333,39 +333,65 @@ __global__ __launch_bounds__(256) void k_sweep_check(Status *st, unsigned long l
     }
 }
 
-// Returns the number of per-workgroup maxima written to c.partial.
-template <typename PT>
-static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
-                          int check_blocks) {
+// Workgroups of k_sweep<AM, PT> the device holds at once (occupancy x CUs),
+// queried once per kernel instance.
+template <int AM, typename PT>
+static int sweep_resident(const Ctx &c) {
+    static int cached = 0;
+    if (cached == 0) {
+        int per_cu = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<AM, PT>, 64 * sweep_rows<PT>(), 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device) != hipSuccess || ncu < 1)
+            ncu = 256;
+        cached = per_cu * ncu;
+    }
+    return cached;
+}
+
+// Returns the number of per-workgroup maxima written to c.partial.  The z
+// chunks are sized so that the whole grid is resident at once (one round of
+// workgroups: a partial second round leaves a tail; measured on the
+// 60x220x85 model, 41.7 -> 39.5 us in FP64).
+template <int AM, typename PT>
+static int sweep_launch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
+                        int check_blocks) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    // z chunks sized for about 4096 wavefronts
     constexpr int kSweepRows = sweep_rows<PT>();
     const int nxt = cdiv(c.nx, 64), ngy = cdiv(c.ny, kSweepRows);
-    const int rows = nxt * ngy * kSweepRows;
-    int nzc = std::min(c.nz, std::max(1, cdiv(4096, rows)));
+    int nzc = std::min(c.nz, std::max(1, sweep_resident<AM, PT>(c) / (ngy * nxt)));
     const int zc = cdiv(c.nz, nzc);
     nzc = cdiv(c.nz, zc);
     const int nblk = nzc * ngy * nxt;
     const dim3 grid(xcd_grid(nblk)), blk(64 * kSweepRows);
     const PT om = (PT)c.opt.omega;
     const int *done = &c.status->done;
+    hipEvent_t e0, e1;  // timed by the dispatch when sweeps are profiled
+    prof_pair(c, MSRSB_K_SWEEP, &e0, &e1);
+    hipExtLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, e0, e1, 0, s.cart, g, tx, ty, tz, in, out, om,
+                          c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,
+                          (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);
+    return nblk;
+}
+
+template <typename PT>
+static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
+                          int check_blocks) {
     int am = 0;
     for (int a = 0; a < 3; ++a)
         if (s.cart.bit[a] >= 0) am |= 1 << a;
-    hipEvent_t e0, e1;  // timed by the dispatch when sweeps are profiled
-    prof_pair(c, MSRSB_K_SWEEP, &e0, &e1);
-#define MSRSB_SWEEP(AM)                                                                                         \
-    case AM:                                                                                                    \
-        hipExtLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, e0, e1, 0, s.cart, g, tx, ty, tz, in,  \
-                              out, om, c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,          \
-                              (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);        \
-        break;
     switch (am) {
-        MSRSB_SWEEP(0) MSRSB_SWEEP(1) MSRSB_SWEEP(2) MSRSB_SWEEP(3)
-        MSRSB_SWEEP(4) MSRSB_SWEEP(5) MSRSB_SWEEP(6) MSRSB_SWEEP(7)
+    case 0: return sweep_launch<0, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 1: return sweep_launch<1, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 2: return sweep_launch<2, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 3: return sweep_launch<3, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 4: return sweep_launch<4, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 5: return sweep_launch<5, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 6: return sweep_launch<6, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    default: return sweep_launch<7, PT>(c, s, tx, ty, tz, in, out, check_blocks);
     }
-#undef MSRSB_SWEEP
-    return nblk;
 }
 
 template <typename PT>
