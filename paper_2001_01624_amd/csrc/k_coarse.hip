@@ -299,11 +299,16 @@ void launch_coarse_inverse(Ctx &c, Stage &s) {
 }
 
 // p_c = A_c^{-1} d: one workgroup per row.  Thread t adds the entries
-// t, t + 256, ... of the row in order (all loads of a thread issued together;
-// d is read through the caches), then a fixed-order workgroup sum.  Row j is
-// stored at y[map[j]] when a map is given.
+// t, t + 256, ... of the row in order, then a fixed-order workgroup sum.  The
+// entries of a thread are taken NPT at a time with every load issued before
+// the first product (indices past the row clamped to an entry of the row and
+// their terms multiplied by zero), so a row of up to 256 NPT entries costs one
+// memory round trip; a loop with a run-time trip count below its unroll
+// factor would wait on each load in turn.  Row j is stored at y[map[j]] when
+// a map is given.
 constexpr int kGemvThreads = 256;
 
+template <int NPT>
 __global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict__ A, int M, int Mp,
                                                        const double *__restrict__ d, double *__restrict__ y,
                                                        const int32_t *__restrict__ map, const int *done) {
@@ -312,16 +317,42 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict_
     const int row = blockIdx.x;
     const double *a = A + (long)row * Mp;
     double s = 0.0;
-#pragma unroll 16
-    for (int k = threadIdx.x; k < M; k += kGemvThreads) s += a[k] * d[k];
+    for (int k0 = threadIdx.x; k0 < M; k0 += NPT * kGemvThreads) {
+        double av[NPT], dv[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int k = k0 + j * kGemvThreads;
+            const int kc = k < M ? k : k0;
+            av[j] = a[kc];
+            dv[j] = d[kc];
+        }
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const double m = k0 + j * kGemvThreads < M ? 1.0 : 0.0;
+            s = fma(av[j], dv[j] * m, s);
+        }
+    }
     s = block_sum(s, lds);
     if (threadIdx.x == 0) y[map ? map[row] : row] = s;
 }
 
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done) {
     ProfScope ps(c, MSRSB_K_COARSE);
-    hipLaunchKernelGGL(k_gemv, dim3(s.M), dim3(kGemvThreads), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec, s.pc, s.pc_map,
-                       done);
+    const int npt = cdiv(s.M, kGemvThreads);
+#define MSRSB_GEMV(NPT) \
+    hipLaunchKernelGGL(k_gemv<NPT>, dim3(s.M), dim3(kGemvThreads), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec, s.pc, \
+                       s.pc_map, done)
+    if (npt <= 1) MSRSB_GEMV(1);
+    else if (npt <= 2) MSRSB_GEMV(2);
+    else if (npt <= 3) MSRSB_GEMV(3);
+    else if (npt <= 4) MSRSB_GEMV(4);
+    else if (npt <= 6) MSRSB_GEMV(6);
+    else if (npt <= 8) MSRSB_GEMV(8);
+    else if (npt <= 9) MSRSB_GEMV(9);
+    else if (npt <= 10) MSRSB_GEMV(10);
+    else if (npt <= 12) MSRSB_GEMV(12);
+    else MSRSB_GEMV(16);
+#undef MSRSB_GEMV
 }
 
 }  // namespace msrsb
