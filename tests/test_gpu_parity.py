@@ -53,6 +53,12 @@ CASES = {
     "edge64": (lambda: make_lognormal_box((64, 5, 4), rng_for(7, 4), sigma=1.5, corr=(4, 2, 1)), (5, 2, 1)),
     "wide": (lambda: make_lognormal_box((70, 9, 5), rng_for(7, 5), sigma=1.5, corr=(3, 2, 1)), (5, 2, 2)),
     "wider": (lambda: make_config2(dims=(130, 6, 4), seed=4), (9, 2, 2)),
+    # degenerate shapes: rows of one cell along y or z only (one active lane
+    # per wavefront, every x face a boundary face), and the longest row the
+    # library accepts (256 cells: four full 64-cell runs)
+    "zline": (lambda: make_lognormal_box((1, 1, 40), rng_for(7, 6), sigma=1.5, corr=(1, 1, 3)), (1, 1, 5)),
+    "yline": (lambda: make_lognormal_box((1, 37, 1), rng_for(7, 7), sigma=1.5, corr=(1, 3, 1)), (1, 4, 1)),
+    "maxrow": (lambda: make_lognormal_box((256, 3, 2), rng_for(7, 8), sigma=1.5, corr=(8, 1, 1)), (16, 1, 1)),
 }
 
 
@@ -85,7 +91,8 @@ def test_residual_and_matvec(capi, name):
     assert np.all(r[~prob.active] == 0) and np.all(y[~prob.active] == 0)
 
 
-@pytest.mark.parametrize("name", ["cfg0", "ragged3d", "faulted_inactive", "edge62", "edge64", "wide", "wider"])
+@pytest.mark.parametrize("name", ["cfg0", "ragged3d", "faulted_inactive", "edge62", "edge64", "wide", "wider",
+                                  "zline", "yline", "maxrow"])
 @pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
 def test_smoother(capi, name, smoother):
     prob, g, o = build(capi, name, smoother=smoother)
@@ -178,7 +185,7 @@ def test_richardson_converges_cfg0(capi, smoother):
     assert np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b) <= 1.0001e-10
 
 
-@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide"])
+@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide", "zline", "maxrow"])
 def test_gmres_converges(capi, name):
     prob, g, o = build(capi, name, smoother="ilu0_rb", outer="gmres")
     g.update_basis(max_sweeps=60, tol=1e-3)
@@ -291,9 +298,36 @@ def test_error_paths(capi):
     with pytest.raises(capi.MsrsbError) as e:
         capi.Solver(prob, [{"kind": "cartesian", "coarse_dims": (61, 1, 1)}])
     assert e.value.code == capi.E_INVAL
+    # size limits: rows of at most 256 cells, at most 1024 coarse layers
+    for dims, cd in (((257, 2, 1), (4, 1, 1)), ((1, 1, 1100), (1, 1, 1025))):
+        with pytest.raises(capi.MsrsbError) as e:
+            capi.Solver(make_lognormal_box(dims, rng_for(7, 9)), [{"kind": "cartesian", "coarse_dims": cd}])
+        assert e.value.code == capi.E_INVAL
     g.update_basis(max_sweeps=3, tol=0.0)
     it, rel, rc = g.solve(p, rtol=1e-14, max_iters=1)
     assert rc == capi.E_NOCONV and it == 1 and 0 < rel < 1
+
+
+@pytest.mark.parametrize("outer", ["richardson", "gmres"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_cell(capi, outer, precision):
+    # one cell between the two Dirichlet faces (p = 1 and p = 0) with equal
+    # half-face transmissibilities: the pressure is 1/2, and in FP64 the first
+    # step (exact ILU(0), one block with P = 1) reaches it to rounding.  In
+    # mixed precision a Krylov vector passes through the FP32 smoother, so
+    # GMRES may need a second step
+    prob = make_lognormal_box((1, 1, 1), rng_for(7, 10), sigma=1.0)
+    opt = capi.default_options(smoother="ilu0_rb", outer=outer, precision=precision)
+    g = capi.Solver(prob, [{"kind": "cartesian", "coarse_dims": (1, 1, 1)}], opt)
+    g.update_basis(max_sweeps=5, tol=0.0)
+    p = dev(np.zeros(1))
+    it, rel, rc = g.solve(p, rtol=1e-12, max_iters=10)
+    say(f"single cell {outer} {precision}: {it} iterations, relres {rel:.2e}, p = {host(p)[0]!r}")
+    assert rc == capi.OK and rel <= 1e-12
+    if precision == "fp64":
+        assert it == 1 and abs(host(p)[0] - 0.5) <= 1e-15
+    else:
+        assert abs(host(p)[0] - 0.5) <= 1e-12
 
 
 def test_special_bases(capi):
