@@ -13,7 +13,7 @@
 // D^{-1} of the next pivot block is formed by the workgroup that updates
 // that block, inside the update of the current step, so only the first
 // block inversion is on its own on the critical path.
-// Each cycle then applies the inverse by a GEMV (one wavefront per row).
+// Each cycle then applies the inverse by a GEMV (one workgroup per row).
 #include "dev_util.h"
 #include "msrsb_internal.h"
 
