@@ -29,10 +29,13 @@ namespace msrsb {
 // RES: r is not read but formed per cell as b - A x, with the operations of
 // the residual kernel (so the restricted vector is the same bit for bit).
 // W wavefronts per workgroup, U rows per wavefront in flight.  One workgroup
-// per (dual y-interval Ly, layer z), numbered with z fastest and spread over
-// the XCDs in contiguous ranges, so the layers above and below are read
-// through the same L2.  Rows of at most 64 cells (NCH = 1) take the x
-// neighbours from the adjacent lanes.
+// per (dual y-interval Ly, layer z), numbered with Ly fastest and spread over
+// the XCDs in contiguous ranges: the workgroups in flight on an XCD read
+// whole consecutive layers (one contiguous address range), and the layers
+// above and below go through the same L2.  (Numbering z fastest, so that one
+// XCD walked the layers of an interval, was 10 % slower on the 60x220x85
+// model.)  Rows of at most 64 cells (NCH = 1) take the x neighbours from the
+// adjacent lanes.
 template <int NS, typename PS, int NCH, bool RES, int W, int U>
 __global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
                                                           const double *__restrict__ rb,
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, co
     const int mx = cd.m[0], my = cd.m[1];
     const int t = xcd_block();
     if (t >= my * g.nz) return;
-    const int Ly = t / g.nz, z = t - Ly * g.nz;
+    const int z = t / my, Ly = t - z * my;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int y0 = 0, y1 = g.ny;
     if (cd.bit[1] >= 0) {
