@@ -1108,7 +1108,10 @@ __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__rest
         at[q] = 0.0;
     }
     const int jc = j > 0 ? j - 1 : 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += G * blockDim.x) {
+    const int lb = xcd_block();
+    const int ch = ((g.N + G - 1) / G + 63) & ~63;
+    const int i0 = lb * ch, i1 = min(g.N, i0 + ch);
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double vq[KM - 1];
 #pragma unroll
         for (int q = 0; q < KM - 1; ++q) vq[q] = (double)Q[(long)min(q, jc) * g.N + i];  // slots q >= j unused
@@ -1148,12 +1151,12 @@ __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__rest
     }
     const int nw = blockDim.x >> 6;
     group_sum_lds<KM>(as, red);
-    if ((int)threadIdx.x < j) partial[(long)threadIdx.x * G + blockIdx.x] = red[nw * KM + threadIdx.x];
-    if (threadIdx.x == KM - 1) partial[(long)j * G + blockIdx.x] = red[nw * KM + KM - 1];
+    if ((int)threadIdx.x < j) partial[(long)threadIdx.x * G + lb] = red[nw * KM + threadIdx.x];
+    if (threadIdx.x == KM - 1) partial[(long)j * G + lb] = red[nw * KM + KM - 1];
     if (MV) {
         group_sum_lds<KM>(at, red);
-        if ((int)threadIdx.x < j) partial[(long)(j + 1 + threadIdx.x) * G + blockIdx.x] = red[nw * KM + threadIdx.x];
-        if (threadIdx.x == KM - 1) partial[(long)(2 * j + 1) * G + blockIdx.x] = red[nw * KM + KM - 1];
+        if ((int)threadIdx.x < j) partial[(long)(j + 1 + threadIdx.x) * G + lb] = red[nw * KM + threadIdx.x];
+        if (threadIdx.x == KM - 1) partial[(long)(2 * j + 1) * G + lb] = red[nw * KM + KM - 1];
     }
 }
 
@@ -1298,7 +1301,9 @@ __global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict_
         cq[q] = q < j ? cv : 0.0;
     }
     const double cj = scal[S_DC + j], irho = scal[S_RHO];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const int ch = ((N + (int)gridDim.x - 1) / (int)gridDim.x + 63) & ~63;
+    const int i0 = xcd_block() * ch, i1 = min(N, i0 + ch);
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double vq[KM - 1];
 #pragma unroll
         for (int q = 0; q < KM - 1; ++q) {
