@@ -294,8 +294,24 @@ __global__ __launch_bounds__(kBlock) void k_dyn_restrict(const int32_t *__restri
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     const int j = blockIdx.x;
+    const int p0 = ptr[j], p1 = ptr[j + 1];
+    // thread t adds the cells p0 + t, p0 + t + 256, ... in order, eight at a
+    // time with all index loads, then all value loads, in flight (entries past
+    // the block repeat the first one of the batch and are multiplied by zero)
     double acc = 0.0;
-    for (int p = ptr[j] + threadIdx.x; p < ptr[j + 1]; p += blockDim.x) acc += r[cells[p]];
+    for (int pb = p0 + threadIdx.x; pb < p1; pb += 8 * blockDim.x) {
+        int ci[8];
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int p = pb + q * blockDim.x;
+            ci[q] = cells[p < p1 ? p : pb];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = r[ci[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q] * (pb + q * (int)blockDim.x < p1 ? 1.0 : 0.0);
+    }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) d[j] = s;
 }
