@@ -662,13 +662,16 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
             if (c.h_status->done) break;
             chunk = std::min(chunk * 2, 16);
         }
+        int k;
         if (dcgs && j == m && !c.h_status->done) {
-            // finalise the last column from u_m
+            // finalise the last column from u_m; the step sets jcur = m, so the
+            // host need not wait for it (the restart's status read follows)
             launch_dgmres_step(c, nullptr, w, c.V + (c.Vf ? (long)(m & 1) : (long)m) * N, m, rtol, max_iters, true);
-            if ((rc = read_status(c))) return rc;
+            k = m;
+        } else {
+            k = c.h_status->jcur;
         }
         // x += M^{-1} V y
-        const int k = c.h_status->jcur;
         if (k > 0) {
             launch_gmres_solve_small(c, m);
             zero_vec(c, c.u, nullptr);
