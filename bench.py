@@ -328,8 +328,8 @@ def main():
         cpu_leg()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
-              f"in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver path is single-GPU "
+              f"and no multi-GPU run is built", file=sys.stderr)
         sys.exit(2)
     import torch
 
