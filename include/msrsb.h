@@ -24,9 +24,11 @@
  *  - A context is not thread-safe.  Distinct contexts may be used from
  *    distinct threads at the same time, each on its own stream.
  *  - All device work of a context runs on the stream given at setup (or the
- *    null stream).  The library allocates its device memory with hipMalloc
- *    at setup and when dynamic bases are added; msrsb_footprint_bytes tells
- *    the amount in advance.
+ *    null stream).  The library allocates its device memory itself,
+ *    stream-ordered from the device's default memory pool: at setup one
+ *    arena of about msrsb_footprint_bytes that the set-up buffers are carved
+ *    from (anything beyond it is allocated on its own), and further blocks
+ *    when dynamic bases are added or a stage is exported.
  */
 #ifndef MSRSB_H
 #define MSRSB_H
@@ -126,8 +128,8 @@ size_t msrsb_footprint_bytes(const msrsb_grid *grid, int n_part, const msrsb_par
  * msrsb_grid), build every partition and support, and factor the smoother.
  * hip_stream: a hipStream_t (NULL = null stream); every device operation of
  * the context, its allocations included (stream-ordered, from the device's
- * default memory pool), runs on that stream, and msrsb_setup returns after
- * synchronising it alone.  On success *out owns all device memory of the
+ * default memory pool; the set-up buffers share one arena), runs on that
+ * stream, and msrsb_setup returns after synchronising it alone.  On success *out owns all device memory of the
  * context.  Errors: E_INVAL (bad sizes, non-finite or
  * negative T, a face touching an inactive cell or leaving the box, a BC on
  * an inactive cell), E_SINGULAR (an active connected component without any

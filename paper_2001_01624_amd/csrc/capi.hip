@@ -51,6 +51,12 @@ static void keep_pool_memory(int device) {
 void *ctx_alloc(Ctx &c, size_t bytes) {
     void *p = nullptr;
     if (bytes == 0) bytes = 8;
+    const size_t rb = (bytes + 255) & ~(size_t)255;
+    if (c.arena_open && c.arena && c.arena_off + rb <= c.arena_size) {
+        p = c.arena + c.arena_off;
+        c.arena_off += rb;
+        return p;
+    }
     keep_pool_memory(c.device);
     if (hipMallocAsync(&p, bytes, c.stream) != hipSuccess) {
         (void)hipGetLastError();
@@ -857,12 +863,32 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         dst = (double *)ctx_alloc(*c, sizeof(double) * N);
         return dst && upload(*c, dst, h, sizeof(double) * N);
     };
+    std::vector<float> t32b(N), t32c(N);
+    std::vector<float> *t32s[3] = {&t32, &t32b, &t32c};
+    int n32 = 0;
     auto up32 = [&](float *&dst, const double *h) -> bool {
-        for (int i = 0; i < N; ++i) t32[i] = (float)h[i];
+        std::vector<float> &t = *t32s[n32++];  // one host buffer per array, alive until the set-up's final wait
+        for (int i = 0; i < N; ++i) t[i] = (float)h[i];
         dst = (float *)ctx_alloc(*c, sizeof(float) * N);
-        // t32 is reused for every array: wait for each copy
-        return dst && upload(*c, dst, t32.data(), sizeof(float) * N) && hipStreamSynchronize(c->stream) == hipSuccess;
+        return dst && upload(*c, dst, t.data(), sizeof(float) * N);
     };
+    // the set-up's buffers come from one arena of the estimated set-up size
+    {
+        const size_t est = msrsb_footprint_bytes(g, n_part, parts, &o);
+        if (est > 0) {
+            keep_pool_memory(c->device);
+            void *a = nullptr;
+            const size_t sz = est + est / 32 + ((size_t)1 << 20);
+            if (hipMallocAsync(&a, sz, c->stream) == hipSuccess) {
+                c->allocs.push_back(a);
+                c->arena = (char *)a;
+                c->arena_size = sz;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        c->arena_open = true;
+    }
     if (!up(c->tx, g->tx) || !up(c->ty, g->ty) || !up(c->tz, g->tz) || !up(c->bcdiag, bcd.data()) ||
         !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !up32(c->tx32, g->tx) || !up32(c->ty32, g->ty) ||
         !up32(c->tz32, g->tz))
@@ -927,6 +953,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     hipMemsetAsync(c->tmp, 0, 8 * (size_t)N, c->stream);
     launch_assemble(*c);
     launch_ilu_factor(*c);
+    c->arena_open = false;  // later allocations (dynamic stages, exports) are freed on their own
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return fail(hip_fail(e, "setup kernels"));

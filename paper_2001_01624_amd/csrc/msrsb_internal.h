@@ -138,6 +138,12 @@ struct Ctx {
     std::vector<Stage> stages;    // general + static
     std::vector<Stage> dyn;       // dynamic, newest first
     std::vector<void *> allocs;   // every device allocation (freed at destroy)
+    // set-up arena: one allocation that the set-up's buffers are carved from
+    // (256-byte aligned); later allocations, and any that do not fit, are
+    // allocations of their own
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_off = 0;
+    bool arena_open = false;
 };
 
 // Brackets the launches of one kernel class with HIP events when that class
