@@ -912,7 +912,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     c->scal = (double *)alloc(8 * 16384);
     c->status = (Status *)alloc(sizeof(Status));
     c->maxbits = (unsigned long long *)alloc(8 * 65536);
-    c->flag = (int *)alloc(sizeof(int));
+    c->flag = (int *)alloc(2 * sizeof(int));  // [1]: the second sweep of a stop-rule pair
     if (!c->diag || !c->b || !c->dtil || !c->dtil32 || !c->diag32 || !c->r || !c->e || !c->tmp || !c->z || !c->u ||
         !c->partial || !c->scal || !c->status || !c->maxbits || !c->flag)
         return fail(MSRSB_E_NOMEM);

@@ -333,6 +333,47 @@ __global__ __launch_bounds__(256) void k_sweep_check(Status *st, unsigned long l
     }
 }
 
+// Stop rule after the sweeps k and k+1 of a pair (npair = 2), or after sweep
+// k alone (npair = 1): the maxima of sweep k are in part[0..n0), those of
+// sweep k+1 in part[stride..stride+n1), and sweep k+1 raised its row-sum flag
+// in flag[1].  Sweep k is decided first, exactly as alone; if it stops, the
+// extra sweep k+1 does not count (its result went to the other buffer and its
+// flag is dropped), otherwise sweep k+1 is decided and its flag kept.
+__global__ __launch_bounds__(256) void k_sweep_check_pair(Status *st, unsigned long long *maxbits, int k,
+                                                          int npair, double tol, int max_sweeps,
+                                                          const double *__restrict__ part, int n0, int n1,
+                                                          int stride, int *flag) {
+    __shared__ double lds[4];
+    if (st->done) return;
+    double m0 = 0.0, m1 = 0.0;
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) m0 = fmax(m0, part[t]);
+    m0 = block_max(m0, lds);
+    if (npair > 1) {
+        for (int t = threadIdx.x; t < n1; t += blockDim.x) m1 = fmax(m1, part[stride + t]);
+        m1 = block_max(m1, lds);
+    }
+    if (threadIdx.x == 0) {
+        maxbits[k] = (unsigned long long)__double_as_longlong(m0);
+        st->iters = k + 1;
+        st->relres = m0;
+        if (m0 <= tol || k + 1 >= max_sweeps) {
+            st->done = 1;
+            flag[1] = 0;
+        } else if (npair > 1) {
+            maxbits[k + 1] = (unsigned long long)__double_as_longlong(m1);
+            st->iters = k + 2;
+            st->relres = m1;
+            flag[0] |= flag[1];
+            flag[1] = 0;
+            if (m1 <= tol || k + 2 >= max_sweeps) st->done = 1;
+        }
+    }
+}
+
+// Offset of the second sweep's maxima in c.partial (which holds at least
+// twice as many doubles).
+constexpr int kSweepPartStride = 65536;
+
 // Workgroups of k_sweep<AM, PT> the device holds at once (occupancy x CUs),
 // queried once per kernel instance.
 template <int AM, typename PT>
@@ -357,7 +398,7 @@ static int sweep_resident(const Ctx &c) {
 // 60x220x85 model, 41.7 -> 39.5 us in FP64).
 template <int AM, typename PT>
 static int sweep_launch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
-                        int check_blocks) {
+                        int check_blocks, double *part, int *flag) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     constexpr int kSweepRows = sweep_rows<PT>();
     const int nxt = cdiv(c.nx, 64), ngy = cdiv(c.ny, kSweepRows);
@@ -371,26 +412,26 @@ static int sweep_launch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *
     hipEvent_t e0, e1;  // timed by the dispatch when sweeps are profiled
     prof_pair(c, MSRSB_K_SWEEP, &e0, &e1);
     hipExtLaunchKernelGGL((k_sweep<AM, PT>), grid, blk, 0, c.stream, e0, e1, 0, s.cart, g, tx, ty, tz, in, out, om,
-                          c.partial, c.flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,
+                          part, flag, check_blocks, done, nxt, ngy, nzc, zc, nblk,
                           (const unsigned long long *)s.cart.xmask, s.cart.pack[1], s.cart.pack[2]);
     return nblk;
 }
 
 template <typename PT>
 static int sweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const PT *tz, const PT *in, PT *out,
-                          int check_blocks) {
+                          int check_blocks, double *part, int *flag) {
     int am = 0;
     for (int a = 0; a < 3; ++a)
         if (s.cart.bit[a] >= 0) am |= 1 << a;
     switch (am) {
-    case 0: return sweep_launch<0, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 1: return sweep_launch<1, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 2: return sweep_launch<2, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 3: return sweep_launch<3, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 4: return sweep_launch<4, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 5: return sweep_launch<5, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    case 6: return sweep_launch<6, PT>(c, s, tx, ty, tz, in, out, check_blocks);
-    default: return sweep_launch<7, PT>(c, s, tx, ty, tz, in, out, check_blocks);
+    case 0: return sweep_launch<0, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 1: return sweep_launch<1, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 2: return sweep_launch<2, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 3: return sweep_launch<3, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 4: return sweep_launch<4, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 5: return sweep_launch<5, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    case 6: return sweep_launch<6, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
+    default: return sweep_launch<7, PT>(c, s, tx, ty, tz, in, out, check_blocks, part, flag);
     }
 }
 
@@ -415,7 +456,8 @@ __global__ void k_status_reset(Status *st, int *flag) {
     st->done = 0;
     st->iters = 0;
     st->relres = 0.0;
-    *flag = 0;
+    flag[0] = 0;
+    flag[1] = 0;
 }
 
 // Run up to max_sweeps sweeps (device-side stop rule); returns MSRSB status.
@@ -436,23 +478,47 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
             return hip_fail(hipGetLastError(), "memset");
         int k = 0;
         int chunk = 8;
+        // a sweep has at most max(resident workgroups, row groups x x tiles)
+        // workgroups; pairs need that many maxima per half of c.partial
+        const bool pairs = s.kind != 2 && (long)cdiv(c.ny, 4) * cdiv(c.nx, 64) <= kSweepPartStride;
         while (k < max_sweeps) {
             const int kend = std::min(max_sweeps, k + chunk);
-            for (; k < kend; ++k) {
-                const int in = (s.cur + k) & 1, out = in ^ 1;
-                int npart = 0;
-                if (s.kind == 2) {
-                    ProfScope ps(c, MSRSB_K_SWEEP);
-                    npart = launch_xsweep(c, s, in, out);
-                } else {
-                    if (mixed)
+            while (k < kend) {
+                if (!pairs) {
+                    const int in = (s.cur + k) & 1, out = in ^ 1;
+                    int npart = 0;
+                    if (s.kind == 2) {
+                        ProfScope ps(c, MSRSB_K_SWEEP);
+                        npart = launch_xsweep(c, s, in, out);
+                    } else if (mixed) {
                         npart = sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out],
-                                                      check_blocks);
-                    else
-                        npart = sweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out], check_blocks);
+                                                      check_blocks, c.partial, c.flag);
+                    } else {
+                        npart = sweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out], check_blocks,
+                                                       c.partial, c.flag);
+                    }
+                    hipLaunchKernelGGL(k_sweep_check, dim3(1), dim3(256), 0, c.stream, c.status, c.maxbits, k, tol,
+                                       max_sweeps, c.partial, npart);
+                    ++k;
+                    continue;
                 }
-                hipLaunchKernelGGL(k_sweep_check, dim3(1), dim3(256), 0, c.stream, c.status, c.maxbits, k, tol,
-                                   max_sweeps, c.partial, npart);
+                // rectilinear stages: two sweeps per stop-rule check (one
+                // launch fewer per pair), each with its own maxima and flag
+                const int npair = k + 1 < kend ? 2 : 1;
+                int np[2] = {0, 0};
+                for (int q = 0; q < npair; ++q) {
+                    const int in = (s.cur + k + q) & 1, out = in ^ 1;
+                    double *part = c.partial + (size_t)q * kSweepPartStride;
+                    if (mixed)
+                        np[q] = sweep_dispatch<float>(c, s, c.tx32, c.ty32, c.tz32, s.P32[in], s.P32[out],
+                                                      check_blocks, part, c.flag + q);
+                    else
+                        np[q] = sweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out], check_blocks,
+                                                       part, c.flag + q);
+                }
+                hipLaunchKernelGGL(k_sweep_check_pair, dim3(1), dim3(256), 0, c.stream, c.status, c.maxbits, k,
+                                   npair, tol, max_sweeps, c.partial, np[0], np[1], kSweepPartStride, c.flag);
+                k += npair;
             }
             hipError_t e = hipMemcpyAsync(c.h_status, c.status, sizeof(Status), hipMemcpyDeviceToHost, c.stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
