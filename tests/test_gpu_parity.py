@@ -141,6 +141,25 @@ def test_basis_stop_rule(capi, name):
         assert ch == pytest.approx(o.stages[0].change, rel=1e-9)
 
 
+@pytest.mark.parametrize("name", ["cfg0", "layered"])
+def test_stop_rule_equals_fixed_count(capi, name):
+    # the device decides sweeps in pairs: when the first of a pair meets the
+    # tolerance the second has already run and must leave no trace, so the
+    # basis, the count and the last change equal those of exactly that many
+    # sweeps; the tolerances give stopping counts of both parities
+    prob, g, o = build(capi, name)
+    counts = []
+    for tol in (3e-2, 1e-2, 5e-3, 3e-3, 2e-3, 1e-3):
+        n, ch = g.update_basis(max_sweeps=100, tol=tol)
+        P = g.dense_basis(0)
+        n2, ch2 = g.update_basis(max_sweeps=n, tol=0.0)
+        say(f"{name}: tol {tol:g}: {n} sweeps, change {ch:.3e}")
+        assert n2 == n and ch2 == ch
+        assert np.array_equal(g.dense_basis(0), P)
+        counts.append(n)
+    assert {n % 2 for n in counts} == {0, 1}
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
 def test_preconditioner(capi, name, smoother):
