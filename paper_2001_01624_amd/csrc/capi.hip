@@ -656,8 +656,9 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
                 if (dcgs) {
                     // column j from u_j = V(j) (u_0 = r); q_j and u_{j+1} land in V
                     const double *uj = c.V + (c.Vf ? (long)(j & 1) : (long)j) * N;
-                    cycle(c, uj, c.z, false, done, true);
-                    launch_dgmres_step(c, c.z, w, uj, j, rtol, max_iters, false);
+                    double *zj = c.Z + (long)j * N;  // kept for the solution update
+                    cycle(c, uj, zj, false, done, true);
+                    launch_dgmres_step(c, zj, w, uj, j, rtol, max_iters, false);
                 } else {
                     double *vj = c.V + (long)j * N;
                     cycle(c, vj, c.z, false, done, true);
@@ -677,8 +678,12 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
         } else {
             k = c.h_status->jcur;
         }
-        // x += M^{-1} V y
-        if (k > 0) {
+        // x += M^{-1} V y.  DCGS2: M^-1 Q = Z T^-1 from the stored candidates,
+        // so x += Z (T^-1 y) without another application of the cycle
+        if (k > 0 && dcgs) {
+            launch_gmres_solve_small(c, m, true);
+            launch_multiaxpy(c, c.Z, k, c.scal + kScalW, x, 1.0, false, nullptr);
+        } else if (k > 0) {
             launch_gmres_solve_small(c, m);
             zero_vec(c, c.u, nullptr);
             if (c.Vf) launch_multiaxpy(c, c.Vf, k, c.scal + 4608, c.u, 1.0, false, nullptr);
@@ -800,6 +805,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     b += N * 8 * 5;                                          // work vectors
     b += (size_t)kRedBlocks * (2 * kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
     if (o.outer == MSRSB_GMRES) b += fp32_basis(o) ? N * 8 * 2 + (size_t)o.restart * N * 4 : (size_t)(o.restart + 1) * N * 8;
+    if (o.outer == MSRSB_GMRES && o.restart <= kDcgsMax) b += (size_t)o.restart * N * 8;  // candidates M^-1 u_j
     b += (size_t)g->n_bc * 24;
     long cb = 0;
     for (int k = 0; k < n_part; ++k) {
@@ -936,6 +942,10 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         } else {
             c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
             if (!c->V) return fail(MSRSB_E_NOMEM);
+        }
+        if (o.restart <= kDcgsMax) {
+            c->Z = (double *)alloc(8 * (size_t)o.restart * N);
+            if (!c->Z) return fail(MSRSB_E_NOMEM);
         }
     }
     c->stages.resize(n_part);

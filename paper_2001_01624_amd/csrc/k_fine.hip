@@ -726,7 +726,9 @@ void launch_gmres_scale(Ctx &c, const double *w, double *v, int /*j*/) {
 }
 
 // Back substitution R y = g over the jcur completed steps.
-__global__ void k_gmres_solve_small(Status *st, double *scal) {
+// y = H^-1 g by back substitution (k = jcur columns); with zform also
+// w = T^-1 y, so that M^-1 Q y = Z w for the stored candidates Z.
+__global__ void k_gmres_solve_small(Status *st, double *scal, int zform) {
     const double *H = scal + S_H;
     const double *g = scal + S_G;
     double *y = scal + S_Y;
@@ -737,10 +739,20 @@ __global__ void k_gmres_solve_small(Status *st, double *scal) {
         for (int m = i + 1; m < k; ++m) s -= H[i + ld * m] * y[m];
         y[i] = s / H[i + ld * i];
     }
+    if (zform) {
+        const double *T = scal + kScalT;
+        double *w = scal + kScalW;
+        constexpr int lt = kDcgsMax + 1;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int m = i + 1; m < k; ++m) s -= T[i + lt * m] * w[m];
+            w[i] = s / T[i + lt * i];
+        }
+    }
 }
 
-void launch_gmres_solve_small(Ctx &c, int /*restart*/) {
-    hipLaunchKernelGGL(k_gmres_solve_small, dim3(1), dim3(1), 0, c.stream, c.status, c.scal);
+void launch_gmres_solve_small(Ctx &c, int /*restart*/, bool zform) {
+    hipLaunchKernelGGL(k_gmres_solve_small, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, zform ? 1 : 0);
 }
 
 __global__ void k_axpy(int N, double *__restrict__ x, const double *__restrict__ z, const int *done) {
@@ -1218,6 +1230,9 @@ __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int 
     }
     __syncthreads();
     const double rho = sh[0];
+    // column j of T: q_j = (u_j - Q s) / rho, so M^-1 u_j = M^-1 Q s + rho M^-1 q_j
+    if (!final_)
+        for (int i = tid; i <= j; i += blockDim.x) scal[kScalT + i + (kDcgsMax + 1) * j] = i < j ? A[i] : rho;
     if (j > 0) {
         // finalise column j-1 of the Arnoldi matrix and of its rotated copy
         const int c = j - 1;

@@ -134,6 +134,7 @@ struct Ctx {
     // precision and the DCGS2 path) V holds only the two candidate vectors
     // u_j [2 * N] and Vf the basis [restart * N]
     double *V = nullptr;
+    double *Z = nullptr;          // DCGS2: preconditioned candidates M^-1 u_j, one per column
     float *Vf = nullptr;
     std::vector<Stage> stages;    // general + static
     std::vector<Stage> dyn;       // dynamic, newest first
@@ -188,6 +189,9 @@ void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool ass
 void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
                         bool final_);
 constexpr int kDcgsMax = 31;  // largest restart served by the DCGS2 kernels
+// c.scal regions of the DCGS2 solution update: the triangle T with
+// M^-1 Q = Z T^-1 (column-major, ld kDcgsMax + 1) and the coefficients T^-1 y
+constexpr int kScalT = 13000, kScalW = 14100;
 void launch_zero_inactive(Ctx &c, double *x);
 void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
 void launch_check(Ctx &c, double rtol, int max_iters, int count);
@@ -205,7 +209,7 @@ void launch_multiaxpy(Ctx &c, const float *V, int k, const double *h, double *w,
 void launch_gmres_start(Ctx &c, const double *r, double *v0, int restart);
 void launch_gmres_step(Ctx &c, int j, double rtol, int max_iters, int restart);
 void launch_gmres_scale(Ctx &c, const double *w, double *v, int j);
-void launch_gmres_solve_small(Ctx &c, int restart);
+void launch_gmres_solve_small(Ctx &c, int restart, bool zform = false);
 void launch_axpy(Ctx &c, double *x, const double *z, const int *done);
 void launch_reorth_check(Ctx &c, int k);
 void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart);
