@@ -219,6 +219,25 @@ def test_gmres_converges(capi, name):
     assert relerr(x, o.direct_solve()) <= 1e-7
 
 
+@pytest.mark.parametrize("restart", [1, 2, 5])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gmres_short_restarts(capi, restart, precision):
+    # every restart ends with the update x += Z T^-1 y over the kept
+    # preconditioned candidates; with restart 1 or 2 the triangle T is 1x1 or
+    # 2x2 and the last column is finalised after every step or two
+    prob = make_config0(0)
+    parts = [{"kind": "cartesian", "coarse_dims": (6, 6, 1)}]
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=restart, precision=precision)
+    g = capi.Solver(prob, parts, opt)
+    o = O.Oracle(prob, parts, smoother="ilu0_rb")
+    g.update_basis(max_sweeps=60, tol=1e-3)
+    p = dev(np.zeros(prob.n_cells))
+    it, rel, rc = g.solve(p, rtol=1e-8, max_iters=3000)
+    true = np.linalg.norm(o.residual(host(p))) / np.linalg.norm(o.b)
+    say(f"GMRES({restart}) {precision}: {it} iterations, reported {rel:.2e}, true {true:.2e}")
+    assert rc == capi.OK and true <= 1.0001e-8
+
+
 def test_gmres_first_steps_match_oracle(capi):
     prob, g, o = build(capi, "layered", smoother="ilu0_rb", outer="gmres")
     g.update_basis(max_sweeps=30, tol=0.0)
