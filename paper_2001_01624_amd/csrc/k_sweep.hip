@@ -131,6 +131,11 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
     const bool own = row_ok && x < nx;
     const int xc = min(x, nx - 1);
     const int z0 = zk * zc, z1 = min(nz, z0 + zc);
+    // neighbouring z chunks march in opposite directions (up in even chunks,
+    // down in odd ones), so the layers around a common boundary are read by
+    // both chunks at about the same time, through the same L2
+    const int dir = (zk & 1) ? -1 : 1;
+    const int zs = dir > 0 ? z0 : z1 - 1;
 
     const __amdgpu_buffer_rsrc_t rP = rsrc(Pin, (long)NS * N * SZ), rO = rsrc(Pout, (long)NS * N * SZ);
     const __amdgpu_buffer_rsrc_t rX = rsrc(tx, (long)N * SZ), rY = rsrc(ty, (long)N * SZ), rZ = rsrc(tz, (long)N * SZ);
@@ -159,15 +164,19 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
         soyp[s] = syp_[s] * NSZ;
     }
     const int base = xc + nx * yc;
-    int i = base + nxy * z0;
+    // Pm: the layer behind in the walk; tzm: the face between it and the
+    // current layer (tz holds each cell's face to the layer above)
+    int i = base + nxy * zs;
+    const bool hasb = dir > 0 ? zs > 0 : zs + 1 < nz;
+    const int ib = hasb ? i - dir * nxy : i;
     PT Pm[NS], Pc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         Pc[s] = bload<PT>(rP, i * SZ, s * NSZ);
-        Pm[s] = bload<PT>(rP, (z0 > 0 ? i - nxy : i) * SZ, s * NSZ);
+        Pm[s] = bload<PT>(rP, ib * SZ, s * NSZ);
     }
-    const PT tzm0 = bload<PT>(rZ, (z0 > 0 ? i - nxy : i) * SZ, 0);
-    PT tzm = z0 > 0 ? tzm0 : (PT)0;
+    const PT tzm0 = bload<PT>(rZ, (dir > 0 ? ib : i) * SZ, 0);
+    PT tzm = hasb ? tzm0 : (PT)0;
     double chg = 0.0;
 
     // rows y-1 and y+1 of the current layer: from the neighbouring
@@ -175,15 +184,16 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
     // first and last row of the workgroup load the row beyond from memory
     __shared__ PT rowbuf[2][kSweepRows][NS][64];
     const bool ym_mem = wv == 0, yp_mem = wv == kSweepRows - 1;
-    for (int z = z0; z < z1; ++z, i += nxy) {
-        const bool fzp = z + 1 < nz;
+    for (int st = 0; st < z1 - z0; ++st, i += dir * nxy) {
+        const int z = zs + st * dir;
+        const bool fza = dir > 0 ? z + 1 < nz : z > 0;  // a layer ahead in the walk
         const int lym = fym ? i - nx : i, lyp = fyp ? i + nx : i;
-        const int buf = (z - z0) & 1;
+        const int buf = st & 1;
 #pragma unroll
         for (int s = 0; s < NS; ++s) rowbuf[buf][wv][s][lane] = Pc[s];
         PT Pn[NS], Ym[NS], Yp[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) Pn[s] = bload<PT>(rP, (fzp ? i + nxy : i) * SZ, s * NSZ);
+        for (int s = 0; s < NS; ++s) Pn[s] = bload<PT>(rP, (fza ? i + dir * nxy : i) * SZ, s * NSZ);
         if (ym_mem) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) Ym[s] = bload<PT>(rP, lym * SZ, soym[s]);
@@ -193,7 +203,8 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
             for (int s = 0; s < NS; ++s) Yp[s] = bload<PT>(rP, lyp * SZ, soyp[s]);
         }
         const PT txc = bload<PT>(rX, i * SZ, 0), tym = bload<PT>(rY, lym * SZ, 0);
-        const PT tyc = bload<PT>(rY, i * SZ, 0), tzc = bload<PT>(rZ, i * SZ, 0);
+        const PT tyc = bload<PT>(rY, i * SZ, 0);
+        const PT tzc = bload<PT>(rZ, (dir > 0 || !fza ? i : i - nxy) * SZ, 0);  // face toward the layer ahead
         const double dg = bload<double>(rD, i * 8, 0);
         const int wz = (AM & 4) ? packz[z] : 0;
         const bool shz0 = (AM & 4) && ((wz >> 21) & 1), shz1 = (AM & 4) && ((wz >> 22) & 1);
@@ -238,11 +249,17 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
             nb[1][s] = (mX && (s & mX) && shx1) ? xp[s & ~mX] : xp[s];
             nb[2][s] = Ym[s];
             nb[3][s] = Yp[s];
-            nb[4][s] = (mZ && !(s & mZ) && shz0) ? Pm[s | mZ] : Pm[s];
-            nb[5][s] = (mZ && (s & mZ) && shz1) ? Pn[s & ~mZ] : Pn[s];
+            // below (z - 1) and above (z + 1): behind and ahead in an upward
+            // walk, ahead and behind in a downward one
+            const PT lo = dir > 0 ? Pm[s] : Pn[s], lo2 = dir > 0 ? Pm[s | mZ] : Pn[s | mZ];
+            const PT up = dir > 0 ? Pn[s] : Pm[s], up2 = dir > 0 ? Pn[s & ~mZ] : Pm[s & ~mZ];
+            nb[4][s] = (mZ && !(s & mZ) && shz0) ? lo2 : lo;
+            nb[5][s] = (mZ && (s & mZ) && shz1) ? up2 : up;
         }
         const bool sh[6] = {shx0, shx1, shy0, shy1, shz0, shz1};
-        const PT T[6] = {fxm ? txm : (PT)0, txc, fym ? tym : (PT)0, fyp ? tyc : (PT)0, tzm, fzp ? tzc : (PT)0};
+        const PT tza = fza ? tzc : (PT)0;
+        const PT T[6] = {fxm ? txm : (PT)0, txc, fym ? tym : (PT)0, fyp ? tyc : (PT)0, dir > 0 ? tzm : tza,
+                         dir > 0 ? tza : tzm};
 
         PT acc[NS];
 #pragma unroll
