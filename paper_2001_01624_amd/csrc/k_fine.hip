@@ -727,32 +727,54 @@ void launch_gmres_scale(Ctx &c, const double *w, double *v, int /*j*/) {
 
 // Back substitution R y = g over the jcur completed steps.
 // y = H^-1 g by back substitution (k = jcur columns); with zform also
-// w = T^-1 y, so that M^-1 Q y = Z w for the stored candidates Z.
-__global__ void k_gmres_solve_small(Status *st, double *scal, int zform) {
+// w = T^-1 y, so that M^-1 Q y = Z w for the stored candidates Z.  One
+// wavefront stages the triangles and g in LDS; lane 0 then substitutes in the
+// same order as a plain loop would (the global loads were its latency).
+__global__ __launch_bounds__(64) void k_gmres_solve_small(Status *st, double *scal, int zform) {
+    constexpr int KM = kMaxRestart;
+    __shared__ double Hs[KM * KM];
+    __shared__ double gs[KM], ys[KM];
     const double *H = scal + S_H;
     const double *g = scal + S_G;
-    double *y = scal + S_Y;
     const int ld = kMaxRestart + 1;
-    const int k = st->jcur;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int m = i + 1; m < k; ++m) s -= H[i + ld * m] * y[m];
-        y[i] = s / H[i + ld * i];
+    const int k = min(st->jcur, KM);
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e / k, m = e % k;
+        Hs[e] = m >= i ? H[i + ld * m] : 0.0;
     }
-    if (zform) {
-        const double *T = scal + kScalT;
-        double *w = scal + kScalW;
-        constexpr int lt = kDcgsMax + 1;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *y = scal + S_Y;
         for (int i = k - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int m = i + 1; m < k; ++m) s -= T[i + lt * m] * w[m];
-            w[i] = s / T[i + lt * i];
+            double s = gs[i];
+            for (int m = i + 1; m < k; ++m) s -= Hs[i * k + m] * ys[m];
+            ys[i] = s / Hs[i * k + i];
+            y[i] = ys[i];
+        }
+    }
+    if (!zform) return;
+    __syncthreads();
+    const double *T = scal + kScalT;
+    constexpr int lt = kDcgsMax + 1;
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e / k, m = e % k;
+        Hs[e] = m >= i ? T[i + lt * m] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *w = scal + kScalW;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = ys[i];
+            for (int m = i + 1; m < k; ++m) s -= Hs[i * k + m] * gs[m];
+            gs[i] = s / Hs[i * k + i];  // gs now holds w
+            w[i] = gs[i];
         }
     }
 }
 
 void launch_gmres_solve_small(Ctx &c, int /*restart*/, bool zform) {
-    hipLaunchKernelGGL(k_gmres_solve_small, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, zform ? 1 : 0);
+    hipLaunchKernelGGL(k_gmres_solve_small, dim3(1), dim3(64), 0, c.stream, c.status, c.scal, zform ? 1 : 0);
 }
 
 __global__ void k_axpy(int N, double *__restrict__ x, const double *__restrict__ z, const int *done) {
