@@ -1206,8 +1206,15 @@ __global__ __launch_bounds__(kBlock) void k_finish_n(const double *__restrict__ 
 // Finalise column j-1 and (unless final) prepare column j.  The pass-A
 // totals and the needed part of the unrotated Hessenberg matrix are staged
 // in LDS; sums run in index order.
+// With G > 0 the step first forms the pass-A totals itself from the G
+// per-block partials (one wavefront per total, lanes over the blocks, then
+// the fixed wavefront tree) and stores them where pass B reads them; used
+// when the grid of pass A is small enough that a separate finishing launch
+// would cost more than the sums.
+constexpr int kDstepFuseBlocks = 256;
+
 __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int j, double rtol, int max_iters,
-                                                  int final_) {
+                                                  int final_, const double *__restrict__ partial, int G) {
     constexpr int HL = kDcgsMax + 2;  // rows of the staged Hessenberg block
     __shared__ double Hs[HL][HL];     // Hs[l][i] = Hu(l, i)
     __shared__ double rcs[kDcgsMax + 1], rsn[kDcgsMax + 1], gv[kDcgsMax + 2];
@@ -1223,7 +1230,20 @@ __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int 
     double *cs = scal + S_CS;
     double *sn = scal + S_SN;
     const int na = final_ ? j + 1 : 2 * j + 2;
-    for (int i = tid; i < na; i += blockDim.x) A[i] = scal[S_DA + i];
+    if (G > 0) {
+        const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+        for (int q = wv; q < na; q += nwv) {
+            double v = 0.0;
+            for (int b = lane; b < G; b += 64) v += partial[(long)q * G + b];
+            v = wave_sum(v);
+            if (lane == 0) {
+                A[q] = v;
+                scal[S_DA + q] = v;
+            }
+        }
+    } else {
+        for (int i = tid; i < na; i += blockDim.x) A[i] = scal[S_DA + i];
+    }
     // columns 0..j-1, rows 0..j (upper Hessenberg: rows up to i + 1)
     for (int e = tid; e < j * (j + 1); e += blockDim.x) {
         const int i = e / (j + 1), l = e % (j + 1);
@@ -1376,10 +1396,12 @@ static void dgmres_step_k(Ctx &c, const VT *Q, VT *qout, double *unext, const do
             hipLaunchKernelGGL((k_dpass_a<KM, true, VT>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
                                c.partial, done);
     }
-    hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, G,
-                       c.scal + S_DA, st);
+    const bool fuse = G <= kDstepFuseBlocks;
+    if (!fuse)
+        hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, G,
+                           c.scal + S_DA, st);
     hipLaunchKernelGGL(k_dstep, dim3(1), dim3(kBlock), 0, c.stream, c.status, c.scal, j, rtol, max_iters,
-                       final_ ? 1 : 0);
+                       final_ ? 1 : 0, c.partial, fuse ? G : 0);
     if (final_) return;
     ProfScope ps(c, MSRSB_K_ORTHO);
     hipLaunchKernelGGL((k_dpass_b<KM, VT>), dim3(G), dim3(kBlock), 0, c.stream, c.N, Q, u, w, j, qout, unext, c.scal,
