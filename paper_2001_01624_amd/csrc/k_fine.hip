@@ -1213,6 +1213,14 @@ __global__ __launch_bounds__(kBlock) void k_finish_n(const double *__restrict__ 
 // would cost more than the sums.
 constexpr int kDstepFuseBlocks = 256;
 
+// Grid of pass A: at most three workgroups per CU (256 CUs), so that with the
+// FP64 matrix-vector form (about 133 VGPRs, three wavefronts per SIMD) every
+// workgroup is resident at once and each XCD gets the same number.  On the
+// 60x220x85 model this ran the 16-vector pass in 32.9 instead of 36.0 us
+// (FP32 basis: 21.2 instead of 26.0 us) against the 2048 blocks of the other
+// reductions; 512 was close, and 640 or 384 (uneven per CU) slower.
+constexpr int kPassABlocks = 768;
+
 __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int j, double rtol, int max_iters,
                                                   int final_, const double *__restrict__ partial, int G) {
     constexpr int HL = kDcgsMax + 2;  // rows of the staged Hessenberg block
@@ -1384,24 +1392,24 @@ template <int KM, typename VT>
 static void dgmres_step_k(Ctx &c, const VT *Q, VT *qout, double *unext, const double *z, double *w, const double *u,
                           int j, double rtol, int max_iters, bool final_) {
     Fine g = fine_of(c);
-    const int G = red_grid(c.N);
+    const int G = red_grid(c.N), GA = std::min(G, kPassABlocks);
     const int *done = &c.status->done;
     const Status *st = c.status;
     {
         ProfScope ps(c, final_ ? MSRSB_K_ORTHO : MSRSB_K_MATVEC);
         if (final_)
-            hipLaunchKernelGGL((k_dpass_a<KM, false, VT>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
+            hipLaunchKernelGGL((k_dpass_a<KM, false, VT>), dim3(GA), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
                                c.partial, done);
         else
-            hipLaunchKernelGGL((k_dpass_a<KM, true, VT>), dim3(G), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
+            hipLaunchKernelGGL((k_dpass_a<KM, true, VT>), dim3(GA), dim3(kBlock), 0, c.stream, g, z, w, Q, u, j,
                                c.partial, done);
     }
-    const bool fuse = G <= kDstepFuseBlocks;
+    const bool fuse = GA <= kDstepFuseBlocks;
     if (!fuse)
-        hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, G,
+        hipLaunchKernelGGL(k_finish_n, dim3(final_ ? j + 1 : 2 * j + 2), dim3(kBlock), 0, c.stream, c.partial, GA,
                            c.scal + S_DA, st);
     hipLaunchKernelGGL(k_dstep, dim3(1), dim3(kBlock), 0, c.stream, c.status, c.scal, j, rtol, max_iters,
-                       final_ ? 1 : 0, c.partial, fuse ? G : 0);
+                       final_ ? 1 : 0, c.partial, fuse ? GA : 0);
     if (final_) return;
     ProfScope ps(c, MSRSB_K_ORTHO);
     hipLaunchKernelGGL((k_dpass_b<KM, VT>), dim3(G), dim3(kBlock), 0, c.stream, c.N, Q, u, w, j, qout, unext, c.scal,
