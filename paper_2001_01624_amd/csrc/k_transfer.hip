@@ -269,9 +269,12 @@ __global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fin
     }
 }
 
-// four wavefronts with two rows each in flight measured fastest on the
-// 60x220x85 model (4x3, 4x4, 8x2, 8x3, 16x1 and 16x2 were slower)
-constexpr int kRestrictWaves = 4, kRestrictUnroll = 2;
+// four wavefronts with one row each in flight measured fastest on the
+// 60x220x85 model (25.6 and 28.0 us on its two stages, against 26.5 and
+// 28.8 us with two rows each: fewer registers, more wavefronts resident);
+// 8x1 won on one stage and lost on the other, and 2x1, 2x2, 4x3, 4x4, 8x2,
+// 8x3, 16x1 and 16x2 were slower
+constexpr int kRestrictWaves = 4, kRestrictUnroll = 1;
 
 template <typename PS, bool RES>
 static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, const double *x, const int *done) {
