@@ -463,8 +463,10 @@ def dynamic_partition(prob, dp, general_block, n_bins=4, max_blocks=4096):
             if lab[c] not in first:
                 first[lab[c]] = (int(general_block[c]), int(c))
         order = sorted(first.items(), key=lambda kv: kv[1])
-        if len(order) <= max_blocks or nb == 1:
+        if len(order) <= max_blocks:
             break
+        if nb == 1:
+            raise OracleError(E_INVAL, "dynamic partition exceeds max_blocks even with one bin")
         nb //= 2
     newid = {key: j for j, (key, _) in enumerate(order)}
     block = np.full(prob.n_cells, -1, dtype=np.int64)
