@@ -119,7 +119,11 @@ typedef struct {
 void msrsb_default_options(msrsb_options *opt);
 
 /* Device bytes msrsb_setup will allocate for this input (dynamic stages
- * excluded: each adds about 12*N + 16*M^2 bytes).  Returns 0 on invalid input. */
+ * excluded: each adds about 8*N + 16*M^2 bytes, M padded to a multiple of
+ * 64).  Returns 0 on invalid input, including grids the kernels cannot
+ * address: N = nx*ny*nz at most (2^31 - 1)/8 cells, and for every stage
+ * (slots per cell) * N * 8 bytes below 2^31 (a 3-D rectilinear stage has 8
+ * slots per cell, so N <= 33,554,431 there). */
 size_t msrsb_footprint_bytes(const msrsb_grid *grid, int n_part, const msrsb_partition *parts,
                              const msrsb_options *opt);
 
@@ -159,7 +163,8 @@ int msrsb_update_basis(msrsb_ctx *ctx, int stage, int max_sweeps, double tol, in
  * cells get bin = #{k = 1..n_bins-1 : a <= ldexp(max a, -2k)}, cells with
  * the same (stage-0 block, bin) key that are face connected form one block,
  * blocks are numbered by (stage-0 block, smallest cell index); if more than
- * max_dyn_blocks result, n_bins is halved and the binning repeated.  An
+ * max_dyn_blocks result, n_bins is halved and the binning repeated (E_INVAL
+ * if even one bin gives more; no stage of that call is kept then).  An
  * increment with max |dp| = 0 or non-finite adds no stage (count 0).
  * Replaces any previous dynamic stages.  n_dyn_blocks[k] (host, may be NULL)
  * receives the block count of each increment.
@@ -179,10 +184,12 @@ int msrsb_clear_dynamic_basis(msrsb_ctx *ctx);
  * runs after every full cycle.  outer = GMRES: restarted GMRES with one such
  * cycle (from a zero guess) as right preconditioner (section "Description of
  * the solution procedure").  max_iters bounds cycles / GMRES iterations.
- * iters, relres (host, may be NULL): iterations used and final relative
- * residual (FP64, recomputed from the final iterate for Richardson; the
- * least-squares estimate for GMRES).  Returns E_NOCONV with the last
- * iterate in d_p if the limit is reached; E_STATE before update_basis.
+ * iters, relres (host, may be NULL): iterations used and the relative
+ * residual ||b - A p||_2 / ||b||_2 of the returned iterate, computed in FP64
+ * from that iterate (for GMRES at the restart that ends the solve; the
+ * least-squares estimate only decides when an inner cycle stops).  Returns
+ * E_NOCONV with the last iterate in d_p if the limit is reached; E_STATE
+ * before update_basis.
  */
 int msrsb_solve(msrsb_ctx *ctx, const double *d_source, double *d_p, double rtol, int max_iters,
                 int *iters, double *relres);
@@ -222,6 +229,17 @@ int msrsb_stage_info(msrsb_ctx *ctx, int stage, int *M, int *kind, int *n_slots)
  */
 int msrsb_export_stage(msrsb_ctx *ctx, int stage, int32_t *h_block, int32_t *h_slot_block, double *h_vals,
                        double *h_Ac);
+
+/*
+ * Coarse solve of one stage (eq. pressure_system_reduced; section
+ * "Computational efficiency": the coarse system solved directly): h_pc =
+ * A_c^{-1} h_d with the explicit inverse built by msrsb_update_basis or
+ * msrsb_add_dynamic_basis, applied by the same kernel every cycle uses.  Host
+ * arrays of M entries (M from msrsb_stage_info), in the stage's block order.
+ * For tests and inspection.  Errors: E_INVAL (no such stage), E_STATE (the
+ * stage has no coarse operator yet), E_DEVICE.
+ */
+int msrsb_coarse_apply(msrsb_ctx *ctx, int stage, const double *h_d, double *h_pc);
 
 /*
  * Host-only helpers (no device needed):

@@ -76,6 +76,7 @@ def _load():
         "msrsb_num_stages": (I, [VP]),
         "msrsb_stage_info": (I, [VP, I, P(I), P(I), P(I)]),
         "msrsb_export_stage": (I, [VP, I, P(C.c_int32), P(C.c_int32), P(D), P(D)]),
+        "msrsb_coarse_apply": (I, [VP, I, P(D), P(D)]),
         "msrsb_set_stream": (I, [VP, VP]),
         "msrsb_destroy": (None, [VP]),
         "msrsb_validate_grid": (I, [P(Grid)]),
@@ -182,13 +183,17 @@ def footprint_bytes(prob, partitions, options=None) -> int:
     return int(_lib.msrsb_footprint_bytes(C.byref(ga.grid), len(partitions), parts, C.byref(o)))
 
 
-def _dptr(t, dtype="float64"):
-    import torch
-
+def _dptr(t, n=None, device=None, dtype="float64"):
+    """Device address of a contiguous tensor of ``n`` elements on ``device``;
+    anything else is rejected before a kernel could read or write past it."""
     if t is None:
         return None
     if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == f"torch.{dtype}"):
         raise MsrsbError(E_INVAL, f"expected a contiguous {dtype} device tensor")
+    if n is not None and t.numel() != n:
+        raise MsrsbError(E_INVAL, f"expected {n} entries, got {t.numel()}")
+    if device is not None and t.device.index != device:
+        raise MsrsbError(E_INVAL, f"tensor on cuda:{t.device.index}, the context lives on cuda:{device}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -205,12 +210,17 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
         ga = _GridArrays(prob)
         parts = _parts(partitions)
         h = C.c_void_p()
         _check(_lib.msrsb_setup(C.byref(ga.grid), len(partitions), parts, C.byref(self.options),
                                 C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
+
+    def _vec(self, t):
+        """A per-cell device vector of this context ([N] float64 on its device)."""
+        return _dptr(t, n=self.N, device=self.device)
 
     def close(self):
         if getattr(self, "h", None):
@@ -230,7 +240,7 @@ class Solver:
         return sw.value, ch.value
 
     def add_dynamic_basis(self, increments):
-        ptrs = (C.c_void_p * len(increments))(*[_dptr(t).value for t in increments])
+        ptrs = (C.c_void_p * len(increments))(*[self._vec(t).value for t in increments])
         counts = (C.c_int * len(increments))()
         _check(_lib.msrsb_add_dynamic_basis(self.h, len(increments), ptrs, counts))
         return list(counts)
@@ -242,7 +252,8 @@ class Solver:
         """Solve in place on the device tensor ``p``; returns (iters, relres, status)."""
         it = C.c_int(0)
         rel = C.c_double(0.0)
-        rc = _check(_lib.msrsb_solve(self.h, _dptr(source), _dptr(p), rtol, max_iters, C.byref(it), C.byref(rel)),
+        rc = _check(_lib.msrsb_solve(self.h, self._vec(source), self._vec(p), rtol, max_iters, C.byref(it),
+                                     C.byref(rel)),
                     allow=(E_NOCONV,))
         return it.value, rel.value, rc
 
@@ -251,7 +262,7 @@ class Solver:
 
         if out is None:
             out = torch.empty_like(x)
-        _check(_lib.msrsb_apply(self.h, op, _dptr(x), _dptr(out)))
+        _check(_lib.msrsb_apply(self.h, op, self._vec(x), self._vec(out)))
         return out
 
     def fluxes(self, p):
@@ -259,7 +270,7 @@ class Solver:
 
         face = torch.empty(3 * self.N, dtype=torch.float64, device=p.device)
         bcf = torch.empty(max(self.n_bc, 1), dtype=torch.float64, device=p.device)
-        _check(_lib.msrsb_fluxes(self.h, _dptr(p), _dptr(face), _dptr(bcf)))
+        _check(_lib.msrsb_fluxes(self.h, self._vec(p), _dptr(face), _dptr(bcf)))
         return face.view(3, self.N), bcf[: self.n_bc]
 
     def profile_begin(self, kernel_class, max_launches=100000):
@@ -294,6 +305,16 @@ class Solver:
             out["values"] = vals.reshape(ns, self.N)
         if coarse:
             out["Ac"] = Ac.reshape(M, M)
+        return out
+
+    def coarse_apply(self, k, d):
+        """``A_c^{-1} d`` by stage k's coarse solve (host vectors of M entries)."""
+        M, _, _ = self.stage_info(k)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        if d.size != M:
+            raise MsrsbError(E_INVAL, f"expected {M} entries, got {d.size}")
+        out = np.zeros(M)
+        _check(_lib.msrsb_coarse_apply(self.h, k, _ptr(d, C.c_double), _ptr(out, C.c_double)))
         return out
 
     def dense_basis(self, k):

@@ -67,6 +67,16 @@ void *ctx_alloc(Ctx &c, size_t bytes) {
     return p;
 }
 
+// Return a buffer of ctx_alloc to the pool in the stream's order.  Buffers
+// carved from the set-up arena are left alone (the arena is freed whole).
+void ctx_free(Ctx &c, void *p) {
+    if (!p) return;
+    auto it = std::find(c.allocs.begin(), c.allocs.end(), p);
+    if (it == c.allocs.end()) return;
+    (void)hipFreeAsync(p, c.stream);
+    c.allocs.erase(it);
+}
+
 // Host -> device copy on the context's stream (the caller keeps the host
 // buffer alive until the stream is synchronised).
 static bool upload(Ctx &c, void *dst, const void *src, size_t bytes) {
@@ -99,6 +109,12 @@ static void release_pinned_status(Status *p) {
 }
 
 // ------------------------------------------------------------ validation ----
+
+// The basis kernels address a stage's slot-major arrays with 32-bit byte
+// offsets (buffer resources of at most 2^31 - 1 bytes): ns slots of N cells
+// in FP64 must stay below that.
+static bool slots_fit(long ns, long N) { return ns * N * (long)sizeof(double) <= 0x7fffffffL; }
+
 
 struct DSU {
     std::vector<int> p;
@@ -466,6 +482,10 @@ static int build_fault_stage(Ctx &c, const msrsb_partition &p, int index, Stage 
         set_error("fault-cut stage needs %d slots per cell (limit %d)", ns, kMaxXSlots);
         return MSRSB_E_INVAL;
     }
+    if (!slots_fit(ns, N)) {
+        set_error("fault-cut stage: %d basis slots of %d cells exceed the 2^31-byte slot arrays of the kernels", ns, N);
+        return MSRSB_E_INVAL;
+    }
     s.kind = 2;
     s.parent = p.parent;
     s.ns = ns;
@@ -763,11 +783,19 @@ static int check_parts(const msrsb_grid *g, int n_part, const msrsb_partition *p
             return MSRSB_E_INVAL;
         }
         const int n[3] = {g->nx, g->ny, g->nz};
-        for (int a = 0; a < 3; ++a)
+        int nbits = 0;
+        for (int a = 0; a < 3; ++a) {
             if (parts[k].coarse_dims[a] < 1 || parts[k].coarse_dims[a] > n[a]) {
                 set_error("partition %d: coarse_dims[%d] = %d outside [1, %d]", k, a, parts[k].coarse_dims[a], n[a]);
                 return MSRSB_E_INVAL;
             }
+            nbits += parts[k].coarse_dims[a] > 1;
+        }
+        if (!slots_fit(1 << nbits, (long)g->nx * g->ny * g->nz)) {
+            set_error("partition %d: %d basis slots of %ld cells exceed the 2^31-byte slot arrays of the kernels", k,
+                      1 << nbits, (long)g->nx * g->ny * g->nz);
+            return MSRSB_E_INVAL;
+        }
     }
     return MSRSB_OK;
 }
@@ -795,7 +823,9 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     msrsb_options o;
     if (opt) o = *opt;
     else msrsb_default_options(&o);
-    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || check_options(&o) || check_parts(g, n_part, parts)) return 0;
+    if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1 || (long)g->nx * g->ny * g->nz > 0x7fffffffL / 8 ||
+        check_options(&o) || check_parts(g, n_part, parts))
+        return 0;
     Ctx c;
     c.opt = o;
     c.nx = g->nx; c.ny = g->ny; c.nz = g->nz;
@@ -1036,20 +1066,26 @@ int msrsb_add_dynamic_basis(msrsb_ctx *c, int n_incr, const double *const *d_dp,
     if ((int)c->dyn.size() < 2) c->dyn.resize(2);
     for (int k = 0; k < 2; ++k) c->dyn[k].M = 0;
     int slot = 0;
+    // on any failure no dynamic stage of this call stays in the cycle
+    auto fail = [&](int rc) {
+        for (int k = 0; k < 2; ++k) c->dyn[k].M = 0;
+        return rc;
+    };
     for (int k = 0; k < n_incr; ++k) {
         int count = 0;
         Stage &s = c->dyn[slot];
         int rc = build_dynamic_stage(*c, d_dp[k], s, &count);
-        if (rc) return rc;
+        if (rc) return fail(rc);
         if (n_dyn_blocks) n_dyn_blocks[k] = count;
         if (count == 0) continue;
         if (s.Mp > c->cbuf_n) {
+            ctx_free(*c, c->cbuf);
             c->cbuf = (double *)ctx_alloc(*c, 8 * (size_t)(s.Mp + 2 * kTile) * kTile);
-            if (!c->cbuf) return MSRSB_E_NOMEM;
-            c->cbuf_n = s.Mp;
+            c->cbuf_n = c->cbuf ? s.Mp : 0;
+            if (!c->cbuf) return fail(MSRSB_E_NOMEM);
         }
         launch_dyn_rap(*c, s);
-        if ((rc = finish_coarse(*c, s))) return rc;
+        if ((rc = finish_coarse(*c, s))) return fail(rc);
         s.has_basis = true;
         ++slot;
     }
@@ -1242,6 +1278,36 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
                             hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "export A_c");
     }
+    return MSRSB_OK;
+}
+
+int msrsb_coarse_apply(msrsb_ctx *c, int stage, const double *h_d, double *h_pc) {
+    g_err.clear();
+    if (!c || !h_d || !h_pc) {
+        set_error("bad coarse-apply arguments");
+        return MSRSB_E_INVAL;
+    }
+    Stage *s = stage_at(c, stage);
+    if (!s) {
+        set_error("no stage %d", stage);
+        return MSRSB_E_INVAL;
+    }
+    if (!s->has_basis) {
+        set_error("stage %d has no coarse operator yet", stage);
+        return MSRSB_E_STATE;
+    }
+    const int M = s->M;
+    hipError_t e = hipMemcpyAsync(s->dvec, h_d, 8 * (size_t)M, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "coarse apply upload");
+    launch_coarse_solve(*c, *s, nullptr);
+    // rectilinear stages keep p_c per Cartesian block (entry j at present[j])
+    const size_t n = s->pc_map ? (size_t)s->cart.m[0] * s->cart.m[1] * s->cart.m[2] : (size_t)M;
+    std::vector<double> pc(n);
+    e = hipMemcpyAsync(pc.data(), s->pc, 8 * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "coarse apply");
+    for (int j = 0; j < M; ++j) h_pc[j] = s->pc_map ? pc[s->h_present[j]] : pc[j];
     return MSRSB_OK;
 }
 

@@ -392,7 +392,12 @@ int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count) {
         Status st;
         if ((rc = sync_read(c, &st, c.status, sizeof(Status)))) return rc;
         total = st.iters;
-        if (total <= c.opt.max_dyn_blocks || nb == 1) break;
+        if (total <= c.opt.max_dyn_blocks) break;
+        if (nb == 1) {
+            set_error("dynamic partition has %d blocks with one bin, more than max_dyn_blocks = %d", total,
+                      c.opt.max_dyn_blocks);
+            return MSRSB_E_INVAL;
+        }
         nb /= 2;
     }
     // (re)allocate the stage buffers
@@ -403,6 +408,9 @@ int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count) {
         if (!out.dblock || !out.dcells) return MSRSB_E_NOMEM;
     }
     if (Mp > out.Mp) {
+        // the smaller buffers of an earlier increment go back to the pool
+        for (void *p : {(void *)out.dptr, (void *)out.Ac, (void *)out.Ainv, (void *)out.dvec, (void *)out.pc})
+            ctx_free(c, p);
         out.dptr = (int32_t *)ctx_alloc(c, sizeof(int32_t) * (size_t)(Mp + 1));
         out.Ac = (double *)ctx_alloc(c, sizeof(double) * (size_t)Mp * Mp);
         out.Ainv = (double *)ctx_alloc(c, sizeof(double) * (size_t)Mp * Mp);

@@ -1440,9 +1440,9 @@ void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int
                         bool final_) {
     const long N = c.N;
     if (c.Vf)
-        dgmres_step_t<float>(c, c.Vf, c.Vf + j * N, c.V + ((j + 1) & 1) * N, z, w, u, j, rtol, max_iters, final_);
+        dgmres_step_t<float>(c, c.Vf, c.Vf + (long)j * N, c.V + (long)((j + 1) & 1) * N, z, w, u, j, rtol, max_iters, final_);
     else
-        dgmres_step_t<double>(c, c.V, c.V + j * N, c.V + (j + 1) * N, z, w, u, j, rtol, max_iters, final_);
+        dgmres_step_t<double>(c, c.V, c.V + (long)j * N, c.V + (long)(j + 1) * N, z, w, u, j, rtol, max_iters, final_);
 }
 
 void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int max_iters, int restart) {

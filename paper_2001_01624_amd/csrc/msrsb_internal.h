@@ -199,6 +199,7 @@ void launch_gmres_begin(Ctx &c, double rtol, int max_iters);
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
 size_t rap_part_doubles(int ns, int nbox);
 void *ctx_alloc(Ctx &c, size_t bytes);
+void ctx_free(Ctx &c, void *p);
 void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf);
 // GMRES helpers
 void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_out, const int *done);

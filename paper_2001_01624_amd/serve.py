@@ -32,8 +32,10 @@ def request_footprint(req, options) -> int:
     if base == 0:
         return 0
     mdyn = min(options.max_dyn_blocks, int(req.problem.n_active))
-    mp = -(-mdyn // 32) * 32
-    dyn = 2 * (8 * N + 16 * mp * mp + 16 * mp)
+    mp = -(-mdyn // 64) * 64  # coarse matrices are padded to the 64-wide inverse tiles
+    # per stage: block map and cell list, A_c and its inverse, coarse vectors;
+    # plus a coarse-inverse panel of that height should it outgrow the set-up one
+    dyn = 2 * (8 * N + 16 * mp * mp + 24 * mp) + 8 * (mp + 128) * 64
     vecs = 8 * N * (4 + len(req.sources))
     return int(base + dyn + vecs)
 

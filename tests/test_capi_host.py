@@ -95,3 +95,61 @@ def test_footprint_is_positive_and_grows():
     gm = capi.footprint_bytes(p, parts, capi.default_options(outer="gmres"))
     assert f64 > 3600 * 8 * 10 and gm > f64 and mixed > 0
     assert capi.footprint_bytes(p, [{"kind": "cartesian", "coarse_dims": (100, 1, 1)}]) == 0
+
+
+def _bare_grid(nx, ny, nz):
+    # only the box size: msrsb_footprint_bytes reads no per-cell array
+    g = capi.Grid()
+    g.nx, g.ny, g.nz = nx, ny, nz
+    return g
+
+
+def _footprint(dims, cd, **opt):
+    import ctypes
+
+    parts = capi._parts([{"kind": "cartesian", "coarse_dims": cd}])
+    o = capi.default_options(**opt)
+    return int(capi._lib.msrsb_footprint_bytes(ctypes.byref(_bare_grid(*dims)), 1, parts, ctypes.byref(o)))
+
+
+def test_footprint_rejects_grids_beyond_32_bit_slot_offsets():
+    # a 3-D rectilinear stage keeps 8 slots per cell; the basis kernels address
+    # them with 32-bit byte offsets, so 8 slots * N * 8 bytes must stay < 2^31
+    assert _footprint((256, 256, 511), (8, 8, 8)) > 0          # N < 2^25: 8 * N * 8 < 2^31
+    assert _footprint((256, 256, 512), (8, 8, 8)) == 0         # N = 2^25: 8 * N * 8 = 2^31
+    assert _footprint((256, 600, 500), (8, 8, 8)) == 0         # N = 76.8 M: slots overflow
+    assert _footprint((256, 600, 500), (8, 8, 8), precision="mixed") == 0
+    # fewer split axes, fewer slots: a 1-D partition of the same grid fits
+    assert _footprint((256, 600, 500), (8, 1, 1)) > 0
+    # more than (2^31 - 1) / 8 cells is refused outright
+    assert _footprint((1024, 1024, 300), (1, 1, 1)) == 0
+
+
+class _FakeDeviceTensor:
+    """Just enough of a tensor's interface for the binding's argument checks."""
+
+    def __init__(self, n, device=0, dtype="float64", contiguous=True):
+        import types
+
+        self.is_cuda = True
+        self._n, self._c = n, contiguous
+        self.dtype = f"torch.{dtype}"
+        self.device = types.SimpleNamespace(index=device)
+
+    def is_contiguous(self):
+        return self._c
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_rejects_wrong_vectors_before_any_call():
+    assert capi._dptr(_FakeDeviceTensor(10), n=10, device=0).value == 0x1000
+    for bad in (_FakeDeviceTensor(9), _FakeDeviceTensor(11), _FakeDeviceTensor(10, device=1),
+                _FakeDeviceTensor(10, dtype="float32"), _FakeDeviceTensor(10, contiguous=False)):
+        with pytest.raises(capi.MsrsbError) as e:
+            capi._dptr(bad, n=10, device=0)
+        assert e.value.code == capi.E_INVAL

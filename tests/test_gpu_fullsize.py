@@ -118,6 +118,28 @@ def test_full_sweeps_and_galerkin(capi, layered):
         assert relerr(e2["Ac"], Aco) <= 1e-12
 
 
+def test_full_coarse_inverse(capi, layered):
+    """The coarse solves of both general stages (M = 500 and 2244: 8 and 36
+    Gauss-Jordan panels) entry by entry against a Cholesky solve of the same
+    A_c, within M kappa(A_c) eps of the largest entry."""
+    prob, _, parts, g, o = layered
+    g.update_basis(-1, 100, 1e-3)
+    eps = np.finfo(np.float64).eps
+    for k in range(len(parts)):
+        Ac = g.export_stage(k)["Ac"]
+        M = Ac.shape[0]
+        assert np.abs(Ac - Ac.T).max() == 0.0
+        lam = np.linalg.eigvalsh(Ac)
+        kappa = lam[-1] / lam[0]
+        for seed in (0, 1):
+            d = np.random.default_rng(seed).standard_normal(M)
+            ref = O.coarse_solve(O.coarse_factor(Ac), d)
+            pc = g.coarse_apply(k, d)
+            err = np.abs(pc - ref).max() / np.abs(ref).max()
+            say(f"stage {k}: M = {M}, kappa {kappa:.2e}, coarse-solve error {err:.2e}, bound {M * kappa * eps:.2e}")
+            assert err <= M * kappa * eps
+
+
 def test_full_smoother_equation(capi, layered):
     prob, _, parts, g, o = layered
     F = O.ilu0_rb_fill(o.A, o.cells, prob.dims)

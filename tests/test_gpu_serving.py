@@ -21,7 +21,7 @@ def mods():
     return capi, serve
 
 
-def small_requests(n=6, seed=0):
+def small_requests(n=6, seed=0, min_sources=1):
     rng = rng_for(6, seed)
     models = [make_lognormal_box((24, 20, 8), rng_for(6, 100 + k), sigma=2.0, corr=(2, 2, 2)) for k in range(3)]
     big = make_config1(dims=(20, 36, 14), seed=seed)
@@ -33,24 +33,32 @@ def small_requests(n=6, seed=0):
             prob, parts, kind = big, [{"kind": "cartesian", "coarse_dims": (4, 3, 2)}], "large"
         else:
             prob, parts, kind = models[r % 3], [{"kind": "cartesian", "coarse_dims": (4, 4, 2)}], "small"
-        reqs.append(Request(r, t, prob, parts, source_sequence(prob, rng, int(rng.integers(1, 5))), kind))
+        k = max(min_sources, int(rng.integers(1, 5)))
+        reqs.append(Request(r, t, prob, parts, source_sequence(prob, rng, k), kind))
     return reqs
 
 
-def test_alone_equals_mixed(mods):
+@pytest.mark.parametrize("precision,slots", [("fp64", 4), ("fp64", 8), ("mixed", 8)])
+def test_alone_equals_mixed(mods, precision, slots):
+    # each request alone on one slot, then all of them at once on `slots`
+    # slots: every request has at least three solves, so its last solves run
+    # with dynamic stages built from its own increments; every reduction has a
+    # fixed order, so each solution is bit for bit the same in the mix
     capi, serve = mods
-    a, b = small_requests(), small_requests()
-    print("requests", [(r.kind, len(r.sources)) for r in a], flush=True)
-    serve.Server(slots=1, keep_solutions=True).run(a, realtime=False)
-    st = serve.Server(slots=4, keep_solutions=True).run(b, realtime=False)
+    a, b = small_requests(n=10, min_sources=3), small_requests(n=10, min_sources=3)
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=precision)
+    print(precision, slots, "requests", [(r.kind, len(r.sources)) for r in a], flush=True)
+    serve.Server(slots=1, options=opt, keep_solutions=True).run(a, realtime=False)
+    st = serve.Server(slots=slots, options=opt, keep_solutions=True).run(b, realtime=False)
     assert st["completed"] == len(b) and st["all_converged"]
+    assert all(len(r.dyn_blocks) >= 1 and all(c > 0 for c in r.dyn_blocks[-1]) for r in b)
     worst = 0.0
     for ra, rb in zip(a, b):
-        assert ra.iters == rb.iters
+        assert ra.iters == rb.iters and ra.dyn_blocks == rb.dyn_blocks
         for xa, xb in zip(ra.solutions, rb.solutions):
             worst = max(worst, float(np.abs(xa - xb).max() / np.abs(xa).max()))
-    print("alone vs mixed: max relative difference", worst)
-    assert worst <= 1e-12
+    print("alone vs mixed: max relative difference", worst, flush=True)
+    assert worst == 0.0
 
 
 def test_tolerance_on_fp64_residual(mods):

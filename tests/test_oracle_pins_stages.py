@@ -344,3 +344,22 @@ def test_cartesian_support_3d_brute_force(dims, cd):
     np.testing.assert_array_equal(S, expect)
     # and every active cell's own block is in its support
     assert np.all(S[np.arange(cells.size), block[cells]] == 1)
+
+
+def test_dynamic_cap_beyond_one_bin_is_an_error():
+    # With one bin every general block is one key; a general block cut in two
+    # by an inactive column gives two pieces, so 36 general blocks plus the cut
+    # exceed a cap of 36 even with a single bin.
+    from workloads import make_config0
+
+    prob = make_config0(4)
+    o = O.Oracle(prob, [{"kind": "cartesian", "coarse_dims": (6, 6, 1)}], n_bins=1, max_dyn_blocks=36)
+    dp = np.random.default_rng(3).standard_normal(prob.n_cells)
+    blk, M, nb = O.dynamic_partition(prob, dp, o.stages[0].block, n_bins=1, max_blocks=36)
+    assert M == 36 and nb == 1
+    with pytest.raises(O.OracleError) as e:
+        O.dynamic_partition(prob, dp, o.stages[0].block, n_bins=1, max_blocks=35)
+    assert e.value.code == O.msrsb.E_INVAL
+    with pytest.raises(O.OracleError):
+        o2 = O.Oracle(prob, [{"kind": "cartesian", "coarse_dims": (6, 6, 1)}], n_bins=4, max_dyn_blocks=20)
+        o2.add_dynamic_basis([dp])
