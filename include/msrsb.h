@@ -231,6 +231,24 @@ int msrsb_export_stage(msrsb_ctx *ctx, int stage, int32_t *h_block, int32_t *h_s
                        double *h_Ac);
 
 /*
+ * Allocation-free form of msrsb_export_stage, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops
+ * that checkpoint a resident basis, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and errors as msrsb_export_stage, and it calls no
+ * device allocator.  A BF16 (mixed-precision) basis is widened to FP64 one
+ * slot column at a time through a staging array of MSRSB_NOALLOC_MAX_CELLS
+ * doubles (16 MiB) that the library keeps in device memory: each device the
+ * library runs on holds one such array until the process ends.  Grids of
+ * more than MSRSB_NOALLOC_MAX_CELLS cells (nx*ny*nz) are rejected with
+ * E_INVAL.  Every call on one device shares that device's array, so calls
+ * that overlap on one device (contexts on different streams or threads)
+ * race and must be serialised by the caller.
+ */
+#define MSRSB_NOALLOC_MAX_CELLS 2097152
+int msrsb_export_stage_noalloc(msrsb_ctx *ctx, int stage, int32_t *h_block, int32_t *h_slot_block,
+                               double *h_vals, double *h_Ac);
+
+/*
  * Coarse solve of one stage (eq. pressure_system_reduced; section
  * "Computational efficiency": the coarse system solved directly): h_pc =
  * A_c^{-1} h_d with the explicit inverse built by msrsb_update_basis or

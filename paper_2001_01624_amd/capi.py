@@ -21,6 +21,7 @@ SMOOTH_JACOBI, SMOOTH_ILU0_RB = 0, 1
 FP64, MIXED = 0, 1
 RICHARDSON, GMRES = 0, 1
 OP_RESIDUAL, OP_SMOOTH, OP_PRECOND, OP_MATVEC = 0, 1, 2, 3
+NOALLOC_MAX_CELLS = 2097152
 K_CLASSES = {"sweep": 1, "residual": 2, "smooth": 3, "restrict": 4, "prolong": 5, "coarse": 6, "ortho": 7,
              "matvec": 8, "rap": 9, "inverse": 10}
 _NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_SINGULAR", -5: "E_NOCONV", -6: "E_STATE"}
@@ -76,6 +77,7 @@ def _load():
         "msrsb_num_stages": (I, [VP]),
         "msrsb_stage_info": (I, [VP, I, P(I), P(I), P(I)]),
         "msrsb_export_stage": (I, [VP, I, P(C.c_int32), P(C.c_int32), P(D), P(D)]),
+        "msrsb_export_stage_noalloc": (I, [VP, I, P(C.c_int32), P(C.c_int32), P(D), P(D)]),
         "msrsb_coarse_apply": (I, [VP, I, P(D), P(D)]),
         "msrsb_set_stream": (I, [VP, VP]),
         "msrsb_destroy": (None, [VP]),
@@ -292,14 +294,16 @@ class Solver:
         _check(_lib.msrsb_stage_info(self.h, k, C.byref(M), C.byref(kind), C.byref(ns)))
         return M.value, kind.value, ns.value
 
-    def export_stage(self, k, values=True, coarse=True):
+    def export_stage(self, k, values=True, coarse=True, noalloc=False):
+        """Stage k as host arrays; ``noalloc`` uses ``msrsb_export_stage_noalloc``."""
         M, kind, ns = self.stage_info(k)
         block = np.zeros(self.N, np.int32)
         slots = np.zeros(ns * self.N, np.int32)
         vals = np.zeros(ns * self.N) if values else None
         Ac = np.zeros(M * M) if coarse else None
-        _check(_lib.msrsb_export_stage(self.h, k, _ptr(block, C.c_int32), _ptr(slots, C.c_int32),
-                                       _ptr(vals, C.c_double), _ptr(Ac, C.c_double)))
+        fn = _lib.msrsb_export_stage_noalloc if noalloc else _lib.msrsb_export_stage
+        _check(fn(self.h, k, _ptr(block, C.c_int32), _ptr(slots, C.c_int32), _ptr(vals, C.c_double),
+                  _ptr(Ac, C.c_double)))
         out = {"M": M, "kind": kind, "n_slots": ns, "block": block, "slot_block": slots.reshape(ns, self.N)}
         if values:
             out["values"] = vals.reshape(ns, self.N)

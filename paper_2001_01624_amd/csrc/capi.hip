@@ -1281,6 +1281,105 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
     return MSRSB_OK;
 }
 
+// ------------------------------------------------ allocation-free export ----
+// Staging array of msrsb_export_stage_noalloc: one slot column of a BF16
+// basis widened to FP64.  Each device holds its own copy until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy: the
+// name is a host-side stand-in, the device address comes from
+// hipGetSymbolAddress (once per device, with that device current).
+static __device__ __align__(256) double scratch[MSRSB_NOALLOC_MAX_CELLS];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_ptr;  // per device; null until resolved
+
+static int scratch_address(int device, double **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        double *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return MSRSB_OK;
+}
+
+int msrsb_export_stage_noalloc(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slot_block, double *h_vals,
+                               double *h_Ac) {
+    g_err.clear();
+    if (!c) return MSRSB_E_INVAL;
+    Stage *s = stage_at(c, stage);
+    if (!s) {
+        set_error("no stage %d", stage);
+        return MSRSB_E_INVAL;
+    }
+    const int N = c->N;
+    if (N > MSRSB_NOALLOC_MAX_CELLS) {
+        set_error("allocation-free export handles at most %d cells per slot (grid has %d)", MSRSB_NOALLOC_MAX_CELLS,
+                  N);
+        return MSRSB_E_INVAL;
+    }
+    hipError_t e = hipSuccess;
+    if (s->kind == 3) {
+        // constant basis: block per cell straight from the device, slots and
+        // values derived from it on the host
+        int32_t *dst = h_block ? h_block : h_slot_block;
+        if (dst) {
+            e = hipMemcpyAsync(dst, s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(e, "export");
+            if (h_block && h_slot_block) memcpy(h_slot_block, h_block, 4 * (size_t)N);
+            if (h_vals)
+                for (int i = 0; i < N; ++i) h_vals[i] = dst[i] >= 0 ? 1.0 : 0.0;
+        } else if (h_vals) {
+            // no integer output to stage through: the values are 1 on blocks, 0 off them
+            e = hipMemcpyAsync(h_vals, s->dblock, 4 * (size_t)N, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(e, "export");
+            const int32_t *blk = (const int32_t *)h_vals;
+            for (int i = N - 1; i >= 0; --i) h_vals[i] = blk[i] >= 0 ? 1.0 : 0.0;  // widen in place, last first
+        }
+    } else {
+        // integer tables come from the host copies, exactly as msrsb_export_stage
+        if (h_block || h_slot_block) {
+            int rc = msrsb_export_stage(c, stage, h_block, h_slot_block, nullptr, nullptr);
+            if (rc) return rc;
+        }
+        if (h_vals) {
+            if (c->opt.precision == MSRSB_MIXED) {
+                double *sp = nullptr;
+                int rc = scratch_address(c->device, &sp);
+                if (rc) return rc;
+                // one slot column at a time through the staging array
+                for (int sl = 0; sl < s->ns && e == hipSuccess; ++sl) {
+                    launch_export_bf16(*c, s->Pbf + (size_t)sl * N, N, sp);
+                    e = hipMemcpyAsync(h_vals + (size_t)sl * N, sp, 8 * (size_t)N, hipMemcpyDeviceToHost, c->stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                }
+            } else {
+                e = hipMemcpyAsync(h_vals, s->P64[s->cur], 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+            if (e == hipSuccess) e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "export");
+        }
+    }
+    if (h_Ac) {
+        e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(h_Ac, 8 * (size_t)s->M, s->Ac, 8 * (size_t)s->Mp, 8 * (size_t)s->M, s->M,
+                                 hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "export A_c");
+    }
+    return MSRSB_OK;
+}
+
 int msrsb_coarse_apply(msrsb_ctx *c, int stage, const double *h_d, double *h_pc) {
     g_err.clear();
     if (!c || !h_d || !h_pc) {

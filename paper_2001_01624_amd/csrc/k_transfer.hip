@@ -640,6 +640,11 @@ __global__ void k_export_vals(long n, const uint16_t *__restrict__ in, double *_
 }
 
 // Current basis values of a rectilinear stage as FP64 (device buffer).
+// Widen n BF16 basis values to FP64 (d_in and d_out on the context's device).
+void launch_export_bf16(Ctx &c, const uint16_t *d_in, long n, double *d_out) {
+    hipLaunchKernelGGL(k_export_vals, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, d_in, d_out);
+}
+
 void launch_export_cart(Ctx &c, Stage &s, double *d_vals) {
     const long n = (long)s.ns * c.N;
     if (c.opt.precision == MSRSB_MIXED)

@@ -222,6 +222,7 @@ void launch_residual_restrict(Ctx &c, Stage &s, const double *b, const double *x
 void launch_prolong(Ctx &c, Stage &s, double *x, const int *done);
 void launch_rap(Ctx &c, Stage &s);
 void launch_export_cart(Ctx &c, Stage &s, double *d_vals);
+void launch_export_bf16(Ctx &c, const uint16_t *d_in, long n, double *d_out);
 
 // ---- coarse kernels (k_coarse.hip) ----
 void launch_coarse_inverse(Ctx &c, Stage &s);
