@@ -13,7 +13,14 @@ the increment x2 - x1, solve for q3, and compute fluxes.  Every solve runs to
 active cells * steps / wall time (inputs already in HBM; model setup, i.e.
 validation, assembly and integer partition tables, is timed apart as setup_ms).
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+The same line carries the mixed-precision request, the faulted model with a
+fault-cut and two dynamic stages, the serving stream, the batched ensemble,
+a per-class kernel table (HIP events), the roofline of the largest kernel
+class (the fine-grid pass of the residual-restriction) and the oracle timed
+on the host's cores.
+
+Prints one JSON line (progress on stderr).  `--gpus N` with N > 1 exits: this
+build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -44,14 +51,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--kernel", default="sweep", help="kernel class for the roofline object")
+    ap.add_argument("--kernel", default="restrict_rows",
+                    help="kernel class of the roofline object (the largest share of kernel time by default)")
+    ap.add_argument("--no-table", action="store_true", help="skip the per-class kernel table")
+    ap.add_argument("--no-faulted", action="store_true", help="skip the faulted-model (two-stage + dynamic) leg")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-only", action="store_true",
                     help="profiling aid: run only the mixed-precision request and print its record")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble (also skipped by --no-serve)")
-    ap.add_argument("--ensemble-members", type=int, default=32)
+    ap.add_argument("--ensemble-members", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -82,14 +92,18 @@ def workload(dims=DIMS, seed=0):
 
 
 # algorithmic bytes per active cell for one launch of each kernel class
+# (structured 7-point storage: three face T and the diagonal per cell)
 def bytes_per_cell(kernel, ns, mixed):
-    sp = 4 if mixed else 8
+    sp = 4 if mixed else 8       # working precision of the sweeps and the smoother
+    sb = 2 if mixed else 8       # stored basis (BF16 in mixed precision)
     return {
-        "sweep": 2 * ns * sp + 3 * sp + 8,   # read P, write P, three face T, diagonal
-        "residual": 56,                      # x, b, r, three face T, diagonal
-        "smooth": 100,                       # both colours of red-black ILU(0)
-        "matvec": 48,
-    }[kernel]
+        "sweep": 2 * ns * sp + 3 * sp + 8,        # read P, write P, three face T, diagonal
+        "restrict_rows": 48 + ns * sb,            # P, x, b, three face T, diagonal (residual fused)
+        "restrict": 48 + ns * sb,                 # the same, with the final gather of the partial sums
+        "prolong": ns * sb + 16,                  # P, x read and written
+        "residual": 56,                           # x, b, r, three face T, diagonal
+        "smooth": 44 if mixed else 64,            # red-black ILU(0): r, x in/out, three T, diagonal, pivot
+    }.get(kernel)  # the "matvec" class is the Arnoldi pass A (matrix-vector product fused with dots): no entry
 
 
 def gpu_leg(args, precision):
@@ -160,17 +174,8 @@ def gpu_leg(args, precision):
     n_act = prob.n_active
     cells = 3 * n_act * args.steps
     ns = 8
-    bpc = bytes_per_cell(args.kernel, ns, precision == "mixed") if args.kernel in ("sweep", "residual", "smooth",
-                                                                                  "matvec") else None
-    roof = None
-    if bpc is not None and launches > 0:
-        per_launch = bpc * n_act
-        avg_s = kern_ms / launches / 1e3
-        ach = per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_record(args.kernel, precision),
-                "kernel": args.kernel, "launches": launches, "avg_launch_us": round(1e6 * avg_s, 2),
-                "algorithmic_bytes_per_launch": per_launch}
+    roof = roofline(args.kernel, ns, precision, n_act, kern_ms, launches)
+    table = None if args.no_table else kernel_table(g, step, ns, precision, n_act)
     out = {
         "value": cells / wall,
         "ms_per_step": 1e3 * wall / args.steps,
@@ -183,8 +188,114 @@ def gpu_leg(args, precision):
         "relres": max(max(rec["relres"]) for rec in recs),
         "all_converged": all(s == 0 for rec in recs for s in rec["status"]),
         "roofline": roof,
+        "kernel_table": table,
         "cells": n_act,
     }
+    g.close()
+    return out
+
+
+ROOF_KERNEL = {"restrict_rows": "k_restrict_rows", "sweep": "k_sweep", "restrict": "k_restrict_rows+k_restrict_gather",
+               "prolong": "k_prolong_rows", "residual": "k_residual_rows", "smooth": "k_ilu_zm"}
+
+
+def roofline(kernel, ns, precision, n_act, kern_ms, launches):
+    """Roofline object of one kernel class: algorithmic bytes per launch over
+    the average launch time from the HIP events of the timed steps."""
+    bpc = bytes_per_cell(kernel, ns, precision == "mixed")
+    if bpc is None or launches == 0:
+        return None
+    per_launch = bpc * n_act
+    avg_s = kern_ms / launches / 1e3
+    ach = per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_record(kernel, precision),
+            "kernel": ROOF_KERNEL.get(kernel, kernel), "kernel_class": kernel, "launches": launches,
+            "avg_launch_us": round(1e6 * avg_s, 2), "algorithmic_bytes_per_cell": bpc,
+            "algorithmic_bytes_per_launch": per_launch}
+
+
+TABLE_CLASSES = ("restrict_rows", "restrict", "sweep", "prolong", "smooth", "residual", "ortho", "matvec", "coarse",
+                 "rap", "inverse")
+
+
+def kernel_table(g, step, ns, precision, n_act):
+    """One extra (untimed) request per kernel class, that class's launches
+    bracketed by HIP events: launches and milliseconds per request, average
+    launch, and achieved bandwidth where the algorithmic bytes are known."""
+    out = {}
+    for cls in TABLE_CLASSES:
+        g.profile_begin(cls, 200000)
+        step()
+        ms, n = g.profile_end()
+        row = {"launches": n, "ms_per_request": round(ms, 3), "avg_us": round(1e3 * ms / n, 2) if n else None}
+        bpc = bytes_per_cell(cls, ns, precision == "mixed")
+        if bpc is not None and n:
+            gbs = bpc * n_act / (ms / n / 1e3) / 1e9
+            row.update({"bytes_per_cell": bpc, "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        out[cls] = row
+    return out
+
+
+def faulted_leg(args):
+    """The faulted model (60x220x85, three planar faults, 5 % inactive cells)
+    in mixed precision with a rectilinear stage (10x10x5 coarse blocks), its
+    fault-cut stage and up to two dynamic stages: one request = both bases
+    from scratch, then five solves with a moved or rescaled source/sink pair,
+    the increments of the last two solutions becoming dynamic stages from
+    the third solve on (the serving loop's recipe)."""
+    import torch
+
+    from paper_2001_01624_amd import capi
+    from workloads import make_config2, rng_for
+    from workloads.requests import source_sequence
+
+    prob = make_config2(seed=0)
+    sources = source_sequence(prob, rng_for(6, 0), 5)
+    parts = [{"kind": "cartesian", "coarse_dims": (10, 10, 5)}, {"kind": "fault_cut", "parent": 0}]
+    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=RESTART, precision="mixed")
+    g = capi.Solver(prob, parts, opt)
+    q = [torch.as_tensor(s).cuda() for s in sources]
+    N = prob.n_cells
+    xs = [torch.zeros(N, dtype=torch.float64, device="cuda") for _ in q]
+
+    def step():
+        rec = {"iters": [], "relres": [], "status": [], "dyn": [], "solve_ms": []}
+        t = time.perf_counter()
+        g.clear_dynamic_basis()
+        rec["sweeps"] = [g.update_basis(stage=k, max_sweeps=100, tol=1e-3)[0] for k in range(len(parts))]
+        for k in range(len(q)):
+            ts = time.perf_counter()
+            if k >= 2:
+                incs = [xs[k - 1] - xs[k - 2]] + ([xs[k - 2] - xs[k - 3]] if k >= 3 else [])
+                rec["dyn"].append(g.add_dynamic_basis(incs))
+            if k == 0:
+                xs[0].zero_()
+            else:
+                xs[k].copy_(xs[k - 1])
+            it, rel, rc = g.solve(xs[k], source=q[k], rtol=RTOL, max_iters=3000)
+            torch.cuda.synchronize()
+            rec["solve_ms"].append(1e3 * (time.perf_counter() - ts))
+            rec["iters"].append(it)
+            rec["relres"].append(rel)
+            rec["status"].append(rc)
+        rec["ms"] = 1e3 * (time.perf_counter() - t)
+        return rec
+
+    for _ in range(args.warmup):
+        step()
+    recs = [step() for _ in range(args.steps)]
+    wall = sum(r["ms"] for r in recs) / 1e3
+    n_act = prob.n_active
+    out = {"value": len(q) * n_act * len(recs) / wall, "unit": "cells/s", "ms_per_request": 1e3 * wall / len(recs),
+           "solve_ms_3_to_5": [round(x, 2) for x in recs[-1]["solve_ms"][2:]], "iters": recs[-1]["iters"],
+           "sweeps": recs[-1]["sweeps"], "dyn_blocks": recs[-1]["dyn"],
+           "max_relres": max(max(r["relres"]) for r in recs),
+           "all_converged": all(s == 0 for r in recs for s in r["status"]), "cells": n_act,
+           "stages": [g.stage_info(k)[:3:2] for k in range(len(parts))],
+           "workload": "faulted 60x220x85 (3 faults, 5% inactive), mixed precision, rectilinear 10x10x5 + fault-cut "
+                       "+ <=2 dynamic stages, GMRES(16), 5 solves per request (source/sink pair moved or rescaled)"}
+    out["kernel_table"] = None if args.no_table else kernel_table(g, step, 8, "mixed", n_act)
     g.close()
     return out
 
@@ -298,28 +409,59 @@ def cpu_leg():
                       "iters": [i1, i2, i3]}))
 
 
-def run_cpu_baseline():
-    env = dict(os.environ)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
-        env[k] = "1"
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg"], capture_output=True, text=True,
-                       env=env, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    rec = json.loads(r.stdout.strip().splitlines()[-1])
-    cpu = "unknown"
+def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": rec["value"], "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": f"same request recipe at 30x110x21 ({rec['cells']} cells, blocks 6x22x21 and ~10x10x5), "
-                      f"basis + 3 GMRES solves + dynamic stage + fluxes, {rec['seconds']:.1f} s on 1 thread of "
-                      f"{cpu} ({os.cpu_count()} host threads); oracle setup {rec['setup_s']:.1f} s excluded",
-            "iters": rec["iters"]}
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may use: the affinity mask, capped by
+    OMP_NUM_THREADS where the host sets a share."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return max(1, n)
+
+
+def run_cpu_baseline():
+    """The oracle leg on one thread, then on every host core: as many
+    single-threaded oracle processes as cores, each solving the same sample
+    request, started together (throughput = their cells over the wall time
+    from the first start to the last finish)."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg"]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    cores = host_cores()
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for _ in range(cores)]
+    outs = [p.communicate(timeout=1800) for p in procs]
+    wall = time.perf_counter() - t0
+    if any(p.returncode != 0 for p in procs):
+        return {"error": next(o[1][-500:] for p, o in zip(procs, outs) if p.returncode != 0)}
+    recs = [json.loads(o[0].strip().splitlines()[-1]) for o in outs]
+    # each process's own timed region (setup excluded) bounds the wall time used for the rate
+    span = max(rec["seconds"] for rec in recs)
+    allc = sum(3 * rec["cells"] for rec in recs) / span
+    return {"value": allc, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"same request recipe at 30x110x21 ({one['cells']} cells, general blocks 6x22x21 and "
+                      f"~10x10x5): basis + 3 GMRES solves + dynamic stage + fluxes; {cores} single-threaded oracle "
+                      f"processes at once, one request each (slowest {span:.1f} s, all {wall:.1f} s with oracle "
+                      f"set-up); one thread alone: {one['seconds']:.1f} s; host {_cpu_model()}, "
+                      f"{os.cpu_count()} hardware threads",
+            "one_thread": {"value": one["value"], "cores": 1, "seconds": one["seconds"]},
+            "iters": one["iters"]}
 
 
 def main():
@@ -342,11 +484,18 @@ def main():
                           "ms_per_step": rec["ms_per_step"], "iters": rec["iters"], "max_relres": rec["relres"],
                           "roofline": rec["roofline"]}))
         return
-    f64 = gpu_leg(args, "fp64")
-    mixed = None if args.no_mixed else gpu_leg(args, "mixed")
-    served = None if args.no_serve else serve_leg(args)
-    ensemble = None if (args.no_serve or args.no_ensemble) else ensemble_leg(args)
-    cpu = None if args.no_cpu_baseline else run_cpu_baseline()
+    def leg(name, fn, *a):
+        t = time.perf_counter()
+        out = fn(*a)
+        print(f"[bench] {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+        return out
+
+    f64 = leg("fp64 request", gpu_leg, args, "fp64")
+    mixed = None if args.no_mixed else leg("mixed request", gpu_leg, args, "mixed")
+    faulted = None if args.no_faulted else leg("faulted request", faulted_leg, args)
+    served = None if args.no_serve else leg("serving stream", serve_leg, args)
+    ensemble = None if (args.no_serve or args.no_ensemble) else leg("ensemble", ensemble_leg, args)
+    cpu = None if args.no_cpu_baseline else leg("oracle baseline", run_cpu_baseline)
     line = {
         "metric": METRIC,
         "value": f64["value"],
@@ -379,7 +528,11 @@ def main():
         line["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"], "p50_ms": mixed["p50_ms"],
                          "p99_ms": mixed["p99_ms"], "iters": mixed["iters"], "sweeps": mixed["sweeps"],
                          "max_relres": mixed["relres"], "all_converged": mixed["all_converged"],
-                         "roofline": mixed["roofline"], "dtype": "f32 sweeps/smoother, bf16 basis, f64 residual"}
+                         "roofline": mixed["roofline"], "kernel_table": mixed["kernel_table"],
+                         "dtype": "f32 sweeps/smoother, bf16 basis, f64 residual"}
+    line["kernel_table"] = f64["kernel_table"]
+    if faulted is not None:
+        line["faulted"] = faulted
     if served is not None:
         line["served"] = served
     if ensemble is not None:

@@ -290,7 +290,9 @@ enum {
     MSRSB_K_ORTHO = 7,     /* one Gram-Schmidt pass: dots + update */
     MSRSB_K_MATVEC = 8,    /* y = A x */
     MSRSB_K_RAP = 9,       /* Galerkin coarse operator of one stage */
-    MSRSB_K_INVERSE = 10   /* coarse inverse of one stage */
+    MSRSB_K_INVERSE = 10,  /* coarse inverse of one stage */
+    MSRSB_K_RESTRICT_ROWS = 11 /* the fine-grid pass of d = P^T (b - A x) on a
+                                  rectilinear stage, without its final gather */
 };
 int msrsb_profile_begin(msrsb_ctx *ctx, int kernel_class, int max_launches);
 int msrsb_profile_end(msrsb_ctx *ctx, double *total_ms, int *launches);

@@ -23,7 +23,7 @@ RICHARDSON, GMRES = 0, 1
 OP_RESIDUAL, OP_SMOOTH, OP_PRECOND, OP_MATVEC = 0, 1, 2, 3
 NOALLOC_MAX_CELLS = 2097152
 K_CLASSES = {"sweep": 1, "residual": 2, "smooth": 3, "restrict": 4, "prolong": 5, "coarse": 6, "ortho": 7,
-             "matvec": 8, "rap": 9, "inverse": 10}
+             "matvec": 8, "rap": 9, "inverse": 10, "restrict_rows": 11}
 _NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_SINGULAR", -5: "E_NOCONV", -6: "E_STATE"}
 
 

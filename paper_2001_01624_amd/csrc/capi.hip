@@ -1412,7 +1412,7 @@ int msrsb_coarse_apply(msrsb_ctx *c, int stage, const double *h_d, double *h_pc)
 
 int msrsb_profile_begin(msrsb_ctx *c, int kernel_class, int max_launches) {
     g_err.clear();
-    if (!c || kernel_class < 1 || kernel_class > 10 || max_launches < 1 || max_launches > 1000000) {
+    if (!c || kernel_class < 1 || kernel_class > MSRSB_K_RESTRICT_ROWS || max_launches < 1 || max_launches > 1000000) {
         set_error("bad profile arguments");
         return MSRSB_E_INVAL;
     }

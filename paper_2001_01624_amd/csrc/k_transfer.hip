@@ -4,6 +4,8 @@
 // with implicit slots (at most two consecutive blocks per axis).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "cart_util.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -283,8 +285,10 @@ static void restrict_dispatch(Ctx &c, Stage &s, const PS *P, const double *rb, c
     constexpr int W = kRestrictWaves;
     const dim3 grid(xcd_grid(s.cart.m[1] * c.nz)), blk(64 * W), fgrid(cdiv(s.M, 4)), fblk(256);
     const size_t lds = sizeof(double) * W * (size_t)c.nx * s.ns;
+    hipEvent_t e0, e1;  // the pass over the fine grid alone, timed by its dispatch when profiled
+    prof_pair(c, MSRSB_K_RESTRICT_ROWS, &e0, &e1);
 #define MSRSB_RR(NS, NCH, W_, U_) \
-    hipLaunchKernelGGL((k_restrict_rows<NS, PS, NCH, RES, W_, U_>), grid, blk, lds, c.stream, s.cart, g, P, rb, x, s.rpart, done)
+    hipExtLaunchKernelGGL((k_restrict_rows<NS, PS, NCH, RES, W_, U_>), grid, blk, lds, c.stream, e0, e1, 0, s.cart, g, P, rb, x, s.rpart, done)
 #define MSRSB_RNS(NS)                                                                                        \
     {                                                                                                        \
         if (nch == 1) MSRSB_RR(NS, 1, W, kRestrictUnroll);                                                   \
