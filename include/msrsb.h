@@ -91,11 +91,21 @@ typedef struct {
  *     support of a piece is the part of its parent's support reachable from
  *     it without crossing a fault face.
  */
-enum { MSRSB_PART_CARTESIAN = 0, MSRSB_PART_FAULT_CUT = 2 };
+/*   GRAPH: any partition given as a block id per cell (a graph partitioner's
+ *     output, or the well and indicator partitions of msrsb_partition_wells
+ *     and msrsb_partition_indicator): ids >= 0 on active cells (inactive
+ *     entries are ignored), blocks numbered by ascending id with unused ids
+ *     dropped.  The support of a block is every active cell within `overlap`
+ *     face steps of the block (faces with T > 0); overlap 0 keeps the block
+ *     itself, i.e. a constant basis.  At most 32 supports may hold a cell.
+ */
+enum { MSRSB_PART_CARTESIAN = 0, MSRSB_PART_GRAPH = 1, MSRSB_PART_FAULT_CUT = 2 };
 typedef struct {
     int32_t kind;
     int32_t coarse_dims[3];    /* CARTESIAN: blocks per axis, 1 <= m <= n */
     int32_t parent;            /* FAULT_CUT: index of the parent stage */
+    const int32_t *block_of_cell; /* GRAPH: host [N] block id per cell (read during setup only) */
+    int32_t overlap;           /* GRAPH: support reach in face steps, >= 0 */
 } msrsb_partition;
 
 enum { MSRSB_SMOOTH_JACOBI = 0, MSRSB_SMOOTH_ILU0_RB = 1 };
@@ -214,7 +224,7 @@ int msrsb_apply(msrsb_ctx *ctx, int op, const double *d_in, double *d_out);
 int msrsb_fluxes(msrsb_ctx *ctx, const double *d_p, double *d_face_flux, double *d_bc_flux);
 
 /* Number of stages (general + static + dynamic) and, for one stage, its
- * block count M, its kind (0 general, 2 fault cut, 3 dynamic) and the
+ * block count M, its kind (0 rectilinear, 1 graph, 2 fault cut, 3 dynamic) and the
  * number of basis slots per cell. */
 int msrsb_num_stages(msrsb_ctx *ctx);
 int msrsb_stage_info(msrsb_ctx *ctx, int stage, int *M, int *kind, int *n_slots);
@@ -258,6 +268,36 @@ int msrsb_export_stage_noalloc(msrsb_ctx *ctx, int stage, int32_t *h_block, int3
  * stage has no coarse operator yet), E_DEVICE.
  */
 int msrsb_coarse_apply(msrsb_ctx *ctx, int stage, const double *h_d, double *h_pc);
+
+/*
+ * Static partitions for GRAPH stages (subsection "Iterative multiscale
+ * multibasis solver", type "Static"; section "Numerical examples", Example 2:
+ * well bases and partitions agglomerated from a flow indicator).  Host-only,
+ * integer work; both write block[N] (host, caller-allocated) with -1 on
+ * inactive cells, and return E_INVAL for an invalid grid or arguments.
+ *
+ * msrsb_partition_wells: one block per well plus one for the rest, so that
+ *   the blocks cover the grid.  Cell i joins well w if its distance in face
+ *   steps (faces with T > 0) to the cells of well w is at most `radius` and
+ *   smaller than to any other well (ties to the lower well index); every
+ *   other active cell joins block n_wells.  Well w's cells are
+ *   well_cells[well_ptr[w] .. well_ptr[w+1]-1] (host; active cells, at least
+ *   one per well).
+ * msrsb_partition_indicator: agglomeration by a cell indicator (e.g. log
+ *   permeability or a velocity magnitude, host [N], finite on active cells):
+ *   (1) equal-count bins: active cells ranked by (indicator, cell index),
+ *   bin = floor(rank * n_bins / n_active); (2) pieces: face-connected cells
+ *   with the same (bin, rectilinear parent block of coarse_dims, as in
+ *   CARTESIAN); (3) while a piece has fewer than min_cells cells and a
+ *   face-neighbour piece in the same parent block, the smallest such piece
+ *   (size, then smallest cell index) joins the neighbour piece it shares the
+ *   most faces with (ties: the one with the smaller smallest cell index);
+ *   (4) blocks numbered by their smallest cell index.
+ */
+int msrsb_partition_wells(const msrsb_grid *grid, int n_wells, const int32_t *well_ptr, const int32_t *well_cells,
+                          int radius, int32_t *block);
+int msrsb_partition_indicator(const msrsb_grid *grid, const double *indicator, int n_bins,
+                              const int32_t coarse_dims[3], int min_cells, int32_t *block);
 
 /*
  * Host-only helpers (no device needed):

@@ -10,6 +10,9 @@ from .msrsb import (  # noqa: F401
     cartesian_partition,
     cartesian_support,
     fault_cut_partition,
+    graph_partition,
+    well_partition,
+    indicator_partition,
     msrsb_basis,
     galerkin,
     coarse_factor,

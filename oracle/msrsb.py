@@ -50,7 +50,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
-from scipy.sparse.csgraph import connected_components
+from scipy.sparse.csgraph import connected_components, shortest_path
 
 E_INVAL = -1
 E_SINGULAR = -4
@@ -276,6 +276,146 @@ def fault_cut_partition(prob, parent_block, parent_S, cells):
     S = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(cells.size, M)).tocsr()
     S.sort_indices()
     return block, M, S
+
+
+def _active_adjacency(prob, cells):
+    """Symmetric 0/1 adjacency of the active cells (local numbering) over the
+    faces with ``T > 0``."""
+    N = prob.n_cells
+    loc = np.full(N, -1, dtype=np.int64)
+    loc[cells] = np.arange(cells.size)
+    a, b, _ = _faces(prob)
+    G = sp.coo_matrix((np.ones(a.size), (loc[a], loc[b])), shape=(cells.size, cells.size)).tocsr()
+    return ((G + G.T) > 0).astype(np.float64).tocsr()
+
+
+def graph_partition(prob, block_of_cell, overlap, cells):
+    """Partition given as a block id per cell (types "General" from a graph
+    partitioner, "Static" from indicators or wells): the ids of the active
+    cells, renumbered by ascending id with unused ids dropped.  The support of
+    a block is every active cell within ``overlap`` face steps of it, i.e.
+    ``R_0`` = block indicator and ``R_{t+1} = R_t or G R_t`` with ``G`` the
+    face adjacency.  Returns ``(block, M, S)``."""
+    if overlap < 0:
+        raise OracleError(E_INVAL, "overlap must be >= 0")
+    ids = np.asarray(block_of_cell, dtype=np.int64)[cells]
+    if np.any(ids < 0):
+        raise OracleError(E_INVAL, "an active cell has a negative block id")
+    present = np.unique(ids)
+    local = np.searchsorted(present, ids)
+    M = present.size
+    block = np.full(prob.n_cells, -1, dtype=np.int64)
+    block[cells] = local
+    G = _active_adjacency(prob, cells)
+    R = indicator(local, M)
+    for _ in range(overlap):
+        R = ((R + G @ R) > 0).astype(np.float64).tocsr()
+    R.sort_indices()
+    return block, M, R
+
+
+def well_partition(prob, well_cells, radius):
+    """Well partition (type "Static": one block per well plus one block for
+    the rest, so that the blocks cover the grid): cell ``i`` joins well
+    ``w`` when its face-step distance to the well's cells (faces with
+    ``T > 0``) is at most ``radius`` and smaller than to any other well (ties
+    to the lower well index); every other active cell joins block
+    ``n_wells``.  ``well_cells`` is a list of box-index arrays.  Returns the
+    block per cell in box numbering (-1 inactive)."""
+    cells = np.nonzero(prob.active)[0]
+    N = prob.n_cells
+    loc = np.full(N, -1, dtype=np.int64)
+    loc[cells] = np.arange(cells.size)
+    G = _active_adjacency(prob, cells)
+    n_w = len(well_cells)
+    if n_w < 1 or radius < 0:
+        raise OracleError(E_INVAL, "need at least one well and radius >= 0")
+    # unweighted shortest paths from a virtual node joined to all cells of one well
+    dist = np.full((n_w, cells.size), np.inf)
+    n = cells.size
+    for w, wc in enumerate(well_cells):
+        wc = np.asarray(wc, dtype=np.int64)
+        if wc.size == 0 or np.any(wc < 0) or np.any(wc >= N) or not np.all(prob.active[wc]):
+            raise OracleError(E_INVAL, "well cells must be active cells of the grid")
+        src = np.zeros(n + 1)
+        Gs = sp.bmat([[G, sp.csr_matrix((np.ones(wc.size), (loc[wc], np.zeros(wc.size))), shape=(n, 1))],
+                      [sp.csr_matrix((np.ones(wc.size), (np.zeros(wc.size), loc[wc])), shape=(1, n)), None]]).tocsr()
+        d = shortest_path(Gs, unweighted=True, indices=n, directed=False)
+        dist[w] = d[:n] - 1.0
+    best = np.argmin(dist, axis=0)  # first minimum: the lower well index wins ties
+    dmin = dist[best, np.arange(n)]
+    out = np.full(N, -1, dtype=np.int64)
+    out[cells] = np.where(dmin <= radius, best, n_w)
+    return out
+
+
+def indicator_partition(prob, ind, n_bins, coarse_dims, min_cells):
+    """Indicator agglomeration (type "Static": blocks that follow a cell
+    indicator such as log-permeability or a velocity magnitude):
+
+    1. equal-count bins: the active cells ranked by (indicator, cell index),
+       ``bin = floor(rank * n_bins / n_active)``;
+    2. pieces: face-connected cells (``T > 0``) with the same (rectilinear
+       parent block of ``coarse_dims``, bin);
+    3. merging: while a piece has fewer than ``min_cells`` cells and a
+       face-neighbour piece in the same parent block, the smallest such piece
+       (by size, then smallest cell index) joins the neighbour piece it shares
+       the most faces with (ties: the neighbour with the smaller smallest
+       cell index);
+    4. blocks numbered by their smallest cell index.
+    Returns the block per cell in box numbering (-1 inactive)."""
+    cells = np.nonzero(prob.active)[0]
+    N, n = prob.n_cells, cells.size
+    ind = np.asarray(ind, dtype=np.float64)
+    if n_bins < 1 or min_cells < 0 or not np.all(np.isfinite(ind[cells])):
+        raise OracleError(E_INVAL, "n_bins >= 1, min_cells >= 0 and a finite indicator on active cells")
+    order = np.lexsort((cells, ind[cells]))  # by value, then cell index
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    bins = np.full(N, -1, dtype=np.int64)
+    bins[cells] = rank * n_bins // n
+    parent, _, _ = cartesian_partition(prob.dims, coarse_dims, np.ones(N, dtype=bool))
+    a, b, _ = _faces(prob)
+    same = (bins[a] == bins[b]) & (parent[a] == parent[b])
+    Gk = sp.coo_matrix((np.ones(int(same.sum())), (a[same], b[same])), shape=(N, N))
+    _, lab = connected_components(Gk, directed=False)
+    piece = {}
+    for c in cells:  # ascending: the first cell seen is the smallest
+        piece.setdefault(int(lab[c]), []).append(int(c))
+    members = {min(v): set(v) for v in piece.values()}  # pieces keyed by their smallest cell
+    owner = np.full(N, -1, dtype=np.int64)
+    for key, v in members.items():
+        owner[list(v)] = key
+    while True:
+        cand = None
+        for key, v in members.items():
+            if len(v) >= min_cells:
+                continue
+            # shared faces with each neighbour piece of the same parent block
+            count = {}
+            for c in v:
+                for d, (T, step) in enumerate(((prob.tx, 1), (prob.ty, prob.dims[0]),
+                                               (prob.tz, prob.dims[0] * prob.dims[1]))):
+                    for nb, t in ((c + step, T[c]), (c - step, T[c - step] if c - step >= 0 else 0.0)):
+                        if t > 0 and owner[nb] != key and parent[nb] == parent[c]:
+                            count[int(owner[nb])] = count.get(int(owner[nb]), 0) + 1
+            if not count:
+                continue
+            if cand is None or (len(v), key) < (len(members[cand[0]]), cand[0]):
+                target = min(count, key=lambda k: (-count[k], k))
+                cand = (key, target)
+        if cand is None:
+            break
+        small, target = cand
+        merged = members.pop(small) | members.pop(target)
+        newkey = min(small, target)
+        members[newkey] = merged
+        owner[list(merged)] = newkey
+    keys = sorted(members)
+    out = np.full(N, -1, dtype=np.int64)
+    for j, key in enumerate(keys):
+        out[list(members[key])] = j
+    return out
 
 
 def indicator(block_local, M):
@@ -528,6 +668,8 @@ class Oracle:
             elif part["kind"] == "fault_cut":
                 par = self.stages[part["parent"]]
                 block, M, S = fault_cut_partition(prob, par.block, par.S, self.cells)
+            elif part["kind"] == "graph":
+                block, M, S = graph_partition(prob, part["block_of_cell"], part.get("overlap", 0), self.cells)
             else:
                 raise OracleError(E_INVAL, f"unknown partition kind {part['kind']}")
             self.stages.append(_Stage(part["kind"], block, M, S))

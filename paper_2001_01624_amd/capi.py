@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsrsb.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
-PART_CARTESIAN, PART_FAULT_CUT = 0, 2
+PART_CARTESIAN, PART_GRAPH, PART_FAULT_CUT = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_ILU0_RB = 0, 1
 FP64, MIXED = 0, 1
 RICHARDSON, GMRES = 0, 1
@@ -44,7 +44,8 @@ class Grid(C.Structure):
 
 
 class Partition(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("coarse_dims", C.c_int32 * 3), ("parent", C.c_int32)]
+    _fields_ = [("kind", C.c_int32), ("coarse_dims", C.c_int32 * 3), ("parent", C.c_int32),
+                ("block_of_cell", C.POINTER(C.c_int32)), ("overlap", C.c_int32)]
 
 
 class Options(C.Structure):
@@ -83,6 +84,8 @@ def _load():
         "msrsb_destroy": (None, [VP]),
         "msrsb_validate_grid": (I, [P(Grid)]),
         "msrsb_axis_support": (I, [I, I, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
+        "msrsb_partition_wells": (I, [P(Grid), I, P(C.c_int32), P(C.c_int32), I, P(C.c_int32)]),
+        "msrsb_partition_indicator": (I, [P(Grid), P(D), I, P(C.c_int32), I, P(C.c_int32)]),
         "msrsb_profile_begin": (I, [VP, I, I]),
         "msrsb_profile_end": (I, [VP, P(D), P(I)]),
     }
@@ -152,15 +155,32 @@ class _GridArrays:
         self.grid = g
 
 
+class _Parts:
+    """Partition structs plus the block vectors they point into (kept alive
+    for the duration of the call)."""
+
+    def __init__(self, partitions):
+        self.arr = (Partition * len(partitions))()
+        self.keep = []
+        for k, p in enumerate(partitions):
+            kind = p.get("kind", "cartesian")
+            self.arr[k].kind = {"cartesian": PART_CARTESIAN, "graph": PART_GRAPH,
+                                "fault_cut": PART_FAULT_CUT}.get(kind, kind)
+            cd = p.get("coarse_dims", (1, 1, 1))
+            self.arr[k].coarse_dims[0], self.arr[k].coarse_dims[1], self.arr[k].coarse_dims[2] = (int(x) for x in cd)
+            self.arr[k].parent = int(p.get("parent", 0))
+            if p.get("block_of_cell") is not None:
+                b = np.ascontiguousarray(p["block_of_cell"], dtype=np.int32)
+                self.keep.append(b)
+                self.arr[k].block_of_cell = _ptr(b, C.c_int32)
+            self.arr[k].overlap = int(p.get("overlap", 0))
+
+    def __len__(self):
+        return len(self.arr)
+
+
 def _parts(partitions):
-    arr = (Partition * len(partitions))()
-    for k, p in enumerate(partitions):
-        kind = p.get("kind", "cartesian")
-        arr[k].kind = {"cartesian": PART_CARTESIAN, "fault_cut": PART_FAULT_CUT}.get(kind, kind)
-        cd = p.get("coarse_dims", (1, 1, 1))
-        arr[k].coarse_dims[0], arr[k].coarse_dims[1], arr[k].coarse_dims[2] = (int(x) for x in cd)
-        arr[k].parent = int(p.get("parent", 0))
-    return arr
+    return _Parts(partitions)
 
 
 def validate_grid(prob) -> int:
@@ -178,11 +198,36 @@ def axis_support(n: int, m: int):
     return lo, nv, slo, shi
 
 
+def partition_wells(prob, wells, radius=0):
+    """Well partition (``msrsb_partition_wells``): ``wells`` is a list of
+    arrays of box cell indices; returns the block per cell (-1 inactive)."""
+    ga = _GridArrays(prob)
+    ptr = np.zeros(len(wells) + 1, np.int32)
+    ptr[1:] = np.cumsum([len(w) for w in wells])
+    cells = np.ascontiguousarray(np.concatenate([np.asarray(w) for w in wells]), dtype=np.int32)
+    out = np.zeros(int(np.prod(prob.dims)), np.int32)
+    _check(_lib.msrsb_partition_wells(C.byref(ga.grid), len(wells), _ptr(ptr, C.c_int32), _ptr(cells, C.c_int32),
+                                      int(radius), _ptr(out, C.c_int32)))
+    return out
+
+
+def partition_indicator(prob, indicator, n_bins, coarse_dims, min_cells):
+    """Indicator agglomeration (``msrsb_partition_indicator``); returns the
+    block per cell (-1 inactive)."""
+    ga = _GridArrays(prob)
+    ind = np.ascontiguousarray(indicator, dtype=np.float64)
+    cd = np.ascontiguousarray(coarse_dims, dtype=np.int32)
+    out = np.zeros(int(np.prod(prob.dims)), np.int32)
+    _check(_lib.msrsb_partition_indicator(C.byref(ga.grid), _ptr(ind, C.c_double), int(n_bins), _ptr(cd, C.c_int32),
+                                          int(min_cells), _ptr(out, C.c_int32)))
+    return out
+
+
 def footprint_bytes(prob, partitions, options=None) -> int:
     ga = _GridArrays(prob)
     parts = _parts(partitions)
     o = options if options is not None else default_options()
-    return int(_lib.msrsb_footprint_bytes(C.byref(ga.grid), len(partitions), parts, C.byref(o)))
+    return int(_lib.msrsb_footprint_bytes(C.byref(ga.grid), len(partitions), parts.arr, C.byref(o)))
 
 
 def _dptr(t, n=None, device=None, dtype="float64"):
@@ -216,7 +261,7 @@ class Solver:
         ga = _GridArrays(prob)
         parts = _parts(partitions)
         h = C.c_void_p()
-        _check(_lib.msrsb_setup(C.byref(ga.grid), len(partitions), parts, C.byref(self.options),
+        _check(_lib.msrsb_setup(C.byref(ga.grid), len(partitions), parts.arr, C.byref(self.options),
                                 C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 

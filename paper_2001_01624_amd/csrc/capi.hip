@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <queue>
 
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -388,6 +389,8 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
 // (parent block, smallest cell); the support of a piece is what a breadth-
 // first search from it reaches inside the parent block's support box
 // without crossing a fault face.  Integer work on the host.
+static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std::vector<int>> &slots);
+
 static int build_fault_stage(Ctx &c, const msrsb_partition &p, int index, Stage &s, const double *T3[3]) {
     if (p.parent < 0 || p.parent >= index || c.stages[p.parent].kind != 0) {
         set_error("FAULT_CUT partition %d: parent must be an earlier CARTESIAN partition", index);
@@ -476,18 +479,96 @@ static int build_fault_stage(Ctx &c, const msrsb_partition &p, int index, Stage 
         }
         for (int i : reached) slots[i].push_back(j);  // j ascending: lists stay sorted
     }
+    s.kind = 2;
+    s.parent = p.parent;
+    return explicit_stage_tables(c, s, M, slots);
+}
+
+// Graph stage (partition types "General" from a graph partitioner and
+// "Static" from indicators or wells): the caller's block id per cell, blocks
+// renumbered by ascending id (ids without an active cell dropped); the
+// support of a block is every active cell within `overlap` face steps of it
+// (breadth-first over the faces with T > 0).  Integer work on the host.
+static int build_graph_stage(Ctx &c, const msrsb_partition &p, int index, Stage &s, const double *T3[3]) {
+    const int N = c.N, nx = c.nx, nxy = c.nx * c.ny;
+    const int step[3] = {1, nx, nxy};
+    if (!p.block_of_cell || p.overlap < 0) {
+        set_error("GRAPH partition %d: block_of_cell is NULL or overlap < 0", index);
+        return MSRSB_E_INVAL;
+    }
+    int maxid = -1;
+    for (int i = 0; i < N; ++i) {
+        if (!c.h_active[i]) continue;
+        const int b = p.block_of_cell[i];
+        if (b < 0) {
+            set_error("GRAPH partition %d: active cell %d has block %d", index, i, b);
+            return MSRSB_E_INVAL;
+        }
+        maxid = std::max(maxid, b);
+    }
+    if (maxid < 0) {
+        set_error("GRAPH partition %d: no active cell", index);
+        return MSRSB_E_INVAL;
+    }
+    std::vector<int32_t> newid((size_t)maxid + 1, -1);
+    for (int i = 0; i < N; ++i)
+        if (c.h_active[i]) newid[p.block_of_cell[i]] = 1;
+    int M = 0;
+    for (auto &v : newid)
+        if (v > 0) v = M++;
+    s.h_xpblock.assign(N, -1);
+    std::vector<std::vector<int>> members(M);
+    for (int i = 0; i < N; ++i)
+        if (c.h_active[i]) {
+            s.h_xpblock[i] = newid[p.block_of_cell[i]];
+            members[s.h_xpblock[i]].push_back(i);
+        }
+    std::vector<std::vector<int>> slots(N);
+    std::vector<int> stamp(N, -1), frontier, next;
+    for (int j = 0; j < M; ++j) {
+        frontier = members[j];
+        for (int i : frontier) stamp[i] = j;
+        std::vector<int> reached = frontier;
+        for (int d = 0; d < p.overlap && !frontier.empty(); ++d) {
+            next.clear();
+            for (int i : frontier)
+                for (int a = 0; a < 3; ++a) {
+                    if (T3[a][i] != 0.0 && stamp[i + step[a]] != j) {
+                        stamp[i + step[a]] = j;
+                        next.push_back(i + step[a]);
+                    }
+                    if (i >= step[a] && T3[a][i - step[a]] != 0.0 && stamp[i - step[a]] != j) {
+                        stamp[i - step[a]] = j;
+                        next.push_back(i - step[a]);
+                    }
+                }
+            reached.insert(reached.end(), next.begin(), next.end());
+            frontier.swap(next);
+        }
+        for (int i : reached) slots[i].push_back(j);  // j ascending: lists stay sorted
+    }
+    s.kind = 2;
+    s.graph = true;
+    s.parent = -1;
+    return explicit_stage_tables(c, s, M, slots);
+}
+
+// Slot tables, per-block support lists and basis buffers of an explicit-slot
+// stage from the sorted block list of every cell (s.h_xpblock holds the block
+// of each cell, -1 inactive).
+static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std::vector<int>> &slots) {
+    const int N = c.N;
     int ns = 1;
     for (int i = 0; i < N; ++i) ns = std::max(ns, (int)slots[i].size());
     if (ns > kMaxXSlots) {
-        set_error("fault-cut stage needs %d slots per cell (limit %d)", ns, kMaxXSlots);
+        set_error("explicit-slot stage needs %d slots per cell (limit %d)", ns, kMaxXSlots);
         return MSRSB_E_INVAL;
     }
     if (!slots_fit(ns, N)) {
-        set_error("fault-cut stage: %d basis slots of %d cells exceed the 2^31-byte slot arrays of the kernels", ns, N);
+        set_error("explicit-slot stage: %d basis slots of %d cells exceed the 2^31-byte slot arrays of the kernels", ns,
+                  N);
         return MSRSB_E_INVAL;
     }
-    s.kind = 2;
-    s.parent = p.parent;
     s.ns = ns;
     s.M = M;
     s.Mp = cdiv(M, kTile) * kTile;
@@ -778,6 +859,13 @@ static int check_parts(const msrsb_grid *g, int n_part, const msrsb_partition *p
             }
             continue;
         }
+        if (parts[k].kind == MSRSB_PART_GRAPH) {
+            if (!parts[k].block_of_cell || parts[k].overlap < 0) {
+                set_error("partition %d: GRAPH needs block_of_cell and overlap >= 0", k);
+                return MSRSB_E_INVAL;
+            }
+            continue;
+        }
         if (parts[k].kind != MSRSB_PART_CARTESIAN) {
             set_error("partition %d: unknown kind %d", k, parts[k].kind);
             return MSRSB_E_INVAL;
@@ -797,6 +885,176 @@ static int check_parts(const msrsb_grid *g, int n_part, const msrsb_partition *p
             return MSRSB_E_INVAL;
         }
     }
+    return MSRSB_OK;
+}
+
+// ---------------------------------------------- static partition builders ----
+
+// Face neighbours (T > 0) of cell i, written to nb; returns the count.
+static int face_nbrs(const msrsb_grid *g, int i, int nb[6]) {
+    const int nxy = g->nx * g->ny, N = nxy * g->nz;
+    const int step[3] = {1, g->nx, nxy};
+    const double *T[3] = {g->tx, g->ty, g->tz};
+    int n = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (T[a][i] > 0.0 && i + step[a] < N) nb[n++] = i + step[a];
+        if (i >= step[a] && T[a][i - step[a]] > 0.0) nb[n++] = i - step[a];
+    }
+    return n;
+}
+
+int msrsb_partition_wells(const msrsb_grid *g, int n_wells, const int32_t *well_ptr, const int32_t *well_cells,
+                          int radius, int32_t *block) {
+    g_err.clear();
+    int rc = validate(g);
+    if (rc) return rc;
+    if (n_wells < 1 || !well_ptr || !well_cells || radius < 0 || !block) {
+        set_error("need n_wells >= 1, well lists, radius >= 0 and an output array");
+        return MSRSB_E_INVAL;
+    }
+    const int N = g->nx * g->ny * g->nz;
+    auto act = [&](int i) { return !g->active || g->active[i]; };
+    std::vector<int32_t> lab(N, -1);
+    std::vector<int> frontier;
+    // layer 0: the wells' own cells (a cell listed by two wells goes to the lower index)
+    for (int w = 0; w < n_wells; ++w) {
+        if (well_ptr[w + 1] <= well_ptr[w]) {
+            set_error("well %d has no cells", w);
+            return MSRSB_E_INVAL;
+        }
+        for (int k = well_ptr[w]; k < well_ptr[w + 1]; ++k) {
+            const int i = well_cells[k];
+            if (i < 0 || i >= N || !act(i)) {
+                set_error("well %d: cell %d is not an active cell of the grid", w, i);
+                return MSRSB_E_INVAL;
+            }
+            if (lab[i] < 0) {
+                lab[i] = w;
+                frontier.push_back(i);
+            }
+        }
+    }
+    // layer d + 1: unlabelled neighbours of layer d take the lowest label among
+    // the layer-d cells next to them (smallest distance, ties to the lower well)
+    std::vector<int> next;
+    std::vector<int32_t> cand(N, INT32_MAX);
+    int nb[6];
+    for (int d = 0; d < radius && !frontier.empty(); ++d) {
+        next.clear();
+        for (int i : frontier) {
+            const int n = face_nbrs(g, i, nb);
+            for (int t = 0; t < n; ++t) {
+                const int l = nb[t];
+                if (lab[l] >= 0) continue;
+                if (cand[l] == INT32_MAX) next.push_back(l);
+                cand[l] = std::min(cand[l], lab[i]);
+            }
+        }
+        for (int l : next) {
+            lab[l] = cand[l];
+            cand[l] = INT32_MAX;
+        }
+        frontier.swap(next);
+    }
+    for (int i = 0; i < N; ++i) block[i] = act(i) ? (lab[i] >= 0 ? lab[i] : n_wells) : -1;
+    return MSRSB_OK;
+}
+
+int msrsb_partition_indicator(const msrsb_grid *g, const double *ind, int n_bins, const int32_t coarse_dims[3],
+                              int min_cells, int32_t *block) {
+    g_err.clear();
+    int rc = validate(g);
+    if (rc) return rc;
+    const int n3[3] = {g->nx, g->ny, g->nz};
+    if (!ind || n_bins < 1 || min_cells < 0 || !coarse_dims || !block) {
+        set_error("need an indicator, n_bins >= 1, min_cells >= 0, coarse_dims and an output array");
+        return MSRSB_E_INVAL;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (coarse_dims[a] < 1 || coarse_dims[a] > n3[a]) {
+            set_error("coarse_dims[%d] = %d outside [1, %d]", a, coarse_dims[a], n3[a]);
+            return MSRSB_E_INVAL;
+        }
+    const int N = g->nx * g->ny * g->nz, nx = g->nx, nxy = g->nx * g->ny;
+    auto act = [&](int i) { return !g->active || g->active[i]; };
+    std::vector<int> cells;
+    for (int i = 0; i < N; ++i)
+        if (act(i)) {
+            if (!std::isfinite(ind[i])) {
+                set_error("indicator not finite at active cell %d", i);
+                return MSRSB_E_INVAL;
+            }
+            cells.push_back(i);
+        }
+    const long na = (long)cells.size();
+    // 1. equal-count bins over the ranking by (indicator, cell)
+    std::vector<int> ord(cells);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return ind[a] < ind[b]; });
+    std::vector<int32_t> key(N, -1);
+    auto parent = [&](int i) {
+        const int c3[3] = {i % nx, (i / nx) % g->ny, i / nxy};
+        int J[3];
+        for (int a = 0; a < 3; ++a) J[a] = (int)(((long)c3[a] * coarse_dims[a]) / n3[a]);
+        return J[0] + coarse_dims[0] * (J[1] + coarse_dims[1] * J[2]);
+    };
+    std::vector<int32_t> bin(N, -1), par(N, -1);
+    for (long r = 0; r < na; ++r) bin[ord[r]] = (int32_t)(r * n_bins / na);
+    for (int i : cells) par[i] = parent(i);
+    // 2. pieces: face-connected cells with equal (parent, bin); root = smallest cell
+    DSU d(N);
+    int nb[6];
+    for (int i : cells) {
+        const int n = face_nbrs(g, i, nb);
+        for (int t = 0; t < n; ++t)
+            if (nb[t] > i && bin[nb[t]] == bin[i] && par[nb[t]] == par[i]) d.unite(i, nb[t]);
+    }
+    // pieces keyed by their smallest cell; member lists
+    std::vector<int32_t> own(N, -1);
+    std::vector<std::vector<int>> mem(N);
+    for (int i : cells) {
+        own[i] = d.find(i);
+        mem[own[i]].push_back(i);
+    }
+    // 3. merging, smallest (size, key) first, through a lazy min-heap
+    typedef std::pair<long, int> Item;  // (size, key)
+    std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+    for (int i : cells)
+        if (own[i] == i && (long)mem[i].size() < min_cells) heap.push({(long)mem[i].size(), i});
+    std::vector<int> cnt_key;
+    std::vector<int32_t> cnt(N, 0);
+    while (!heap.empty()) {
+        const Item it = heap.top();
+        heap.pop();
+        const int k = it.second;
+        if (mem[k].empty() || (long)mem[k].size() != it.first) continue;  // stale entry
+        // shared faces with each same-parent neighbour piece
+        cnt_key.clear();
+        for (int i : mem[k]) {
+            const int n = face_nbrs(g, i, nb);
+            for (int t = 0; t < n; ++t) {
+                const int l = nb[t];
+                if (own[l] == k || par[l] != par[i]) continue;
+                if (cnt[own[l]]++ == 0) cnt_key.push_back(own[l]);
+            }
+        }
+        if (cnt_key.empty()) continue;  // no neighbour in its parent block: stays as it is
+        int tgt = -1;
+        for (int q : cnt_key)
+            if (tgt < 0 || cnt[q] > cnt[tgt] || (cnt[q] == cnt[tgt] && q < tgt)) tgt = q;
+        for (int q : cnt_key) cnt[q] = 0;
+        // merge: the merged piece is keyed by the smaller key
+        const int keep = std::min(k, tgt), gone = std::max(k, tgt);
+        for (int i : mem[gone]) own[i] = keep;
+        mem[keep].insert(mem[keep].end(), mem[gone].begin(), mem[gone].end());
+        std::vector<int>().swap(mem[gone]);
+        if ((long)mem[keep].size() < min_cells) heap.push({(long)mem[keep].size(), keep});
+    }
+    // 4. blocks numbered by their smallest cell
+    std::vector<int32_t> id(N, -1);
+    int M = 0;
+    for (int i : cells)
+        if (own[i] == i && !mem[i].empty()) id[i] = M++;
+    for (int i = 0; i < N; ++i) block[i] = act(i) ? id[own[i]] : -1;
     return MSRSB_OK;
 }
 
@@ -839,6 +1097,18 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     b += (size_t)g->n_bc * 24;
     long cb = 0;
     for (int k = 0; k < n_part; ++k) {
+        if (parts[k].kind == MSRSB_PART_GRAPH) {
+            // blocks and slots from the block vector (supports as in build_graph_stage would need the
+            // faces: estimated at 8 slots per cell)
+            long M = 0;
+            for (size_t i = 0; i < N; ++i)
+                if (!g->active || g->active[i]) M = std::max(M, (long)parts[k].block_of_cell[i] + 1);
+            const long Mp = cdiv(M, kTile) * kTile;
+            const size_t nsN = (size_t)8 * N;
+            b += (o.precision == MSRSB_MIXED ? nsN * 10 : nsN * 16) + nsN * 9 + N * 4 + 16 * (size_t)Mp * Mp + 16 * Mp;
+            cb = std::max(cb, Mp);
+            continue;
+        }
         const msrsb_partition &pk = parts[k].kind == MSRSB_PART_FAULT_CUT ? parts[parts[k].parent] : parts[k];
         b += cart_bytes(c, pk);
         if (parts[k].kind == MSRSB_PART_FAULT_CUT) b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
@@ -983,6 +1253,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     const double *T3[3] = {g->tx, g->ty, g->tz};
     for (int k = 0; k < n_part; ++k) {
         if (parts[k].kind == MSRSB_PART_FAULT_CUT) rc = build_fault_stage(*c, parts[k], k, c->stages[k], T3);
+        else if (parts[k].kind == MSRSB_PART_GRAPH) rc = build_graph_stage(*c, parts[k], k, c->stages[k], T3);
         else rc = build_cart_stage(*c, parts[k], c->stages[k]);
         if (rc) return fail(rc);
         cb = std::max(cb, (long)c->stages[k].Mp);
@@ -1193,7 +1464,7 @@ int msrsb_stage_info(msrsb_ctx *c, int stage, int *M, int *kind, int *n_slots) {
         return MSRSB_E_INVAL;
     }
     if (M) *M = s->M;
-    if (kind) *kind = s->kind;
+    if (kind) *kind = s->graph ? MSRSB_PART_GRAPH : s->kind;
     if (n_slots) *n_slots = s->ns;
     return MSRSB_OK;
 }

@@ -44,7 +44,8 @@ struct CartDev {
 };
 
 struct Stage {
-    int kind = 0;                 // 0 general (Cartesian), 2 fault cut (explicit slots), 3 dynamic
+    int kind = 0;                 // 0 general (Cartesian), 2 explicit slots (fault cut or graph), 3 dynamic
+    bool graph = false;           // explicit-slot stage built from a caller's block vector
     int M = 0, Mp = 0;            // blocks; padded to a multiple of kTile
     int ns = 1;                   // slots per cell
     // Cartesian tables

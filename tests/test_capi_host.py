@@ -109,7 +109,7 @@ def _footprint(dims, cd, **opt):
 
     parts = capi._parts([{"kind": "cartesian", "coarse_dims": cd}])
     o = capi.default_options(**opt)
-    return int(capi._lib.msrsb_footprint_bytes(ctypes.byref(_bare_grid(*dims)), 1, parts, ctypes.byref(o)))
+    return int(capi._lib.msrsb_footprint_bytes(ctypes.byref(_bare_grid(*dims)), 1, parts.arr, ctypes.byref(o)))
 
 
 def test_footprint_rejects_grids_beyond_32_bit_slot_offsets():
@@ -153,3 +153,51 @@ def test_binding_rejects_wrong_vectors_before_any_call():
         with pytest.raises(capi.MsrsbError) as e:
             capi._dptr(bad, n=10, device=0)
         assert e.value.code == capi.E_INVAL
+
+
+# --- static partition builders (host functions of the library) against the oracle
+
+def _small_models():
+    from workloads import make_config1, make_lognormal_box, rng_for
+
+    return [make_config2(dims=(9, 8, 5), seed=3), make_config1(dims=(12, 14, 6), seed=1),
+            make_lognormal_box((20, 16, 3), rng_for(9, 2), sigma=2.0, corr=(2.0, 2.0, 1.0))]
+
+
+@pytest.mark.parametrize("radius", [0, 1, 2, 5])
+def test_partition_wells_matches_oracle(radius):
+    import oracle as O
+
+    for k, prob in enumerate(_small_models()):
+        rng = np.random.default_rng(100 + k)
+        cells = np.nonzero(prob.active)[0]
+        wells = [rng.choice(cells, size=int(rng.integers(1, 5)), replace=False) for _ in range(4)]
+        wells.append(wells[0][:1])  # a cell shared by two wells goes to the lower index
+        got = capi.partition_wells(prob, wells, radius)
+        assert np.array_equal(got, O.well_partition(prob, wells, radius))
+
+
+@pytest.mark.parametrize("n_bins,cd,min_cells", [(2, (1, 1, 1), 0), (4, (3, 2, 1), 5), (3, (2, 2, 2), 12),
+                                                 (6, (1, 1, 1), 40)])
+def test_partition_indicator_matches_oracle(n_bins, cd, min_cells):
+    import oracle as O
+
+    for prob in _small_models():
+        ind = np.log(prob.perm)
+        ind = np.round(ind, 1)  # ties between cells exercise the rank order
+        got = capi.partition_indicator(prob, ind, n_bins, cd, min_cells)
+        assert np.array_equal(got, O.indicator_partition(prob, ind, n_bins, cd, min_cells))
+
+
+def test_partition_builders_reject_bad_input():
+    prob = make_config0(0)
+    with pytest.raises(capi.MsrsbError):
+        capi.partition_wells(prob, [np.array([-1])], 1)
+    with pytest.raises(capi.MsrsbError):
+        capi.partition_wells(prob, [np.array([0])], -1)
+    ind = np.zeros(prob.n_cells)
+    ind[5] = np.nan
+    with pytest.raises(capi.MsrsbError):
+        capi.partition_indicator(prob, ind, 4, (2, 2, 1), 0)
+    with pytest.raises(capi.MsrsbError):
+        capi.partition_indicator(prob, np.zeros(prob.n_cells), 0, (2, 2, 1), 0)
