@@ -24,11 +24,12 @@
  *  - A context is not thread-safe.  Distinct contexts may be used from
  *    distinct threads at the same time, each on its own stream.
  *  - All device work of a context runs on the stream given at setup (or the
- *    null stream).  The library allocates its device memory itself,
- *    stream-ordered from the device's default memory pool: at setup one
- *    arena of about msrsb_footprint_bytes that the set-up buffers are carved
- *    from (anything beyond it is allocated on its own), and further blocks
- *    when dynamic bases are added or a stage is exported.
+ *    null stream).  Device memory comes from the allocator given at setup
+ *    (msrsb_allocator) or, without one, stream-ordered from the device's
+ *    default memory pool: at setup one arena of about msrsb_footprint_bytes
+ *    that the set-up buffers are carved from (anything beyond it is
+ *    allocated on its own), and further blocks when dynamic bases are added
+ *    or a stage is exported.
  */
 #ifndef MSRSB_H
 #define MSRSB_H
@@ -138,19 +139,36 @@ size_t msrsb_footprint_bytes(const msrsb_grid *grid, int n_part, const msrsb_par
                              const msrsb_options *opt);
 
 /*
+ * Device memory source of a context.  alloc returns `bytes` of device memory
+ * on the context's device, aligned to at least 256 bytes, usable in the order
+ * of `hip_stream` (the context's stream), or NULL on failure; free returns a
+ * block from alloc with its size.  Both are called from the thread that
+ * calls into the library, during msrsb_setup, msrsb_add_dynamic_basis,
+ * msrsb_export_stage and msrsb_destroy.  `user` is passed through.  (The
+ * Python binding passes PyTorch's caching allocator here.)
+ */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *hip_stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *hip_stream, void *user);
+    void *user;
+} msrsb_allocator;
+
+/*
  * Validate the grid, assemble A and b on the device (two-point operator, see
  * msrsb_grid), build every partition and support, and factor the smoother.
+ * alloc: the context's device allocator (copied), or NULL for the library's
+ * own: stream-ordered allocations from the device's default memory pool.
  * hip_stream: a hipStream_t (NULL = null stream); every device operation of
- * the context, its allocations included (stream-ordered, from the device's
- * default memory pool; the set-up buffers share one arena), runs on that
- * stream, and msrsb_setup returns after synchronising it alone.  On success *out owns all device memory of the
- * context.  Errors: E_INVAL (bad sizes, non-finite or
- * negative T, a face touching an inactive cell or leaving the box, a BC on
- * an inactive cell), E_SINGULAR (an active connected component without any
- * bc connection), E_NOMEM, E_DEVICE.
+ * the context, its allocations included (the set-up buffers share one
+ * arena), runs on that stream, and msrsb_setup returns after synchronising it
+ * alone.  On success *out owns all device memory of the context.  Errors:
+ * E_INVAL (bad sizes, non-finite or negative T, a face touching an inactive
+ * cell or leaving the box, a BC on an inactive cell, an allocator without
+ * both functions), E_SINGULAR (an active connected component without any bc
+ * connection), E_NOMEM, E_DEVICE.
  */
 int msrsb_setup(const msrsb_grid *grid, int n_part, const msrsb_partition *parts,
-                const msrsb_options *opt, void *hip_stream, msrsb_ctx **out);
+                const msrsb_options *opt, const msrsb_allocator *alloc, void *hip_stream, msrsb_ctx **out);
 
 /*
  * Build the restricted-smoothing basis of one stage (stage >= 0) or of every
@@ -161,9 +179,19 @@ int msrsb_setup(const msrsb_grid *grid, int n_part, const msrsb_partition *parts
  * multibasis solver").  Sweeps stop after the first sweep whose largest
  * entry change is <= tol, or after max_sweeps (>= 0).  sweeps_done and
  * last_change (may be NULL) report the last stage processed.
- * Errors: E_INVAL, E_SINGULAR (row sum <= 0 or A_c not SPD), E_DEVICE.
+ * new_trans (host [3N]: tx, ty, tz as in msrsb_grid, or NULL to keep): the
+ * operator's face transmissibilities change first ("changing reservoir/fluid
+ * properties", same subsection), validated as at setup; A, b and the
+ * smoother are rebuilt, the stages named by `stage` are smoothed with the
+ * new operator (warm = 1 continues from their current basis: the local
+ * update), and every other stage, dynamic ones included, keeps its basis
+ * and gets its coarse operator and inverse rebuilt for the new A.
+ * Partitions and supports keep the structure of setup.
+ * Errors: E_INVAL, E_SINGULAR (row sum <= 0, A_c not SPD, or new_trans
+ * leaves a component without a boundary connection), E_STATE (warm start
+ * of a stage without a basis), E_DEVICE.
  */
-int msrsb_update_basis(msrsb_ctx *ctx, int stage, int max_sweeps, double tol, int warm,
+int msrsb_update_basis(msrsb_ctx *ctx, int stage, const double *new_trans, int max_sweeps, double tol, int warm,
                        int *sweeps_done, double *last_change);
 
 /*

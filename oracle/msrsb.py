@@ -674,19 +674,39 @@ class Oracle:
                 raise OracleError(E_INVAL, f"unknown partition kind {part['kind']}")
             self.stages.append(_Stage(part["kind"], block, M, S))
         self.dyn = []
-        if smoother == "jacobi":
-            self.fac = None
-        elif smoother == "ilu0_nat":
-            self.fac = ilu0_factor(self.A, natural_order(self.cells, prob.dims))
-        elif smoother == "ilu0_rb":
-            self.fac = ilu0_factor(self.A, red_black_order(self.cells, prob.dims))
-        else:
-            raise OracleError(E_INVAL, f"unknown smoother {smoother}")
+        self._factor_smoother()
         self.ready = False
 
     # -- basis ---------------------------------------------------------------
-    def update_basis(self, max_sweeps=100, tol=1e-3, stage=-1, warm=False):
+    def _factor_smoother(self):
+        if self.smoother == "jacobi":
+            self.fac = None
+        elif self.smoother == "ilu0_nat":
+            self.fac = ilu0_factor(self.A, natural_order(self.cells, self.prob.dims))
+        elif self.smoother == "ilu0_rb":
+            self.fac = ilu0_factor(self.A, red_black_order(self.cells, self.prob.dims))
+        else:
+            raise OracleError(E_INVAL, f"unknown smoother {self.smoother}")
+
+    def update_basis(self, max_sweeps=100, tol=1e-3, stage=-1, warm=False, new_trans=None):
+        """Restricted smoothing of one stage (or all general/static stages),
+        then Galerkin operators and coarse factors.  ``new_trans = (tx, ty,
+        tz)`` first replaces the face transmissibilities ("changing
+        reservoir/fluid properties"): the operator and smoother are rebuilt,
+        the named stages are smoothed with the new operator (from their
+        current basis when ``warm``), and every other stage keeps its basis
+        and gets its coarse operator rebuilt for the new operator."""
+        import copy
+
         todo = range(len(self.stages)) if stage < 0 else [stage]
+        if new_trans is not None:
+            prob = copy.copy(self.prob)
+            prob.tx, prob.ty, prob.tz = (np.asarray(t, dtype=np.float64).copy() for t in new_trans)
+            A, b, Ab, cells = assemble(prob)
+            if not np.array_equal(cells, self.cells):
+                raise OracleError(E_INVAL, "the active cells cannot change")
+            self.prob, self.A, self.b, self.Ab = prob, A, b, Ab
+            self._factor_smoother()
         for s in todo:
             st = self.stages[s]
             P0 = st.P if (warm and st.P is not None) else None
@@ -694,6 +714,14 @@ class Oracle:
                                                      max_sweeps, P0)
             st.Ac = galerkin(st.P, self.A)
             st.L = coarse_factor(st.Ac)
+        if new_trans is not None:
+            for k, st in enumerate(self.stages):
+                if k not in todo and st.P is not None:
+                    st.Ac = galerkin(st.P, self.A)
+                    st.L = coarse_factor(st.Ac)
+            for st in self.dyn:
+                st.Ac = galerkin(st.P, self.A)
+                st.L = coarse_factor(st.Ac)
         self.ready = all(st.P is not None for st in self.stages)
         return [self.stages[s].sweeps for s in todo]
 

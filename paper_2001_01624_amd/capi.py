@@ -54,6 +54,37 @@ class Options(C.Structure):
                 ("outer", C.c_int32), ("restart", C.c_int32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+def torch_allocator(device):
+    """An ``msrsb_allocator`` backed by PyTorch's caching allocator on
+    ``device``: blocks are taken on the context's stream and returned to the
+    cache (``caching_allocator_alloc`` / ``caching_allocator_delete``)."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=int(stream or 0))
+        except Exception:  # out of memory or a bad stream: the library reports E_NOMEM
+            return None
+
+    def _free(ptr, nbytes, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    a = Allocator()
+    a.alloc, a.free, a.user = _ALLOC_FN(_alloc), _FREE_FN(_free), None
+    return a
+
+
 def _load():
     # PyTorch ships its own HIP runtime (same soname as the system one).  Load
     # it first so that the library binds to that runtime: one runtime per
@@ -68,8 +99,8 @@ def _load():
         "msrsb_last_error": (C.c_char_p, []),
         "msrsb_default_options": (None, [P(Options)]),
         "msrsb_footprint_bytes": (C.c_size_t, [P(Grid), I, P(Partition), P(Options)]),
-        "msrsb_setup": (I, [P(Grid), I, P(Partition), P(Options), VP, P(VP)]),
-        "msrsb_update_basis": (I, [VP, I, I, D, I, P(I), P(D)]),
+        "msrsb_setup": (I, [P(Grid), I, P(Partition), P(Options), P(Allocator), VP, P(VP)]),
+        "msrsb_update_basis": (I, [VP, I, P(D), I, D, I, P(I), P(D)]),
         "msrsb_add_dynamic_basis": (I, [VP, I, P(VP), P(I)]),
         "msrsb_clear_dynamic_basis": (I, [VP]),
         "msrsb_solve": (I, [VP, VP, VP, D, I, P(I), P(D)]),
@@ -247,7 +278,9 @@ def _dptr(t, n=None, device=None, dtype="float64"):
 class Solver:
     """One problem on the device (``msrsb_setup`` ... ``msrsb_destroy``)."""
 
-    def __init__(self, prob, partitions, options=None, stream=None):
+    def __init__(self, prob, partitions, options=None, stream=None, allocator=None):
+        """``allocator``: None for the library's own stream-ordered pool, or
+        "torch" for PyTorch's caching allocator (``msrsb_allocator``)."""
         import torch
 
         self.prob_dims = tuple(prob.dims)
@@ -261,7 +294,12 @@ class Solver:
         ga = _GridArrays(prob)
         parts = _parts(partitions)
         h = C.c_void_p()
+        # the callbacks must outlive the context
+        self._alloc = torch_allocator(self.device) if allocator == "torch" else None
+        if allocator not in (None, "torch"):
+            raise MsrsbError(E_INVAL, f"unknown allocator {allocator!r}")
         _check(_lib.msrsb_setup(C.byref(ga.grid), len(partitions), parts.arr, C.byref(self.options),
+                                C.byref(self._alloc) if self._alloc is not None else None,
                                 C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
 
@@ -280,10 +318,18 @@ class Solver:
         except Exception:
             pass
 
-    def update_basis(self, stage=-1, max_sweeps=100, tol=1e-3, warm=False):
+    def update_basis(self, stage=-1, max_sweeps=100, tol=1e-3, warm=False, new_trans=None):
+        """``new_trans``: optional ``(tx, ty, tz)`` host arrays replacing the
+        face transmissibilities before the sweeps."""
         sw = C.c_int(0)
         ch = C.c_double(0.0)
-        _check(_lib.msrsb_update_basis(self.h, stage, max_sweeps, tol, int(warm), C.byref(sw), C.byref(ch)))
+        T = None
+        if new_trans is not None:
+            T = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1) for t in new_trans]))
+            if T.size != 3 * self.N:
+                raise MsrsbError(E_INVAL, f"expected 3 x {self.N} transmissibilities, got {T.size}")
+        _check(_lib.msrsb_update_basis(self.h, stage, _ptr(T, C.c_double), max_sweeps, tol, int(warm), C.byref(sw),
+                                       C.byref(ch)))
         return sw.value, ch.value
 
     def add_dynamic_basis(self, increments):

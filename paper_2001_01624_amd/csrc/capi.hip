@@ -49,33 +49,59 @@ static void keep_pool_memory(int device) {
     done.push_back(device);
 }
 
-void *ctx_alloc(Ctx &c, size_t bytes) {
+// One device allocation of the context: from the caller's allocator when one
+// was given at setup, else from the device's stream-ordered pool.
+static void *raw_alloc(Ctx &c, size_t bytes) {
     void *p = nullptr;
-    if (bytes == 0) bytes = 8;
-    const size_t rb = (bytes + 255) & ~(size_t)255;
-    if (c.arena_open && c.arena && c.arena_off + rb <= c.arena_size) {
-        p = c.arena + c.arena_off;
-        c.arena_off += rb;
-        return p;
+    if (c.ua.alloc) {
+        p = c.ua.alloc(bytes, (void *)c.stream, c.ua.user);
+        if (p && ((uintptr_t)p & 255)) {  // the arena carving assumes 256-byte alignment
+            c.ua.free(p, bytes, (void *)c.stream, c.ua.user);
+            set_error("the caller's allocator returned a pointer not aligned to 256 bytes");
+            return nullptr;
+        }
+    } else {
+        keep_pool_memory(c.device);
+        if (hipMallocAsync(&p, bytes, c.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
     }
-    keep_pool_memory(c.device);
-    if (hipMallocAsync(&p, bytes, c.stream) != hipSuccess) {
-        (void)hipGetLastError();
+    if (!p) {
         set_error("device allocation of %zu bytes failed", bytes);
         return nullptr;
     }
     c.allocs.push_back(p);
+    c.alloc_bytes.push_back(bytes);
     return p;
 }
 
-// Return a buffer of ctx_alloc to the pool in the stream's order.  Buffers
-// carved from the set-up arena are left alone (the arena is freed whole).
+static void raw_free(Ctx &c, void *p, size_t bytes) {
+    if (c.ua.alloc) c.ua.free(p, bytes, (void *)c.stream, c.ua.user);
+    else (void)hipFreeAsync(p, c.stream);
+}
+
+void *ctx_alloc(Ctx &c, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    const size_t rb = (bytes + 255) & ~(size_t)255;
+    if (c.arena_open && c.arena && c.arena_off + rb <= c.arena_size) {
+        void *p = c.arena + c.arena_off;
+        c.arena_off += rb;
+        return p;
+    }
+    return raw_alloc(c, bytes);
+}
+
+// Return a buffer of ctx_alloc in the stream's order.  Buffers carved from
+// the set-up arena are left alone (the arena is freed whole).
 void ctx_free(Ctx &c, void *p) {
     if (!p) return;
     auto it = std::find(c.allocs.begin(), c.allocs.end(), p);
     if (it == c.allocs.end()) return;
-    (void)hipFreeAsync(p, c.stream);
+    const size_t k = it - c.allocs.begin();
+    raw_free(c, p, c.alloc_bytes[k]);
     c.allocs.erase(it);
+    c.alloc_bytes.erase(c.alloc_bytes.begin() + k);
 }
 
 // Host -> device copy on the context's stream (the caller keeps the host
@@ -569,6 +595,10 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
                   N);
         return MSRSB_E_INVAL;
     }
+    if (M > kMaxXBlocks) {
+        set_error("explicit-slot stage has %d blocks (limit %d)", M, kMaxXBlocks);
+        return MSRSB_E_INVAL;
+    }
     s.ns = ns;
     s.M = M;
     s.Mp = cdiv(M, kTile) * kTile;
@@ -597,6 +627,31 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
         return MSRSB_E_NOMEM;
     s.xslot = (uint8_t *)ctx_alloc(c, std::max<size_t>(slot.size(), 1));
     if (!s.xslot || !upload(c, s.xslot, slot.data(), slot.size())) return MSRSB_E_NOMEM;
+    // chunk tables of the support lists
+    std::vector<int32_t> cblk, cfirst(M + 1), rcblk, rcfirst(M + 1), rrow;
+    int nrow = 0;
+    for (int j = 0; j < M; ++j) {
+        const int len = cnt[j + 1] - cnt[j];
+        cfirst[j] = (int32_t)cblk.size();
+        for (int k = 0; k < std::max(1, cdiv(len, kXChunk)); ++k) cblk.push_back(j);
+        rcfirst[j] = (int32_t)rcblk.size();
+        const int nr = std::max(1, cdiv(len, kXRapChunk));
+        for (int k = 0; k < nr; ++k) {
+            rcblk.push_back(j);
+            rrow.push_back(nr > 1 ? nrow++ : -1);
+        }
+    }
+    cfirst[M] = (int32_t)cblk.size();
+    rcfirst[M] = (int32_t)rcblk.size();
+    s.nxch = (int)cblk.size();
+    s.nxrch = (int)rcblk.size();
+    s.nxrrow = nrow;
+    if (!upi(s.xcblk, cblk) || !upi(s.xcfirst, cfirst) || !upi(s.xrcblk, rcblk) || !upi(s.xrcfirst, rcfirst) ||
+        !upi(s.xrrow, rrow))
+        return MSRSB_E_NOMEM;
+    s.xpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.nxch);
+    s.xrpart = (double *)ctx_alloc(c, sizeof(double) * std::max<size_t>((size_t)nrow * s.Mp, 1));
+    if (!s.xpart || !s.xrpart) return MSRSB_E_NOMEM;
     // the host tables above are local: wait for their copies
     if (hipStreamSynchronize(c.stream) != hipSuccess) return hip_fail(hipGetLastError(), "upload fault tables");
     const size_t nsN = (size_t)ns * N;
@@ -1106,12 +1161,17 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             const long Mp = cdiv(M, kTile) * kTile;
             const size_t nsN = (size_t)8 * N;
             b += (o.precision == MSRSB_MIXED ? nsN * 10 : nsN * 16) + nsN * 9 + N * 4 + 16 * (size_t)Mp * Mp + 16 * Mp;
+            b += (2 * nsN / kXRapChunk + 1) * (size_t)Mp * 8 + (nsN / kXChunk + M) * 8;  // chunk partials
             cb = std::max(cb, Mp);
             continue;
         }
         const msrsb_partition &pk = parts[k].kind == MSRSB_PART_FAULT_CUT ? parts[parts[k].parent] : parts[k];
         b += cart_bytes(c, pk);
-        if (parts[k].kind == MSRSB_PART_FAULT_CUT) b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
+        if (parts[k].kind == MSRSB_PART_FAULT_CUT) {
+            const long Mf = 2L * pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
+            b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
+            b += (2 * 16 * N / kXRapChunk + 1) * (size_t)cdiv(Mf, kTile) * kTile * 8 + (16 * N / kXChunk + Mf) * 8;
+        }
         long M = (long)pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
         if (parts[k].kind == MSRSB_PART_FAULT_CUT) M *= 2;
         cb = std::max(cb, (long)cdiv(M, kTile) * kTile);
@@ -1122,7 +1182,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
 }
 
 int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, const msrsb_options *opt,
-                void *hip_stream, msrsb_ctx **out) {
+                const msrsb_allocator *alloc, void *hip_stream, msrsb_ctx **out) {
     g_err.clear();
     if (!out) {
         set_error("out is NULL");
@@ -1135,9 +1195,14 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     if (opt) o = *opt;
     else msrsb_default_options(&o);
     if ((rc = check_options(&o)) || (rc = check_parts(g, n_part, parts))) return rc;
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        set_error("an allocator needs both alloc and free");
+        return MSRSB_E_INVAL;
+    }
     msrsb_ctx *c = new msrsb_ctx();
     c->opt = o;
     c->stream = (hipStream_t)hip_stream;
+    if (alloc) c->ua = *alloc;
     (void)hipGetDevice(&c->device);
     c->nx = g->nx; c->ny = g->ny; c->nz = g->nz;
     const int N = c->N = g->nx * g->ny * g->nz;
@@ -1182,16 +1247,13 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     {
         const size_t est = msrsb_footprint_bytes(g, n_part, parts, &o);
         if (est > 0) {
-            keep_pool_memory(c->device);
-            void *a = nullptr;
             const size_t sz = est + est / 32 + ((size_t)1 << 20);
-            if (hipMallocAsync(&a, sz, c->stream) == hipSuccess) {
-                c->allocs.push_back(a);
+            void *a = raw_alloc(*c, sz);  // on failure the buffers are allocated one by one
+            if (a) {
                 c->arena = (char *)a;
                 c->arena_size = sz;
-            } else {
-                (void)hipGetLastError();
             }
+            g_err.clear();
         }
         c->arena_open = true;
     }
@@ -1199,34 +1261,34 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !up32(c->tx32, g->tx) || !up32(c->ty32, g->ty) ||
         !up32(c->tz32, g->tz))
         return fail(MSRSB_E_NOMEM);
-    auto alloc = [&](size_t bytes) { return ctx_alloc(*c, bytes); };
-    c->diag = (double *)alloc(8 * (size_t)N);
-    c->b = (double *)alloc(8 * (size_t)N);
-    c->dtil = (double *)alloc(8 * (size_t)N);
-    c->dtil32 = (float *)alloc(4 * (size_t)N);
-    c->diag32 = (float *)alloc(4 * (size_t)N);
-    c->r = (double *)alloc(8 * (size_t)N);
-    c->e = (double *)alloc(8 * (size_t)N);
-    c->tmp = (double *)alloc(8 * (size_t)N);
-    c->z = (double *)alloc(8 * (size_t)N);
-    c->u = (double *)alloc(8 * (size_t)N);
+    auto dalloc = [&](size_t bytes) { return ctx_alloc(*c, bytes); };
+    c->diag = (double *)dalloc(8 * (size_t)N);
+    c->b = (double *)dalloc(8 * (size_t)N);
+    c->dtil = (double *)dalloc(8 * (size_t)N);
+    c->dtil32 = (float *)dalloc(4 * (size_t)N);
+    c->diag32 = (float *)dalloc(4 * (size_t)N);
+    c->r = (double *)dalloc(8 * (size_t)N);
+    c->e = (double *)dalloc(8 * (size_t)N);
+    c->tmp = (double *)dalloc(8 * (size_t)N);
+    c->z = (double *)dalloc(8 * (size_t)N);
+    c->u = (double *)dalloc(8 * (size_t)N);
     // reduction partials: dot/norm kernels, and one maximum per sweep workgroup
     const size_t npart = std::max({(size_t)kRedBlocks * (2 * kMaxRestart + 2),
                                    (size_t)cdiv(g->nx, 64) * cdiv((long)g->ny * g->nz, 4),
                                    (size_t)cdiv(N, kBlock)});
-    c->partial = (double *)alloc(8 * npart);
-    c->scal = (double *)alloc(8 * 16384);
-    c->status = (Status *)alloc(sizeof(Status));
-    c->maxbits = (unsigned long long *)alloc(8 * 65536);
-    c->flag = (int *)alloc(2 * sizeof(int));  // [1]: the second sweep of a stop-rule pair
+    c->partial = (double *)dalloc(8 * npart);
+    c->scal = (double *)dalloc(8 * 16384);
+    c->status = (Status *)dalloc(sizeof(Status));
+    c->maxbits = (unsigned long long *)dalloc(8 * 65536);
+    c->flag = (int *)dalloc(2 * sizeof(int));  // [1]: the second sweep of a stop-rule pair
     if (!c->diag || !c->b || !c->dtil || !c->dtil32 || !c->diag32 || !c->r || !c->e || !c->tmp || !c->z || !c->u ||
         !c->partial || !c->scal || !c->status || !c->maxbits || !c->flag)
         return fail(MSRSB_E_NOMEM);
     if (!(c->h_status = pinned_status())) return fail(MSRSB_E_NOMEM);
     if (g->n_bc > 0) {
-        c->bc_cell = (int32_t *)alloc(4 * (size_t)g->n_bc);
-        c->bc_trans = (double *)alloc(8 * (size_t)g->n_bc);
-        c->bc_value = (double *)alloc(8 * (size_t)g->n_bc);
+        c->bc_cell = (int32_t *)dalloc(4 * (size_t)g->n_bc);
+        c->bc_trans = (double *)dalloc(8 * (size_t)g->n_bc);
+        c->bc_value = (double *)dalloc(8 * (size_t)g->n_bc);
         if (!c->bc_cell || !c->bc_trans || !c->bc_value) return fail(MSRSB_E_NOMEM);
         upload(*c, c->bc_cell, g->bc_cell, 4 * (size_t)g->n_bc);
         upload(*c, c->bc_trans, g->bc_trans, 8 * (size_t)g->n_bc);
@@ -1234,17 +1296,17 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     }
     if (o.outer == MSRSB_GMRES) {
         if (fp32_basis(o)) {
-            c->V = (double *)alloc(8 * 2 * (size_t)N);
-            c->Vf = (float *)alloc(4 * (size_t)o.restart * N);
+            c->V = (double *)dalloc(8 * 2 * (size_t)N);
+            c->Vf = (float *)dalloc(4 * (size_t)o.restart * N);
             if (!c->V || !c->Vf) return fail(MSRSB_E_NOMEM);
             if (hipMemsetAsync(c->Vf, 0, 4 * (size_t)o.restart * N, c->stream) != hipSuccess)
                 return fail(MSRSB_E_DEVICE);
         } else {
-            c->V = (double *)alloc(8 * (size_t)(o.restart + 1) * N);
+            c->V = (double *)dalloc(8 * (size_t)(o.restart + 1) * N);
             if (!c->V) return fail(MSRSB_E_NOMEM);
         }
         if (o.restart <= kDcgsMax) {
-            c->Z = (double *)alloc(8 * (size_t)o.restart * N);
+            c->Z = (double *)dalloc(8 * (size_t)o.restart * N);
             if (!c->Z) return fail(MSRSB_E_NOMEM);
         }
     }
@@ -1258,7 +1320,7 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         if (rc) return fail(rc);
         cb = std::max(cb, (long)c->stages[k].Mp);
     }
-    c->cbuf = (double *)alloc(8 * (size_t)(cb + 2 * kTile) * kTile);  // + two diagonal-block inverses
+    c->cbuf = (double *)dalloc(8 * (size_t)(cb + 2 * kTile) * kTile);  // + two diagonal-block inverses
     c->cbuf_n = cb;
     if (!c->cbuf) return fail(MSRSB_E_NOMEM);
     hipMemsetAsync(c->tmp, 0, 8 * (size_t)N, c->stream);
@@ -1287,8 +1349,39 @@ static int finish_coarse(Ctx &c, Stage &s) {
     return MSRSB_OK;
 }
 
-int msrsb_update_basis(msrsb_ctx *c, int stage, int max_sweeps, double tol, int warm, int *sweeps_done,
-                       double *last_change) {
+// Replace the face transmissibilities (host [3N]: tx, ty, tz) and rebuild
+// what depends on them on the device: diagonal, right-hand side, FP32 copies
+// and the smoother's pivots.  Partitions and supports keep their set-up
+// structure.
+static int set_transmissibility(Ctx &c, const double *T) {
+    const int N = c.N;
+    msrsb_grid g{};
+    g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
+    g.active = c.h_active.data();
+    g.tx = T; g.ty = T + N; g.tz = T + 2 * (size_t)N;
+    g.n_bc = c.n_bc;
+    g.bc_cell = c.h_bc_cell.data();
+    g.bc_trans = c.h_bc_trans.data();
+    g.bc_value = c.h_bc_value.data();
+    int rc = validate(&g);
+    if (rc) return rc;
+    std::vector<float> t32((size_t)3 * N);
+    for (size_t i = 0; i < (size_t)3 * N; ++i) t32[i] = (float)T[i];
+    double *d64[3] = {c.tx, c.ty, c.tz};
+    float *d32[3] = {c.tx32, c.ty32, c.tz32};
+    for (int a = 0; a < 3; ++a)
+        if (!upload(c, d64[a], T + (size_t)a * N, 8 * (size_t)N) || !upload(c, d32[a], t32.data() + (size_t)a * N, 4 * (size_t)N))
+            return hip_fail(hipGetLastError(), "transmissibility upload");
+    launch_assemble(c);
+    launch_ilu_factor(c);
+    hipError_t e = hipStreamSynchronize(c.stream);  // the host copies above are local
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "transmissibility update");
+    return MSRSB_OK;
+}
+
+int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max_sweeps, double tol, int warm,
+                       int *sweeps_done, double *last_change) {
     g_err.clear();
     if (!c) {
         set_error("ctx is NULL");
@@ -1299,17 +1392,34 @@ int msrsb_update_basis(msrsb_ctx *c, int stage, int max_sweeps, double tol, int 
         return MSRSB_E_INVAL;
     }
     const int s0 = stage < 0 ? 0 : stage, s1 = stage < 0 ? (int)c->stages.size() : stage + 1;
-    for (int k = s0; k < s1; ++k) {
-        Stage &s = c->stages[k];
-        if (warm && !s.has_basis) {
+    for (int k = s0; k < s1; ++k)
+        if (warm && !c->stages[k].has_basis) {
             set_error("warm start of stage %d before its basis exists", k);
             return MSRSB_E_STATE;
         }
-        int rc = launch_sweeps(*c, s, max_sweeps, tol, warm != 0, sweeps_done, last_change);
+    int rc;
+    if (new_trans && (rc = set_transmissibility(*c, new_trans))) return rc;
+    for (int k = s0; k < s1; ++k) {
+        Stage &s = c->stages[k];
+        rc = launch_sweeps(*c, s, max_sweeps, tol, warm != 0, sweeps_done, last_change);
         if (rc) return rc;
         launch_rap(*c, s);
         if ((rc = finish_coarse(*c, s))) return rc;
         s.has_basis = true;
+    }
+    if (new_trans) {
+        // every other stage keeps its basis; its coarse operator follows the new A
+        for (int k = 0; k < (int)c->stages.size(); ++k) {
+            Stage &s = c->stages[k];
+            if ((k >= s0 && k < s1) || !s.has_basis) continue;
+            launch_rap(*c, s);
+            if ((rc = finish_coarse(*c, s))) return rc;
+        }
+        for (auto &s : c->dyn)
+            if (s.M > 0) {
+                launch_dyn_rap(*c, s);
+                if ((rc = finish_coarse(*c, s))) return rc;
+            }
     }
     return MSRSB_OK;
 }
@@ -1490,8 +1600,7 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
             e = hipStreamSynchronize(c->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            hipFreeAsync(dv, c->stream);
-            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
+            ctx_free(*c, dv);
             if (e != hipSuccess) return hip_fail(e, "export");
         }
     } else if (s->kind == 3) {
@@ -1537,8 +1646,7 @@ int msrsb_export_stage(msrsb_ctx *c, int stage, int32_t *h_block, int32_t *h_slo
             e = hipStreamSynchronize(c->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(h_vals, dv, 8 * (size_t)s->ns * N, hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            hipFreeAsync(dv, c->stream);
-            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)dv), c->allocs.end());
+            ctx_free(*c, dv);
             if (e != hipSuccess) return hip_fail(e, "export");
         }
     }
@@ -1729,7 +1837,7 @@ int msrsb_set_stream(msrsb_ctx *c, void *hip_stream) {
 void msrsb_destroy(msrsb_ctx *c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);
-    for (void *p : c->allocs) hipFreeAsync(p, c->stream);
+    for (size_t k = 0; k < c->allocs.size(); ++k) raw_free(*c, c->allocs[k], c->alloc_bytes[k]);
     for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
     release_pinned_status(c->h_status);
     delete c;

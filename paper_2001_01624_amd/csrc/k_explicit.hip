@@ -137,24 +137,39 @@ int launch_xsweep(Ctx &c, Stage &s, int in, int out) {
     return xsweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out]);
 }
 
-// d_j = sum over the support list of block j of P_ij r_i (one workgroup per
-// block, fixed-order sum).
+// d_j = sum over the support list of block j of P_ij r_i, in two fixed-order
+// passes: one workgroup per chunk of at most kXChunk list entries (a block
+// whose support spans the grid is spread over many workgroups), then one
+// thread per block adds its chunks in order.
 template <typename PS>
 __global__ __launch_bounds__(kBlock) void k_xrestrict(int N, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ cblk,
+                                                      const int32_t *__restrict__ cfirst,
                                                       const int32_t *__restrict__ cell,
                                                       const uint8_t *__restrict__ slot, const PS *__restrict__ P,
-                                                      const double *__restrict__ r, double *__restrict__ d,
+                                                      const double *__restrict__ r, double *__restrict__ part,
                                                       const int *done) {
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
-    const int j = blockIdx.x;
+    const int ch = blockIdx.x, j = cblk[ch];
+    const int k0 = ptr[j] + (ch - cfirst[j]) * kXChunk, k1 = min(k0 + kXChunk, ptr[j + 1]);
     double acc = 0.0;
-    for (int k = ptr[j] + threadIdx.x; k < ptr[j + 1]; k += blockDim.x) {
+    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
         const int i = cell[k];
         acc += ld_basis(P, (long)slot[k] * N + i) * r[i];
     }
     const double s = block_sum(acc, lds);
-    if (threadIdx.x == 0) d[j] = s;
+    if (threadIdx.x == 0) part[ch] = s;
+}
+
+__global__ void k_xrestrict_finish(int M, const int32_t *__restrict__ cfirst, const double *__restrict__ part,
+                                   double *__restrict__ d, const int *done) {
+    if (done && *done) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    double s = 0.0;
+    for (int c = cfirst[j]; c < cfirst[j + 1]; ++c) s += part[c];
+    d[j] = s;
 }
 
 template <typename PS>
@@ -175,11 +190,13 @@ __global__ __launch_bounds__(kBlock) void k_xprolong(int N, int ns, const int32_
 
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done) {
     if (c.opt.precision == MSRSB_MIXED)
-        hipLaunchKernelGGL(k_xrestrict<uint16_t>, dim3(s.M), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcell, s.xslot,
-                           s.Pbf, r, s.dvec, done);
+        hipLaunchKernelGGL(k_xrestrict<uint16_t>, dim3(s.nxch), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcblk,
+                           s.xcfirst, s.xcell, s.xslot, s.Pbf, r, s.xpart, done);
     else
-        hipLaunchKernelGGL(k_xrestrict<double>, dim3(s.M), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcell, s.xslot,
-                           s.P64[s.cur], r, s.dvec, done);
+        hipLaunchKernelGGL(k_xrestrict<double>, dim3(s.nxch), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcblk,
+                           s.xcfirst, s.xcell, s.xslot, s.P64[s.cur], r, s.xpart, done);
+    hipLaunchKernelGGL(k_xrestrict_finish, dim3(cdiv(s.M, kBlock)), dim3(kBlock), 0, c.stream, s.M, s.xcfirst, s.xpart,
+                       s.dvec, done);
 }
 
 void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done) {
@@ -196,15 +213,21 @@ void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done) {
 // P_aj - P_bj != 0 is taken once (from a, and from b only when a is not in
 // the support), and its contributions T g_j g_k are summed per column k by
 // fixed-shape wave reductions committed in a fixed order.
+// One wavefront per chunk of at most kXRapChunk entries of a block's list; a
+// block with several chunks sums each into a partial row of its own, added
+// in chunk order by k_xrap_finish.
 template <typename PS>
 __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__restrict__ sb,
-                                             const int32_t *__restrict__ ptr, const int32_t *__restrict__ cell,
+                                             const int32_t *__restrict__ ptr, const int32_t *__restrict__ rcblk,
+                                             const int32_t *__restrict__ rcfirst, const int32_t *__restrict__ rrow,
+                                             const int32_t *__restrict__ cell,
                                              const uint8_t *__restrict__ slot, const PS *__restrict__ P,
-                                             const double *__restrict__ bcdiag, double *__restrict__ Ac, int Mp) {
-    const int j = blockIdx.x, lane = threadIdx.x;
+                                             const double *__restrict__ bcdiag, double *__restrict__ Ac,
+                                             double *__restrict__ rpart, int Mp) {
+    const int ch = blockIdx.x, j = rcblk[ch], lane = threadIdx.x;
     const long N = g.N;
-    double *row = Ac + (long)j * Mp;
-    const int k0 = ptr[j], k1 = ptr[j + 1];
+    double *row = rrow[ch] >= 0 ? rpart + (long)rrow[ch] * Mp : Ac + (long)j * Mp;
+    const int k0 = ptr[j] + (ch - rcfirst[j]) * kXRapChunk, k1 = min(k0 + kXRapChunk, ptr[j + 1]);
     for (int base = k0; base < k1; base += 64) {
         const int k = base + lane;
         const bool live = k < k1;
@@ -303,17 +326,35 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
     }
 }
 
+// Rows of blocks with several chunks: A_c[j][k] = sum of the chunks' partial
+// rows, in chunk order (one thread per column).
+__global__ void k_xrap_finish(int M, int Mp, const int32_t *__restrict__ rcfirst, const int32_t *__restrict__ rrow,
+                              const double *__restrict__ rpart, double *__restrict__ Ac) {
+    const int j = blockIdx.y;
+    const int c0 = rcfirst[j], c1 = rcfirst[j + 1];
+    if (c1 - c0 < 2) return;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < M; k += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int c = c0; c < c1; ++c) v += rpart[(long)rrow[c] * Mp + k];
+        Ac[(long)j * Mp + k] = v;
+    }
+}
+
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
 
 void launch_xrap(Ctx &c, Stage &s) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
+    if (s.nxrrow > 0) hipMemsetAsync(s.xrpart, 0, sizeof(double) * (size_t)s.nxrrow * s.Mp, c.stream);
     if (c.opt.precision == MSRSB_MIXED)
-        hipLaunchKernelGGL(k_xrap<uint16_t>, dim3(s.M), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xcell,
-                           s.xslot, s.Pbf, c.bcdiag, s.Ac, s.Mp);
+        hipLaunchKernelGGL(k_xrap<uint16_t>, dim3(s.nxrch), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xrcblk,
+                           s.xrcfirst, s.xrrow, s.xcell, s.xslot, s.Pbf, c.bcdiag, s.Ac, s.xrpart, s.Mp);
     else
-        hipLaunchKernelGGL(k_xrap<double>, dim3(s.M), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xcell,
-                           s.xslot, s.P64[s.cur], c.bcdiag, s.Ac, s.Mp);
+        hipLaunchKernelGGL(k_xrap<double>, dim3(s.nxrch), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xrcblk,
+                           s.xrcfirst, s.xrrow, s.xcell, s.xslot, s.P64[s.cur], c.bcdiag, s.Ac, s.xrpart, s.Mp);
+    if (s.nxrrow > 0)
+        hipLaunchKernelGGL(k_xrap_finish, dim3(cdiv(s.M, kBlock), s.M), dim3(kBlock), 0, c.stream, s.M, s.Mp,
+                           s.xrcfirst, s.xrrow, s.xrpart, s.Ac);
     launch_symmetrize(c, s.Ac, s.M, s.Mp);
 }
 

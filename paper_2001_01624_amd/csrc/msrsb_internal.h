@@ -17,6 +17,9 @@ constexpr int kRedBlocks = 2048;   // fixed grid of the norm/dot kernels (determ
 constexpr int kTile = 64;          // coarse inverse tile / panel width
 constexpr int kMaxRestart = 64;
 constexpr int kMaxXSlots = 32;   // slots per cell of an explicit (fault-cut) stage
+constexpr int kMaxXBlocks = 32768;  // blocks of an explicit stage (dense coarse operator)
+constexpr int kXChunk = 2048;    // support-list entries per restriction workgroup (explicit stages)
+constexpr int kXRapChunk = 8192; // support-list entries per Galerkin-row wavefront (explicit stages)
 
 // Geometry of the fine box as the kernels see it.
 struct Fine {
@@ -83,6 +86,14 @@ struct Stage {
     int parent = -1;
     int32_t *xsb = nullptr, *xpblock = nullptr, *xptr = nullptr, *xcell = nullptr;
     uint8_t *xslot = nullptr;
+    // the support lists cut into chunks of at most kXChunk entries (restriction)
+    // and kXRapChunk entries (Galerkin rows): block of each chunk, first chunk
+    // of each block; Galerkin chunks of blocks with more than one chunk sum
+    // into partial rows (xrrow: row of each chunk, -1 = straight into A_c)
+    int nxch = 0, nxrch = 0, nxrrow = 0;
+    int32_t *xcblk = nullptr, *xcfirst = nullptr;
+    int32_t *xrcblk = nullptr, *xrcfirst = nullptr, *xrrow = nullptr;
+    double *xpart = nullptr, *xrpart = nullptr;
     std::vector<int32_t> h_xsb, h_xpblock;
 };
 
@@ -140,6 +151,8 @@ struct Ctx {
     std::vector<Stage> stages;    // general + static
     std::vector<Stage> dyn;       // dynamic, newest first
     std::vector<void *> allocs;   // every device allocation (freed at destroy)
+    std::vector<size_t> alloc_bytes;  // their sizes (the caller's allocator is told them)
+    msrsb_allocator ua{};         // caller's device allocator (ua.alloc == NULL: the library's pool)
     // set-up arena: one allocation that the set-up's buffers are carved from
     // (256-byte aligned); later allocations, and any that do not fit, are
     // allocations of their own

@@ -363,3 +363,77 @@ def test_dynamic_cap_beyond_one_bin_is_an_error():
     with pytest.raises(O.OracleError):
         o2 = O.Oracle(prob, [{"kind": "cartesian", "coarse_dims": (6, 6, 1)}], n_bins=4, max_dyn_blocks=20)
         o2.add_dynamic_basis([dp])
+
+
+# --- transmissibility updates with local basis updates ("changing reservoir/fluid
+# properties ... iterating a few times extra", subsection "Iterative multiscale
+# multibasis solver")
+
+def _scaled_trans(prob, factor=10.0):
+    """Face transmissibilities multiplied by `factor` on the faces of a
+    y-slab of cells (a changed mobility region)."""
+    nx, ny, nz = prob.dims
+    y = (np.arange(prob.n_cells) // nx) % ny
+    band = (y >= ny // 3) & (y < ny // 2)
+    return tuple(np.where(band, T * factor, T) for T in (prob.tx, prob.ty, prob.tz))
+
+
+def test_trans_update_equals_fresh_setup():
+    from workloads import make_config2
+
+    prob = make_config2(dims=(10, 12, 5), seed=2)
+    parts = [{"kind": "cartesian", "coarse_dims": (2, 3, 2)}, {"kind": "fault_cut", "parent": 0}]
+    o = O.Oracle(prob, parts, smoother="ilu0_rb")
+    o.update_basis(max_sweeps=4, tol=0.0)
+    T = _scaled_trans(prob)
+    o.update_basis(max_sweeps=6, tol=0.0, new_trans=T)
+    fresh_prob = prob.with_source()
+    fresh_prob.tx, fresh_prob.ty, fresh_prob.tz = T
+    f = O.Oracle(fresh_prob, parts, smoother="ilu0_rb")
+    f.update_basis(max_sweeps=6, tol=0.0)
+    assert (o.A != f.A).nnz == 0 and np.array_equal(o.b, f.b)
+    for a, b in zip(o.stages, f.stages):
+        assert (a.P != b.P).nnz == 0 and np.array_equal(a.Ac, b.Ac)
+    x1, c1, r1, _ = o.solve(rtol=1e-9)
+    x2, c2, r2, _ = f.solve(rtol=1e-9)
+    assert c1 == c2 and np.array_equal(x1, x2)
+
+
+def test_trans_update_keeps_other_bases_and_rebuilds_their_coarse_operators():
+    from workloads import make_config1
+
+    prob = make_config1(dims=(8, 10, 4), seed=3)
+    parts = [{"kind": "cartesian", "coarse_dims": (2, 2, 2)}, {"kind": "cartesian", "coarse_dims": (4, 2, 1)}]
+    o = O.Oracle(prob, parts)
+    o.update_basis(max_sweeps=5, tol=0.0)
+    P0 = o.stages[0].P.copy()
+    dp = np.zeros(prob.n_cells)
+    dp[:prob.n_cells // 3] = 1.0
+    o.add_dynamic_basis([dp])
+    T = _scaled_trans(prob, 7.0)
+    # only stage 1 is smoothed again (warm, two extra sweeps)
+    P1 = o.stages[1].P.copy()
+    o.update_basis(max_sweeps=2, tol=0.0, stage=1, warm=True, new_trans=T)
+    assert (o.stages[0].P != P0).nnz == 0
+    # stage 0: the dense triple product with the new operator
+    dense = P0.toarray().T @ o.A.toarray() @ P0.toarray()
+    assert np.abs(o.stages[0].Ac - dense).max() <= 1e-13 * np.abs(dense).max()
+    # stage 1: two sweeps of the new basis operator from the old basis
+    Pw, _, _ = O.msrsb_basis(o.Ab, o.stages[1].block[o.cells], o.stages[1].S, max_sweeps=2, tol=0.0, P0=P1)
+    assert abs(o.stages[1].P - Pw).max() == 0.0
+    # dynamic stage: constant basis, so A_c is the coarse two-point operator of the new T
+    st = o.dyn[0]
+    blk = st.block
+    nx, ny = prob.dims[0], prob.dims[1]
+    Ac = np.zeros((st.M, st.M))
+    for Tarr, step in ((T[0], 1), (T[1], nx), (T[2], nx * ny)):
+        for i in np.nonzero(Tarr)[0]:
+            j, k = blk[i], blk[i + step]
+            if j != k:
+                Ac[j, k] -= Tarr[i]
+                Ac[k, j] -= Tarr[i]
+                Ac[j, j] += Tarr[i]
+                Ac[k, k] += Tarr[i]
+    for c, t in zip(prob.bc_cell, prob.bc_trans):
+        Ac[blk[c], blk[c]] += t
+    assert np.abs(st.Ac - Ac).max() <= 1e-13 * np.abs(Ac).max()
