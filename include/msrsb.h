@@ -233,6 +233,37 @@ int msrsb_solve(msrsb_ctx *ctx, const double *d_source, double *d_p, double rtol
                 int *iters, double *relres);
 
 /*
+ * Finite-volume multiscale solve with conservative fine fluxes (section
+ * "Multiscale methods": when fine-scale fluxes are needed, a restriction that
+ * sums the cells of each block instead of R = P^T).  For general or static
+ * stage `stage` (0 .. number of general/static stages - 1, basis built):
+ *   A_fv = R_fv A P (R_fv sums the stage's own blocks; not symmetric in
+ *   general), inverted by the Gauss-Jordan sweep of the coarse solves without
+ *   pivoting (rebuilt whenever the basis or the operator changed; a zero
+ *   pivot is E_SINGULAR);
+ *   d_p = P A_fv^{-1} R_fv b, the multiscale pressure, whose fluxes balance
+ *   every block;
+ *   inside every block the fine pressure p' solves the block's problem with
+ *   the fluxes of d_p imposed on the faces leaving the block (Jacobi-
+ *   preconditioned conjugate gradients from p' = d_p, to ||r|| <= local_rtol
+ *   ||rhs|| per block or max_local_iters steps);
+ *   d_face_flux [3N] (layout of msrsb_fluxes): T (p'_a - p'_b) on faces
+ *   inside a block, T (p_a - p_b) on faces between blocks; d_bc_flux
+ *   [n_bc] (may be NULL): bc_trans (p'_i - bc_value) from p'.
+ * These fluxes balance every cell (outflow - q_i = 0) up to the local
+ * solves' residual, provided each block is face-connected or anchored by a
+ * boundary term.  d_source (device [N] or NULL) replaces the source first;
+ * d_p_fine (device [N], may be NULL) receives p'.  local_iters (host, may be
+ * NULL): the most conjugate-gradient steps any block took; max_imbalance
+ * (host, may be NULL): max over cells of |outflow - q_i| of the returned
+ * fluxes.  Blocks of at most 8192 cells (E_INVAL otherwise).  Device
+ * vectors are the context's; E_STATE if the stage has no basis.
+ */
+int msrsb_solve_fv(msrsb_ctx *ctx, int stage, const double *d_source, double *d_p, double *d_p_fine,
+                   double *d_face_flux, double *d_bc_flux, double local_rtol, int max_local_iters, int *local_iters,
+                   double *max_imbalance);
+
+/*
  * Apply one operator of the path to a device vector (for testing single
  * steps; d_in, d_out device [N], distinct):
  *   op 0 RESIDUAL:  d_out = b - A d_in

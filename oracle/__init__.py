@@ -26,5 +26,10 @@ from .msrsb import (  # noqa: F401
     dynamic_partition,
     indicator,
     fluxes,
+    fv_restriction,
+    fv_multiscale_pressure,
+    conservative_pressure,
+    reconstructed_fluxes,
+    cell_imbalance,
     Oracle,
 )

@@ -615,6 +615,94 @@ def dynamic_partition(prob, dp, general_block, n_bins=4, max_blocks=4096):
 
 
 # ---------------------------------------------------------------------------
+# Finite-volume restriction and conservative flux reconstruction (section
+# "Multiscale methods": for fine-scale fluxes, a restriction operator that sums
+# the entries of the cells of each block).
+# ---------------------------------------------------------------------------
+
+def fv_restriction(block_local, M):
+    """``R_fv[j, i] = 1`` for cell ``i`` in block ``j`` (sparse ``M x n``)."""
+    return indicator(block_local, M).T.tocsr()
+
+
+def fv_multiscale_pressure(P, A, b, block_local, M):
+    """``A_fv = R_fv A P`` and ``p_ms = P A_fv^{-1} R_fv b`` (dense LU for the
+    coarse system).  Returns ``(p_ms, A_fv)`` over the active cells."""
+    R = fv_restriction(block_local, M)
+    Afv = np.asarray((R @ (A @ P)).todense())
+    pc = np.linalg.solve(Afv, R @ b)
+    return P @ pc, Afv
+
+
+def conservative_pressure(A, b, block_local, M, pms, bc_diag):
+    """Fine pressure ``p'`` inside every block from the block's own equations
+    with the fluxes of ``pms`` imposed on the faces leaving it: for ``I`` the
+    cells of a block, ``A_N = A[I, I] + diag(sum_{l not in I} A_il)`` and
+    ``rhs_i = b_i + sum_{l not in I} A_il (pms_i - pms_l)``.  Each connected
+    piece of a block is solved on its own; a piece without a boundary or well
+    term (``bc_diag = 0`` on all its cells) has a singular ``A_N``, and its
+    ``p'`` is the solution with the same sum as ``pms`` on the piece (that sum
+    as an extra equation with a multiplier)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    pf = np.zeros(n)
+    for j in range(M):
+        I = np.nonzero(block_local == j)[0]
+        out = np.setdiff1d(np.arange(n), I)
+        AII = A[I][:, I]
+        AIo = A[I][:, out]
+        off = np.asarray(AIo.sum(axis=1)).ravel()
+        AN = (AII + sp.diags(off)).tocsr()
+        rhs = b[I] + off * pms[I] - AIo @ pms[out]
+        ncomp, lab = connected_components(AN, directed=False)
+        for c in range(ncomp):
+            C = np.nonzero(lab == c)[0]
+            ACC = AN[C][:, C].tocsc()
+            if np.any(bc_diag[I[C]] > 0):
+                pf[I[C]] = spla.spsolve(ACC, rhs[C]) if C.size > 1 else rhs[C] / ACC.toarray()[0, 0]
+            else:
+                one = sp.csc_matrix(np.ones((C.size, 1)))
+                K = sp.bmat([[ACC, one], [one.T, None]]).tocsc()
+                sol = spla.spsolve(K, np.append(rhs[C], pms[I[C]].sum()))
+                pf[I[C]] = sol[:C.size]
+    return pf
+
+
+def reconstructed_fluxes(prob, cells, block_local, pms, pf):
+    """Face fluxes in the structured layout ``[3, N]``: ``T (p'_a - p'_b)`` on
+    faces inside a block, ``T (pms_a - pms_b)`` on faces between blocks; well
+    and boundary fluxes ``T_bc (p'_i - p_bc)``."""
+    nx, ny, nz = prob.dims
+    N = prob.n_cells
+    blk = np.full(N, -1, dtype=np.int64)
+    blk[cells] = block_local
+    P = np.zeros(N)
+    F = np.zeros(N)
+    P[cells] = pms
+    F[cells] = pf
+    out = np.zeros((3, N))
+    for d, (T, step) in enumerate(((prob.tx, 1), (prob.ty, nx), (prob.tz, nx * ny))):
+        a = np.nonzero(T)[0]
+        inside = blk[a] == blk[a + step]
+        out[d, a] = np.where(inside, T[a] * (F[a] - F[a + step]), T[a] * (P[a] - P[a + step]))
+    bc = np.asarray(prob.bc_trans) * (F[np.asarray(prob.bc_cell)] - np.asarray(prob.bc_value))
+    return out, bc
+
+
+def cell_imbalance(prob, face, bcf, source=None):
+    """Per-cell ``outflow - q_i`` of face and connection fluxes (box numbering)."""
+    nx, ny, nz = prob.dims
+    N = prob.n_cells
+    q = np.asarray(prob.source if source is None else source, dtype=np.float64)
+    out = np.zeros(N)
+    for d, step in enumerate((1, nx, nx * ny)):
+        out += face[d]
+        out[step:] -= face[d][:N - step]
+    np.add.at(out, np.asarray(prob.bc_cell), bcf)
+    return np.where(prob.active, out - q, 0.0)
+
+
+# ---------------------------------------------------------------------------
 # Post-processing: fluxes and mass balance.
 # ---------------------------------------------------------------------------
 
@@ -853,6 +941,23 @@ class Oracle:
         if history:
             return xb, its, rel, status, hist
         return xb, its, rel, status
+
+    def solve_fv(self, stage=0, source=None):
+        """Finite-volume multiscale pressure of a general/static stage and the
+        conservative reconstruction.  Returns ``(pms_box, pfine_box, face[3,
+        N], bc_flux, A_fv)``."""
+        if not self.ready:
+            raise OracleError(E_STATE, "update_basis has not run")
+        st = self.stages[stage]
+        b = self.b if source is None else rhs_for(self.prob, self.cells, source)
+        bl = st.block[self.cells]
+        pms, Afv = fv_multiscale_pressure(st.P, self.A, b, bl, st.M)
+        bcd = np.zeros(self.prob.n_cells)
+        np.add.at(bcd, np.asarray(self.prob.bc_cell), np.asarray(self.prob.bc_trans))
+        pf = conservative_pressure(self.A, b, bl, st.M, pms, bcd[self.cells])
+        face, bcf = reconstructed_fluxes(self.prob, self.cells, bl, pms, pf)
+        box = lambda v: np.bincount(self.cells, weights=v, minlength=self.prob.n_cells)
+        return box(pms), box(pf), face, bcf, Afv
 
     def direct_solve(self, source=None):
         """The exact fine-scale solution ``A^{-1} b`` (sparse LU)."""

@@ -105,6 +105,7 @@ def _load():
         "msrsb_clear_dynamic_basis": (I, [VP]),
         "msrsb_solve": (I, [VP, VP, VP, D, I, P(I), P(D)]),
         "msrsb_apply": (I, [VP, I, VP, VP]),
+        "msrsb_solve_fv": (I, [VP, I, VP, VP, VP, VP, VP, D, I, P(I), P(D)]),
         "msrsb_fluxes": (I, [VP, VP, VP, VP]),
         "msrsb_num_stages": (I, [VP]),
         "msrsb_stage_info": (I, [VP, I, P(I), P(I), P(I)]),
@@ -349,6 +350,23 @@ class Solver:
                                      C.byref(rel)),
                     allow=(E_NOCONV,))
         return it.value, rel.value, rc
+
+    def solve_fv(self, stage=0, source=None, local_rtol=1e-12, max_local_iters=5000, fine=True):
+        """Finite-volume multiscale pressure of one stage and conservative
+        fluxes (``msrsb_solve_fv``).  Returns ``(p_ms, p_fine, face[3, N],
+        bc_flux, local_iters, max_imbalance)`` as device tensors and floats."""
+        import torch
+
+        dev = torch.device("cuda", self.device)
+        p = torch.empty(self.N, dtype=torch.float64, device=dev)
+        pf = torch.empty(self.N, dtype=torch.float64, device=dev) if fine else None
+        face = torch.empty(3 * self.N, dtype=torch.float64, device=dev)
+        bcf = torch.empty(max(self.n_bc, 1), dtype=torch.float64, device=dev)
+        its = C.c_int(0)
+        imb = C.c_double(0.0)
+        _check(_lib.msrsb_solve_fv(self.h, int(stage), self._vec(source), self._vec(p), self._vec(pf), _dptr(face),
+                                   _dptr(bcf), float(local_rtol), int(max_local_iters), C.byref(its), C.byref(imb)))
+        return p, pf, face.view(3, self.N), bcf[: self.n_bc], its.value, imb.value
 
     def apply(self, op, x, out=None):
         import torch

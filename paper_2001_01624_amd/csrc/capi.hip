@@ -1403,11 +1403,13 @@ int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max
         Stage &s = c->stages[k];
         rc = launch_sweeps(*c, s, max_sweeps, tol, warm != 0, sweeps_done, last_change);
         if (rc) return rc;
+        s.version++;
         launch_rap(*c, s);
         if ((rc = finish_coarse(*c, s))) return rc;
         s.has_basis = true;
     }
     if (new_trans) {
+        for (auto &s : c->stages) s.version++;
         // every other stage keeps its basis; its coarse operator follows the new A
         for (int k = 0; k < (int)c->stages.size(); ++k) {
             Stage &s = c->stages[k];
@@ -1421,6 +1423,154 @@ int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max
                 if ((rc = finish_coarse(*c, s))) return rc;
             }
     }
+    return MSRSB_OK;
+}
+
+// ------------------------------------------------------ finite volume ----
+
+// Host tables of a stage's own blocks for the finite-volume mode (once per
+// stage): block per cell, cell lists, list positions, an explicit slot table
+// for rectilinear stages, chunk tables over the lists, operator buffers.
+static int fv_prepare(Ctx &c, Stage &s) {
+    const int N = c.N, M = s.M;
+    std::vector<int32_t> blk(N, -1), sbv;
+    if (s.kind == 2) {
+        blk = s.h_xpblock;
+    } else {
+        sbv.assign((size_t)s.ns * N, -1);
+        const CartDev &cd = s.cart;
+        const int32_t *T = s.h_tab.data();
+        const int cmap_off = (int)(cd.cmap - s.d_tab);
+        for (int i = 0; i < N; ++i) {
+            if (!c.h_active[i]) continue;
+            const int c3[3] = {i % c.nx, (i / c.nx) % c.ny, i / (c.nx * c.ny)};
+            int J[3], lo[3], nv[3];
+            for (int a = 0; a < 3; ++a) {
+                J[a] = (int)(((long)c3[a] * cd.m[a]) / cd.n[a]);
+                lo[a] = T[s.tab_off[a][0] + c3[a]];
+                nv[a] = T[s.tab_off[a][1] + c3[a]];
+            }
+            blk[i] = T[cmap_off + J[0] + cd.m[0] * (J[1] + cd.m[1] * J[2])];
+            for (int sl = 0; sl < s.ns; ++sl) {
+                int K[3];
+                bool ok = true;
+                for (int a = 0; a < 3; ++a) {
+                    const int bit = cd.bit[a] >= 0 ? (sl >> cd.bit[a]) & 1 : 0;
+                    if (bit >= nv[a]) ok = false;
+                    K[a] = lo[a] + bit;
+                }
+                if (ok) sbv[(size_t)sl * N + i] = T[cmap_off + K[0] + cd.m[0] * (K[1] + cd.m[1] * K[2])];
+            }
+        }
+    }
+    std::vector<int32_t> ptr(M + 1, 0), loc(N, -1);
+    for (int i = 0; i < N; ++i)
+        if (blk[i] >= 0) ptr[blk[i] + 1]++;
+    int maxc = 0;
+    for (int j = 0; j < M; ++j) {
+        maxc = std::max(maxc, ptr[j + 1]);
+        ptr[j + 1] += ptr[j];
+    }
+    if (maxc > kFvMaxCells) {
+        set_error("finite-volume mode: a block of %d cells exceeds the %d-cell limit of the local solves", maxc,
+                  kFvMaxCells);
+        return MSRSB_E_INVAL;
+    }
+    std::vector<int32_t> cells(std::max(ptr[M], 1)), pos(ptr.begin(), ptr.end() - 1);
+    for (int i = 0; i < N; ++i)
+        if (blk[i] >= 0) {
+            loc[i] = pos[blk[i]] - ptr[blk[i]];
+            cells[pos[blk[i]]++] = i;
+        }
+    std::vector<int32_t> rcblk, rcfirst(M + 1), rrow;
+    int nrow = 0;
+    for (int j = 0; j < M; ++j) {
+        const int nr = std::max(1, cdiv(ptr[j + 1] - ptr[j], kXRapChunk));
+        rcfirst[j] = (int32_t)rcblk.size();
+        for (int k = 0; k < nr; ++k) {
+            rcblk.push_back(j);
+            rrow.push_back(nr > 1 ? nrow++ : -1);
+        }
+    }
+    rcfirst[M] = (int32_t)rcblk.size();
+    auto upi = [&](int32_t *&dst, const std::vector<int32_t> &h) -> bool {
+        dst = (int32_t *)ctx_alloc(c, sizeof(int32_t) * std::max<size_t>(h.size(), 1));
+        return dst && upload(c, dst, h.data(), sizeof(int32_t) * h.size());
+    };
+    if (!upi(s.fvblock, blk) || !upi(s.fvptr, ptr) || !upi(s.fvcells, cells) || !upi(s.fvloc, loc) ||
+        !upi(s.fvrcblk, rcblk) || !upi(s.fvrcfirst, rcfirst) || !upi(s.fvrrow, rrow) ||
+        (s.kind != 2 && !upi(s.fvsb, sbv)))
+        return MSRSB_E_NOMEM;
+    s.nfvrch = (int)rcblk.size();
+    s.nfvrrow = nrow;
+    s.fvrpart = (double *)ctx_alloc(c, sizeof(double) * std::max<size_t>((size_t)nrow * s.Mp, 1));
+    s.Afv = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    s.Afvinv = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.Mp * s.Mp);
+    if (!s.fvrpart || !s.Afv || !s.Afvinv) return MSRSB_E_NOMEM;
+    hipError_t e = hipStreamSynchronize(c.stream);  // the host tables above are local
+    if (e != hipSuccess) return hip_fail(e, "finite-volume tables");
+    s.fv_maxcells = maxc;
+    s.fv_ready = true;
+    return MSRSB_OK;
+}
+
+int msrsb_solve_fv(msrsb_ctx *c, int stage, const double *d_source, double *d_p, double *d_p_fine,
+                   double *d_face_flux, double *d_bc_flux, double local_rtol, int max_local_iters, int *local_iters,
+                   double *max_imbalance) {
+    g_err.clear();
+    if (!c || !d_p || !d_face_flux || !(local_rtol >= 0.0) || max_local_iters < 0) {
+        set_error("bad finite-volume solve arguments");
+        return MSRSB_E_INVAL;
+    }
+    if (stage < 0 || stage >= (int)c->stages.size()) {
+        set_error("finite-volume mode needs a general or static stage (0..%d)", (int)c->stages.size() - 1);
+        return MSRSB_E_INVAL;
+    }
+    Stage &s = c->stages[stage];
+    if (!s.has_basis) {
+        set_error("stage %d has no basis yet", stage);
+        return MSRSB_E_STATE;
+    }
+    int rc;
+    if (!s.fv_ready && (rc = fv_prepare(*c, s))) return rc;
+    if (s.fv_version != s.version) {
+        launch_fv_rap(*c, s);
+        hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
+        launch_coarse_inverse_of(*c, s.Afv, s.Afvinv, s.Mp, true);
+        int flag = 0;
+        hipError_t e = hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "finite-volume coarse operator");
+        if (flag & 1) {
+            set_error("finite-volume coarse operator of stage %d has a zero pivot", stage);
+            return MSRSB_E_SINGULAR;
+        }
+        s.fv_version = s.version;
+    }
+    if (d_source) launch_source_update(*c, d_source);
+    launch_fv_restrict(*c, s, c->b);
+    launch_coarse_solve_with(*c, s, s.Afvinv, nullptr);
+    zero_vec(*c, d_p, nullptr);
+    launch_prolong(*c, s, d_p, nullptr);
+    double *pf = d_p_fine ? d_p_fine : c->e;
+    zero_vec(*c, pf, nullptr);
+    int *iters_dev = (int *)(c->maxbits + 1);
+    hipMemsetAsync(c->maxbits, 0, 2 * sizeof(unsigned long long), c->stream);
+    if ((rc = launch_fv_local(*c, s, d_p, pf, local_rtol, max_local_iters, iters_dev))) {
+        set_error("finite-volume local solves: block size not supported");
+        return rc;
+    }
+    launch_fv_faces(*c, s, d_p, pf, d_face_flux);
+    if (d_bc_flux) launch_fluxes(*c, pf, nullptr, d_bc_flux);
+    launch_fv_imbalance(*c, d_face_flux, pf, c->maxbits);
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, c->maxbits, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "finite-volume solve");
+    if (local_iters) *local_iters = (int)(h[1] & 0xffffffffu);
+    if (max_imbalance) memcpy(max_imbalance, &h[0], sizeof(double));
     return MSRSB_OK;
 }
 

@@ -32,7 +32,7 @@ constexpr int kLd = T_ + 1;   // LDS row pitch (bank spread)
 //   3. M[i,j] <- M[i,j] - Cb[i,:] W[:,j] for rows i off the block (with 0 in
 //      place of M[i,j] on the block columns), M[s,:] <- W[s,:].
 // W is 16 x kLd and Cb 64 x 17 doubles of LDS scratch.
-__device__ inline void gj_invert_lds(double (*M)[kLd], double (*W)[kLd], double (*Cb)[17], int *flag) {
+__device__ inline void gj_invert_lds(double (*M)[kLd], double (*W)[kLd], double (*Cb)[17], int *flag, bool general) {
     const int t = threadIdx.x;
 #pragma unroll 1
     for (int sb = 0; sb < T_ / 16; ++sb) {
@@ -48,8 +48,10 @@ __device__ inline void gj_invert_lds(double (*M)[kLd], double (*W)[kLd], double 
 #pragma unroll 4
             for (int k = 0; k < 16; ++k) {  // k & 3 is fixed within the unrolled body
                 const double p = __shfl(x[k & 3], 4 * k + (k >> 2), 64);
-                if (t == 0 && !(p > 0.0)) atomicOr(flag, 1);
-                const double ip = p > 0.0 ? 1.0 / p : 0.0;
+                // SPD: every pivot is positive; a general matrix needs non-zero pivots
+                const bool ok = general ? (p != 0.0 && isfinite(p)) : p > 0.0;
+                if (t == 0 && !ok) atomicOr(flag, 1);
+                const double ip = ok ? 1.0 / p : 0.0;
                 const double dik = __shfl(x[k & 3], 4 * r + (k >> 2), 64);
                 double rowk[4];
 #pragma unroll
@@ -163,11 +165,11 @@ __device__ inline void load_tile(double (*S)[kLd], const double *__restrict__ sr
 }
 
 __global__ __launch_bounds__(kGJThreads) void k_gj_diag(const double *__restrict__ A, int Mp, int k0,
-                                                        double *__restrict__ Dinv, int *flag) {
+                                                        double *__restrict__ Dinv, int *flag, bool general) {
     __shared__ double Ms[T_][kLd], Ws[16][kLd], Cb[T_][17];
     load_tile(Ms, A + (long)k0 * Mp + k0, Mp);
     __syncthreads();
-    gj_invert_lds(Ms, Ws, Cb, flag);
+    gj_invert_lds(Ms, Ws, Cb, flag, general);
     for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dinv[e] = Ms[e / T_][e % T_];
 }
 
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A,
 __global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A, int Mp, int K, int nt,
                                                           const double *__restrict__ Dinv,
                                                           const double *__restrict__ C, double *__restrict__ Dnext,
-                                                          int *flag) {
+                                                          int *flag, bool general) {
     __shared__ double Cs[T_][kLd], Bs[T_][kLd];
     // tile of this workgroup: 0 -> (K+1, K+1) (when it exists), then the rest
     const int L = K + 1 < nt ? K + 1 : -1;
@@ -277,24 +279,28 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) Cs[ti + a][tj + bb] = nv[a][bb];
         __syncthreads();
-        gj_invert_lds(Cs, Bs, reinterpret_cast<double (*)[17]>(&Bs[16][0]), flag);
+        gj_invert_lds(Cs, Bs, reinterpret_cast<double (*)[17]>(&Bs[16][0]), flag, general);
         for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dnext[e] = Cs[e / T_][e % T_];
     }
 }
 
-void launch_coarse_inverse(Ctx &c, Stage &s) {
+void launch_coarse_inverse(Ctx &c, Stage &s) { launch_coarse_inverse_of(c, s.Ac, s.Ainv, s.Mp, false); }
+
+// Ainv = A^{-1} for a padded Mp x Mp matrix (Mp a multiple of kTile).  Without
+// pivoting: an SPD matrix has positive pivots (a non-positive one is flagged);
+// a general one (general = true) needs non-zero leading principal minors.
+void launch_coarse_inverse_of(Ctx &c, const double *Asrc, double *A, int Mp, bool general) {
     ProfScope ps(c, MSRSB_K_INVERSE);
-    const int nt = s.Mp / T_;
-    double *A = s.Ainv;
-    hipMemcpyAsync(A, s.Ac, sizeof(double) * (size_t)s.Mp * s.Mp, hipMemcpyDeviceToDevice, c.stream);
+    const int nt = Mp / T_;
+    hipMemcpyAsync(A, Asrc, sizeof(double) * (size_t)Mp * Mp, hipMemcpyDeviceToDevice, c.stream);
     double *C = c.cbuf;                                       // Mp * kTile doubles
     double *Dbuf[2] = {c.cbuf + (size_t)c.cbuf_n * T_, c.cbuf + (size_t)(c.cbuf_n + T_) * T_};
-    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(kGJThreads), 0, c.stream, A, s.Mp, 0, Dbuf[0], c.flag);
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(kGJThreads), 0, c.stream, A, Mp, 0, Dbuf[0], c.flag, general);
     for (int K = 0; K < nt; ++K) {
         double *D = Dbuf[K & 1], *Dn = Dbuf[(K + 1) & 1];
-        hipLaunchKernelGGL(k_gj_panel, dim3(nt), dim3(kGJThreads), 0, c.stream, A, s.Mp, K, D, C);
-        hipLaunchKernelGGL(k_gj_update, dim3(nt * nt), dim3(kGJThreads), 0, c.stream, A, s.Mp, K, nt, D, C, Dn,
-                           c.flag);
+        hipLaunchKernelGGL(k_gj_panel, dim3(nt), dim3(kGJThreads), 0, c.stream, A, Mp, K, D, C);
+        hipLaunchKernelGGL(k_gj_update, dim3(nt * nt), dim3(kGJThreads), 0, c.stream, A, Mp, K, nt, D, C, Dn,
+                           c.flag, general);
     }
 }
 
@@ -336,11 +342,15 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict_
     if (threadIdx.x == 0) y[map ? map[row] : row] = s;
 }
 
-void launch_coarse_solve(Ctx &c, Stage &s, const int *done) {
+void launch_coarse_solve(Ctx &c, Stage &s, const int *done) { launch_coarse_solve_with(c, s, s.Ainv, done); }
+
+// p_c = Ainv d with the stage's coarse vectors (Ainv: the Galerkin inverse or
+// another inverse of the stage's size).
+void launch_coarse_solve_with(Ctx &c, Stage &s, const double *Ainv, const int *done) {
     ProfScope ps(c, MSRSB_K_COARSE);
     const int npt = cdiv(s.M, kGemvThreads);
 #define MSRSB_GEMV(NPT) \
-    hipLaunchKernelGGL(k_gemv<NPT>, dim3(s.M), dim3(kGemvThreads), 0, c.stream, s.Ainv, s.M, s.Mp, s.dvec, s.pc, \
+    hipLaunchKernelGGL(k_gemv<NPT>, dim3(s.M), dim3(kGemvThreads), 0, c.stream, Ainv, s.M, s.Mp, s.dvec, s.pc, \
                        s.pc_map, done)
     if (npt <= 1) MSRSB_GEMV(1);
     else if (npt <= 2) MSRSB_GEMV(2);

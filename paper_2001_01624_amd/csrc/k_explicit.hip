@@ -340,6 +340,12 @@ __global__ void k_xrap_finish(int M, int Mp, const int32_t *__restrict__ rcfirst
     }
 }
 
+void launch_partial_rows_finish(Ctx &c, int M, int Mp, const int32_t *rcfirst, const int32_t *rrow,
+                                const double *rpart, double *A) {
+    hipLaunchKernelGGL(k_xrap_finish, dim3(cdiv(M, kBlock), M), dim3(kBlock), 0, c.stream, M, Mp, rcfirst, rrow, rpart,
+                       A);
+}
+
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
 
 void launch_xrap(Ctx &c, Stage &s) {

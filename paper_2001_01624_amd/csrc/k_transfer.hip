@@ -590,6 +590,10 @@ __global__ void k_symmetrize(double *A, int M, int Mp) {
     A[(long)j * Mp + i] = v;
 }
 
+void launch_pad_identity(Ctx &c, double *A, int M, int Mp) {
+    if (Mp > M) hipLaunchKernelGGL(k_pad_identity, dim3(cdiv(Mp - M, 64)), dim3(64), 0, c.stream, A, M, Mp);
+}
+
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp) {
     hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(M, 16), cdiv(M, 16)), dim3(16, 16), 0, c.stream, A, M, Mp);
     if (Mp > M) hipLaunchKernelGGL(k_pad_identity, dim3(cdiv(Mp - M, 64)), dim3(64), 0, c.stream, A, M, Mp);

@@ -94,6 +94,18 @@ struct Stage {
     int32_t *xcblk = nullptr, *xcfirst = nullptr;
     int32_t *xrcblk = nullptr, *xrcfirst = nullptr, *xrrow = nullptr;
     double *xpart = nullptr, *xrpart = nullptr;
+    // finite-volume mode: the stage's own blocks as cell lists, position of
+    // each cell in its list, explicit slot table of a rectilinear stage
+    // (-1 = slot unused), the operator R_fv A P and its inverse, Galerkin-style
+    // chunk tables over the own-cell lists; fv_version is the basis version
+    // the operator was built from
+    bool fv_ready = false;
+    int fv_version = -1, fv_maxcells = 0;
+    int32_t *fvblock = nullptr, *fvptr = nullptr, *fvcells = nullptr, *fvloc = nullptr, *fvsb = nullptr;
+    int nfvrch = 0, nfvrrow = 0;
+    int32_t *fvrcblk = nullptr, *fvrcfirst = nullptr, *fvrrow = nullptr;
+    double *fvrpart = nullptr, *Afv = nullptr, *Afvinv = nullptr;
+    int version = 0;              // incremented whenever the basis or the operator changes
     std::vector<int32_t> h_xsb, h_xpblock;
 };
 
@@ -248,6 +260,16 @@ int launch_xsweep(Ctx &c, Stage &s, int in, int out);
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done);
 void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done);
 void launch_xrap(Ctx &c, Stage &s);
+
+// ---- finite-volume restriction and flux reconstruction (k_fv.hip) ----
+constexpr int kFvMaxCells = 8192;  // cells of one block in the local solves (LDS-resident direction)
+void launch_fv_rap(Ctx &c, Stage &s);
+void launch_fv_restrict(Ctx &c, Stage &s, const double *b);
+int launch_fv_local(Ctx &c, Stage &s, const double *pms, double *pf, double rtol, int max_iters, int *iters_max);
+void launch_fv_faces(Ctx &c, Stage &s, const double *pms, const double *pf, double *face);
+void launch_fv_imbalance(Ctx &c, const double *face, const double *pf, unsigned long long *maxbits);
+void launch_coarse_inverse_of(Ctx &c, const double *A, double *Ainv, int Mp, bool general);
+void launch_coarse_solve_with(Ctx &c, Stage &s, const double *Ainv, const int *done);
 
 // ---- dynamic basis kernels (k_dyn.hip) ----
 int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count);
