@@ -179,8 +179,9 @@ int msrsb_setup(const msrsb_grid *grid, int n_part, const msrsb_partition *parts
  * multibasis solver").  Sweeps stop after the first sweep whose largest
  * entry change is <= tol, or after max_sweeps (>= 0).  sweeps_done and
  * last_change (may be NULL) report the last stage processed.
- * new_trans (host [3N]: tx, ty, tz as in msrsb_grid, or NULL to keep): the
- * operator's face transmissibilities change first ("changing reservoir/fluid
+ * new_trans (host [3N]: tx, ty, tz as in msrsb_grid, or NULL to keep) and
+ * new_bc_trans (host [n_bc]: the connections' bc_trans, or NULL to keep):
+ * the operator's coefficients change first ("changing reservoir/fluid
  * properties", same subsection), validated as at setup; A, b and the
  * smoother are rebuilt, the stages named by `stage` are smoothed with the
  * new operator (warm = 1 continues from their current basis: the local
@@ -191,8 +192,8 @@ int msrsb_setup(const msrsb_grid *grid, int n_part, const msrsb_partition *parts
  * leaves a component without a boundary connection), E_STATE (warm start
  * of a stage without a basis), E_DEVICE.
  */
-int msrsb_update_basis(msrsb_ctx *ctx, int stage, const double *new_trans, int max_sweeps, double tol, int warm,
-                       int *sweeps_done, double *last_change);
+int msrsb_update_basis(msrsb_ctx *ctx, int stage, const double *new_trans, const double *new_bc_trans,
+                       int max_sweeps, double tol, int warm, int *sweeps_done, double *last_change);
 
 /*
  * Dynamic stages (subsection "Iterative multiscale multibasis solver", type
@@ -357,6 +358,65 @@ int msrsb_partition_wells(const msrsb_grid *grid, int n_wells, const int32_t *we
                           int radius, int32_t *block);
 int msrsb_partition_indicator(const msrsb_grid *grid, const double *indicator, int n_bins,
                               const int32_t coarse_dims[3], int min_cells, int32_t *block);
+
+/*
+ * Two-phase fully implicit model with the two-stage CPR preconditioner
+ * (sections "Model equations" and "Discrete equations": water and oil, one
+ * component each, backward Euler, two-point fluxes with single-point
+ * upstream mobilities, no gravity or capillary pressure; section
+ * "Preconditioning: the constrained pressure residual (CPR) method" and
+ * "Description of the solution procedure").  Unknowns per cell: pressure p
+ * and water saturation s.  Full-system vectors ([2N], device) interleave
+ * them per cell in box numbering: v[2i] water equation / pressure, v[2i+1]
+ * oil equation / saturation; inactive cells hold 0.  Residuals:
+ *   R_w,i =  pv_i/dt (s_i - s_old,i) + sum_f T_f lw(up) (p_i - p_l)
+ *            + sum_c WI_c lw(s_i) (p_i - p_c) - q_i
+ *   R_o,i = -pv_i/dt (s_i - s_old,i) + sum_f T_f lo(up) (p_i - p_l)
+ *            + sum_c WI_c lo(s_i) (p_i - p_c)
+ * with T_f the pressure context's face transmissibilities at
+ * msrsb_tp_create, WI_c / p_c its connections' bc_trans / bc_value, q the
+ * injected water rate, lw = s^n_w / mu_w, lo = (1-s)^n_o / mu_o, and up the
+ * cell a face's flux leaves (for the face a < b: a when p_a >= p_b).
+ * CPR: IMPES weights (1/2, 1/2) cancel the accumulation derivatives, so the
+ * pressure block is the two-point operator with face coefficients
+ * T lambda_t(up)/2 and connection terms WI lambda_t/2, which
+ * msrsb_tp_assemble installs in the pressure context (its bases smoothed
+ * basis_sweeps more times from their current state: local updates).  One
+ * preconditioner application: dp = one multistage cycle of the pressure
+ * context on (v_w + v_o)/2, then y = (dp, 0) + ILU0(J)^{-1} (v - J (dp, 0))
+ * with block ILU(0) of the full system in red-black cell order.
+ * The two-phase context borrows the pressure context (which must outlive it
+ * and whose bases must exist); its device memory comes from the pressure
+ * context's allocator.
+ */
+typedef struct msrsb_tp_ctx msrsb_tp_ctx;
+typedef struct {
+    double mu_w, mu_o;  /* viscosities, > 0 */
+    double n_w, n_o;    /* Corey exponents, >= 1 */
+} msrsb_fluid;
+/* pore_volume: host [N], > 0 on active cells; restart: GMRES restart length
+ * in [1, 200]. */
+int msrsb_tp_create(msrsb_ctx *pressure, const double *pore_volume, const msrsb_fluid *fluid, int restart,
+                    msrsb_tp_ctx **out);
+/* Residual and Jacobian at (d_p, d_s) (device [N]) with old saturation
+ * d_s_old and injected rate d_q (device [N]; NULL = the pressure context's
+ * source), the IMPES operator into the pressure context and the full-system
+ * ILU(0).  d_res (device [2N], may be NULL) receives R; res_norm (host, may
+ * be NULL) ||R||_2.  E_SINGULAR on a singular 2x2 ILU pivot, E_STATE if the
+ * pressure bases do not exist. */
+int msrsb_tp_assemble(msrsb_tp_ctx *tp, double dt, const double *d_p, const double *d_s, const double *d_s_old,
+                      const double *d_q, int basis_sweeps, double *d_res, double *res_norm);
+/* op 0: d_out = J d_in; op 1: d_out = CPR^{-1} d_in ([2N] device, distinct). */
+int msrsb_tp_apply(msrsb_tp_ctx *tp, int op, const double *d_in, double *d_out);
+/* GMRES(restart) on J dx = -R from dx = 0 with CPR as right preconditioner,
+ * to ||-R - J dx||_2 <= rtol ||R||_2 (true residual, at a restart);
+ * E_NOCONV with the last iterate after max_iters iterations. */
+int msrsb_tp_solve(msrsb_tp_ctx *tp, double *d_dx, double rtol, int max_iters, int *iters, double *relres);
+/* Newton update on active cells: p += dx_p, s = min(1, max(0, s + dx_s)). */
+int msrsb_tp_update(msrsb_tp_ctx *tp, const double *d_dx, double *d_p, double *d_s);
+/* Frees the two-phase context; call it before msrsb_destroy of its pressure
+ * context (its device buffers are that context's allocations). */
+void msrsb_tp_destroy(msrsb_tp_ctx *tp);
 
 /*
  * Host-only helpers (no device needed):

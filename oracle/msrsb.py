@@ -504,11 +504,13 @@ def red_black_order(cells, dims):
     return np.concatenate([loc[col == 0], loc[col == 1]])
 
 
-def ilu0_factor(A, order):
+def ilu0_factor(A, order, positive=True):
     """Textbook ILU(0) (row-wise IKJ elimination restricted to the pattern of
     the matrix) of ``A`` permuted to ``order``.  Returns ``(L, U, order)``
     with ``L`` unit lower triangular and ``U`` upper triangular, both CSR in
-    the permuted numbering."""
+    the permuted numbering.  Pivots must be positive (the M-matrices of the
+    pressure equation) or, with ``positive=False`` (a general matrix such as
+    the two-phase Jacobian), non-zero."""
     B = A[order][:, order].tocsr()
     B.sort_indices()
     n = B.shape[0]
@@ -524,8 +526,9 @@ def ilu0_factor(A, order):
             for j, ukj in rows[k].items():
                 if j > k and j in row:
                     row[j] -= lik * ukj
-        if not row.get(i, 0.0) > 0.0:
-            raise OracleError(E_SINGULAR, "ILU(0) pivot not positive")
+        piv = row.get(i, 0.0)
+        if not (piv > 0.0 if positive else (piv != 0.0 and np.isfinite(piv))):
+            raise OracleError(E_SINGULAR, "ILU(0) pivot not positive" if positive else "ILU(0) pivot zero")
     lr, lc, lv, ur, uc, uv = [], [], [], [], [], []
     for i, row in enumerate(rows):
         for j, v in row.items():
@@ -776,20 +779,25 @@ class Oracle:
         else:
             raise OracleError(E_INVAL, f"unknown smoother {self.smoother}")
 
-    def update_basis(self, max_sweeps=100, tol=1e-3, stage=-1, warm=False, new_trans=None):
+    def update_basis(self, max_sweeps=100, tol=1e-3, stage=-1, warm=False, new_trans=None, new_bc_trans=None):
         """Restricted smoothing of one stage (or all general/static stages),
         then Galerkin operators and coarse factors.  ``new_trans = (tx, ty,
         tz)`` first replaces the face transmissibilities ("changing
-        reservoir/fluid properties"): the operator and smoother are rebuilt,
+        reservoir/fluid properties"; ``new_bc_trans`` likewise replaces the
+        boundary/well connection coefficients): the operator and smoother are rebuilt,
         the named stages are smoothed with the new operator (from their
         current basis when ``warm``), and every other stage keeps its basis
         and gets its coarse operator rebuilt for the new operator."""
         import copy
 
         todo = range(len(self.stages)) if stage < 0 else [stage]
-        if new_trans is not None:
+        changed = new_trans is not None or new_bc_trans is not None
+        if changed:
             prob = copy.copy(self.prob)
-            prob.tx, prob.ty, prob.tz = (np.asarray(t, dtype=np.float64).copy() for t in new_trans)
+            if new_trans is not None:
+                prob.tx, prob.ty, prob.tz = (np.asarray(t, dtype=np.float64).copy() for t in new_trans)
+            if new_bc_trans is not None:
+                prob.bc_trans = np.asarray(new_bc_trans, dtype=np.float64).copy()
             A, b, Ab, cells = assemble(prob)
             if not np.array_equal(cells, self.cells):
                 raise OracleError(E_INVAL, "the active cells cannot change")
@@ -802,7 +810,7 @@ class Oracle:
                                                      max_sweeps, P0)
             st.Ac = galerkin(st.P, self.A)
             st.L = coarse_factor(st.Ac)
-        if new_trans is not None:
+        if changed:
             for k, st in enumerate(self.stages):
                 if k not in todo and st.P is not None:
                     st.Ac = galerkin(st.P, self.A)

@@ -85,6 +85,10 @@ def torch_allocator(device):
     return a
 
 
+class Fluid(C.Structure):
+    _fields_ = [("mu_w", C.c_double), ("mu_o", C.c_double), ("n_w", C.c_double), ("n_o", C.c_double)]
+
+
 def _load():
     # PyTorch ships its own HIP runtime (same soname as the system one).  Load
     # it first so that the library binds to that runtime: one runtime per
@@ -100,7 +104,7 @@ def _load():
         "msrsb_default_options": (None, [P(Options)]),
         "msrsb_footprint_bytes": (C.c_size_t, [P(Grid), I, P(Partition), P(Options)]),
         "msrsb_setup": (I, [P(Grid), I, P(Partition), P(Options), P(Allocator), VP, P(VP)]),
-        "msrsb_update_basis": (I, [VP, I, P(D), I, D, I, P(I), P(D)]),
+        "msrsb_update_basis": (I, [VP, I, P(D), P(D), I, D, I, P(I), P(D)]),
         "msrsb_add_dynamic_basis": (I, [VP, I, P(VP), P(I)]),
         "msrsb_clear_dynamic_basis": (I, [VP]),
         "msrsb_solve": (I, [VP, VP, VP, D, I, P(I), P(D)]),
@@ -118,6 +122,12 @@ def _load():
         "msrsb_axis_support": (I, [I, I, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]),
         "msrsb_partition_wells": (I, [P(Grid), I, P(C.c_int32), P(C.c_int32), I, P(C.c_int32)]),
         "msrsb_partition_indicator": (I, [P(Grid), P(D), I, P(C.c_int32), I, P(C.c_int32)]),
+        "msrsb_tp_create": (I, [VP, P(D), P(Fluid), I, P(VP)]),
+        "msrsb_tp_assemble": (I, [VP, D, VP, VP, VP, VP, I, VP, P(D)]),
+        "msrsb_tp_apply": (I, [VP, I, VP, VP]),
+        "msrsb_tp_solve": (I, [VP, VP, D, I, P(I), P(D)]),
+        "msrsb_tp_update": (I, [VP, VP, VP, VP]),
+        "msrsb_tp_destroy": (None, [VP]),
         "msrsb_profile_begin": (I, [VP, I, I]),
         "msrsb_profile_end": (I, [VP, P(D), P(I)]),
     }
@@ -309,6 +319,9 @@ class Solver:
         return _dptr(t, n=self.N, device=self.device)
 
     def close(self):
+        # two-phase contexts borrow this one: they go first
+        for dep in list(getattr(self, "_dependents", ())):
+            dep.close()
         if getattr(self, "h", None):
             _lib.msrsb_destroy(self.h)
             self.h = None
@@ -319,9 +332,10 @@ class Solver:
         except Exception:
             pass
 
-    def update_basis(self, stage=-1, max_sweeps=100, tol=1e-3, warm=False, new_trans=None):
+    def update_basis(self, stage=-1, max_sweeps=100, tol=1e-3, warm=False, new_trans=None, new_bc_trans=None):
         """``new_trans``: optional ``(tx, ty, tz)`` host arrays replacing the
-        face transmissibilities before the sweeps."""
+        face transmissibilities before the sweeps; ``new_bc_trans``: optional
+        connection coefficients (``n_bc``)."""
         sw = C.c_int(0)
         ch = C.c_double(0.0)
         T = None
@@ -329,8 +343,13 @@ class Solver:
             T = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1) for t in new_trans]))
             if T.size != 3 * self.N:
                 raise MsrsbError(E_INVAL, f"expected 3 x {self.N} transmissibilities, got {T.size}")
-        _check(_lib.msrsb_update_basis(self.h, stage, _ptr(T, C.c_double), max_sweeps, tol, int(warm), C.byref(sw),
-                                       C.byref(ch)))
+        B = None
+        if new_bc_trans is not None:
+            B = np.ascontiguousarray(new_bc_trans, dtype=np.float64).reshape(-1)
+            if B.size != self.n_bc:
+                raise MsrsbError(E_INVAL, f"expected {self.n_bc} connection coefficients, got {B.size}")
+        _check(_lib.msrsb_update_basis(self.h, stage, _ptr(T, C.c_double), _ptr(B, C.c_double), max_sweeps, tol,
+                                       int(warm), C.byref(sw), C.byref(ch)))
         return sw.value, ch.value
 
     def add_dynamic_basis(self, increments):
@@ -439,3 +458,75 @@ class Solver:
             m = blk >= 0
             P[np.nonzero(m)[0], blk[m]] += e["values"][s][m]
         return P
+
+
+class TwoPhase:
+    """Two-phase CPR solver on a pressure ``Solver`` (``msrsb_tp_*``): the
+    Jacobian and residual of the water/oil model, the two-stage
+    preconditioner and GMRES on the full system.  State vectors are device
+    tensors of the pressure context's size; full-system vectors interleave
+    (water/pressure, oil/saturation) per cell."""
+
+    OP_MATVEC, OP_CPR = 0, 1
+
+    def __init__(self, solver, pore_volume, fluid, restart=30):
+        self.ms = solver
+        self.N = solver.N
+        f = Fluid(float(fluid["mu_w"]), float(fluid["mu_o"]), float(fluid["n_w"]), float(fluid["n_o"]))
+        pv = np.ascontiguousarray(pore_volume, dtype=np.float64)
+        if pv.size != self.N:
+            raise MsrsbError(E_INVAL, f"expected {self.N} pore volumes, got {pv.size}")
+        h = C.c_void_p()
+        _check(_lib.msrsb_tp_create(solver.h, _ptr(pv, C.c_double), C.byref(f), int(restart), C.byref(h)))
+        self.h = h
+        import weakref
+
+        if not hasattr(solver, "_dependents"):
+            solver._dependents = weakref.WeakSet()
+        solver._dependents.add(self)
+
+    def _vec2(self, t):
+        return _dptr(t, n=2 * self.N, device=self.ms.device)
+
+    def assemble(self, dt, p, s, s_old, q=None, basis_sweeps=3, res=None):
+        """Returns ``||R||_2``; ``res`` (a [2N] device tensor) receives R."""
+        nr = C.c_double(0.0)
+        _check(_lib.msrsb_tp_assemble(self.h, float(dt), self.ms._vec(p), self.ms._vec(s), self.ms._vec(s_old),
+                                      self.ms._vec(q), int(basis_sweeps), self._vec2(res), C.byref(nr)))
+        return nr.value
+
+    def apply(self, op, x, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(_lib.msrsb_tp_apply(self.h, int(op), self._vec2(x), self._vec2(out)))
+        return out
+
+    def solve(self, rtol=1e-8, max_iters=500, dx=None):
+        """GMRES + CPR on ``J dx = -R``; returns ``(dx, iterations, relres, status)``."""
+        import torch
+
+        if dx is None:
+            dx = torch.empty(2 * self.N, dtype=torch.float64, device=torch.device("cuda", self.ms.device))
+        it = C.c_int(0)
+        rel = C.c_double(0.0)
+        rc = _check(_lib.msrsb_tp_solve(self.h, self._vec2(dx), float(rtol), int(max_iters), C.byref(it),
+                                        C.byref(rel)), allow=(E_NOCONV,))
+        return dx, it.value, rel.value, rc
+
+    def update(self, dx, p, s):
+        _check(_lib.msrsb_tp_update(self.h, self._vec2(dx), self.ms._vec(p), self.ms._vec(s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            # the pressure context must still exist (its close() closes this first)
+            if getattr(self.ms, "h", None):
+                _lib.msrsb_tp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

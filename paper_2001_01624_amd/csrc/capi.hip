@@ -13,6 +13,8 @@
 #include "dev_util.h"
 #include "msrsb_internal.h"
 
+static int finish_coarse(msrsb::Ctx &c, msrsb::Stage &s);
+
 namespace msrsb {
 
 static thread_local std::string g_err;
@@ -851,6 +853,79 @@ static int solve_gmres(Ctx &c, const double *b, double *x, double rtol, int max_
     return MSRSB_OK;
 }
 
+// ---- hooks for the two-phase CPR preconditioner (tp_capi.hip) ----
+
+// One multistage cycle from zero: x = M^{-1} r (the multiscale multibasis
+// preconditioner of the pressure system).
+void ms_precondition(Ctx &c, const double *r, double *x) { cycle(c, r, x, false, nullptr, true); }
+
+__global__ void k_to_f32(long n, const double *__restrict__ a, float *__restrict__ b) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// Per-cell sums of the connection terms in a fixed order (the connections of
+// a cell in list order).
+__global__ void k_bc_sums(int N, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                          const double *__restrict__ bct, const double *__restrict__ bcv, double *__restrict__ bcd,
+                          double *__restrict__ bcr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double d = 0.0, r = 0.0;
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        d += bct[idx[k]];
+        r += bct[idx[k]] * bcv[idx[k]];
+    }
+    bcd[i] = d;
+    bcr[i] = r;
+}
+
+// Replace the operator from device arrays (face coefficients [3N] and
+// connection coefficients [n_bc], either may be null) with the same
+// connectivity: no host validation, so the caller guarantees T >= 0 exactly
+// where the set-up faces had T > 0.  Rebuilds A, b, FP32 copies and pivots.
+int set_operator_device(Ctx &c, const double *d_t3, const double *d_bc) {
+    const size_t N = c.N;
+    if (d_t3) {
+        double *d64[3] = {c.tx, c.ty, c.tz};
+        float *d32[3] = {c.tx32, c.ty32, c.tz32};
+        for (int a = 0; a < 3; ++a) {
+            if (hipMemcpyAsync(d64[a], d_t3 + a * N, 8 * N, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+                return hip_fail(hipGetLastError(), "operator copy");
+            hipLaunchKernelGGL(k_to_f32, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, c.stream, (long)N, d64[a], d32[a]);
+        }
+    }
+    if (d_bc && c.n_bc > 0) {
+        if (hipMemcpyAsync(c.bc_trans, d_bc, 8 * (size_t)c.n_bc, hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+            return hip_fail(hipGetLastError(), "connection copy");
+        hipLaunchKernelGGL(k_bc_sums, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, c.stream, (int)N, c.bcptr, c.bcidx,
+                           c.bc_trans, c.bc_value, c.bcdiag, c.bcrhs);
+    }
+    launch_assemble(c);
+    launch_ilu_factor(c);
+    return MSRSB_OK;
+}
+
+// After an operator change: `sweeps` more smoothing sweeps of every general
+// and static basis from its current state (the local updates), then new
+// Galerkin operators and inverses for every stage, dynamic ones included.
+int refresh_bases(Ctx &c, int sweeps) {
+    int rc;
+    for (auto &s : c.stages) {
+        if (!s.has_basis) continue;
+        if (sweeps > 0 && (rc = launch_sweeps(c, s, sweeps, 0.0, true, nullptr, nullptr))) return rc;
+        s.version++;
+        launch_rap(c, s);
+        if ((rc = finish_coarse(c, s))) return rc;
+    }
+    for (auto &s : c.dyn)
+        if (s.M > 0) {
+            launch_dyn_rap(c, s);
+            if ((rc = finish_coarse(c, s))) return rc;
+        }
+    return MSRSB_OK;
+}
+
 }  // namespace msrsb
 
 using namespace msrsb;
@@ -1285,6 +1360,19 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         !c->partial || !c->scal || !c->status || !c->maxbits || !c->flag)
         return fail(MSRSB_E_NOMEM);
     if (!(c->h_status = pinned_status())) return fail(MSRSB_E_NOMEM);
+    // connections grouped by cell (list order kept) for device-side updates
+    std::vector<int32_t> bcptr(N + 1, 0), bcidx(std::max(g->n_bc, 1));
+    for (int k = 0; k < g->n_bc; ++k) bcptr[g->bc_cell[k] + 1]++;
+    for (int i = 0; i < N; ++i) bcptr[i + 1] += bcptr[i];
+    {
+        std::vector<int32_t> pos(bcptr.begin(), bcptr.end() - 1);
+        for (int k = 0; k < g->n_bc; ++k) bcidx[pos[g->bc_cell[k]]++] = k;
+    }
+    c->bcptr = (int32_t *)dalloc(4 * (size_t)(N + 1));
+    c->bcidx = (int32_t *)dalloc(4 * bcidx.size());
+    if (!c->bcptr || !c->bcidx) return fail(MSRSB_E_NOMEM);
+    upload(*c, c->bcptr, bcptr.data(), 4 * (size_t)(N + 1));
+    upload(*c, c->bcidx, bcidx.data(), 4 * bcidx.size());
     if (g->n_bc > 0) {
         c->bc_cell = (int32_t *)dalloc(4 * (size_t)g->n_bc);
         c->bc_trans = (double *)dalloc(8 * (size_t)g->n_bc);
@@ -1353,15 +1441,24 @@ static int finish_coarse(Ctx &c, Stage &s) {
 // what depends on them on the device: diagonal, right-hand side, FP32 copies
 // and the smoother's pivots.  Partitions and supports keep their set-up
 // structure.
-static int set_transmissibility(Ctx &c, const double *T) {
+static int set_transmissibility(Ctx &c, const double *T, const double *bct) {
     const int N = c.N;
+    std::vector<double> tcur;
+    if (!T) {  // only the connections change: validate with the current faces
+        tcur.resize((size_t)3 * N);
+        const double *d64[3] = {c.tx, c.ty, c.tz};
+        for (int a = 0; a < 3; ++a)
+            if (hipMemcpy(tcur.data() + (size_t)a * N, d64[a], 8 * (size_t)N, hipMemcpyDeviceToHost) != hipSuccess)
+                return hip_fail(hipGetLastError(), "transmissibility read");
+        T = tcur.data();
+    }
     msrsb_grid g{};
     g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
     g.active = c.h_active.data();
     g.tx = T; g.ty = T + N; g.tz = T + 2 * (size_t)N;
     g.n_bc = c.n_bc;
     g.bc_cell = c.h_bc_cell.data();
-    g.bc_trans = c.h_bc_trans.data();
+    g.bc_trans = bct ? bct : c.h_bc_trans.data();
     g.bc_value = c.h_bc_value.data();
     int rc = validate(&g);
     if (rc) return rc;
@@ -1372,6 +1469,19 @@ static int set_transmissibility(Ctx &c, const double *T) {
     for (int a = 0; a < 3; ++a)
         if (!upload(c, d64[a], T + (size_t)a * N, 8 * (size_t)N) || !upload(c, d32[a], t32.data() + (size_t)a * N, 4 * (size_t)N))
             return hip_fail(hipGetLastError(), "transmissibility upload");
+    std::vector<double> bcd, bcr;
+    if (bct && c.n_bc > 0) {
+        c.h_bc_trans.assign(bct, bct + c.n_bc);
+        bcd.assign(N, 0.0);
+        bcr.assign(N, 0.0);
+        for (int k = 0; k < c.n_bc; ++k) {
+            bcd[c.h_bc_cell[k]] += bct[k];
+            bcr[c.h_bc_cell[k]] += bct[k] * c.h_bc_value[k];
+        }
+        if (!upload(c, c.bc_trans, bct, 8 * (size_t)c.n_bc) || !upload(c, c.bcdiag, bcd.data(), 8 * (size_t)N) ||
+            !upload(c, c.bcrhs, bcr.data(), 8 * (size_t)N))
+            return hip_fail(hipGetLastError(), "connection upload");
+    }
     launch_assemble(c);
     launch_ilu_factor(c);
     hipError_t e = hipStreamSynchronize(c.stream);  // the host copies above are local
@@ -1380,8 +1490,8 @@ static int set_transmissibility(Ctx &c, const double *T) {
     return MSRSB_OK;
 }
 
-int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max_sweeps, double tol, int warm,
-                       int *sweeps_done, double *last_change) {
+int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, const double *new_bc_trans, int max_sweeps,
+                       double tol, int warm, int *sweeps_done, double *last_change) {
     g_err.clear();
     if (!c) {
         set_error("ctx is NULL");
@@ -1398,7 +1508,8 @@ int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max
             return MSRSB_E_STATE;
         }
     int rc;
-    if (new_trans && (rc = set_transmissibility(*c, new_trans))) return rc;
+    const bool changed = new_trans || new_bc_trans;
+    if (changed && (rc = set_transmissibility(*c, new_trans, new_bc_trans))) return rc;
     for (int k = s0; k < s1; ++k) {
         Stage &s = c->stages[k];
         rc = launch_sweeps(*c, s, max_sweeps, tol, warm != 0, sweeps_done, last_change);
@@ -1408,7 +1519,7 @@ int msrsb_update_basis(msrsb_ctx *c, int stage, const double *new_trans, int max
         if ((rc = finish_coarse(*c, s))) return rc;
         s.has_basis = true;
     }
-    if (new_trans) {
+    if (changed) {
         for (auto &s : c->stages) s.version++;
         // every other stage keeps its basis; its coarse operator follows the new A
         for (int k = 0; k < (int)c->stages.size(); ++k) {

@@ -144,6 +144,7 @@ struct Ctx {
     float *dtil32 = nullptr, *diag32 = nullptr;
     int32_t *bc_cell = nullptr;
     double *bc_trans = nullptr, *bc_value = nullptr;
+    int32_t *bcptr = nullptr, *bcidx = nullptr;  // connections grouped by cell ([N+1], [n_bc])
     // work vectors [N]
     double *r = nullptr, *e = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr;
     double *partial = nullptr;    // [kRedBlocks * (2 * kMaxRestart + 2)]
@@ -270,6 +271,11 @@ void launch_fv_faces(Ctx &c, Stage &s, const double *pms, const double *pf, doub
 void launch_fv_imbalance(Ctx &c, const double *face, const double *pf, unsigned long long *maxbits);
 void launch_coarse_inverse_of(Ctx &c, const double *A, double *Ainv, int Mp, bool general);
 void launch_coarse_solve_with(Ctx &c, Stage &s, const double *Ainv, const int *done);
+
+// ---- two-phase CPR hooks (capi.hip) ----
+void ms_precondition(Ctx &c, const double *r, double *x);
+int set_operator_device(Ctx &c, const double *d_t3, const double *d_bc);
+int refresh_bases(Ctx &c, int sweeps);
 
 // ---- dynamic basis kernels (k_dyn.hip) ----
 int build_dynamic_stage(Ctx &c, const double *dp, Stage &out, int *count);
