@@ -55,6 +55,8 @@ def parse():
                     help="kernel class of the roofline object (the largest share of kernel time by default)")
     ap.add_argument("--no-table", action="store_true", help="skip the per-class kernel table")
     ap.add_argument("--no-faulted", action="store_true", help="skip the faulted-model (two-stage + dynamic) leg")
+    ap.add_argument("--faulted-only", action="store_true",
+                    help="profiling aid: run only the faulted-model request and print its record")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-only", action="store_true",
                     help="profiling aid: run only the mixed-precision request and print its record")
@@ -478,6 +480,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X", file=sys.stderr)
         sys.exit(1)
+    if args.faulted_only:
+        rec = faulted_leg(args)
+        print(json.dumps({"leg": "faulted", "metric": METRIC, **rec}))
+        return
     if args.mixed_only:
         rec = gpu_leg(args, "mixed")
         print(json.dumps({"leg": "mixed", "metric": METRIC, "value": rec["value"], "unit": "cells/s",
