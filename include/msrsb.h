@@ -109,7 +109,12 @@ typedef struct {
     int32_t overlap;           /* GRAPH: support reach in face steps, >= 0 */
 } msrsb_partition;
 
-enum { MSRSB_SMOOTH_JACOBI = 0, MSRSB_SMOOTH_ILU0_RB = 1 };
+/* Smoothers: damped Jacobi; ILU(0) in red-black cell order (the colour of a
+ * cell is the parity of i+j+k, red = even first); ILU(0) in z-line red-black
+ * order (whole columns (i, j) coloured by the parity of i+j, red columns
+ * first, each column's cells in ascending k: columns are solved along z,
+ * which suits strong vertical coupling). */
+enum { MSRSB_SMOOTH_JACOBI = 0, MSRSB_SMOOTH_ILU0_RB = 1, MSRSB_SMOOTH_ILU0_LINE = 2 };
 enum { MSRSB_FP64 = 0, MSRSB_MIXED = 1 };
 enum { MSRSB_RICHARDSON = 0, MSRSB_GMRES = 1 };
 

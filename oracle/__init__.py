@@ -22,6 +22,7 @@ from .msrsb import (  # noqa: F401
     ilu0_apply,
     ilu0_rb_fill,
     red_black_order,
+    zline_red_black_order,
     natural_order,
     dynamic_partition,
     indicator,

@@ -504,6 +504,16 @@ def red_black_order(cells, dims):
     return np.concatenate([loc[col == 0], loc[col == 1]])
 
 
+def zline_red_black_order(cells, dims):
+    """Whole columns (i, j) coloured by the parity of ``i + j``, even columns
+    first; within a colour column by column, each column's cells in
+    ascending ``k``."""
+    ix, iy, iz = _coords(dims)
+    nx = dims[0]
+    c = cells
+    return np.lexsort((iz[c], iy[c] * nx + ix[c], (ix[c] + iy[c]) % 2))
+
+
 def ilu0_factor(A, order, positive=True):
     """Textbook ILU(0) (row-wise IKJ elimination restricted to the pattern of
     the matrix) of ``A`` permuted to ``order``.  Returns ``(L, U, order)``
@@ -776,6 +786,8 @@ class Oracle:
             self.fac = ilu0_factor(self.A, natural_order(self.cells, self.prob.dims))
         elif self.smoother == "ilu0_rb":
             self.fac = ilu0_factor(self.A, red_black_order(self.cells, self.prob.dims))
+        elif self.smoother == "ilu0_line":
+            self.fac = ilu0_factor(self.A, zline_red_black_order(self.cells, self.prob.dims))
         else:
             raise OracleError(E_INVAL, f"unknown smoother {self.smoother}")
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmsrsb.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR, E_NOCONV, E_STATE = 0, -1, -2, -3, -4, -5, -6
 PART_CARTESIAN, PART_GRAPH, PART_FAULT_CUT = 0, 1, 2
-SMOOTH_JACOBI, SMOOTH_ILU0_RB = 0, 1
+SMOOTH_JACOBI, SMOOTH_ILU0_RB, SMOOTH_ILU0_LINE = 0, 1, 2
 FP64, MIXED = 0, 1
 RICHARDSON, GMRES = 0, 1
 OP_RESIDUAL, OP_SMOOTH, OP_PRECOND, OP_MATVEC = 0, 1, 2, 3
@@ -156,7 +156,7 @@ def default_options(**kw) -> Options:
     _lib.msrsb_default_options(C.byref(o))
     for k, v in kw.items():
         if k == "smoother" and isinstance(v, str):
-            v = {"jacobi": SMOOTH_JACOBI, "ilu0_rb": SMOOTH_ILU0_RB}[v]
+            v = {"jacobi": SMOOTH_JACOBI, "ilu0_rb": SMOOTH_ILU0_RB, "ilu0_line": SMOOTH_ILU0_LINE}[v]
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FP64, "mixed": MIXED}[v]
         if k == "outer" and isinstance(v, str):

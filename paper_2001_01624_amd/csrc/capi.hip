@@ -953,7 +953,8 @@ static int check_options(const msrsb_options *o) {
         set_error("omega and omega_s must lie in (0, 2)");
         return MSRSB_E_INVAL;
     }
-    if (o->smoother != MSRSB_SMOOTH_JACOBI && o->smoother != MSRSB_SMOOTH_ILU0_RB) {
+    if (o->smoother != MSRSB_SMOOTH_JACOBI && o->smoother != MSRSB_SMOOTH_ILU0_RB &&
+        o->smoother != MSRSB_SMOOTH_ILU0_LINE) {
         set_error("unknown smoother %d", o->smoother);
         return MSRSB_E_INVAL;
     }
@@ -1221,6 +1222,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     const size_t N = c.N;
     size_t b = N * 8 * 3 + N * 4 * 3 + N * 8 * 6 + N * 4 * 2;  // T, T32, diag/b/src/bcdiag/bcrhs/dtil, f32 copies
     b += N * 8 * 5;                                          // work vectors
+    if (o.smoother == MSRSB_SMOOTH_ILU0_LINE) b += N * 24;   // z-line ILU(0) factors
     b += (size_t)kRedBlocks * (2 * kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
     if (o.outer == MSRSB_GMRES) b += fp32_basis(o) ? N * 8 * 2 + (size_t)o.restart * N * 4 : (size_t)(o.restart + 1) * N * 8;
     if (o.outer == MSRSB_GMRES && o.restart <= kDcgsMax) b += (size_t)o.restart * N * 8;  // candidates M^-1 u_j
@@ -1342,6 +1344,13 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     c->dtil = (double *)dalloc(8 * (size_t)N);
     c->dtil32 = (float *)dalloc(4 * (size_t)N);
     c->diag32 = (float *)dalloc(4 * (size_t)N);
+    if (o.smoother == MSRSB_SMOOTH_ILU0_LINE) {
+        c->ldinv = (double *)dalloc(8 * (size_t)N);
+        c->lcz = (double *)dalloc(8 * (size_t)N);
+        c->ldinv32 = (float *)dalloc(4 * (size_t)N);
+        c->lcz32 = (float *)dalloc(4 * (size_t)N);
+        if (!c->ldinv || !c->lcz || !c->ldinv32 || !c->lcz32) return fail(MSRSB_E_NOMEM);
+    }
     c->r = (double *)dalloc(8 * (size_t)N);
     c->e = (double *)dalloc(8 * (size_t)N);
     c->tmp = (double *)dalloc(8 * (size_t)N);

@@ -91,6 +91,7 @@ void launch_ilu_factor(Ctx &c) {
     Fine g = fine_of(c);
     hipLaunchKernelGGL(k_ilu_factor, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, c.dtil, c.dtil32,
                        c.diag32);
+    if (c.opt.smoother == MSRSB_SMOOTH_ILU0_LINE) launch_lilu_factor(c);
 }
 
 template <bool NORM>
@@ -445,6 +446,10 @@ template <bool ASSIGN>
 static void smooth_dispatch(Ctx &c, const double *r, double *x, const int *done) {
     Fine g = fine_of(c);
     const bool mixed = c.opt.precision == MSRSB_MIXED;
+    if (c.opt.smoother == MSRSB_SMOOTH_ILU0_LINE) {
+        launch_lilu_apply(c, r, x, done, ASSIGN);
+        return;
+    }
     if (c.opt.smoother == MSRSB_SMOOTH_JACOBI) {
         if (mixed)
             hipLaunchKernelGGL((k_jacobi<float, ASSIGN>), dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N,

@@ -142,6 +142,9 @@ struct Ctx {
     double *bcdiag = nullptr, *bcrhs = nullptr;
     double *dtil = nullptr;       // red-black ILU(0) pivots
     float *dtil32 = nullptr, *diag32 = nullptr;
+    // z-line red-black ILU(0): inverse pivots and Tz_{k-1} / p_{k-1} per cell
+    double *ldinv = nullptr, *lcz = nullptr;
+    float *ldinv32 = nullptr, *lcz32 = nullptr;
     int32_t *bc_cell = nullptr;
     double *bc_trans = nullptr, *bc_value = nullptr;
     int32_t *bcptr = nullptr, *bcidx = nullptr;  // connections grouped by cell ([N+1], [n_bc])
@@ -213,6 +216,8 @@ void launch_ilu_factor(Ctx &c);
 void launch_residual(Ctx &c, const double *b, const double *x, double *r, bool norm, const int *done);
 void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *done);
 void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool assign = false);
+void launch_lilu_factor(Ctx &c);
+void launch_lilu_apply(Ctx &c, const double *r, double *x, const int *done, bool assign);
 void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
                         bool final_);
 constexpr int kDcgsMax = 31;  // largest restart served by the DCGS2 kernels

@@ -59,6 +59,10 @@ CASES = {
     "zline": (lambda: make_lognormal_box((1, 1, 40), rng_for(7, 6), sigma=1.5, corr=(1, 1, 3)), (1, 1, 5)),
     "yline": (lambda: make_lognormal_box((1, 37, 1), rng_for(7, 7), sigma=1.5, corr=(1, 3, 1)), (1, 4, 1)),
     "maxrow": (lambda: make_lognormal_box((256, 3, 2), rng_for(7, 8), sigma=1.5, corr=(8, 1, 1)), (16, 1, 1)),
+    # tall columns around the z-line ILU layout limit: 512 cells (64 chunks of
+    # 8 held in registers) and 600 (the kernel that walks chunks from memory)
+    "tall512": (lambda: make_lognormal_box((5, 3, 512), rng_for(7, 12), sigma=1.5, corr=(1, 1, 8)), (2, 1, 16)),
+    "tall600": (lambda: make_lognormal_box((4, 3, 600), rng_for(7, 13), sigma=1.5, corr=(1, 1, 8)), (2, 1, 16)),
 }
 
 
@@ -69,7 +73,7 @@ def build(capi, name, smoother="jacobi", outer="richardson", precision="fp64"):
     opt = capi.default_options(smoother=smoother, outer=outer, precision=precision)
     say(f"case {name} dims={prob.dims} coarse={cd} smoother={smoother} outer={outer} precision={precision}")
     g = capi.Solver(prob, parts, opt)
-    o = O.Oracle(prob, parts, smoother={"jacobi": "jacobi", "ilu0_rb": "ilu0_rb"}[smoother])
+    o = O.Oracle(prob, parts, smoother=smoother)
     return prob, g, o
 
 
@@ -92,8 +96,8 @@ def test_residual_and_matvec(capi, name):
 
 
 @pytest.mark.parametrize("name", ["cfg0", "ragged3d", "faulted_inactive", "edge62", "edge64", "wide", "wider",
-                                  "zline", "yline", "maxrow"])
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+                                  "zline", "yline", "maxrow", "tall512", "tall600"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_smoother(capi, name, smoother):
     prob, g, o = build(capi, name, smoother=smoother)
     r = np.random.default_rng(2).standard_normal(prob.n_cells) * prob.active
@@ -161,7 +165,7 @@ def test_stop_rule_equals_fixed_count(capi, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_preconditioner(capi, name, smoother):
     prob, g, o = build(capi, name, smoother=smoother)
     g.update_basis(max_sweeps=20, tol=0.0)
@@ -174,7 +178,7 @@ def test_preconditioner(capi, name, smoother):
 
 
 @pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive"])
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_richardson_fixed_cycles(capi, name, smoother):
     prob, g, o = build(capi, name, smoother=smoother)
     g.update_basis(max_sweeps=30, tol=0.0)
@@ -187,7 +191,7 @@ def test_richardson_fixed_cycles(capi, name, smoother):
     assert rel == pytest.approx(relo, rel=1e-8)
 
 
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_richardson_converges_cfg0(capi, smoother):
     prob, g, o = build(capi, "cfg0", smoother=smoother)
     g.update_basis(max_sweeps=100, tol=1e-3)
@@ -204,9 +208,11 @@ def test_richardson_converges_cfg0(capi, smoother):
     assert np.linalg.norm(o.residual(x)) / np.linalg.norm(o.b) <= 1.0001e-10
 
 
-@pytest.mark.parametrize("name", ["cfg0", "layered", "faulted_inactive", "wide", "zline", "maxrow"])
-def test_gmres_converges(capi, name):
-    prob, g, o = build(capi, name, smoother="ilu0_rb", outer="gmres")
+@pytest.mark.parametrize("name,smoother", [(n, "ilu0_rb") for n in ("cfg0", "layered", "faulted_inactive", "wide",
+                                                                     "zline", "maxrow")]
+                         + [(n, "ilu0_line") for n in ("layered", "faulted_inactive", "zline", "wide")])
+def test_gmres_converges(capi, name, smoother):
+    prob, g, o = build(capi, name, smoother=smoother, outer="gmres")
     g.update_basis(max_sweeps=60, tol=1e-3)
     o.update_basis(max_sweeps=60, tol=1e-3)
     p = dev(np.zeros(prob.n_cells))
@@ -434,7 +440,7 @@ def test_fault_cut_basis_and_coarse(capi, sweeps):
         assert relerr(g.export_stage(k)["Ac"], o.stages[k].Ac) <= 1e-12
 
 
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_fault_cut_cycles(capi, smoother):
     prob, g, o = build_fault(capi, smoother=smoother)
     g.update_basis(max_sweeps=20, tol=0.0)

@@ -107,8 +107,10 @@ def test_coarse_solve_dynamic_and_fault_stages(capi):
     ("layered", lambda: make_config1(dims=(20, 36, 14), seed=1), (4, 3, 2)),
     ("faulted_inactive", lambda: make_config2(dims=(18, 30, 12), seed=2), (3, 3, 2)),
     ("wider", lambda: make_config2(dims=(130, 6, 4), seed=4), (9, 2, 2)),
+    ("tall512", lambda: make_lognormal_box((5, 3, 512), rng_for(7, 12), sigma=1.5, corr=(1, 1, 8)), (2, 1, 16)),
+    ("tall600", lambda: make_lognormal_box((4, 3, 600), rng_for(7, 13), sigma=1.5, corr=(1, 1, 8)), (2, 1, 16)),
 ])
-@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb"])
+@pytest.mark.parametrize("smoother", ["jacobi", "ilu0_rb", "ilu0_line"])
 def test_mixed_smoother_bound(capi, name, mk, cd, smoother):
     prob = mk()
     parts = [{"kind": "cartesian", "coarse_dims": cd}]
@@ -121,7 +123,10 @@ def test_mixed_smoother_bound(capi, name, mk, cd, smoother):
     assert np.all(mag >= 0)
     ratio = np.abs(e - eo).max() / mag.max()
     say(f"mixed {smoother} smoother on {name}: max |e - e*| / max M^-1|r| = {ratio:.2e}")
-    assert np.all(np.abs(e - eo) <= 2.0 ** -17 * mag)
+    # the z-line order runs recurrences along whole columns: at most about 16 nz + 64
+    # correctly rounded FP32 operations per entry
+    bound = 2.0 ** -24 * (16 * prob.dims[2] + 64) if smoother == "ilu0_line" else 2.0 ** -17
+    assert np.all(np.abs(e - eo) <= bound * mag)
 
 
 def oracle_on_exported_basis(g, prob, parts, smoother):

@@ -574,3 +574,45 @@ def test_fault_cut_partition_splits_blocks():
     assert st.S.toarray().tolist() == [[1, 0], [1, 0], [0, 1], [0, 1]]
     o.update_basis(max_sweeps=10, tol=0.0)
     np.testing.assert_array_equal(o.export_basis(1), [[1, 0], [1, 0], [0, 1], [0, 1]])
+
+
+# --- ILU(0) in z-line red-black order (the ordering of the GPU's line smoother)
+
+def test_zline_order_structure():
+    from workloads import make_lognormal_box, rng_for
+
+    prob = make_lognormal_box((5, 4, 6), rng_for(7, 9), sigma=1.0)
+    cells = np.nonzero(prob.active)[0]
+    order = O.zline_red_black_order(cells, prob.dims)
+    nx, ny = prob.dims[0], prob.dims[1]
+    c = cells[order]
+    ix, iy, iz = c % nx, (c // nx) % ny, c // (nx * ny)
+    colour = (ix + iy) % 2
+    assert np.all(np.diff(colour) >= 0)  # even columns first
+    col = iy * nx + ix
+    for a in range(len(c) - 1):  # a column's cells are consecutive, k ascending
+        if col[a] == col[a + 1]:
+            assert iz[a + 1] == iz[a] + 1
+
+
+def test_zline_ilu0_is_exact_on_a_column():
+    # one column (nx = ny = 1): ILU(0) keeps the whole tridiagonal pattern, so it is the exact LU
+    from workloads import make_lognormal_box, rng_for
+
+    prob = make_lognormal_box((1, 1, 17), rng_for(7, 10), sigma=2.0)
+    A, b, _, cells = O.assemble(prob)
+    fac = O.ilu0_factor(A, O.zline_red_black_order(cells, prob.dims))
+    r = np.random.default_rng(1).standard_normal(cells.size)
+    assert np.abs(O.ilu0_apply(fac, r) - np.linalg.solve(A.toarray(), r)).max() <= 1e-12 * np.abs(r).max() * 1e3
+
+
+def test_zline_ilu0_equals_point_red_black_in_2d():
+    # one layer: every column is a single cell and the colours are those of the red-black order
+    from workloads import make_lognormal_box, rng_for
+
+    prob = make_lognormal_box((9, 7, 1), rng_for(7, 11), sigma=1.5)
+    A, b, _, cells = O.assemble(prob)
+    r = np.random.default_rng(2).standard_normal(cells.size)
+    f1 = O.ilu0_factor(A, O.zline_red_black_order(cells, prob.dims))
+    f2 = O.ilu0_factor(A, O.red_black_order(cells, prob.dims))
+    assert np.abs(O.ilu0_apply(f1, r) - O.ilu0_apply(f2, r)).max() <= 1e-13 * np.abs(O.ilu0_apply(f2, r)).max()
