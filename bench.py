@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--kernel", default="restrict_rows",
                     help="kernel class of the roofline object (the largest share of kernel time by default)")
     ap.add_argument("--no-table", action="store_true", help="skip the per-class kernel table")
+    ap.add_argument("--smoother", default="ilu0_line", choices=["ilu0_line", "ilu0_rb", "jacobi"],
+                    help="fine-scale smoother of every GPU leg and of the oracle baseline")
     ap.add_argument("--no-faulted", action="store_true", help="skip the faulted-model (two-stage + dynamic) leg")
     ap.add_argument("--faulted-only", action="store_true",
                     help="profiling aid: run only the faulted-model request and print its record")
@@ -95,16 +97,24 @@ def workload(dims=DIMS, seed=0):
 
 # algorithmic bytes per active cell for one launch of each kernel class
 # (structured 7-point storage: three face T and the diagonal per cell)
-def bytes_per_cell(kernel, ns, mixed):
+SMOOTHER_NAMES = {"ilu0_line": "ILU(0) in z-line red-black order", "ilu0_rb": "red-black ILU(0)",
+                  "jacobi": "damped Jacobi"}
+
+
+def bytes_per_cell(kernel, ns, mixed, smoother="ilu0_line"):
     sp = 4 if mixed else 8       # working precision of the sweeps and the smoother
     sb = 2 if mixed else 8       # stored basis (BF16 in mixed precision)
+    if smoother == "ilu0_line":  # r, x in/out, three T, diagonal, pivot, z coupling, scratch written and read
+        smooth = 8 + 16 + 3 * sp + 8 + 2 * sp + 16
+    else:                        # r, x in/out, three T, diagonal, pivot
+        smooth = 44 if mixed else 64
     return {
         "sweep": 2 * ns * sp + 3 * sp + 8,        # read P, write P, three face T, diagonal
         "restrict_rows": 48 + ns * sb,            # P, x, b, three face T, diagonal (residual fused)
         "restrict": 48 + ns * sb,                 # the same, with the final gather of the partial sums
         "prolong": ns * sb + 16,                  # P, x read and written
         "residual": 56,                           # x, b, r, three face T, diagonal
-        "smooth": 44 if mixed else 64,            # red-black ILU(0): r, x in/out, three T, diagonal, pivot
+        "smooth": smooth,
     }.get(kernel)  # the "matvec" class is the Arnoldi pass A (matrix-vector product fused with dots): no entry
 
 
@@ -116,7 +126,7 @@ def gpu_leg(args, precision):
 
     prob, sources = workload()
     parts = [{"kind": "cartesian", "coarse_dims": cd} for cd in STAGES]
-    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=RESTART, precision=precision)
+    opt = capi.default_options(smoother=args.smoother, outer="gmres", restart=RESTART, precision=precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = capi.Solver(prob, parts, opt)
@@ -176,8 +186,8 @@ def gpu_leg(args, precision):
     n_act = prob.n_active
     cells = 3 * n_act * args.steps
     ns = 8
-    roof = roofline(args.kernel, ns, precision, n_act, kern_ms, launches)
-    table = None if args.no_table else kernel_table(g, step, ns, precision, n_act)
+    roof = roofline(args.kernel, ns, precision, n_act, kern_ms, launches, args.smoother)
+    table = None if args.no_table else kernel_table(g, step, ns, precision, n_act, args.smoother)
     out = {
         "value": cells / wall,
         "ms_per_step": 1e3 * wall / args.steps,
@@ -198,13 +208,14 @@ def gpu_leg(args, precision):
 
 
 ROOF_KERNEL = {"restrict_rows": "k_restrict_rows", "sweep": "k_sweep", "restrict": "k_restrict_rows+k_restrict_gather",
-               "prolong": "k_prolong_rows", "residual": "k_residual_rows", "smooth": "k_ilu_zm"}
+               "prolong": "k_prolong_rows", "residual": "k_residual_rows"}
+SMOOTH_KERNEL = {"ilu0_line": "k_lilu_reg (three colour passes)", "ilu0_rb": "k_ilu_zm", "jacobi": "k_jacobi"}
 
 
-def roofline(kernel, ns, precision, n_act, kern_ms, launches):
+def roofline(kernel, ns, precision, n_act, kern_ms, launches, smoother):
     """Roofline object of one kernel class: algorithmic bytes per launch over
     the average launch time from the HIP events of the timed steps."""
-    bpc = bytes_per_cell(kernel, ns, precision == "mixed")
+    bpc = bytes_per_cell(kernel, ns, precision == "mixed", smoother)
     if bpc is None or launches == 0:
         return None
     per_launch = bpc * n_act
@@ -212,7 +223,8 @@ def roofline(kernel, ns, precision, n_act, kern_ms, launches):
     ach = per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_record(kernel, precision),
-            "kernel": ROOF_KERNEL.get(kernel, kernel), "kernel_class": kernel, "launches": launches,
+            "kernel": SMOOTH_KERNEL[smoother] if kernel == "smooth" else ROOF_KERNEL.get(kernel, kernel),
+            "kernel_class": kernel, "launches": launches,
             "avg_launch_us": round(1e6 * avg_s, 2), "algorithmic_bytes_per_cell": bpc,
             "algorithmic_bytes_per_launch": per_launch}
 
@@ -221,7 +233,7 @@ TABLE_CLASSES = ("restrict_rows", "restrict", "sweep", "prolong", "smooth", "res
                  "rap", "inverse")
 
 
-def kernel_table(g, step, ns, precision, n_act):
+def kernel_table(g, step, ns, precision, n_act, smoother):
     """One extra (untimed) request per kernel class, that class's launches
     bracketed by HIP events: launches and milliseconds per request, average
     launch, and achieved bandwidth where the algorithmic bytes are known."""
@@ -231,7 +243,7 @@ def kernel_table(g, step, ns, precision, n_act):
         step()
         ms, n = g.profile_end()
         row = {"launches": n, "ms_per_request": round(ms, 3), "avg_us": round(1e3 * ms / n, 2) if n else None}
-        bpc = bytes_per_cell(cls, ns, precision == "mixed")
+        bpc = bytes_per_cell(cls, ns, precision == "mixed", smoother)
         if bpc is not None and n:
             gbs = bpc * n_act / (ms / n / 1e3) / 1e9
             row.update({"bytes_per_cell": bpc, "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
@@ -255,7 +267,7 @@ def faulted_leg(args):
     prob = make_config2(seed=0)
     sources = source_sequence(prob, rng_for(6, 0), 5)
     parts = [{"kind": "cartesian", "coarse_dims": (10, 10, 5)}, {"kind": "fault_cut", "parent": 0}]
-    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", restart=RESTART, precision="mixed")
+    opt = capi.default_options(smoother=args.smoother, outer="gmres", restart=RESTART, precision="mixed")
     g = capi.Solver(prob, parts, opt)
     q = [torch.as_tensor(s).cuda() for s in sources]
     N = prob.n_cells
@@ -297,7 +309,7 @@ def faulted_leg(args):
            "stages": [g.stage_info(k)[:3:2] for k in range(len(parts))],
            "workload": "faulted 60x220x85 (3 faults, 5% inactive), mixed precision, rectilinear 10x10x5 + fault-cut "
                        "+ <=2 dynamic stages, GMRES(16), 5 solves per request (source/sink pair moved or rescaled)"}
-    out["kernel_table"] = None if args.no_table else kernel_table(g, step, 8, "mixed", n_act)
+    out["kernel_table"] = None if args.no_table else kernel_table(g, step, 8, "mixed", n_act, args.smoother)
     g.close()
     return out
 
@@ -317,14 +329,14 @@ def serve_leg(args):
     out = {}
     for name, slots, prec in (("fp64_plain", 1, "fp64"), ("mixed_served", 8, "mixed")):
         reqs = poisson_stream(args.serve_requests, 200.0, seed=0)
-        opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=prec)
+        opt = capi.default_options(smoother=args.smoother, outer="gmres", precision=prec)
         st = Server(slots=slots, options=opt, rtol=RTOL).run(reqs, realtime=True)
         out[name] = {"cells_per_s": st["cells_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                      "solves": st["solves"], "requests": st["completed"], "makespan_s": st["makespan_s"],
                      "all_converged": st["all_converged"], "max_relres": st["max_relres"], "slots": slots}
     # maximum sustainable rate: the same stream with every request available at once
     reqs = poisson_stream(args.serve_requests, 200.0, seed=0)
-    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision="mixed")
+    opt = capi.default_options(smoother=args.smoother, outer="gmres", precision="mixed")
     st = Server(slots=8, options=opt, rtol=RTOL).run(reqs, realtime=False)
     out["mixed_served"]["max_rate_cells_per_s"] = st["cells_per_s"]
     out["speedup"] = out["mixed_served"]["cells_per_s"] / out["fp64_plain"]["cells_per_s"]
@@ -347,7 +359,7 @@ def ensemble_leg(args):
     out, sols = {}, {}
     for prec in ("fp64", "mixed"):
         reqs = ensemble_batch(args.ensemble_members, seed=0)
-        opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=prec)
+        opt = capi.default_options(smoother=args.smoother, outer="gmres", precision=prec)
         st = Server(slots=8, options=opt, rtol=RTOL, keep_solutions=True, dynamic=False).run(reqs, realtime=False)
         out[prec] = {"cells_per_s": st["cells_per_s"], "makespan_s": st["makespan_s"], "solves": st["solves"],
                      "all_converged": st["all_converged"], "max_relres": st["max_relres"]}
@@ -388,7 +400,7 @@ def traffic_record(kernel, precision):
     return rec.get("bytes_per_launch")
 
 
-def cpu_leg():
+def cpu_leg(smoother):
     """The oracle, as it stands, on a bounded sample of the same request
     (same recipe and block shapes at 30 x 110 x 21 cells): basis, three
     solves, dynamic stage, fluxes.  Single thread."""
@@ -397,7 +409,7 @@ def cpu_leg():
     prob, sources = workload(dims=(30, 110, 21))
     parts = [{"kind": "cartesian", "coarse_dims": (5, 5, 1)}, {"kind": "cartesian", "coarse_dims": (3, 11, 4)}]
     t0 = time.perf_counter()
-    o = O.Oracle(prob, parts, smoother="ilu0_rb")
+    o = O.Oracle(prob, parts, smoother=smoother)
     setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     o.update_basis(100, 1e-3)
@@ -431,7 +443,7 @@ def host_cores():
     return max(1, n)
 
 
-def run_cpu_baseline():
+def run_cpu_baseline(smoother):
     """The oracle leg on one thread, then on every host core: as many
     single-threaded oracle processes as cores, each solving the same sample
     request, started together (throughput = their cells over the wall time
@@ -439,7 +451,7 @@ def run_cpu_baseline():
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg"]
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--smoother", smoother]
     r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
     if r.returncode != 0:
         return {"error": r.stderr[-500:]}
@@ -469,7 +481,7 @@ def run_cpu_baseline():
 def main():
     args = parse()
     if args.cpu_leg:
-        cpu_leg()
+        cpu_leg(args.smoother)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver path is single-GPU "
@@ -501,7 +513,7 @@ def main():
     faulted = None if args.no_faulted else leg("faulted request", faulted_leg, args)
     served = None if args.no_serve else leg("serving stream", serve_leg, args)
     ensemble = None if (args.no_serve or args.no_ensemble) else leg("ensemble", ensemble_leg, args)
-    cpu = None if args.no_cpu_baseline else leg("oracle baseline", run_cpu_baseline)
+    cpu = None if args.no_cpu_baseline else leg("oracle baseline", run_cpu_baseline, args.smoother)
     line = {
         "metric": METRIC,
         "value": f64["value"],
@@ -516,7 +528,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "layered lognormal+channel five-spot 60x220x85 (20x10x2 cells); general stages "
-                               "10x10x5 and 6x22x17 coarse blocks; MsRSB tol 1e-3 <= 100 sweeps; red-black ILU(0); "
+                               "10x10x5 and 6x22x17 coarse blocks; MsRSB tol 1e-3 <= 100 sweeps; "
+                               f"{SMOOTHER_NAMES[args.smoother]}; "
                                f"GMRES({RESTART}) with the multistage cycle; 3 solves per request (+1 dynamic stage)",
                    "cells": f64["cells"], "solves_per_step": 3, "rtol": RTOL},
         "p50_ms": f64["p50_ms"],

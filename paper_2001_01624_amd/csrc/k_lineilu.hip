@@ -195,13 +195,21 @@ struct LineRegArgs {
     int cw, nch, L;  // columns per workgroup, chunks per column, cells per chunk (<= kLineLMax)
 };
 
+// Branch-free: every load is issued at an in-bounds index (the cell itself
+// where the neighbour does not exist) and the product is dropped afterwards,
+// so the loads of all cells of a chunk can be in flight together; a dropped
+// product never reaches the sum, whatever the value read.
 template <typename TT>
 __device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, const double *__restrict__ v) {
-    TT s = (TT)0, t;
-    if (x > 0 && (t = a.tx[i - 1]) != (TT)0) s += t * (TT)v[i - 1];
-    if (x + 1 < a.g.nx && (t = a.tx[i]) != (TT)0) s += t * (TT)v[i + 1];
-    if (y > 0 && (t = a.ty[i - a.g.nx]) != (TT)0) s += t * (TT)v[i - a.g.nx];
-    if (y + 1 < a.g.ny && (t = a.ty[i]) != (TT)0) s += t * (TT)v[i + a.g.nx];
+    const bool hxm = x > 0, hxp = x + 1 < a.g.nx, hym = y > 0, hyp = y + 1 < a.g.ny;
+    const int ixm = hxm ? i - 1 : i, iym = hym ? i - a.g.nx : i;
+    const int ixp = hxp ? i + 1 : i, iyp = hyp ? i + a.g.nx : i;
+    const TT pxm = a.tx[ixm] * (TT)v[ixm], pxp = a.tx[i] * (TT)v[ixp];
+    const TT pym = a.ty[iym] * (TT)v[iym], pyp = a.ty[i] * (TT)v[iyp];
+    TT s = hxm ? pxm : (TT)0;
+    s += hxp ? pxp : (TT)0;
+    s += hym ? pym : (TT)0;
+    s += hyp ? pyp : (TT)0;
     return s;
 }
 
