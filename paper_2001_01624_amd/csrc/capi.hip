@@ -1222,7 +1222,10 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
     const size_t N = c.N;
     size_t b = N * 8 * 3 + N * 4 * 3 + N * 8 * 6 + N * 4 * 2;  // T, T32, diag/b/src/bcdiag/bcrhs/dtil, f32 copies
     b += N * 8 * 5;                                          // work vectors
-    if (o.smoother == MSRSB_SMOOTH_ILU0_LINE) b += N * 24;   // z-line ILU(0) factors
+    if (o.smoother == MSRSB_SMOOTH_ILU0_LINE) {             // z-line ILU(0) factors, packed copies
+        b += N * 24;
+        if (lilu_reg_chunks(c.nz)) b += 8 * lilu_slots(c.nx, c.ny, c.nz) * (o.precision == MSRSB_MIXED ? 4 : 8);
+    }
     b += (size_t)kRedBlocks * (2 * kMaxRestart + 2) * 8 + 8192 * 8 + 65536 * 8;
     if (o.outer == MSRSB_GMRES) b += fp32_basis(o) ? N * 8 * 2 + (size_t)o.restart * N * 4 : (size_t)(o.restart + 1) * N * 8;
     if (o.outer == MSRSB_GMRES && o.restart <= kDcgsMax) b += (size_t)o.restart * N * 8;  // candidates M^-1 u_j
@@ -1350,6 +1353,12 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         c->ldinv32 = (float *)dalloc(4 * (size_t)N);
         c->lcz32 = (float *)dalloc(4 * (size_t)N);
         if (!c->ldinv || !c->lcz || !c->ldinv32 || !c->lcz32) return fail(MSRSB_E_NOMEM);
+        if (lilu_reg_chunks(c->nz)) {
+            const size_t S = lilu_slots(c->nx, c->ny, c->nz), w = o.precision == MSRSB_MIXED ? 4 : 8;
+            c->lpack = dalloc(6 * S * w);
+            c->lpe = dalloc(2 * S * w);
+            if (!c->lpack || !c->lpe) return fail(MSRSB_E_NOMEM);
+        }
     }
     c->r = (double *)dalloc(8 * (size_t)N);
     c->e = (double *)dalloc(8 * (size_t)N);

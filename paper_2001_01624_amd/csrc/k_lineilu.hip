@@ -20,11 +20,15 @@
 // loads its chunk's coefficients into registers, composes the chunk's affine
 // map y_out = A + B y_in, the maps of one column are combined in LDS in chunk
 // order, and the thread walks its chunk again from the incoming value out of
-// registers.  Threads take only columns of the phase's colour (packed: the
-// p-th column of a colour in row-major order), so no lane idles on the other
+// registers.  Threads take only columns of the phase's colour (the p-th
+// column of a colour in row-major order), so no lane idles on the other
 // colour, and the black phase keeps its forward result in registers for the
-// backward sweep.  Columns taller than kLineLMax * 64 cells use a second
-// kernel that walks each chunk twice from memory.
+// backward sweep.  The factors and the corrections are stored per colour in
+// that packed order, so each pass reads only its own colour's factors and
+// the other colour's corrections, contiguously; r, x and the face
+// coefficients keep the natural layout.  Columns taller than kLineLMax * 64
+// cells use a second kernel that walks each chunk twice from memory over the
+// natural layout.
 #include <hip/hip_runtime.h>
 
 #include "dev_util.h"
@@ -70,11 +74,27 @@ __global__ void k_lilu_factor(Fine g, double *__restrict__ dinv, double *__restr
     }
 }
 
+// forward declarations of the register path's layout (defined below)
+int lilu_reg_chunks(int nz);
+template <typename TT>
+__global__ void k_lilu_pack(Fine g, int hx, int ncol, const double *__restrict__ dinv,
+                            const double *__restrict__ cz, const TT *__restrict__ tz, TT *__restrict__ out);
+
 void launch_lilu_factor(Ctx &c) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     const int nb = cdiv(g.nxy, kBlock);
     hipLaunchKernelGGL(k_lilu_factor<0>, dim3(nb), dim3(kBlock), 0, c.stream, g, c.ldinv, c.lcz, c.ldinv32, c.lcz32);
     hipLaunchKernelGGL(k_lilu_factor<1>, dim3(nb), dim3(kBlock), 0, c.stream, g, c.ldinv, c.lcz, c.ldinv32, c.lcz32);
+    if (!c.lpack) return;
+    const int hx = (c.nx + 1) / 2, ncol = hx * c.ny;
+    const size_t S2 = 2 * (size_t)ncol * c.nz;
+    const dim3 grid((unsigned)((S2 + kBlock - 1) / kBlock)), blk(kBlock);
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_lilu_pack<float>, grid, blk, 0, c.stream, g, hx, ncol, c.ldinv, c.lcz, c.tz32,
+                           (float *)c.lpack);
+    else
+        hipLaunchKernelGGL(k_lilu_pack<double>, grid, blk, 0, c.stream, g, hx, ncol, c.ldinv, c.lcz, c.tz,
+                           (double *)c.lpack);
 }
 
 template <typename TT>
@@ -185,27 +205,73 @@ __global__ __launch_bounds__(64 * kLineChunks) void k_lilu_apply(LineArgs<TT> a,
 constexpr int kLineLMax = 8;      // cells per chunk held in registers
 constexpr int kLineThreads = 256;  // threads per workgroup: columns x chunks (power of 2)
 
+// Chunks per column (a power of two) of the register path; 0 if the columns
+// are too tall for it.
+int lilu_reg_chunks(int nz) {
+    int nchp = 1;
+    while (nchp * kLineLMax < nz) nchp *= 2;
+    return nchp <= kLineThreads / 4 ? nchp : 0;
+}
+
+// Colour-packed layout of the register path: slot p of colour c is column
+// (x, y) with y = p / hx, x = 2 (p % hx) + ((c + y) & 1), hx = ceil(nx / 2)
+// (slots with x >= nx are padding), and entry (k, p) sits at k * ncol + p,
+// ncol = hx * ny.  Per colour three factor arrays (1/p, cz, Tz/p) and one
+// correction array (w for red, z for black), so that every pass reads and
+// writes only its own colour's entries, contiguously.
+size_t lilu_slots(int nx, int ny, int nz) { return (size_t)((nx + 1) / 2) * ny * nz; }
+
+template <typename TT>
+__global__ void k_lilu_pack(Fine g, int hx, int ncol, const double *__restrict__ dinv,
+                            const double *__restrict__ cz, const TT *__restrict__ tz, TT *__restrict__ out) {
+    const size_t S = (size_t)ncol * g.nz;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 2 * S) return;
+    const int c = q >= S;
+    const size_t rem = q - c * S;
+    const int k = (int)(rem / ncol), p = (int)(rem % ncol);
+    const int y = p / hx, x = 2 * (p % hx) + ((c + y) & 1);
+    TT d = (TT)0, cc = (TT)0, t = (TT)0;
+    if (x < g.nx) {
+        const int i = x + g.nx * y + g.nxy * k;
+        d = (TT)dinv[i];
+        cc = (TT)cz[i];
+        if (k + 1 < g.nz) t = tz[i] * d;
+    }
+    out[(3 * c + 0) * S + rem] = d;
+    out[(3 * c + 1) * S + rem] = cc;
+    out[(3 * c + 2) * S + rem] = t;
+}
+
 template <typename TT>
 struct LineRegArgs {
     Fine g;
-    const TT *tx, *ty, *tz, *dinv, *cz;
+    const TT *tx, *ty;             // face coefficients, natural layout
+    const TT *pd, *pc, *pt;        // this colour's packed 1/p, cz, Tz/p
+    TT *eself;                     // this colour's packed corrections
+    const TT *eother;              // the other colour's packed corrections
     const double *r;
-    double *e, *x;
-    int hx, ncol;    // columns of one colour per row, ceil(nx / 2), and hx * ny
-    int cw, nch, L;  // columns per workgroup, chunks per column, cells per chunk (<= kLineLMax)
+    double *x;
+    int hx, ncol;                  // slots per row of one colour, hx * ny
+    int cw, nch, L;                // columns per workgroup, chunks per column, cells per chunk (<= kLineLMax)
 };
 
-// Branch-free: every load is issued at an in-bounds index (the cell itself
-// where the neighbour does not exist) and the product is dropped afterwards,
-// so the loads of all cells of a chunk can be in flight together; a dropped
-// product never reaches the sum, whatever the value read.
+// Sum over the x/y neighbours (other colour) of T * correction.  Branch-free:
+// every load is issued at an in-bounds index (the cell's own where the
+// neighbour does not exist) and the product is dropped afterwards, so the
+// loads of all cells of a chunk can be in flight together; a dropped product
+// never reaches the sum, whatever the value read.  par = x & 1 relation:
+// x = 2 j + par, the x neighbours are slots j + par - 1 and j + par of the
+// other colour's row, the y neighbours slot j of the rows above and below.
 template <typename TT>
-__device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, const double *__restrict__ v) {
+__device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, int j, int par, size_t kq) {
     const bool hxm = x > 0, hxp = x + 1 < a.g.nx, hym = y > 0, hyp = y + 1 < a.g.ny;
-    const int ixm = hxm ? i - 1 : i, iym = hym ? i - a.g.nx : i;
-    const int ixp = hxp ? i + 1 : i, iyp = hyp ? i + a.g.nx : i;
-    const TT pxm = a.tx[ixm] * (TT)v[ixm], pxp = a.tx[i] * (TT)v[ixp];
-    const TT pym = a.ty[iym] * (TT)v[iym], pyp = a.ty[i] * (TT)v[iyp];
+    const int row = y * a.hx;
+    const int own = row + j;
+    const int qxm = hxm ? row + j + par - 1 : own, qxp = hxp ? row + j + par : own;
+    const int qym = hym ? own - a.hx : own, qyp = hyp ? own + a.hx : own;
+    const TT pxm = a.tx[hxm ? i - 1 : i] * a.eother[kq + qxm], pxp = a.tx[i] * a.eother[kq + qxp];
+    const TT pym = a.ty[hym ? i - a.g.nx : i] * a.eother[kq + qym], pyp = a.ty[i] * a.eother[kq + qyp];
     TT s = hxm ? pxm : (TT)0;
     s += hxp ? pxp : (TT)0;
     s += hym ? pym : (TT)0;
@@ -213,9 +279,11 @@ __device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, con
     return s;
 }
 
-// PHASE 0: red forward (writes w = y / p to e); 1: black forward and backward
-// (writes z to e and x); 2: red backward (writes x).  Thread layout: column
-// slot cl = threadIdx % cw, chunk ch = threadIdx / cw.
+// PHASE 0: red forward (writes w = y / p); 1: black forward and backward
+// (writes z); 2: red backward (reads w, writes x of both colours).  Thread layout:
+// column slot cl = threadIdx % cw, chunk ch = threadIdx / cw.  A cell is
+// active where its 1/p is nonzero (inactive cells and non-positive pivots;
+// their correction is exactly zero).
 template <typename TT, int PHASE, bool ASSIGN>
 __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, const int *done) {
     __shared__ TT sA[kLineThreads], sB[kLineThreads];
@@ -223,28 +291,31 @@ __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, co
     const int b = xcd_block();
     if (b * a.cw >= a.ncol) return;
     const int cl = threadIdx.x % a.cw, ch = threadIdx.x / a.cw;
-    const int p = b * a.cw + cl;
+    int p = b * a.cw + cl;
     const int colour = PHASE == 1 ? 1 : 0;
-    int y = p / a.hx, x = 2 * (p % a.hx) + ((colour + y) & 1);
+    int y = p / a.hx, j = p % a.hx;
+    const int par = (colour + y) & 1;
+    int x = 2 * j + par;
     const bool mine = p < a.ncol && x < a.g.nx && ch < a.nch;
     const int z0 = ch * a.L;
     const int n = mine ? min(a.L, a.g.nz - z0) : 0;
-    if (!mine) x = y = 0;  // loads below stay in bounds; nothing is written
+    if (!mine) x = y = j = p = 0;  // loads below stay in bounds; nothing is written
     const int col = x + a.g.nx * y, nxy = a.g.nxy, nz = a.g.nz;
-    auto cell = [&](int t) { return col + nxy * min(z0 + min(t, max(n - 1, 0)), nz - 1); };
+    auto layer = [&](int t) { return min(z0 + min(t, max(n - 1, 0)), nz - 1); };
     TT al[kLineLMax], be[kLineLMax], dv[kLineLMax];
-    bool act[kLineLMax];
     TT v;
     if (PHASE <= 1) {
         // forward: y_k = al_k + be_k y_{k-1}
 #pragma unroll
         for (int t = 0; t < kLineLMax; ++t) {
-            const int i = cell(t);
+            const int k = layer(t);
+            const size_t kq = (size_t)k * a.ncol;
+            const int i = col + nxy * k;
             TT s = (TT)a.r[i];
-            if (PHASE == 1) s += xy_sum_r(a, i, x, y, a.e);
+            if (PHASE == 1) s += xy_sum_r(a, i, x, y, j, par, kq);
             al[t] = s;
-            be[t] = a.cz[i];
-            dv[t] = a.dinv[i];
+            be[t] = a.pc[kq + p];
+            dv[t] = a.pd[kq + p];
         }
         TT A = (TT)0, B = (TT)1;
 #pragma unroll
@@ -262,7 +333,7 @@ __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, co
         for (int t = 0; t < kLineLMax; ++t)
             if (t < n) {
                 v = al[t] + be[t] * v;
-                if (PHASE == 0) a.e[col + nxy * (z0 + t)] = (double)(v * dv[t]);
+                if (PHASE == 0) a.eself[(size_t)(z0 + t) * a.ncol + p] = v * dv[t];
                 else al[t] = v;  // y, kept for the backward sweep
             }
         if (PHASE == 0) return;
@@ -271,15 +342,16 @@ __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, co
     // backward: z_k = al_k + be_k z_{k+1}, be_k = Tz_k / p_k
 #pragma unroll
     for (int t = 0; t < kLineLMax; ++t) {
-        const int i = cell(t);
+        const int k = layer(t);
+        const size_t kq = (size_t)k * a.ncol;
         if (PHASE == 2) {
-            dv[t] = a.dinv[i];
-            al[t] = (TT)a.e[i] + dv[t] * xy_sum_r(a, i, x, y, a.e);
+            const int i = col + nxy * k;
+            dv[t] = a.pd[kq + p];
+            al[t] = a.eself[kq + p] + dv[t] * xy_sum_r(a, i, x, y, j, par, kq);
         } else {
             al[t] = al[t] * dv[t];
         }
-        be[t] = z0 + t + 1 < nz ? a.tz[i] * dv[t] : (TT)0;
-        act[t] = a.g.diag[i] > 0.0;
+        be[t] = a.pt[kq + p];
     }
     TT A = (TT)0, B = (TT)1;
 #pragma unroll
@@ -294,36 +366,61 @@ __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, co
     if (!mine) return;
     v = (TT)0;
     for (int c = a.nch - 1; c > ch; --c) v = sA[c * a.cw + cl] + sB[c * a.cw + cl] * v;
+    // x is updated in whole pairs {x, x ^ 1} of a row: the red pass writes
+    // its cell and the black partner (black slot p as well: x ^ 1 = 2j + 1 -
+    // par), so x is read and written once; the black pass writes x only
+    // where the partner lies outside the row (odd nx).  A correction is
+    // exactly zero where 1/p is.
+    const bool partner = (x ^ 1) < a.g.nx;
+    const int ib = (x ^ 1) + a.g.nx * y;
 #pragma unroll
     for (int t = kLineLMax - 1; t >= 0; --t)
         if (t < n) {
             v = al[t] + be[t] * v;
+            const size_t q = (size_t)(z0 + t) * a.ncol + p;
             const int i = col + nxy * (z0 + t);
-            if (PHASE == 1) a.e[i] = (double)v;
-            if (act[t]) a.x[i] = ASSIGN ? (double)v : a.x[i] + (double)v;
-            else if (ASSIGN) a.x[i] = 0.0;
+            if (PHASE == 1) a.eself[q] = v;
+            if (PHASE == 2 || !partner) {
+                if (dv[t] != (TT)0) a.x[i] = ASSIGN ? (double)v : a.x[i] + (double)v;
+                else if (ASSIGN) a.x[i] = 0.0;
+            }
+            if (PHASE == 2 && partner) {
+                const int i2 = ib + nxy * (z0 + t);
+                const double zb = (double)a.eother[q];
+                a.x[i2] = ASSIGN ? zb : a.x[i2] + zb;
+            }
         }
 }
 
 template <typename TT, bool ASSIGN>
 static void lilu_dispatch(Ctx &c, const TT *tx, const TT *ty, const TT *tz, const TT *dinv, const TT *cz,
-                          const double *r, double *x, const int *done) {
+                          TT *packed, TT *pe, const double *r, double *x, const int *done) {
     const Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
-    int nchp = 1;  // chunks per column rounded up to a power of two
-    while (nchp * kLineLMax < c.nz) nchp *= 2;
-    if (nchp <= kLineThreads / 4) {
+    const int nchp = lilu_reg_chunks(c.nz);
+    if (nchp) {
+        const size_t S = lilu_slots(c.nx, c.ny, c.nz);
         LineRegArgs<TT> q;
         q.g = g;
-        q.tx = tx; q.ty = ty; q.tz = tz; q.dinv = dinv; q.cz = cz;
-        q.r = r; q.e = c.e; q.x = x;
+        q.tx = tx; q.ty = ty;
+        q.r = r; q.x = x;
         q.hx = (c.nx + 1) / 2;
         q.ncol = q.hx * c.ny;
         q.cw = kLineThreads / nchp;
         q.L = cdiv(c.nz, nchp);
         q.nch = cdiv(c.nz, q.L);
         const dim3 grid(xcd_grid(cdiv(q.ncol, q.cw))), blk(kLineThreads);
+        TT *e_red = pe, *e_black = pe + S;
+        // red forward
+        q.pd = packed; q.pc = packed + S; q.pt = packed + 2 * S;
+        q.eself = e_red; q.eother = e_black;
         hipLaunchKernelGGL((k_lilu_reg<TT, 0, ASSIGN>), grid, blk, 0, c.stream, q, done);
+        // black forward and backward
+        q.pd = packed + 3 * S; q.pc = packed + 4 * S; q.pt = packed + 5 * S;
+        q.eself = e_black; q.eother = e_red;
         hipLaunchKernelGGL((k_lilu_reg<TT, 1, ASSIGN>), grid, blk, 0, c.stream, q, done);
+        // red backward
+        q.pd = packed; q.pc = packed + S; q.pt = packed + 2 * S;
+        q.eself = e_red; q.eother = e_black;
         hipLaunchKernelGGL((k_lilu_reg<TT, 2, ASSIGN>), grid, blk, 0, c.stream, q, done);
         return;
     }
@@ -343,11 +440,13 @@ static void lilu_dispatch(Ctx &c, const TT *tx, const TT *ty, const TT *tz, cons
 
 void launch_lilu_apply(Ctx &c, const double *r, double *x, const int *done, bool assign) {
     if (c.opt.precision == MSRSB_MIXED) {
-        if (assign) lilu_dispatch<float, true>(c, c.tx32, c.ty32, c.tz32, c.ldinv32, c.lcz32, r, x, done);
-        else lilu_dispatch<float, false>(c, c.tx32, c.ty32, c.tz32, c.ldinv32, c.lcz32, r, x, done);
+        float *pk = (float *)c.lpack, *pe = (float *)c.lpe;
+        if (assign) lilu_dispatch<float, true>(c, c.tx32, c.ty32, c.tz32, c.ldinv32, c.lcz32, pk, pe, r, x, done);
+        else lilu_dispatch<float, false>(c, c.tx32, c.ty32, c.tz32, c.ldinv32, c.lcz32, pk, pe, r, x, done);
     } else {
-        if (assign) lilu_dispatch<double, true>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, r, x, done);
-        else lilu_dispatch<double, false>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, r, x, done);
+        double *pk = (double *)c.lpack, *pe = (double *)c.lpe;
+        if (assign) lilu_dispatch<double, true>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, pk, pe, r, x, done);
+        else lilu_dispatch<double, false>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, pk, pe, r, x, done);
     }
 }
 

@@ -145,6 +145,9 @@ struct Ctx {
     // z-line red-black ILU(0): inverse pivots and Tz_{k-1} / p_{k-1} per cell
     double *ldinv = nullptr, *lcz = nullptr;
     float *ldinv32 = nullptr, *lcz32 = nullptr;
+    // its register path's colour-packed factors [colour][1/p, cz, Tz/p][slot] and
+    // corrections [colour][slot], in the working precision (null: not used)
+    void *lpack = nullptr, *lpe = nullptr;
     int32_t *bc_cell = nullptr;
     double *bc_trans = nullptr, *bc_value = nullptr;
     int32_t *bcptr = nullptr, *bcidx = nullptr;  // connections grouped by cell ([N+1], [n_bc])
@@ -218,6 +221,8 @@ void launch_matvec(Ctx &c, const double *x, double *y, bool norm, const int *don
 void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool assign = false);
 void launch_lilu_factor(Ctx &c);
 void launch_lilu_apply(Ctx &c, const double *r, double *x, const int *done, bool assign);
+int lilu_reg_chunks(int nz);                          // 0: columns too tall for the register path
+size_t lilu_slots(int nx, int ny, int nz);            // packed slots of one colour
 void launch_dgmres_step(Ctx &c, const double *z, double *w, const double *u, int j, double rtol, int max_iters,
                         bool final_);
 constexpr int kDcgsMax = 31;  // largest restart served by the DCGS2 kernels
