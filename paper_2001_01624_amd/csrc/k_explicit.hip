@@ -216,7 +216,10 @@ void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done) {
 // One wavefront per chunk of at most kXRapChunk entries of a block's list; a
 // block with several chunks sums each into a partial row of its own, added
 // in chunk order by k_xrap_finish.
-template <typename PS>
+// LDSROW: the row is accumulated in LDS (Mp doubles) and stored once at the
+// end; otherwise in its global row (rows too long for LDS).  The additions
+// are the same, in the same order, either way.
+template <int NSX, typename PS, bool LDSROW>
 __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__restrict__ sb,
                                              const int32_t *__restrict__ ptr, const int32_t *__restrict__ rcblk,
                                              const int32_t *__restrict__ rcfirst, const int32_t *__restrict__ rrow,
@@ -224,34 +227,51 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
                                              const uint8_t *__restrict__ slot, const PS *__restrict__ P,
                                              const double *__restrict__ bcdiag, double *__restrict__ Ac,
                                              double *__restrict__ rpart, int Mp) {
+    extern __shared__ double srow[];
     const int ch = blockIdx.x, j = rcblk[ch], lane = threadIdx.x;
     const long N = g.N;
-    double *row = rrow[ch] >= 0 ? rpart + (long)rrow[ch] * Mp : Ac + (long)j * Mp;
+    double *grow = rrow[ch] >= 0 ? rpart + (long)rrow[ch] * Mp : Ac + (long)j * Mp;
+    double *row = LDSROW ? srow : grow;
+    if (LDSROW) {
+        for (int k = lane; k < Mp; k += 64) srow[k] = 0.0;
+        __syncthreads();
+    }
     const int k0 = ptr[j] + (ch - rcfirst[j]) * kXRapChunk, k1 = min(k0 + kXRapChunk, ptr[j + 1]);
+    // each wavefront sums one row's contributions per column k with a
+    // ballot over the lanes' columns and a wave sum per distinct column
+    auto commit = [&](int kb, double v) {
+        unsigned long long pending = __ballot(kb >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int kk = __shfl(kb, leader, 64);
+            const unsigned long long same = __ballot(kb == kk);
+            const double sum = wave_sum(kb == kk ? v : 0.0);
+            if (lane == 0) row[kk] += sum;
+            pending &= ~same;
+        }
+    };
     for (int base = k0; base < k1; base += 64) {
         const int k = base + lane;
         const bool live = k < k1;
         const int a = live ? cell[k] : 0;
+        // a's slot list (blocks ascending, -1 past the last slot) and values,
+        // loaded once for the six faces
+        int la[NSX];
+        double pa[NSX];
+#pragma unroll
+        for (int t = 0; t < NSX; ++t) {
+            la[t] = t < ns ? sb[(long)t * N + a] : -1;
+            pa[t] = t < ns ? ld_basis(P, (long)t * N + a) : 0.0;
+        }
         const double Paj = live ? ld_basis(P, (long)slot[k] * N + a) : 0.0;
         // boundary term: bc_a P_aj P_ak over a's slots
         {
             const double bc = live ? bcdiag[a] : 0.0;
-            for (int t = 0; t < ns; ++t) {
-                int kb = -1;
-                double v = 0.0;
-                if (live && bc > 0.0) {
-                    kb = sb[(long)t * N + a];
-                    if (kb >= 0) v = bc * Paj * ld_basis(P, (long)t * N + a);
-                }
-                unsigned long long pending = __ballot(kb >= 0);
-                while (pending) {
-                    const int leader = __ffsll((long long)pending) - 1;
-                    const int kk = __shfl(kb, leader, 64);
-                    const unsigned long long same = __ballot(kb == kk);
-                    const double sum = wave_sum(kb == kk ? v : 0.0);
-                    if (lane == 0) row[kk] += sum;
-                    pending &= ~same;
-                }
+#pragma unroll
+            for (int t = 0; t < NSX; ++t) {
+                if (t >= ns) break;
+                const bool on = live && bc > 0.0 && la[t] >= 0;
+                commit(on ? la[t] : -1, on ? bc * Paj * pa[t] : 0.0);
             }
         }
         for (int q = 0; q < 6; ++q) {
@@ -270,59 +290,68 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
                     T = Ta[b];
                 }
             }
+            // b's slot list and values (b = a where there is no face: unused)
+            const int bb = T != 0.0 ? b : a;
+            int lb[NSX];
+            double pb[NSX];
+#pragma unroll
+            for (int t = 0; t < NSX; ++t) {
+                lb[t] = t < ns ? sb[(long)t * N + bb] : -1;
+                pb[t] = t < ns ? ld_basis(P, (long)t * N + bb) : 0.0;
+            }
             // value of block j at b, and whether b lies in the support
             double Pbj = 0.0;
             bool bin = false;
             if (T != 0.0) {
-                for (int t = 0; t < ns; ++t) {
-                    const int bl = sb[(long)t * N + b];
-                    if (bl < 0) break;
-                    if (bl == j) {
-                        Pbj = ld_basis(P, (long)t * N + b);
+#pragma unroll
+                for (int t = 0; t < NSX; ++t)
+                    if (lb[t] == j) {
+                        Pbj = pb[t];
                         bin = true;
                     }
-                }
             }
             // each face once: from a, unless b is also in the support and b < a
             const bool take = T != 0.0 && !(bin && b < a);
             const double gj = take ? Paj - Pbj : 0.0;
             const bool act = take && gj != 0.0;
             // columns: blocks of a (with b's value of the same block), then blocks only of b
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int t = 0; t < ns; ++t) {
-                    int kb = -1;
-                    double v = 0.0;
-                    if (act) {
-                        const int src = pass == 0 ? a : b, oth = pass == 0 ? b : a;
-                        kb = sb[(long)t * N + src];
-                        if (kb >= 0) {
-                            const double ps = ld_basis(P, (long)t * N + src);
-                            double po = 0.0;
-                            bool shared = false;
-                            for (int u = 0; u < ns; ++u) {
-                                const int bo = sb[(long)u * N + oth];
-                                if (bo < 0) break;
-                                if (bo == kb) {
-                                    po = ld_basis(P, (long)u * N + oth);
-                                    shared = true;
-                                }
-                            }
-                            if (pass == 1 && shared) kb = -1;  // already taken with a's slots
-                            else v = T * gj * (pass == 0 ? ps - po : -ps);
-                        }
-                    }
-                    unsigned long long pending = __ballot(kb >= 0);
-                    while (pending) {
-                        const int leader = __ffsll((long long)pending) - 1;
-                        const int kk = __shfl(kb, leader, 64);
-                        const unsigned long long same = __ballot(kb == kk);
-                        const double sum = wave_sum(kb == kk ? v : 0.0);
-                        if (lane == 0) row[kk] += sum;
-                        pending &= ~same;
+#pragma unroll
+            for (int t = 0; t < NSX; ++t) {
+                if (t >= ns) break;
+                int kb = -1;
+                double v = 0.0;
+                if (act && la[t] >= 0) {
+                    kb = la[t];
+                    double po = 0.0;
+#pragma unroll
+                    for (int u = 0; u < NSX; ++u)
+                        if (lb[u] == kb) po = pb[u];
+                    v = T * gj * (pa[t] - po);
+                }
+                commit(kb, v);
+            }
+#pragma unroll
+            for (int t = 0; t < NSX; ++t) {
+                if (t >= ns) break;
+                int kb = -1;
+                double v = 0.0;
+                if (act && lb[t] >= 0) {
+                    bool shared = false;
+#pragma unroll
+                    for (int u = 0; u < NSX; ++u)
+                        if (la[u] == lb[t]) shared = true;
+                    if (!shared) {  // blocks of both were taken with a's slots
+                        kb = lb[t];
+                        v = -T * gj * pb[t];
                     }
                 }
+                commit(kb, v);
             }
         }
+    }
+    if (LDSROW) {
+        __syncthreads();
+        for (int k = lane; k < Mp; k += 64) grow[k] = srow[k];
     }
 }
 
@@ -348,16 +377,32 @@ void launch_partial_rows_finish(Ctx &c, int M, int Mp, const int32_t *rcfirst, c
 
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
 
+constexpr size_t kXRapLds = 65536;  // longest row accumulated in LDS: 8192 coarse columns
+
 void launch_xrap(Ctx &c, Stage &s) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     hipMemsetAsync(s.Ac, 0, sizeof(double) * (size_t)s.Mp * s.Mp, c.stream);
     if (s.nxrrow > 0) hipMemsetAsync(s.xrpart, 0, sizeof(double) * (size_t)s.nxrrow * s.Mp, c.stream);
-    if (c.opt.precision == MSRSB_MIXED)
-        hipLaunchKernelGGL(k_xrap<uint16_t>, dim3(s.nxrch), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xrcblk,
-                           s.xrcfirst, s.xrrow, s.xcell, s.xslot, s.Pbf, c.bcdiag, s.Ac, s.xrpart, s.Mp);
-    else
-        hipLaunchKernelGGL(k_xrap<double>, dim3(s.nxrch), dim3(64), 0, c.stream, g, s.ns, s.xsb, s.xptr, s.xrcblk,
-                           s.xrcfirst, s.xrrow, s.xcell, s.xslot, s.P64[s.cur], c.bcdiag, s.Ac, s.xrpart, s.Mp);
+    const size_t lds = sizeof(double) * (size_t)s.Mp;
+#define MSRSB_XRAP1(NSX, PS, PP, L)                                                                             \
+    hipLaunchKernelGGL((k_xrap<NSX, PS, L>), dim3(s.nxrch), dim3(64), L ? lds : 0, c.stream, g, s.ns, s.xsb,     \
+                       s.xptr, s.xrcblk, s.xrcfirst, s.xrrow, s.xcell, s.xslot, PP, c.bcdiag, s.Ac, s.xrpart, s.Mp)
+#define MSRSB_XRAP(PS, PP, L)                                \
+    {                                                        \
+        if (s.ns <= 8) MSRSB_XRAP1(8, PS, PP, L);            \
+        else if (s.ns <= 16) MSRSB_XRAP1(16, PS, PP, L);     \
+        else MSRSB_XRAP1(kMaxXSlots, PS, PP, L);             \
+    }
+    const bool mixed = c.opt.precision == MSRSB_MIXED;
+    if (lds <= kXRapLds) {
+        if (mixed) MSRSB_XRAP(uint16_t, s.Pbf, true)
+        else MSRSB_XRAP(double, s.P64[s.cur], true)
+    } else {
+        if (mixed) MSRSB_XRAP(uint16_t, s.Pbf, false)
+        else MSRSB_XRAP(double, s.P64[s.cur], false)
+    }
+#undef MSRSB_XRAP
+#undef MSRSB_XRAP1
     if (s.nxrrow > 0)
         hipLaunchKernelGGL(k_xrap_finish, dim3(cdiv(s.M, kBlock), s.M), dim3(kBlock), 0, c.stream, s.M, s.Mp,
                            s.xrcfirst, s.xrrow, s.xrpart, s.Ac);

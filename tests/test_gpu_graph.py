@@ -172,3 +172,21 @@ def test_graph_errors(capi):
     # GRAPH cannot be the first (general) stage
     with pytest.raises(capi.MsrsbError):
         capi.Solver(prob, [{"kind": "graph", "block_of_cell": np.zeros(prob.n_cells), "overlap": 1}])
+
+
+def test_graph_long_coarse_rows(capi):
+    # one block per cell on 8,640 cells: coarse rows of 8,640 entries, longer
+    # than the Galerkin kernel keeps in LDS, so the rows are summed in memory
+    prob = make_lognormal_box((24, 24, 15), rng_for(9, 4), sigma=1.0)
+    ids = np.arange(prob.n_cells)
+    parts = [{"kind": "cartesian", "coarse_dims": (2, 2, 1)}, {"kind": "graph", "block_of_cell": ids, "overlap": 1}]
+    say(f"graph long rows dims={prob.dims} M={prob.n_cells}")
+    g = capi.Solver(prob, parts, capi.default_options())
+    o = O.Oracle(prob, parts, smoother="jacobi")
+    g.update_basis(max_sweeps=2, tol=0.0)
+    o.update_basis(max_sweeps=2, tol=0.0)
+    M, kind, ns = g.stage_info(1)
+    assert M == prob.n_cells and 8 * M > 65536
+    A = g.export_stage(1)["Ac"]
+    assert relerr(A, o.stages[1].Ac) <= 1e-12
+    g.close()
