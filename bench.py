@@ -40,10 +40,12 @@ METRIC = "fine cells solved/s to 1e-6 rel. residual (FP64 plain vs mixed+served)
 HBM_PEAK_GBS = 8000.0
 DIMS = (60, 220, 85)
 STAGES = [(10, 10, 5), (6, 22, 17)]
-# GMRES restart length of the request: 12..31 all need 62-68 iterations per
-# solve on this model, and 16 is the fastest (fewer basis vectors per step)
+# GMRES restart length of the request: with the z-line ILU(0) smoother,
+# restarts 10..31 all need 39-42 iterations per solve on this model, and 16
+# and 20 are the fastest (fewer basis vectors per step)
 RESTART = 16
 RTOL = 1e-6
+TWOPHASE_DT = 2.0e4  # time step of the two-phase leg (model units; plain Newton diverges at 2e5)
 
 
 def parse():
@@ -66,6 +68,11 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble (also skipped by --no-serve)")
     ap.add_argument("--ensemble-members", type=int, default=256)
+    ap.add_argument("--no-static", action="store_true", help="skip the static-stage (well, indicator) leg")
+    ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume leg")
+    ap.add_argument("--no-twophase", action="store_true", help="skip the two-phase CPR leg")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="profiling aid: run only the static-stage, finite-volume and two-phase legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -314,6 +321,169 @@ def faulted_leg(args):
     return out
 
 
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, 1e3 * (time.perf_counter() - t)
+
+
+def static_leg(args):
+    """Static stages (partition type "Static": well bases and an indicator
+    agglomeration, GRAPH stages on the explicit-slot kernels) added to the
+    request's two general stages on the 60x220x85 model, FP64: both bases
+    built (<= 100 sweeps, tol 1e-3) and three GMRES solves from zero, per
+    stage set; the oracle on the 30x110x21 sample with the well stage beside."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2001_01624_amd import capi
+
+    prob, sources = workload()
+    base = [{"kind": "cartesian", "coarse_dims": cd} for cd in STAGES]
+
+    def wells_of(p):
+        prod = p.wells["producers"]
+        return [p.wells["injector"]] + [prod[k * (prod.size // 4):(k + 1) * (prod.size // 4)] for k in range(4)]
+
+    wb = capi.partition_wells(prob, wells_of(prob), 3)
+    ib = capi.partition_indicator(prob, np.log(prob.perm), 4, (10, 10, 5), 64)
+    sets = {"general": base,
+            "general+wells": base + [{"kind": "graph", "block_of_cell": wb, "overlap": 8}],
+            "general+indicator": base + [{"kind": "graph", "block_of_cell": ib, "overlap": 2}]}
+    q = [torch.as_tensor(x).cuda() for x in sources]
+    x = torch.zeros(prob.n_cells, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, parts in sets.items():
+        g = capi.Solver(prob, parts, capi.default_options(smoother=args.smoother, outer="gmres", restart=RESTART))
+
+        def request():
+            sw = [g.update_basis(stage=k, max_sweeps=100, tol=1e-3)[0] for k in range(len(parts))]
+            its, rels = [], []
+            for qk in q:
+                x.zero_()
+                it, rel, rc = g.solve(x, source=qk, rtol=RTOL, max_iters=3000)
+                its.append(it)
+                rels.append(rel if rc == capi.OK else float("inf"))
+            return sw, its, rels
+
+        request()
+        (sw, its, rels), ms = _timed(request)
+        out[name] = {"request_ms": round(ms, 2), "value": 3 * prob.n_active / (ms / 1e3), "iters": its,
+                     "sweeps": sw, "max_relres": max(rels),
+                     "stages": [list(g.stage_info(k)[:2]) for k in range(len(parts))]}
+        g.close()
+    sp, ss = workload(dims=(30, 110, 21))
+    t = time.perf_counter()
+    o = O.Oracle(sp, [{"kind": "cartesian", "coarse_dims": (5, 5, 1)}, {"kind": "cartesian", "coarse_dims": (3, 11, 4)},
+                      {"kind": "graph", "block_of_cell": O.msrsb.well_partition(sp, wells_of(sp), 3), "overlap": 8}],
+                 smoother=args.smoother)
+    o.update_basis(100, 1e-3)
+    _, oit, _, _ = o.solve_gmres(source=ss[0], rtol=RTOL, restart=RESTART, max_iters=3000)
+    out["oracle_sample"] = {"seconds": round(time.perf_counter() - t, 2), "cells": sp.n_active, "iters": oit,
+                            "what": "30x110x21 sample, general stages 5x5x1 and 3x11x4 plus the well stage: "
+                                    "set-up, bases and one solve"}
+    out["workload"] = ("60x220x85 layered model, FP64, z-line ILU(0), GMRES(16); static stages: five wells "
+                       "(injector + producers in four groups, radius 3, support overlap 8) and a log-permeability "
+                       "agglomeration (4 bins, parent blocks 10x10x5, >= 64 cells, overlap 2); request = bases + "
+                       "three solves from zero")
+    return out
+
+
+def fv_leg(args):
+    """Finite-volume mode (msrsb_solve_fv) on the 60x220x85 model: the
+    10x10x5 stage's basis, then for each of the request's three sources the
+    multiscale pressure with R_fv and conservative fine fluxes from the
+    per-block Neumann problems; the oracle on the 30x110x21 sample beside."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2001_01624_amd import capi
+
+    prob, sources = workload()
+    parts = [{"kind": "cartesian", "coarse_dims": STAGES[0]}]
+    g = capi.Solver(prob, parts, capi.default_options(smoother=args.smoother))
+    g.update_basis(max_sweeps=100, tol=1e-3)
+    q = [torch.as_tensor(x).cuda() for x in sources]
+    g.solve_fv(0, q[0])
+    recs = []
+    for qk in q:
+        (p, pf, face, bcf, its, imb), ms = _timed(lambda: g.solve_fv(0, qk))
+        recs.append((ms, its, imb / float(torch.abs(qk).max())))
+    g.close()
+    sp, ss = workload(dims=(30, 110, 21))
+    t = time.perf_counter()
+    o = O.Oracle(sp, [{"kind": "cartesian", "coarse_dims": (5, 5, 1)}])
+    o.update_basis(100, 1e-3)
+    o.solve_fv(0, ss[0])
+    return {"ms_per_solve": [round(r[0], 2) for r in recs], "value": prob.n_active / (np.mean([r[0] for r in recs]) / 1e3),
+            "unit": "cells/s", "local_iters": [r[1] for r in recs],
+            "max_cell_imbalance_over_max_source": max(r[2] for r in recs),
+            "oracle_sample": {"seconds": round(time.perf_counter() - t, 2), "cells": sp.n_active,
+                              "what": "30x110x21 sample, 5x5x1 stage: set-up, basis, one finite-volume solve"},
+            "workload": "60x220x85 layered model, FP64, 10x10x5 stage (<= 100 sweeps, tol 1e-3); per source: "
+                        "p_ms = P A_fv^-1 R_fv b and fine fluxes from per-block Neumann problems to 1e-12"}
+
+
+def twophase_leg(args):
+    """Two-phase fully implicit time steps with the CPR preconditioner on the
+    60x220x85 model (water injected at the injector column, producers held at
+    their connection pressures): three backward-Euler steps with Newton,
+    GMRES(30) on the full system, the multistage cycle of the two general
+    stages as the pressure predictor and red-black block ILU(0) as the
+    corrector, dynamic bases from the Newton pressure updates (Dp(Inf));
+    the two-phase oracle on a 16x20x6 sample beside."""
+    import numpy as np
+    import torch
+
+    from oracle import twophase as TP
+    import oracle as O
+    from paper_2001_01624_amd import capi, twophase
+    from workloads import make_config1
+
+    fluid = dict(mu_w=1.0, mu_o=5.0, n_w=2.0, n_o=2.0)
+    prob, _ = workload()
+    parts = [{"kind": "cartesian", "coarse_dims": cd} for cd in STAGES]
+    g = capi.Solver(prob, parts, capi.default_options(smoother=args.smoother, outer="gmres"))
+    g.update_basis(max_sweeps=100, tol=1e-3)
+    pv = np.full(prob.n_cells, 0.2 * np.prod(prob.h)) * prob.active
+    tp = capi.TwoPhase(g, pv, fluid, restart=30)
+    p = torch.zeros(prob.n_cells, dtype=torch.float64, device="cuda")
+    s = torch.as_tensor(np.full(prob.n_cells, 0.2) * prob.active).cuda()
+    dt = TWOPHASE_DT
+    steps, last = [], None
+    for k in range(3):
+        st, ms = _timed(lambda: twophase.time_step(tp, p, s, dt, newton_tol=1e-6, lin_rtol=1e-6, lin_max=1000,
+                                                   last_dp=last))
+        last = st["last_dp"]
+        steps.append({"ms": round(ms, 1), "newton": st["newton"], "linear": st["linear"],
+                      "converged": not st.get("failed") and st["res"][-1] <= 1e-6 * st["res"][0]})
+    tp.close()
+    g.close()
+    tot = sum(x["ms"] for x in steps)
+    small = make_config1(dims=(16, 20, 6), seed=5)
+    t = time.perf_counter()
+    o = O.Oracle(small, [{"kind": "cartesian", "coarse_dims": (2, 2, 2)}], smoother="ilu0_rb")
+    o.update_basis(30, 1e-3)
+    ot = TP.TwoPhase(small, np.full(small.n_cells, 0.2 * np.prod(small.h)) * small.active, fluid, dt, o)
+    z = np.zeros(small.n_cells)
+    s0 = np.full(small.n_cells, 0.2) * small.active
+    _, _, oits, _, _ = ot.newton_step(z, s0.copy(), s0, rtol=1e-6)
+    return {"ms_per_step": round(tot / len(steps), 1), "value": len(steps) * prob.n_active / (tot / 1e3),
+            "unit": "cell-steps/s", "steps": steps,
+            "oracle_sample": {"seconds": round(time.perf_counter() - t, 2), "cells": small.n_active,
+                              "gmres_iters": oits, "what": "16x20x6 sample: set-up, basis, one Newton step with "
+                                                          "GMRES + CPR to 1e-6"},
+            "workload": f"60x220x85 layered model, water/oil (mu 1/5 cP, Corey 2/2), dt {dt:g}, three steps from "
+                        "s = 0.2, Newton to 1e-6, GMRES(30) + CPR (multistage cycle of the 10x10x5 and 6x22x17 "
+                        "stages with z-line ILU(0); red-black block ILU(0) of the full system)"}
+
+
 def serve_leg(args):
     """The same seeded Poisson stream (200 requests/s; 10 % layered
     60x220x85 models with two general stages, 90 % ensemble members
@@ -496,6 +666,14 @@ def main():
         rec = faulted_leg(args)
         print(json.dumps({"leg": "faulted", "metric": METRIC, **rec}))
         return
+    if args.extras_only:
+        for name, fn, skip in (("static", static_leg, args.no_static), ("fv", fv_leg, args.no_fv),
+                               ("twophase", twophase_leg, args.no_twophase)):
+            if not skip:
+                t = time.perf_counter()
+                rec = fn(args)
+                print(json.dumps({"leg": name, **rec, "leg_s": round(time.perf_counter() - t, 1)}), flush=True)
+        return
     if args.mixed_only:
         rec = gpu_leg(args, "mixed")
         print(json.dumps({"leg": "mixed", "metric": METRIC, "value": rec["value"], "unit": "cells/s",
@@ -513,6 +691,9 @@ def main():
     faulted = None if args.no_faulted else leg("faulted request", faulted_leg, args)
     served = None if args.no_serve else leg("serving stream", serve_leg, args)
     ensemble = None if (args.no_serve or args.no_ensemble) else leg("ensemble", ensemble_leg, args)
+    static = None if args.no_static else leg("static stages", static_leg, args)
+    fv = None if args.no_fv else leg("finite volume", fv_leg, args)
+    two = None if args.no_twophase else leg("two-phase", twophase_leg, args)
     cpu = None if args.no_cpu_baseline else leg("oracle baseline", run_cpu_baseline, args.smoother)
     line = {
         "metric": METRIC,
@@ -556,6 +737,12 @@ def main():
         line["served"] = served
     if ensemble is not None:
         line["ensemble"] = ensemble
+    if static is not None:
+        line["static_stages"] = static
+    if fv is not None:
+        line["finite_volume"] = fv
+    if two is not None:
+        line["two_phase"] = two
     line["host"] = platform.node()
     print(json.dumps(line))
 
