@@ -295,6 +295,259 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_local(Fine g, const int32_t *
     if (threadIdx.x == 0) atomicMax(iters_max, it);
 }
 
+// The same Neumann problems for blocks of at most kFvLineCells cells, by
+// conjugate gradients preconditioned with the block's z lines: M = D - L_z -
+// U_z (D the block operator's diagonal, L_z, U_z its couplings along z), whose
+// inverse is a tridiagonal solve per chain of cells linked along +z inside
+// the block.  The strong vertical coupling of layered models then sits in the
+// preconditioner.  Chains are factored once per launch (pivots p_k = (1 +
+// 2^-10) d_k - t_{k-1}^2 / p_{k-1}: the slightly raised diagonal keeps every
+// pivot positive, also on a chain that is a whole singular Neumann block);
+// 1/p and t/p are kept in FP32 (a fixed preconditioner; its application runs
+// in FP64).  Each thread owns the list positions t, t + 1024, t + 2048 and
+// keeps their diagonal, right-hand side, iterate and residual in registers;
+// LDS holds the search direction, the preconditioner's work vector, the
+// factors and the chain links (next and previous position, head flag), 28
+// bytes per cell.  The owner of a chain's lowest cell walks it forward and
+// back.  Stopping, restarts and the zero-sum treatment of unanchored blocks
+// are those of k_fv_local.
+constexpr int kFvLineCells = 2304;
+constexpr int kFvOwn = (kFvLineCells + kFvThreads - 1) / kFvThreads;
+
+__global__ __launch_bounds__(kFvThreads) void k_fv_local_line(Fine g, const int32_t *__restrict__ fvblock,
+                                                              const int32_t *__restrict__ ptr,
+                                                              const int32_t *__restrict__ cells,
+                                                              const int32_t *__restrict__ loc,
+                                                              const double *__restrict__ bcdiag,
+                                                              const double *__restrict__ b,
+                                                              const double *__restrict__ pms, double *__restrict__ xout,
+                                                              double rtol, int max_iters, int *iters_max) {
+    extern __shared__ double smem[];
+    __shared__ double red[kFvThreads / 64];
+    const int j = blockIdx.x;
+    const int c0 = ptr[j], n = ptr[j + 1] - c0;
+    double *pl = smem, *zl = smem + n;
+    float *fip = (float *)(smem + 2 * n), *fe = fip + n;
+    int32_t *lnk = (int32_t *)(fe + n);  // next + 1 | (prev + 1) << 12 | head << 24
+    const int step[3] = {1, g.nx, g.nxy};
+    const double *Ta[3] = {g.tx, g.ty, g.tz};
+    auto diag_of = [&](int i, double *ext) {
+        double d = bcdiag[i], e = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double tu = Ta[a][i];
+            if (tu != 0.0) {
+                if (fvblock[i + step[a]] == j) d += tu;
+                else e += tu * (pms[i] - pms[i + step[a]]);
+            }
+            if (i >= step[a]) {
+                const double td = Ta[a][i - step[a]];
+                if (td != 0.0) {
+                    if (fvblock[i - step[a]] == j) d += td;
+                    else e += td * (pms[i] - pms[i - step[a]]);
+                }
+            }
+        }
+        *ext = e;
+        return d;
+    };
+    auto apply = [&](int i, double d, double own) {
+        double y = d * own;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double tu = Ta[a][i];
+            if (tu != 0.0 && fvblock[i + step[a]] == j) y -= tu * pl[loc[i + step[a]]];
+            if (i >= step[a]) {
+                const double td = Ta[a][i - step[a]];
+                if (td != 0.0 && fvblock[i - step[a]] == j) y -= td * pl[loc[i - step[a]]];
+            }
+        }
+        return y;
+    };
+    int ci[kFvOwn];
+    double dg[kFvOwn], rh[kFvOwn], xr[kFvOwn], rv[kFvOwn];
+    double rhs2 = 0.0, nb = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFvOwn; ++u) {
+        const int k = threadIdx.x + u * kFvThreads;
+        ci[u] = 0;
+        dg[u] = rh[u] = xr[u] = rv[u] = 0.0;
+        if (k >= n) continue;
+        const int i = cells[c0 + k];
+        ci[u] = i;
+        double ext;
+        dg[u] = diag_of(i, &ext);
+        rh[u] = b[i] - ext;
+        xr[u] = pms[i];
+        rhs2 += rh[u] * rh[u];
+        nb += bcdiag[i] > 0.0 ? 1.0 : 0.0;
+        pl[k] = pms[i];
+        // the chain link along +z and the head flag (no link from below)
+        int nx = -1, pv = -1;
+        double t = 0.0;
+        if (g.tz[i] != 0.0 && fvblock[i + g.nxy] == j) {
+            nx = loc[i + g.nxy];
+            t = g.tz[i];
+        }
+        if (i >= g.nxy && g.tz[i - g.nxy] != 0.0 && fvblock[i - g.nxy] == j) pv = loc[i - g.nxy];
+        lnk[k] = (nx + 1) | ((pv + 1) << 12) | (pv < 0 ? 1 << 24 : 0);
+        zl[k] = dg[u];
+        fe[k] = (float)t;  // the link's T until the factorisation replaces it by t / p
+    }
+    rhs2 = block_allsum(rhs2, red);  // its barriers publish pl, zl, fe and lnk
+    const bool anchored = block_allsum(nb, red) > 0.0;
+    auto next_of = [&](int k) { return (lnk[k] & 0xfff) - 1; };
+    auto prev_of = [&](int k) { return ((lnk[k] >> 12) & 0xfff) - 1; };
+    // factor every chain (zl holds d, fe the link T)
+#pragma unroll
+    for (int u = 0; u < kFvOwn; ++u) {
+        const int k = threadIdx.x + u * kFvThreads;
+        if (k >= n || !(lnk[k] >> 24)) continue;
+        double pprev = 0.0, tprev = 0.0;
+        for (int kk = k; kk >= 0; kk = next_of(kk)) {
+            const double d = zl[kk], t = fe[kk];
+            const double p = (1.0 + 0x1p-10) * d - (pprev > 0.0 ? tprev * tprev / pprev : 0.0);
+            const double ip = p > 0.0 ? 1.0 / p : 0.0;
+            fip[kk] = (float)ip;
+            fe[kk] = (float)(t * ip);
+            pprev = p;
+            tprev = t;
+        }
+    }
+    __syncthreads();
+    // z = M^-1 r in zl (the owners wrote r there): forward y_k = r_k +
+    // (t/p)_{k-1} y_{k-1}, w_k = y_k / p_k; backward z_k = w_k + (t/p)_k z_{k+1}
+    auto precond = [&]() {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k >= n || !(lnk[k] >> 24)) continue;
+            double y = 0.0, eprev = 0.0;
+            int tail = k;
+            for (int kk = k; kk >= 0; kk = next_of(kk)) {
+                y = zl[kk] + eprev * y;
+                zl[kk] = y * (double)fip[kk];
+                eprev = (double)fe[kk];
+                tail = kk;
+            }
+            double z = 0.0;
+            for (int kk = tail; kk >= 0; kk = prev_of(kk)) {
+                z = zl[kk] + (double)fe[kk] * z;
+                zl[kk] = z;
+            }
+        }
+        __syncthreads();
+    };
+    double rz = 0.0, rr = 0.0;
+    // after rv holds a residual: zero block sum if unanchored, z = M^-1 r,
+    // rz = (r, z), rr = (r, r)
+    auto finish_residual = [&]() {
+        if (!anchored) {
+            double sum = 0.0;
+#pragma unroll
+            for (int u = 0; u < kFvOwn; ++u) sum += threadIdx.x + u * kFvThreads < n ? rv[u] : 0.0;
+            const double mean = block_allsum(sum, red) / n;
+#pragma unroll
+            for (int u = 0; u < kFvOwn; ++u) rv[u] -= mean;
+        }
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k < n) zl[k] = rv[u];
+        }
+        precond();
+        double rzt = 0.0, rrt = 0.0;
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k >= n) continue;
+            rzt += rv[u] * zl[k];
+            rrt += rv[u] * rv[u];
+        }
+        rz = block_allsum(rzt, red);
+        rr = block_allsum(rrt, red);
+    };
+    // r = rhs - A x, p = z (pl holds x = p_ms)
+    auto true_residual = [&]() {
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k < n) rv[u] = rh[u] - apply(ci[u], dg[u], pl[k]);
+        }
+        finish_residual();  // every read of pl above came before its barriers
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k < n) pl[k] = zl[k];
+        }
+        __syncthreads();
+    };
+    true_residual();
+    const double stop2 = rtol * rtol * rhs2;
+    int it = 0;
+    double prev = INFINITY;
+    for (;;) {
+        if (rr <= stop2) {
+            __syncthreads();  // every read of pl of the step is done
+#pragma unroll
+            for (int u = 0; u < kFvOwn; ++u) {
+                const int k = threadIdx.x + u * kFvThreads;
+                if (k < n) pl[k] = xr[u];
+            }
+            __syncthreads();
+            true_residual();
+            if (rr <= stop2 || rr > 0.25 * prev) break;
+            prev = rr;
+        }
+        if (!(it < max_iters && rz > 0.0)) break;
+        double pq = 0.0, qv[kFvOwn];
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            qv[u] = 0.0;
+            if (k >= n) continue;
+            qv[u] = apply(ci[u], dg[u], pl[k]);
+            pq += pl[k] * qv[u];
+        }
+        pq = block_allsum(pq, red);
+        if (!(pq > 0.0)) break;
+        const double alpha = rz / pq;
+        double rrn = 0.0;
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k >= n) continue;
+            xr[u] += alpha * pl[k];
+            rv[u] -= alpha * qv[u];
+            rrn += rv[u] * rv[u];
+            zl[k] = rv[u];
+        }
+        rr = block_allsum(rrn, red);  // every read of pl in this step came before these barriers
+        precond();
+        double rzn = 0.0;
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k < n) rzn += rv[u] * zl[k];
+        }
+        rzn = block_allsum(rzn, red);
+        const double beta = rzn / rz;
+        rz = rzn;
+#pragma unroll
+        for (int u = 0; u < kFvOwn; ++u) {
+            const int k = threadIdx.x + u * kFvThreads;
+            if (k < n) pl[k] = zl[k] + beta * pl[k];
+        }
+        __syncthreads();  // the new direction is visible before the next step reads it
+        ++it;
+    }
+#pragma unroll
+    for (int u = 0; u < kFvOwn; ++u)
+        if (threadIdx.x + u * kFvThreads < n) xout[ci[u]] = xr[u];
+    if (threadIdx.x == 0) atomicMax(iters_max, it);
+}
+
 // Face fluxes of the reconstruction (layout of msrsb_fluxes): inside a block
 // from p', between blocks from p_ms.
 __global__ void k_fv_faces(Fine g, const int32_t *__restrict__ fvblock, const double *__restrict__ pms,
@@ -365,6 +618,12 @@ void launch_fv_restrict(Ctx &c, Stage &s, const double *b) {
 int launch_fv_local(Ctx &c, Stage &s, const double *pms, double *pf, double rtol, int max_iters, int *iters_max) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     if (s.fv_maxcells > kFvMaxCells) return MSRSB_E_INVAL;
+    if (s.fv_maxcells <= kFvLineCells) {
+        const size_t lds = 28 * (size_t)std::max(s.fv_maxcells, 1);
+        hipLaunchKernelGGL(k_fv_local_line, dim3(s.M), dim3(kFvThreads), lds, c.stream, g, s.fvblock, s.fvptr,
+                           s.fvcells, s.fvloc, c.bcdiag, c.b, pms, pf, rtol, max_iters, iters_max);
+        return MSRSB_OK;
+    }
     const size_t lds = sizeof(double) * (size_t)std::max(s.fv_maxcells, 1);
     hipLaunchKernelGGL(k_fv_local, dim3(s.M), dim3(kFvThreads), lds, c.stream, g, s.fvblock, s.fvptr, s.fvcells,
                        s.fvloc, c.bcdiag, c.b, pms, pf, c.r, c.tmp, rtol, max_iters, iters_max);

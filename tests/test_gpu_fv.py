@@ -55,6 +55,14 @@ FCASES = {
         {"kind": "cartesian", "coarse_dims": (2, 2, 2)},
         {"kind": "graph", "block_of_cell": c.partition_indicator(p, np.log(p.perm), 3, (2, 3, 2), 16),
          "overlap": 2}]),
+    # blocks that are single columns (most of them without a boundary term:
+    # singular Neumann chains) for the z-line preconditioned local solves
+    "columns": (lambda: make_config1(dims=(6, 5, 12), seed=8), lambda c, p: [
+        {"kind": "cartesian", "coarse_dims": (6, 5, 2)}]),
+    # one block of 3,840 cells: above the z-line local solver's 2,304-cell
+    # limit, solved by the Jacobi-preconditioned kernel
+    "large_block": (lambda: make_config1(dims=(24, 20, 8), seed=7), lambda c, p: [
+        {"kind": "cartesian", "coarse_dims": (1, 1, 1)}]),
 }
 
 
