@@ -250,9 +250,11 @@ int msrsb_solve(msrsb_ctx *ctx, const double *d_source, double *d_p, double rtol
  *   d_p = P A_fv^{-1} R_fv b, the multiscale pressure, whose fluxes balance
  *   every block;
  *   inside every block the fine pressure p' solves the block's problem with
- *   the fluxes of d_p imposed on the faces leaving the block (Jacobi-
- *   preconditioned conjugate gradients from p' = d_p, to ||r|| <= local_rtol
- *   ||rhs|| per block or max_local_iters steps);
+ *   the fluxes of d_p imposed on the faces leaving the block (conjugate
+ *   gradients from p' = d_p, to ||r|| <= local_rtol ||rhs|| per block or
+ *   max_local_iters steps; preconditioned by tridiagonal solves along the
+ *   block's z lines for blocks of at most 2304 cells, by the diagonal for
+ *   larger ones);
  *   d_face_flux [3N] (layout of msrsb_fluxes): T (p'_a - p'_b) on faces
  *   inside a block, T (p_a - p_b) on faces between blocks; d_bc_flux
  *   [n_bc] (may be NULL): bc_trans (p'_i - bc_value) from p'.
