@@ -629,6 +629,10 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
         return MSRSB_E_NOMEM;
     s.xslot = (uint8_t *)ctx_alloc(c, std::max<size_t>(slot.size(), 1));
     if (!s.xslot || !upload(c, s.xslot, slot.data(), slot.size())) return MSRSB_E_NOMEM;
+    s.xcnt = (uint8_t *)ctx_alloc(c, (size_t)N);
+    s.xnmap = (uint8_t *)ctx_alloc(c, (size_t)6 * ns * N);
+    if (!s.xcnt || !s.xnmap) return MSRSB_E_NOMEM;
+    launch_xmap_build(c, s);
     // chunk tables of the support lists
     std::vector<int32_t> cblk, cfirst(M + 1), rcblk, rcfirst(M + 1), rrow;
     int nrow = 0;
@@ -1241,6 +1245,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             const long Mp = cdiv(M, kTile) * kTile;
             const size_t nsN = (size_t)8 * N;
             b += (o.precision == MSRSB_MIXED ? nsN * 10 : nsN * 16) + nsN * 9 + N * 4 + 16 * (size_t)Mp * Mp + 16 * Mp;
+            b += 6 * nsN + N;  // neighbour slot maps
             b += (2 * nsN / kXRapChunk + 1) * (size_t)Mp * 8 + (nsN / kXChunk + M) * 8;  // chunk partials
             cb = std::max(cb, Mp);
             continue;
@@ -1250,6 +1255,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
         if (parts[k].kind == MSRSB_PART_FAULT_CUT) {
             const long Mf = 2L * pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
             b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
+            b += (size_t)6 * 16 * N + N;  // neighbour slot maps
             b += (2 * 16 * N / kXRapChunk + 1) * (size_t)cdiv(Mf, kTile) * kTile * 8 + (16 * N / kXChunk + Mf) * 8;
         }
         long M = (long)pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];

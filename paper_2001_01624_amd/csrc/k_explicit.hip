@@ -20,10 +20,53 @@ __global__ void k_xinit(int N, int ns, const int32_t *__restrict__ sb, const int
     for (int s = 0; s < ns; ++s) P[(long)s * N + i] = (own >= 0 && sb[(long)s * N + i] == own) ? (PT)1 : (PT)0;
 }
 
+// Neighbour slot maps (once per stage; the structure does not change): the
+// slot count of every cell, and for face q (axis q/2, +/- as q%2) and slot s
+// of cell i the slot of the same block in the face neighbour's list, or 255.
+__global__ void k_xmap_build(Fine g, int ns, const int32_t *__restrict__ sb, uint8_t *__restrict__ cnt,
+                             uint8_t *__restrict__ map) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    const long N = g.N;
+    int c = 0;
+    for (int s = 0; s < ns; ++s)
+        if (sb[s * N + i] >= 0) c = s + 1;
+    cnt[i] = (uint8_t)c;
+    for (int q = 0; q < 6; ++q) {
+        const int a = q >> 1;
+        const int step = a == 0 ? 1 : (a == 1 ? g.nx : g.nxy);
+        const int l = (q & 1) ? i + step : i - step;
+        const bool in = (q & 1) ? l < g.N : i >= step;
+        for (int s = 0; s < ns; ++s) {
+            int u = 255;
+            if (in && s < c) {
+                const int bo = sb[s * N + i];
+                for (int t = 0; t < ns; ++t) {
+                    const int bl = sb[t * N + l];
+                    if (bl < 0) break;
+                    if (bl == bo) {
+                        u = t;
+                        break;
+                    }
+                }
+            }
+            map[(size_t)(q * ns + s) * N + i] = (uint8_t)u;
+        }
+    }
+}
+
+void launch_xmap_build(Ctx &c, Stage &s) {
+    Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
+    hipLaunchKernelGGL(k_xmap_build, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, s.ns, s.xsb, s.xcnt,
+                       s.xnmap);
+}
+
 // One restricted-smoothing sweep (same definition as the rectilinear one):
-// the neighbour's value of block j is found by comparing slot lists.
+// the neighbour's value of block j is read at the slot the neighbour slot map
+// gives (each face adds to a slot at most once, faces in a fixed order).
 template <int NSX, typename PT>
-__global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t *__restrict__ sb,
+__global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const uint8_t *__restrict__ cntv,
+                                                   const uint8_t *__restrict__ nmap,
                                                    const PT *__restrict__ tx, const PT *__restrict__ ty,
                                                    const PT *__restrict__ tz, const PT *__restrict__ Pin,
                                                    PT *__restrict__ Pout, PT omega, double *__restrict__ part,
@@ -34,11 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t
     double chg = 0.0;
     if (i < g.N) {
         const long N = g.N;
-        int bi[NSX];
+        const int cn = cntv[i];
         PT p[NSX], acc[NSX];
 #pragma unroll
         for (int s = 0; s < NSX; ++s) {
-            bi[s] = s < ns ? sb[s * N + i] : -1;
             p[s] = s < ns ? Pin[s * N + i] : (PT)0;
             acc[s] = (PT)0;
         }
@@ -64,13 +106,12 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t
                 }
                 if (T == (PT)0) continue;
                 db += T;
-                for (int t = 0; t < ns; ++t) {
-                    const int bl = sb[t * N + l];
-                    if (bl < 0) break;
-                    const PT v = Pin[t * N + l];
+                const uint8_t *mq = nmap + (size_t)q * ns * N + i;
 #pragma unroll
-                    for (int s = 0; s < NSX; ++s)
-                        if (bi[s] == bl) acc[s] += T * v;
+                for (int s = 0; s < NSX; ++s) {
+                    if (s >= cn) break;
+                    const int u = mq[(size_t)s * N];
+                    if (u != 255) acc[s] += T * Pin[u * N + l];
                 }
             }
             const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
@@ -79,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const int32_t
 #pragma unroll
             for (int s = 0; s < NSX; ++s) {
                 PT v = (PT)0;
-                if (bi[s] >= 0) v = db > (PT)0 ? p[s] - omega * (p[s] - acc[s] * idb) : p[s];
+                if (s < cn) v = db > (PT)0 ? p[s] - omega * (p[s] - acc[s] * idb) : p[s];
                 pn[s] = v;
                 rs += v;
             }
@@ -111,13 +152,13 @@ static int xsweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const P
     const int *done = &c.status->done;
     double *part = c.partial;
     if (s.ns <= 8)
-        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, part,
+        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out, om, part,
                            c.flag, done);
     else if (s.ns <= 16)
-        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out, om, part,
+        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out, om, part,
                            c.flag, done);
     else
-        hipLaunchKernelGGL((k_xsweep<kMaxXSlots, PT>), grid, blk, 0, c.stream, g, s.ns, s.xsb, tx, ty, tz, in, out,
+        hipLaunchKernelGGL((k_xsweep<kMaxXSlots, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out,
                            om, part, c.flag, done);
     return (int)grid.x;
 }

@@ -85,6 +85,9 @@ struct Stage {
     // per-block support lists (cells ascending, with the block's slot there)
     int parent = -1;
     int32_t *xsb = nullptr, *xpblock = nullptr, *xptr = nullptr, *xcell = nullptr;
+    // per cell: its slot count, and for each of its six faces and each of its
+    // slots the slot of the same block in the face neighbour's list (255: none)
+    uint8_t *xcnt = nullptr, *xnmap = nullptr;
     uint8_t *xslot = nullptr;
     // the support lists cut into chunks of at most kXChunk entries (restriction)
     // and kXRapChunk entries (Galerkin rows): block of each chunk, first chunk
@@ -267,6 +270,7 @@ void launch_coarse_solve(Ctx &c, Stage &s, const int *done);
 
 // ---- explicit-slot stage kernels (k_explicit.hip) ----
 void launch_xinit(Ctx &c, Stage &s);
+void launch_xmap_build(Ctx &c, Stage &s);
 int launch_xsweep(Ctx &c, Stage &s, int in, int out);
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done);
 void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done);
