@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--kernel", default="restrict_rows",
-                    help="kernel class of the roofline object (the largest share of kernel time by default)")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel class of the roofline object; auto: the single-kernel class with the largest "
+                         "time per request, from the kernel table taken before the timed steps")
     ap.add_argument("--no-table", action="store_true", help="skip the per-class kernel table")
     ap.add_argument("--smoother", default="ilu0_line", choices=["ilu0_line", "ilu0_rb", "jacobi"],
                     help="fine-scale smoother of every GPU leg and of the oracle baseline")
@@ -174,9 +175,18 @@ def gpu_leg(args, precision):
 
     for _ in range(args.warmup):
         step()
+    n_act = prob.n_active
+    ns = 8
+    # per-class kernel times (untimed requests), and the roofline's class
+    table = None if args.no_table else kernel_table(g, step, ns, precision, n_act, args.smoother)
+    roof_class = args.kernel
+    if roof_class == "auto":
+        cand = table if table is not None else kernel_table(g, step, ns, precision, n_act, args.smoother,
+                                                            ROOF_CANDIDATES)
+        roof_class = max(ROOF_CANDIDATES, key=lambda c: cand[c]["ms_per_request"])
     torch.cuda.synchronize()
     recs = []
-    g.profile_begin(args.kernel, 200000)
+    g.profile_begin(roof_class, 200000)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         recs.append(step())
@@ -190,11 +200,8 @@ def gpu_leg(args, precision):
         b.copy_(a)
         torch.cuda.synchronize()
     ms = sorted(rec["ms"] for rec in recs)
-    n_act = prob.n_active
     cells = 3 * n_act * args.steps
-    ns = 8
-    roof = roofline(args.kernel, ns, precision, n_act, kern_ms, launches, args.smoother)
-    table = None if args.no_table else kernel_table(g, step, ns, precision, n_act, args.smoother)
+    roof = roofline(roof_class, ns, precision, n_act, kern_ms, launches, args.smoother)
     out = {
         "value": cells / wall,
         "ms_per_step": 1e3 * wall / args.steps,
@@ -240,12 +247,17 @@ TABLE_CLASSES = ("restrict_rows", "restrict", "sweep", "prolong", "smooth", "res
                  "rap", "inverse")
 
 
-def kernel_table(g, step, ns, precision, n_act, smoother):
+# single-kernel classes the roofline object may name (the fine-grid passes of
+# the basis construction and of the multistage cycle)
+ROOF_CANDIDATES = ("sweep", "restrict_rows", "prolong", "residual")
+
+
+def kernel_table(g, step, ns, precision, n_act, smoother, classes=None):
     """One extra (untimed) request per kernel class, that class's launches
     bracketed by HIP events: launches and milliseconds per request, average
     launch, and achieved bandwidth where the algorithmic bytes are known."""
     out = {}
-    for cls in TABLE_CLASSES:
+    for cls in classes or TABLE_CLASSES:
         g.profile_begin(cls, 200000)
         step()
         ms, n = g.profile_end()
