@@ -38,16 +38,17 @@ def small_requests(n=6, seed=0, min_sources=1):
     return reqs
 
 
-@pytest.mark.parametrize("precision,slots", [("fp64", 4), ("fp64", 8), ("mixed", 8)])
-def test_alone_equals_mixed(mods, precision, slots):
+@pytest.mark.parametrize("precision,slots,smoother", [("fp64", 4, "ilu0_rb"), ("fp64", 8, "ilu0_rb"),
+                                                      ("mixed", 8, "ilu0_rb"), ("mixed", 8, "ilu0_line")])
+def test_alone_equals_mixed(mods, precision, slots, smoother):
     # each request alone on one slot, then all of them at once on `slots`
     # slots: every request has at least three solves, so its last solves run
     # with dynamic stages built from its own increments; every reduction has a
     # fixed order, so each solution is bit for bit the same in the mix
     capi, serve = mods
     a, b = small_requests(n=10, min_sources=3), small_requests(n=10, min_sources=3)
-    opt = capi.default_options(smoother="ilu0_rb", outer="gmres", precision=precision)
-    print(precision, slots, "requests", [(r.kind, len(r.sources)) for r in a], flush=True)
+    opt = capi.default_options(smoother=smoother, outer="gmres", precision=precision)
+    print(precision, slots, smoother, "requests", [(r.kind, len(r.sources)) for r in a], flush=True)
     serve.Server(slots=1, options=opt, keep_solutions=True).run(a, realtime=False)
     st = serve.Server(slots=slots, options=opt, keep_solutions=True).run(b, realtime=False)
     assert st["completed"] == len(b) and st["all_converged"]

@@ -60,14 +60,14 @@ CASES = {
 }
 
 
-def setup(capi, name, sweeps=3, dt=20.0, seed=0):
+def setup(capi, name, sweeps=3, dt=20.0, seed=0, smoother="ilu0_rb"):
     mk, cd = CASES[name]
     prob = mk()
     parts = [{"kind": "cartesian", "coarse_dims": cd}]
     pv = pore_volume(prob)
-    g = capi.Solver(prob, parts, capi.default_options(smoother="ilu0_rb", outer="gmres"))
+    g = capi.Solver(prob, parts, capi.default_options(smoother=smoother, outer="gmres"))
     g.update_basis(max_sweeps=20, tol=0.0)
-    o = O.Oracle(prob, parts, smoother="ilu0_rb")
+    o = O.Oracle(prob, parts, smoother=smoother)
     o.update_basis(max_sweeps=20, tol=0.0)
     tp = capi.TwoPhase(g, pv, FLUID, restart=30)
     rng = np.random.default_rng(seed)
@@ -78,9 +78,10 @@ def setup(capi, name, sweeps=3, dt=20.0, seed=0):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_residual_jacobian_and_cpr(capi, name):
-    prob, pv, g, o, tp, p, s, s_old = setup(capi, name)
-    say(f"two-phase {name} dims={prob.dims}")
+@pytest.mark.parametrize("smoother", ["ilu0_rb", "ilu0_line"])
+def test_residual_jacobian_and_cpr(capi, name, smoother):
+    prob, pv, g, o, tp, p, s, s_old = setup(capi, name, smoother=smoother)
+    say(f"two-phase {name} dims={prob.dims} pressure smoother {smoother}")
     N = prob.n_cells
     res = torch.empty(2 * N, dtype=torch.float64, device="cuda")
     nr = tp.assemble(20.0, dev(p), dev(s), dev(s_old), basis_sweeps=3, res=res)
