@@ -426,8 +426,8 @@ def indicator(block_local, M):
 
 # ---------------------------------------------------------------------------
 # Restricted-smoothing basis (MsRSB, cited in section "Multiscale methods";
-# "iterating a few times extra" for local updates, subsection "Iterative
-# multiscale multibasis solver").
+# local updates by a few extra iterations, subsection "Iterative multiscale
+# multibasis solver").
 # ---------------------------------------------------------------------------
 
 def msrsb_basis(Ab, block_local, S, omega=2.0 / 3.0, tol=1e-3, max_sweeps=100, P0=None):
