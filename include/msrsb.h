@@ -272,6 +272,32 @@ int msrsb_solve_fv(msrsb_ctx *ctx, int stage, const double *d_source, double *d_
                    double *max_imbalance);
 
 /*
+ * Asynchronous solve (eq. iterative_multiscale: the multistage cycle as a
+ * stationary iteration, whatever the context's outer option): enqueues on
+ * the context's stream, without any host synchronisation, the source update
+ * (d_source device [N] or NULL), the initial residual and max_cycles cycles,
+ * each followed by the residual test; once the test is met (or max_cycles
+ * reached) the remaining enqueued kernels return at once.  d_p (device [N])
+ * holds the guess and receives the iterate; the result is written on the
+ * stream to d_result (device memory, may be NULL) when the enqueued work
+ * ends: status MSRSB_OK or MSRSB_E_NOCONV, the cycles taken and the
+ * relative residual.  The caller synchronises the stream before reading
+ * d_p or d_result.  Returns E_INVAL (bad arguments, max_cycles outside
+ * 1..100000) or E_STATE (no basis yet) at once; launch failures as
+ * E_DEVICE.  Each enqueued cycle is about a dozen kernel launches, so
+ * max_cycles should bound the expected count rather than exceed it
+ * greatly.  The iterates are those of msrsb_solve with the Richardson outer
+ * loop, bit for bit.
+ */
+typedef struct {
+    int32_t status;   /* MSRSB_OK or MSRSB_E_NOCONV */
+    int32_t cycles;   /* cycles taken */
+    double relres;    /* ||b - A p|| / ||b|| of the returned iterate */
+} msrsb_result;
+int msrsb_solve_async(msrsb_ctx *ctx, const double *d_source, double *d_p, double rtol, int max_cycles,
+                      msrsb_result *d_result);
+
+/*
  * Apply one operator of the path to a device vector (for testing single
  * steps; d_in, d_out device [N], distinct):
  *   op 0 RESIDUAL:  d_out = b - A d_in
@@ -436,6 +462,21 @@ void msrsb_tp_destroy(msrsb_tp_ctx *tp);
  *   slo[J], shi[J] (host [m]) first and last cell of the support of block J.
  *   Any pointer may be NULL.  E_INVAL unless 1 <= m <= n.
  */
+/*
+ * msrsb_faces_to_box: face-list input for box grids (the grid described by
+ *   its cell pairs and face transmissibilities, section "Discrete
+ *   equations": two-point fluxes over the faces shared by two cells).  Cells
+ *   are numbered x fastest in an nx x ny x nz box; face f joins cells
+ *   face_cells[2f] < face_cells[2f+1], which must be neighbours along x, y
+ *   or z; face_trans[f] >= 0 and finite.  Writes the structured arrays of
+ *   msrsb_grid: tx, ty, tz (host [N], caller-allocated) with the face's T at
+ *   its lower cell and zero elsewhere.  E_INVAL for a pair that is not a box
+ *   neighbour (grids that are not boxes are not supported), a repeated face,
+ *   a cell outside the box or a negative or non-finite T; the outputs are
+ *   then unspecified.
+ */
+int msrsb_faces_to_box(int32_t nx, int32_t ny, int32_t nz, int32_t n_faces, const int32_t *face_cells,
+                       const double *face_trans, double *tx, double *ty, double *tz);
 int msrsb_validate_grid(const msrsb_grid *grid);
 int msrsb_axis_support(int n, int m, int32_t *lo, int32_t *nv, int32_t *slo, int32_t *shi);
 

@@ -108,6 +108,9 @@ def _load():
         "msrsb_add_dynamic_basis": (I, [VP, I, P(VP), P(I)]),
         "msrsb_clear_dynamic_basis": (I, [VP]),
         "msrsb_solve": (I, [VP, VP, VP, D, I, P(I), P(D)]),
+        "msrsb_solve_async": (I, [VP, VP, VP, D, I, VP]),
+        "msrsb_faces_to_box": (I, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(D), P(D), P(D),
+                                   P(D)]),
         "msrsb_apply": (I, [VP, I, VP, VP]),
         "msrsb_solve_fv": (I, [VP, I, VP, VP, VP, VP, VP, D, I, P(I), P(D)]),
         "msrsb_fluxes": (I, [VP, VP, VP, VP]),
@@ -240,6 +243,22 @@ def axis_support(n: int, m: int):
     return lo, nv, slo, shi
 
 
+def faces_to_box(dims, face_cells, face_trans):
+    """Structured face arrays ``(tx, ty, tz)`` of an ``nx x ny x nz`` box from
+    a face list (``msrsb_faces_to_box``): ``face_cells`` [F, 2] ascending
+    pairs of box neighbours, ``face_trans`` [F]."""
+    nx, ny, nz = (int(d) for d in dims)
+    fc = np.ascontiguousarray(face_cells, dtype=np.int32).reshape(-1)
+    ft = np.ascontiguousarray(face_trans, dtype=np.float64)
+    if fc.size != 2 * ft.size:
+        raise MsrsbError(E_INVAL, "face_cells must hold two cells per face")
+    n = nx * ny * nz
+    t = [np.empty(n, np.float64) for _ in range(3)]
+    _check(_lib.msrsb_faces_to_box(nx, ny, nz, ft.size, _ptr(fc, C.c_int32), _ptr(ft, C.c_double),
+                                   *(_ptr(a, C.c_double) for a in t)))
+    return t[0], t[1], t[2]
+
+
 def partition_wells(prob, wells, radius=0):
     """Well partition (``msrsb_partition_wells``): ``wells`` is a list of
     arrays of box cell indices; returns the block per cell (-1 inactive)."""
@@ -369,6 +388,28 @@ class Solver:
                                      C.byref(rel)),
                     allow=(E_NOCONV,))
         return it.value, rel.value, rc
+
+    def solve_async(self, p, source=None, rtol=1e-6, max_cycles=200, result=None):
+        """Enqueue Richardson cycles on the context's stream without waiting
+        (``msrsb_solve_async``).  ``result`` (a 16-byte uint8 device tensor,
+        allocated when None) receives status, cycles and relative residual;
+        read them with ``read_result`` after synchronising the stream."""
+        import torch
+
+        if result is None:
+            result = torch.zeros(16, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        if result.dtype != torch.uint8 or result.numel() < 16 or not result.is_contiguous():
+            raise MsrsbError(E_INVAL, "result must be a contiguous device tensor of 16 bytes")
+        _check(_lib.msrsb_solve_async(self.h, self._vec(source), self._vec(p), float(rtol), int(max_cycles),
+                                      C.c_void_p(result.data_ptr())))
+        return result
+
+    @staticmethod
+    def read_result(result):
+        """(status, cycles, relres) from a result tensor of ``solve_async``."""
+        b = result.cpu().numpy().tobytes()
+        st, cyc = np.frombuffer(b[:8], dtype=np.int32)
+        return int(st), int(cyc), float(np.frombuffer(b[8:16], dtype=np.float64)[0])
 
     def solve_fv(self, stage=0, source=None, local_rtol=1e-12, max_local_iters=5000, fine=True):
         """Finite-volume multiscale pressure of one stage and conservative

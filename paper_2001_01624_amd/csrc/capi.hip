@@ -1799,6 +1799,84 @@ int msrsb_solve(msrsb_ctx *c, const double *d_source, double *d_p, double rtol, 
     return MSRSB_OK;
 }
 
+__global__ void k_write_result(const Status *st, double rtol, msrsb_result *out) {
+    out->cycles = st->iters;
+    out->relres = st->relres;
+    out->status = st->relres <= rtol ? MSRSB_OK : MSRSB_E_NOCONV;
+}
+
+int msrsb_solve_async(msrsb_ctx *c, const double *d_source, double *d_p, double rtol, int max_cycles,
+                      msrsb_result *d_result) {
+    g_err.clear();
+    if (!c || !d_p || !(rtol >= 0.0) || max_cycles < 1 || max_cycles > 100000) {
+        set_error("bad asynchronous solve arguments");
+        return MSRSB_E_INVAL;
+    }
+    if (!ready(c)) {
+        set_error("solve called before update_basis");
+        return MSRSB_E_STATE;
+    }
+    Ctx &x = *c;
+    if (d_source) launch_source_update(x, d_source);
+    begin_solve(x, x.b, d_p);
+    // the Richardson loop of solve_richardson, every cycle enqueued at once:
+    // after the test is met, `done` turns each later kernel into a no-op
+    launch_residual(x, x.b, d_p, x.r, true, nullptr);
+    launch_norm_finish(x, x.scal, nullptr);
+    launch_check(x, rtol, max_cycles, 0);
+    const int *done = &x.status->done;
+    for (int k = 0; k < max_cycles; ++k) {
+        cycle(x, x.b, d_p, true, done);
+        launch_residual(x, x.b, d_p, x.r, true, done);
+        launch_norm_finish(x, x.scal, done);
+        launch_check(x, rtol, max_cycles, 1);
+    }
+    if (d_result) hipLaunchKernelGGL(k_write_result, dim3(1), dim3(1), 0, x.stream, x.status, rtol, d_result);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "asynchronous solve launches");
+    return MSRSB_OK;
+}
+
+int msrsb_faces_to_box(int32_t nx, int32_t ny, int32_t nz, int32_t n_faces, const int32_t *face_cells,
+                       const double *face_trans, double *tx, double *ty, double *tz) {
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nz < 1 || (long)nx * ny * nz > 0x7fffffffL / 8 || n_faces < 0 ||
+        (n_faces > 0 && (!face_cells || !face_trans)) || !tx || !ty || !tz) {
+        set_error("bad box or face arrays");
+        return MSRSB_E_INVAL;
+    }
+    const long N = (long)nx * ny * nz, nxy = (long)nx * ny;
+    double *T[3] = {tx, ty, tz};
+    for (int a = 0; a < 3; ++a) std::fill(T[a], T[a] + N, 0.0);
+    std::vector<uint8_t> seen((size_t)3 * N, 0);
+    for (int f = 0; f < n_faces; ++f) {
+        const long a = face_cells[2 * (long)f], b = face_cells[2 * (long)f + 1];
+        const double t = face_trans[f];
+        if (a < 0 || b >= N || a >= b) {
+            set_error("face %d: cells (%ld, %ld) not an ascending pair inside the box", f, a, b);
+            return MSRSB_E_INVAL;
+        }
+        int ax = -1;
+        if (b - a == 1 && a % nx + 1 < nx) ax = 0;
+        else if (b - a == nx && (a / nx) % ny + 1 < ny) ax = 1;
+        else if (b - a == nxy) ax = 2;
+        if (ax < 0) {
+            set_error("face %d: cells %ld and %ld are not box neighbours (only box grids are supported)", f, a, b);
+            return MSRSB_E_INVAL;
+        }
+        if (!(t >= 0.0) || !std::isfinite(t)) {
+            set_error("face %d: transmissibility %g is negative or not finite", f, t);
+            return MSRSB_E_INVAL;
+        }
+        if (seen[(size_t)ax * N + a]++) {
+            set_error("face %d: cells %ld and %ld are joined twice", f, a, b);
+            return MSRSB_E_INVAL;
+        }
+        T[ax][a] = t;
+    }
+    return MSRSB_OK;
+}
+
 int msrsb_apply(msrsb_ctx *c, int op, const double *d_in, double *d_out) {
     g_err.clear();
     if (!c || !d_in || !d_out || d_in == d_out) {

@@ -1,8 +1,8 @@
 // Host-side checks of the library's host-only entry points, built with
 // AddressSanitizer and UndefinedBehaviorSanitizer on the host code (see
 // test_host_sanitizer.py): grid validation, rectilinear axis tables, the well
-// and indicator partition builders, footprint estimates and the early error
-// paths of set-up, on seeded random grids and on malformed inputs.  Every
+// and indicator partition builders, face-list conversion, footprint estimates
+// and the early error paths of set-up, on seeded random grids and on malformed inputs.  Every
 // call must return a status (never crash, read out of bounds or overflow);
 // valid inputs must be accepted and malformed ones rejected.
 #include <cmath>
@@ -242,6 +242,55 @@ void check_indicator() {
     }
 }
 
+void check_faces_to_box() {
+    for (int rep = 0; rep < 150; ++rep) {
+        Box b = random_box(9);
+        const int N = b.N(), nx = b.nx, nxy = b.nx * b.ny;
+        std::vector<int32_t> fc;
+        std::vector<double> ft;
+        const std::vector<double> *T[3] = {&b.tx, &b.ty, &b.tz};
+        const int step[3] = {1, nx, nxy};
+        for (int a = 0; a < 3; ++a)
+            for (int i = 0; i < N; ++i)
+                if ((*T[a])[i] != 0.0) {
+                    fc.push_back(i);
+                    fc.push_back(i + step[a]);
+                    ft.push_back((*T[a])[i]);
+                }
+        const int F = (int)ft.size();
+        std::vector<double> tx(N, -1.0), ty(N, -1.0), tz(N, -1.0);
+        EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, F, fc.data(), ft.data(), tx.data(), ty.data(), tz.data()) ==
+               MSRSB_OK);
+        EXPECT(tx == b.tx && ty == b.ty && tz == b.tz);
+        if (F > 0) {  // one defect each
+            const int f = rint_(0, F - 1);
+            std::vector<int32_t> bad = fc;
+            bad[2 * f + 1] = N + rint_(0, 3);
+            EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, F, bad.data(), ft.data(), tx.data(), ty.data(), tz.data()) !=
+                   MSRSB_OK);
+            bad = fc;
+            std::swap(bad[2 * f], bad[2 * f + 1]);
+            EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, F, bad.data(), ft.data(), tx.data(), ty.data(), tz.data()) !=
+                   MSRSB_OK);
+            std::vector<double> badt = ft;
+            badt[f] = -1.0;
+            EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, F, fc.data(), badt.data(), tx.data(), ty.data(), tz.data()) !=
+                   MSRSB_OK);
+            std::vector<int32_t> dup = fc;
+            dup.push_back(fc[2 * f]);
+            dup.push_back(fc[2 * f + 1]);
+            std::vector<double> dupt = ft;
+            dupt.push_back(1.0);
+            EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, F + 1, dup.data(), dupt.data(), tx.data(), ty.data(),
+                                      tz.data()) != MSRSB_OK);
+        }
+        EXPECT(msrsb_faces_to_box(b.nx, b.ny, b.nz, 1, nullptr, ft.data(), tx.data(), ty.data(), tz.data()) !=
+               MSRSB_OK);
+        EXPECT(msrsb_faces_to_box(0, b.ny, b.nz, 0, fc.data(), ft.data(), tx.data(), ty.data(), tz.data()) !=
+               MSRSB_OK);
+    }
+}
+
 void check_footprint_and_setup_errors() {
     for (int rep = 0; rep < 100; ++rep) {
         Box b = random_box(8);
@@ -300,6 +349,7 @@ int main() {
     check_validation();
     check_wells();
     check_indicator();
+    check_faces_to_box();
     check_footprint_and_setup_errors();
     if (g_fail) {
         std::fprintf(stderr, "%d checks failed\n", g_fail);

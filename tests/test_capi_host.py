@@ -201,3 +201,35 @@ def test_partition_builders_reject_bad_input():
         capi.partition_indicator(prob, ind, 4, (2, 2, 1), 0)
     with pytest.raises(capi.MsrsbError):
         capi.partition_indicator(prob, np.zeros(prob.n_cells), 0, (2, 2, 1), 0)
+
+
+# --- face-list input for box grids (msrsb_faces_to_box)
+
+@pytest.mark.parametrize("mk", [lambda: make_config0(3), lambda: make_config2(dims=(9, 11, 6), seed=5),
+                                lambda: make_homogeneous((4, 1, 7))])
+def test_faces_to_box_round_trip(mk):
+    # the oracle's own face enumeration of a model, shuffled, gives back the
+    # model's structured arrays bit for bit
+    from oracle.msrsb import _faces
+
+    prob = mk()
+    a, b, t = _faces(prob)
+    perm = np.random.default_rng(4).permutation(a.size)
+    tx, ty, tz = capi.faces_to_box(prob.dims, np.stack([a, b], axis=1)[perm], t[perm])
+    assert np.array_equal(tx, prob.tx) and np.array_equal(ty, prob.ty) and np.array_equal(tz, prob.tz)
+
+
+def test_faces_to_box_rejects_non_box_faces():
+    dims = (4, 3, 2)
+    ok = [[0, 1], [0, 4], [0, 12]]
+    capi.faces_to_box(dims, ok, [1.0, 2.0, 3.0])
+    for cells, t in (([[3, 4]], [1.0]),      # x "neighbours" across a row end
+                     ([[8, 12]], [1.0]),     # y neighbours across a layer end
+                     ([[0, 2]], [1.0]),      # not adjacent
+                     ([[1, 0]], [1.0]),      # descending pair
+                     ([[0, 24]], [1.0]),     # outside the box
+                     ([[0, 1], [0, 1]], [1.0, 1.0]),  # the same face twice
+                     ([[0, 1]], [-1.0]), ([[0, 1]], [np.nan]), ([[0, 1]], [np.inf])):
+        with pytest.raises(capi.MsrsbError) as ei:
+            capi.faces_to_box(dims, cells, t)
+        assert ei.value.code == capi.E_INVAL

@@ -1,10 +1,12 @@
 """C-ABI boundary through the GPU library: contexts whose device memory comes
-from PyTorch's caching allocator (msrsb_allocator), and transmissibility
-updates with local basis updates in msrsb_update_basis (the subsection
-"Iterative multiscale multibasis solver": bases "updated locally" for
-changing properties by a few extra smoothing iterations) against the oracle
-at fixed sweep counts: basis entries 1e-12, coarse operators 1e-12 relative,
-solves to the tolerance on the oracle's residual of the new operator."""
+from PyTorch's caching allocator (msrsb_allocator); transmissibility updates
+with local basis updates in msrsb_update_basis (the subsection "Iterative
+multiscale multibasis solver": bases brought up to date for changed
+properties by a few extra smoothing iterations) against the oracle at fixed
+sweep counts: basis entries 1e-12, coarse operators 1e-12 relative, solves
+to the tolerance on the oracle's residual of the new operator; and the
+asynchronous solve (msrsb_solve_async) against the synchronous Richardson
+solve, bit for bit."""
 import numpy as np
 import pytest
 
@@ -150,3 +152,47 @@ def test_transmissibility_update_all_stages_from_scratch(capi):
     it, rel, rc = g.solve(p, rtol=1e-10, max_iters=500)
     assert rc == capi.OK and np.linalg.norm(o.residual(host(p))) / np.linalg.norm(o.b) <= 1.0001e-10
     g.close()
+
+
+@pytest.mark.parametrize("outer", ["richardson", "gmres"])
+@pytest.mark.parametrize("smoother", ["ilu0_rb", "ilu0_line"])
+def test_solve_async_equals_richardson(capi, outer, smoother):
+    # msrsb_solve_async enqueues every Richardson cycle at once; its iterates
+    # are those of the synchronous Richardson solve bit for bit, also when the
+    # context's outer option is GMRES
+    prob = make_config1(dims=(20, 24, 8), seed=3)
+    parts = [{"kind": "cartesian", "coarse_dims": (3, 3, 2)}, {"kind": "cartesian", "coarse_dims": (2, 2, 1)}]
+    say(f"async solve, context outer {outer}, smoother {smoother}")
+    ref = capi.Solver(prob, parts, capi.default_options(smoother=smoother, outer="richardson"))
+    g = capi.Solver(prob, parts, capi.default_options(smoother=smoother, outer=outer))
+    for s in (ref, g):
+        s.update_basis(max_sweeps=20, tol=0.0)
+    p1 = dev(np.zeros(prob.n_cells))
+    it, rel, rc = ref.solve(p1, rtol=1e-6, max_iters=400)
+    p2 = dev(np.zeros(prob.n_cells))
+    res = g.solve_async(p2, rtol=1e-6, max_cycles=400)
+    torch.cuda.synchronize()
+    st, cyc, rr = g.read_result(res)
+    say(f"  Richardson cycles {it}, relres {rel:.3e}; async {cyc}, {rr:.3e}")
+    assert st == rc and cyc == it and rr == rel and (rc == capi.OK) == (rel <= 1e-6)
+    assert torch.equal(p1, p2)
+    # a new source and a cycle cap below the count needed: E_NOCONV, the same iterate
+    q = prob.source.copy()
+    q[prob.n_cells // 3] += 0.25
+    p3, p4 = dev(np.zeros(prob.n_cells)), dev(np.zeros(prob.n_cells))
+    it, rel, rc = ref.solve(p3, source=dev(q), rtol=1e-12, max_iters=3)
+    res = g.solve_async(p4, source=dev(q), rtol=1e-12, max_cycles=3)
+    torch.cuda.synchronize()
+    st, cyc, rr = g.read_result(res)
+    assert rc == capi.E_NOCONV and st == capi.E_NOCONV and cyc == it == 3 and rr == rel
+    assert torch.equal(p3, p4)
+    with pytest.raises(capi.MsrsbError) as ei:
+        g.solve_async(p4, max_cycles=0)
+    assert ei.value.code == capi.E_INVAL
+    ref.close()
+    g.close()
+    h = capi.Solver(prob, parts)
+    with pytest.raises(capi.MsrsbError) as ei:
+        h.solve_async(p4)
+    assert ei.value.code == capi.E_STATE
+    h.close()
