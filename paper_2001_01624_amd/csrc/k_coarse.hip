@@ -12,7 +12,8 @@
 //   A[I,K] <- -A[I,K] D^{-1},  A[K,K] <- D^{-1}.
 // D^{-1} of the next pivot block is formed by the workgroup that updates
 // that block, inside the update of the current step, so only the first
-// block inversion is on its own on the critical path.
+// block inversion is on its own on the critical path.  The tile products of
+// the panels and the trailing update run on the FP64 matrix instructions.
 // Each cycle then applies the inverse by a GEMV (one workgroup per row).
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -125,26 +126,35 @@ __device__ inline void gj_invert_lds(double (*M)[kLd], double (*W)[kLd], double 
     }
 }
 
-// acc = X * Y for T x T tiles staged in LDS (X row-major [T][kLd], Y
-// row-major [T][kLd]); thread t computes rows 4 (t / 16) + (0..3), columns
-// 4 (t % 16) + (0..3), summing k = 0..T-1 in order.
-__device__ inline void tile_mm(const double (*X)[kLd], const double (*Y)[kLd], double (&acc)[4][4]) {
-    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+// acc = X * Y for T x T tiles staged in LDS with the FP64 16x16x4 matrix
+// instruction: wavefront w of the four computes the 32 x 32 quadrant at rows
+// 32 (w / 2), columns 32 (w % 2) as 2 x 2 blocks of 16 x 16, summing k in 16
+// steps of 4.  Lane l supplies A[i][k] at i = l % 16, k = l / 16 and B[k][j]
+// at j = l % 16, k = l / 16, and holds entry r of a block's result at row
+// 4 r + l / 16, column l % 16 (mm_row / mm_col below).  One matrix
+// instruction does 16 x 16 x 4 products from two operands per lane, so the
+// LDS traffic per product is an eighth of the 4 x 4 register tiles'.
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int mm_row(int bi, int r) { return 32 * ((threadIdx.x >> 6) >> 1) + 16 * bi + 4 * r + ((threadIdx.x & 63) >> 4); }
+__device__ inline int mm_col(int bj) { return 32 * ((threadIdx.x >> 6) & 1) + 16 * bj + (threadIdx.x & 15); }
+
+__device__ inline void tile_mm_mfma(const double (*X)[kLd], const double (*Y)[kLd], dvec4 (&acc)[2][2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+    const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int k = 0; k < T_; ++k) {
-        double x[4], y[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) x[a] = X[ti + a][k];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) y[b] = Y[k][tj + b];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+    for (int kk = 0; kk < T_; kk += 4) {
+        const double a0 = X[r0 + li][kk + lk], a1 = X[r0 + 16 + li][kk + lk];
+        const double b0 = Y[kk + lk][c0 + li], b1 = Y[kk + lk][c0 + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
 }
 
@@ -197,13 +207,14 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A,
         }
     }
     __syncthreads();
-    double acc[4][4];
-    tile_mm(Ds, Bs, acc);
-    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
+    dvec4 acc[2][2];
+    tile_mm_mfma(Ds, Bs, acc);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) A[(long)(k0 + ti + a) * Mp + c0 + tj + b] = acc[a][b];
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A[(long)(k0 + mm_row(bi, r)) * Mp + c0 + mm_col(bj)] = acc[bi][bj][r];
 }
 
 // Trailing update of step K over all tiles (I, J).  Workgroup 0 takes tile
@@ -242,42 +253,49 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A
         }
         return;
     }
-    const int ti = (threadIdx.x >> 4) * 4, tj = (threadIdx.x & 15) * 4;
-    double old[4][4];
+    double old[2][2][4];
     if (J != K) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) old[a][bb] = A[(long)(r0 + ti + a) * Mp + c0 + tj + bb];
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) old[bi][bj][r] = A[(long)(r0 + mm_row(bi, r)) * Mp + c0 + mm_col(bj)];
     }
     load_tile(Cs, C + (long)r0 * T_, T_);
     if (J == K) load_tile(Bs, Dinv, T_);
     else load_tile(Bs, A + (long)k0 * Mp + c0, Mp);
     __syncthreads();
-    double acc[4][4];
-    tile_mm(Cs, Bs, acc);
+    dvec4 acc[2][2];
+    tile_mm_mfma(Cs, Bs, acc);
     if (J == K) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) A[(long)(r0 + ti + a) * Mp + c0 + tj + bb] = -acc[a][bb];
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) A[(long)(r0 + mm_row(bi, r)) * Mp + c0 + mm_col(bj)] = -acc[bi][bj][r];
         return;
     }
-    double nv[4][4];
+    double nv[2][2][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-            nv[a][bb] = old[a][bb] - acc[a][bb];
-            if (I != L || J != L) A[(long)(r0 + ti + a) * Mp + c0 + tj + bb] = nv[a][bb];
-        }
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                nv[bi][bj][r] = old[bi][bj][r] - acc[bi][bj][r];
+                if (I != L || J != L) A[(long)(r0 + mm_row(bi, r)) * Mp + c0 + mm_col(bj)] = nv[bi][bj][r];
+            }
     if (I == L && J == L) {
         // the next pivot block: stage the updated tile and invert it
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) Cs[ti + a][tj + bb] = nv[a][bb];
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Cs[mm_row(bi, r)][mm_col(bj)] = nv[bi][bj][r];
         __syncthreads();
         gj_invert_lds(Cs, Bs, reinterpret_cast<double (*)[17]>(&Bs[16][0]), flag, general);
         for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dnext[e] = Cs[e / T_][e % T_];
