@@ -2,6 +2,7 @@
 // partitions (integer tables, built once on the host and uploaded), the
 // solver drivers and every extern "C" entry point of msrsb.h.
 #include <algorithm>
+#include <cfloat>
 #include <mutex>
 #include <cmath>
 #include <cstdarg>
@@ -176,31 +177,71 @@ static int validate(const msrsb_grid *g) {
     auto act = [&](int i) { return g->active ? g->active[i] != 0 : true; };
     const double *T[3] = {g->tx, g->ty, g->tz};
     const int step[3] = {1, nx, nxy};
-    for (int i = 0; i < N; ++i) {
-        const int c[3] = {i % nx, (i / nx) % ny, i / nxy};
-        const int n[3] = {nx, ny, nz};
-        for (int a = 0; a < 3; ++a) {
-            const double t = T[a][i];
-            if (!(t >= 0.0) || !std::isfinite(t)) {
-                set_error("transmissibility %c[%d] = %g is negative or not finite", "xyz"[a], i, t);
-                return MSRSB_E_INVAL;
-            }
-            if (t != 0.0) {
-                if (c[a] == n[a] - 1) {
-                    set_error("face %c[%d] leaves the grid", "xyz"[a], i);
-                    return MSRSB_E_INVAL;
+    // One branch-light pass decides whether the per-cell checks below can find
+    // anything, and whether the grid is a full box (every cell active, every
+    // interior face with T > 0: one connected component).  Only a grid that
+    // fails it is walked again by the checks that name the first error.
+    bool bad = false, full = true;
+    {
+        const uint8_t *A = g->active;
+        const double *X = g->tx, *Y = g->ty, *Z = g->tz, *Q = g->source;
+        for (int z = 0, i = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x, ++i) {
+                    const double t0 = X[i], t1 = Y[i], t2 = Z[i];
+                    bad |= !(t0 >= 0.0 && t0 <= DBL_MAX) || !(t1 >= 0.0 && t1 <= DBL_MAX) ||
+                           !(t2 >= 0.0 && t2 <= DBL_MAX);
+                    if (Q) bad |= !std::isfinite(Q[i]);
+                    const bool ai = A ? A[i] != 0 : true;
+                    full &= ai;
+                    if (x + 1 < nx) {
+                        full &= t0 > 0.0;
+                        bad |= t0 != 0.0 && !(ai && (A ? A[i + 1] != 0 : true));
+                    } else {
+                        bad |= t0 != 0.0;
+                    }
+                    if (y + 1 < ny) {
+                        full &= t1 > 0.0;
+                        bad |= t1 != 0.0 && !(ai && (A ? A[i + nx] != 0 : true));
+                    } else {
+                        bad |= t1 != 0.0;
+                    }
+                    if (z + 1 < nz) {
+                        full &= t2 > 0.0;
+                        bad |= t2 != 0.0 && !(ai && (A ? A[i + nxy] != 0 : true));
+                    } else {
+                        bad |= t2 != 0.0;
+                    }
                 }
-                if (!act(i) || !act(i + step[a])) {
-                    set_error("face %c[%d] touches an inactive cell", "xyz"[a], i);
-                    return MSRSB_E_INVAL;
-                }
-            }
-        }
-        if (g->source && !std::isfinite(g->source[i])) {
-            set_error("source[%d] not finite", i);
-            return MSRSB_E_INVAL;
-        }
     }
+    // cells in index order (x fastest), coordinates carried by the loops
+    for (int z = 0, i = 0; bad && z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x, ++i) {
+                const int c[3] = {x, y, z};
+                const int n[3] = {nx, ny, nz};
+                for (int a = 0; a < 3; ++a) {
+                    const double t = T[a][i];
+                    if (!(t >= 0.0) || !std::isfinite(t)) {
+                        set_error("transmissibility %c[%d] = %g is negative or not finite", "xyz"[a], i, t);
+                        return MSRSB_E_INVAL;
+                    }
+                    if (t != 0.0) {
+                        if (c[a] == n[a] - 1) {
+                            set_error("face %c[%d] leaves the grid", "xyz"[a], i);
+                            return MSRSB_E_INVAL;
+                        }
+                        if (!act(i) || !act(i + step[a])) {
+                            set_error("face %c[%d] touches an inactive cell", "xyz"[a], i);
+                            return MSRSB_E_INVAL;
+                        }
+                    }
+                }
+                if (g->source && !std::isfinite(g->source[i])) {
+                    set_error("source[%d] not finite", i);
+                    return MSRSB_E_INVAL;
+                }
+            }
     if (g->n_bc < 0 || (g->n_bc > 0 && (!g->bc_cell || !g->bc_trans || !g->bc_value))) {
         set_error("bad boundary-connection arrays");
         return MSRSB_E_INVAL;
@@ -216,16 +257,40 @@ static int validate(const msrsb_grid *g) {
             return MSRSB_E_INVAL;
         }
     }
-    // every active connected component needs a boundary/well connection
-    DSU d(N);
-    for (int a = 0; a < 3; ++a)
-        for (int i = 0; i < N; ++i)
-            if (T[a][i] != 0.0) d.unite(i, i + step[a]);
-    std::vector<char> anchored(N, 0);
+    // every active connected component needs a boundary/well connection:
+    // breadth-first search over the faces with T > 0 from every cell with a
+    // connection of positive T; the first active cell left unreached (in index
+    // order) is reported.  A full box is one component: one connection of
+    // positive T anchors it.
+    if (full) {
+        for (int k = 0; k < g->n_bc; ++k)
+            if (g->bc_trans[k] > 0.0) return MSRSB_OK;
+        set_error("active cell %d lies in a connected component without boundary or well connection", 0);
+        return MSRSB_E_SINGULAR;
+    }
+    std::vector<uint8_t> seen(N, 0);
+    std::vector<int> queue;
+    queue.reserve(N);
     for (int k = 0; k < g->n_bc; ++k)
-        if (g->bc_trans[k] > 0.0) anchored[d.find(g->bc_cell[k])] = 1;
+        if (g->bc_trans[k] > 0.0 && !seen[g->bc_cell[k]]) {
+            seen[g->bc_cell[k]] = 1;
+            queue.push_back(g->bc_cell[k]);
+        }
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int i = queue[h];
+        for (int a = 0; a < 3; ++a) {
+            if (T[a][i] != 0.0 && !seen[i + step[a]]) {
+                seen[i + step[a]] = 1;
+                queue.push_back(i + step[a]);
+            }
+            if (i >= step[a] && T[a][i - step[a]] != 0.0 && !seen[i - step[a]]) {
+                seen[i - step[a]] = 1;
+                queue.push_back(i - step[a]);
+            }
+        }
+    }
     for (int i = 0; i < N; ++i)
-        if (act(i) && !anchored[d.find(i)]) {
+        if (act(i) && !seen[i]) {
             set_error("active cell %d lies in a connected component without boundary or well connection", i);
             return MSRSB_E_SINGULAR;
         }
