@@ -48,7 +48,7 @@ class Server:
         self.torch = torch
         self.slots = slots
         self.budget = int(hbm_budget)
-        self.options = options if options is not None else capi.default_options(smoother="ilu0_rb", outer="gmres")
+        self.options = options if options is not None else capi.default_options(smoother="ilu0_line", outer="gmres")
         self.rtol, self.max_iters = rtol, max_iters
         self.max_sweeps, self.basis_tol = max_sweeps, basis_tol
         self.keep = keep_solutions
