@@ -298,6 +298,52 @@ int msrsb_solve_async(msrsb_ctx *ctx, const double *d_source, double *d_p, doubl
                       msrsb_result *d_result);
 
 /*
+ * Ensemble batch: many independent contexts (the realisations of an
+ * ensemble, each its own grid and operator) driven in lockstep, with one
+ * kernel launch per step of the path over all members.  Every step is the
+ * same computation as in the member's own calls (the paper's restricted
+ * smoothing of "Iterative multiscale multibasis solver", the multistage
+ * cycle of eq. multiscale-multibasis, GMRES), so each member's bases,
+ * iterates, iteration counts and residuals are those of msrsb_update_basis
+ * and msrsb_solve on that member alone, bit for bit; the batch only removes
+ * the per-member launches that dominate small grids.
+ *
+ * msrsb_batch_create: members[0..n) (host array of n >= 1 distinct contexts,
+ * 1 <= n <= 65536) are borrowed, not owned: they must outlive the batch and
+ * must not be used on their own while a batch call runs.  Every member must
+ * be on the current device with one rectilinear partition (kind CARTESIAN,
+ * no dynamic stages), the GMRES outer loop with restart <= 31, the z-line
+ * ILU(0) smoother with columns of at most 512 cells, and the same
+ * precision, omega and restart as the others.  The members' streams are
+ * switched to `hip_stream` (hipStream_t, NULL = null stream; each member's
+ * old stream is synchronised first) and stay on it.  Errors: E_INVAL (with
+ * the offending member in the message), E_NOMEM, E_DEVICE.
+ *
+ * msrsb_batch_update_basis: builds every member's basis from scratch (up to
+ * max_sweeps sweeps each, member-wise stop at tol as in msrsb_update_basis
+ * with warm = 0), then its Galerkin operator and coarse inverse.  sweeps
+ * (host int32[n], may be NULL) receives the sweeps each member took.
+ * Errors as msrsb_update_basis (E_SINGULAR names the first failing member).
+ *
+ * msrsb_batch_solve: for every member k, solves with source d_source[k]
+ * (device [N_k]; a NULL array or entry keeps that member's current source)
+ * from the guess in d_p[k] (device [N_k], receives the solution) to rtol
+ * within max_iters iterations.  iters, relres and status (host arrays of n,
+ * each may be NULL) receive each member's iteration count, final relative
+ * residual and status (MSRSB_OK or MSRSB_E_NOCONV).  Returns MSRSB_OK when
+ * every member converged, E_NOCONV when some did not (the others hold their
+ * solutions), E_STATE before msrsb_batch_update_basis, E_INVAL, E_DEVICE.
+ *
+ * msrsb_batch_destroy frees the batch's own tables (not the members).
+ */
+typedef struct msrsb_batch msrsb_batch;
+int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb_batch **out);
+int msrsb_batch_update_basis(msrsb_batch *batch, int max_sweeps, double tol, int32_t *sweeps);
+int msrsb_batch_solve(msrsb_batch *batch, const double *const *d_source, double *const *d_p, double rtol,
+                      int max_iters, int32_t *iters, double *relres, int32_t *status);
+void msrsb_batch_destroy(msrsb_batch *batch);
+
+/*
  * Apply one operator of the path to a device vector (for testing single
  * steps; d_in, d_out device [N], distinct):
  *   op 0 RESIDUAL:  d_out = b - A d_in

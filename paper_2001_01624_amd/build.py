@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsrsb.so")
-SOURCES = ["capi.hip", "k_fine.hip", "k_sweep.hip", "k_transfer.hip", "k_coarse.hip", "k_dyn.hip", "k_explicit.hip", "k_fv.hip", "k_twophase.hip", "tp_capi.hip", "k_lineilu.hip"]
+SOURCES = ["capi.hip", "k_fine.hip", "k_sweep.hip", "k_transfer.hip", "k_coarse.hip", "k_dyn.hip", "k_explicit.hip", "k_fv.hip", "k_twophase.hip", "tp_capi.hip", "k_lineilu.hip", "batch.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -131,6 +131,10 @@ def _load():
         "msrsb_tp_solve": (I, [VP, VP, D, I, P(I), P(D)]),
         "msrsb_tp_update": (I, [VP, VP, VP, VP]),
         "msrsb_tp_destroy": (None, [VP]),
+        "msrsb_batch_create": (I, [I, P(VP), VP, P(VP)]),
+        "msrsb_batch_update_basis": (I, [VP, I, D, P(C.c_int32)]),
+        "msrsb_batch_solve": (I, [VP, P(VP), P(VP), D, I, P(C.c_int32), P(D), P(C.c_int32)]),
+        "msrsb_batch_destroy": (None, [VP]),
         "msrsb_profile_begin": (I, [VP, I, I]),
         "msrsb_profile_end": (I, [VP, P(D), P(I)]),
     }
@@ -499,6 +503,64 @@ class Solver:
             m = blk >= 0
             P[np.nonzero(m)[0], blk[m]] += e["values"][s][m]
         return P
+
+
+class Batch:
+    """Ensemble batch over several ``Solver`` contexts (``msrsb_batch_*``):
+    one launch per kernel over all members; each member's results are those
+    of its own ``update_basis`` / ``solve``, bit for bit.  The members are
+    borrowed (they must outlive the batch) and run on ``stream``."""
+
+    def __init__(self, solvers, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.members = list(solvers)
+        n = len(self.members)
+        arr = (C.c_void_p * n)(*[s.h.value for s in self.members])
+        h = C.c_void_p()
+        _check(_lib.msrsb_batch_create(n, arr, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+        for s in self.members:
+            s.stream = stream
+
+    def update_basis(self, max_sweeps=100, tol=1e-3):
+        """Cold basis of every member; returns the sweeps each took."""
+        n = len(self.members)
+        sw = (C.c_int32 * n)()
+        _check(_lib.msrsb_batch_update_basis(self.h, max_sweeps, tol, sw))
+        return list(sw)
+
+    def solve(self, ps, sources=None, rtol=1e-6, max_iters=500):
+        """Solve every member in place on its device tensor ``ps[k]`` (source
+        ``sources[k]``, None keeps the member's source); returns lists of
+        (iters, relres, status)."""
+        n = len(self.members)
+        if len(ps) != n or (sources is not None and len(sources) != n):
+            raise MsrsbError(E_INVAL, f"expected {n} vectors")
+        pp = (C.c_void_p * n)(*[m._vec(p).value for m, p in zip(self.members, ps)])
+        ss = None
+        if sources is not None:
+            ss = (C.c_void_p * n)(*[(m._vec(q).value if q is not None else None)
+                                    for m, q in zip(self.members, sources)])
+        it = (C.c_int32 * n)()
+        rel = (C.c_double * n)()
+        st = (C.c_int32 * n)()
+        _check(_lib.msrsb_batch_solve(self.h, ss, pp, rtol, max_iters, it, rel, st), allow=(E_NOCONV,))
+        return list(it), list(rel), list(st)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.msrsb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class TwoPhase:

@@ -29,6 +29,8 @@ void set_error(const char *fmt, ...) {
     g_err = buf;
 }
 
+void clear_error() { g_err.clear(); }
+
 int hip_fail(hipError_t e, const char *what) {
     set_error("%s: %s", what, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? MSRSB_E_NOMEM : MSRSB_E_DEVICE;
@@ -762,20 +764,6 @@ static size_t cart_bytes(const Ctx &c, const msrsb_partition &p) {
 
 // ---------------------------------------------------------- solve driver ----
 
-__global__ void k_reset(Status *st, int *flag) {
-    st->done = 0;
-    st->iters = 0;
-    st->flag = 0;
-    st->jcur = 0;
-    st->relres = 0.0;
-    *flag = 0;
-}
-
-__global__ void k_set_bnorm(Status *st, const double *sq) {
-    const double n = sqrt(*sq);
-    st->bnorm = n > 0.0 ? n : 1.0;
-}
-
 __global__ void k_zero(int N, double *__restrict__ x, const int *done) {
     if (done && *done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -827,12 +815,7 @@ static int read_status(Ctx &c) {
     return MSRSB_OK;
 }
 
-static void begin_solve(Ctx &c, const double *b, double *x) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, c.stream, c.status, c.flag);
-    launch_zero_inactive(c, x);
-    launch_multidot(c, b, 1, b, c.scal + 1, nullptr);  // ||b||^2 (b is 0 on inactive cells)
-    hipLaunchKernelGGL(k_set_bnorm, dim3(1), dim3(1), 0, c.stream, c.status, c.scal + 1);
-}
+static void begin_solve(Ctx &c, const double *b, double *x) { launch_begin_solve(c, b, x); }
 
 static int solve_richardson(Ctx &c, const double *b, double *x, double rtol, int max_iters) {
     launch_residual(c, b, x, c.r, true, nullptr);
@@ -999,7 +982,6 @@ int refresh_bases(Ctx &c, int sweeps) {
 
 using namespace msrsb;
 
-struct msrsb_ctx : public Ctx {};
 
 extern "C" {
 

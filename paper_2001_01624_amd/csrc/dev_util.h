@@ -67,10 +67,11 @@ __device__ inline double block_max(double v, double *lds) {
 // layer are then read through the same L2.  The grid must be a multiple of
 // kXcd (xcd_grid rounds up); logical ids past the real block count exit.
 constexpr int kXcd = 8;
-__device__ inline int xcd_block() {
-    const int per = gridDim.x / kXcd;
-    return (blockIdx.x % kXcd) * per + blockIdx.x / kXcd;
+__device__ inline int xcd_block(int bid, int nblk) {
+    const int per = nblk / kXcd;
+    return (bid % kXcd) * per + bid / kXcd;
 }
+__device__ inline int xcd_block() { return xcd_block(blockIdx.x, gridDim.x); }
 inline int xcd_grid(int nblocks) { return ((nblocks + kXcd - 1) / kXcd) * kXcd; }
 
 // Traversal order of the stencil kernels: thread t visits the cell with x

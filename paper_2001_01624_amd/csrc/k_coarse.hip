@@ -15,6 +15,7 @@
 // block inversion is on its own on the critical path.  The tile products of
 // the panels and the trailing update run on the FP64 matrix instructions.
 // Each cycle then applies the inverse by a GEMV (one workgroup per row).
+#include "batch.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
 
@@ -333,12 +334,12 @@ void launch_coarse_inverse_of(Ctx &c, const double *Asrc, double *A, int Mp, boo
 constexpr int kGemvThreads = 256;
 
 template <int NPT>
-__global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict__ A, int M, int Mp,
-                                                       const double *__restrict__ d, double *__restrict__ y,
-                                                       const int32_t *__restrict__ map, const int *done) {
+__device__ __forceinline__ void gemv_body(int bid, int nblk, const double *__restrict__ A, int M, int Mp,
+                                          const double *__restrict__ d, double *__restrict__ y,
+                                          const int32_t *__restrict__ map, const int *done) {
     __shared__ double lds[kGemvThreads / 64];
     if (done && *done) return;
-    const int row = blockIdx.x;
+    const int row = bid;
     const double *a = A + (long)row * Mp;
     double s = 0.0;
     for (int k0 = threadIdx.x; k0 < M; k0 += NPT * kGemvThreads) {
@@ -360,27 +361,75 @@ __global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict_
     if (threadIdx.x == 0) y[map ? map[row] : row] = s;
 }
 
+template <int NPT>
+__global__ __launch_bounds__(kGemvThreads) void k_gemv(const double *__restrict__ A, int M, int Mp,
+                                                       const double *__restrict__ d, double *__restrict__ y,
+                                                       const int32_t *__restrict__ map, const int *done) {
+    gemv_body<NPT>(blockIdx.x, gridDim.x, A, M, Mp, d, y, map, done);
+}
+
 void launch_coarse_solve(Ctx &c, Stage &s, const int *done) { launch_coarse_solve_with(c, s, s.Ainv, done); }
 
 // p_c = Ainv d with the stage's coarse vectors (Ainv: the Galerkin inverse or
 // another inverse of the stage's size).
+// loads per thread of the coarse GEMV for M columns
+static int gemv_npt(int M) {
+    const int npt = cdiv(M, kGemvThreads);
+    if (npt <= 4) return std::max(npt, 1);
+    if (npt <= 6) return 6;
+    if (npt <= 8) return 8;
+    if (npt <= 9) return 9;
+    if (npt <= 10) return 10;
+    if (npt <= 12) return 12;
+    return 16;
+}
+
 void launch_coarse_solve_with(Ctx &c, Stage &s, const double *Ainv, const int *done) {
     ProfScope ps(c, MSRSB_K_COARSE);
-    const int npt = cdiv(s.M, kGemvThreads);
-#define MSRSB_GEMV(NPT) \
-    hipLaunchKernelGGL(k_gemv<NPT>, dim3(s.M), dim3(kGemvThreads), 0, c.stream, Ainv, s.M, s.Mp, s.dvec, s.pc, \
-                       s.pc_map, done)
-    if (npt <= 1) MSRSB_GEMV(1);
-    else if (npt <= 2) MSRSB_GEMV(2);
-    else if (npt <= 3) MSRSB_GEMV(3);
-    else if (npt <= 4) MSRSB_GEMV(4);
-    else if (npt <= 6) MSRSB_GEMV(6);
-    else if (npt <= 8) MSRSB_GEMV(8);
-    else if (npt <= 9) MSRSB_GEMV(9);
-    else if (npt <= 10) MSRSB_GEMV(10);
-    else if (npt <= 12) MSRSB_GEMV(12);
-    else MSRSB_GEMV(16);
+#define MSRSB_GEMV(NPT)                                                                                          \
+    case NPT:                                                                                                    \
+        hipLaunchKernelGGL(k_gemv<NPT>, dim3(s.M), dim3(kGemvThreads), 0, c.stream, Ainv, s.M, s.Mp, s.dvec, s.pc, \
+                           s.pc_map, done);                                                                      \
+        break
+    switch (gemv_npt(s.M)) {
+        MSRSB_GEMV(1); MSRSB_GEMV(2); MSRSB_GEMV(3); MSRSB_GEMV(4); MSRSB_GEMV(6);
+        MSRSB_GEMV(8); MSRSB_GEMV(9); MSRSB_GEMV(10); MSRSB_GEMV(12); MSRSB_GEMV(16);
+    default: break;
+    }
 #undef MSRSB_GEMV
+}
+
+// ------------------------------------------------------- batched launches ----
+// p_c = A_c^-1 d for every member, one launch per loads-per-thread key
+// (grid: one workgroup per coarse row).
+int bat_member_gemv(const Stage &s, int *key) {
+    *key = gemv_npt(s.M);
+    return s.M;
+}
+
+template <int NPT>
+__global__ __launch_bounds__(kGemvThreads) void k_gemv_b(const BMember *D, BGroup gp, const int *act) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    gemv_body<NPT>(lb, nb, d.Ainv, d.M, d.Mp, d.dvec, d.pc, d.pc_map, &d.status->done);
+}
+
+void bat_coarse_solve(Batch &B) {
+    for (const HGroup &h : B.gemv) {
+        if (h.g.n == 0) continue;
+        const dim3 grid(h.g.total), blk(kGemvThreads);
+#define MSRSB_BGEMV(NPT)                                                                               \
+    case NPT:                                                                                          \
+        hipLaunchKernelGGL(k_gemv_b<NPT>, grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act);            \
+        break
+        switch (h.key) {
+            MSRSB_BGEMV(1); MSRSB_BGEMV(2); MSRSB_BGEMV(3); MSRSB_BGEMV(4); MSRSB_BGEMV(6);
+            MSRSB_BGEMV(8); MSRSB_BGEMV(9); MSRSB_BGEMV(10); MSRSB_BGEMV(12); MSRSB_BGEMV(16);
+        default: break;
+        }
+#undef MSRSB_BGEMV
+    }
 }
 
 }  // namespace msrsb

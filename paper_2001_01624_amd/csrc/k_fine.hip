@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "batch.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
 #include "stencil.h"
@@ -46,13 +47,19 @@ void launch_assemble(Ctx &c) {
                        c.diag, c.b);
 }
 
-__global__ void k_rhs(int N, const double *__restrict__ diag, const double *__restrict__ bcrhs,
-                      const double *__restrict__ src, double *__restrict__ b, double *__restrict__ keep) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rhs_body(int bid, int nblk, int N, const double *__restrict__ diag,
+                                         const double *__restrict__ bcrhs, const double *__restrict__ src,
+                                         double *__restrict__ b, double *__restrict__ keep) {
+    const int i = bid * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double q = src[i];
     keep[i] = q;
     b[i] = diag[i] > 0.0 ? q + bcrhs[i] : 0.0;
+}
+
+__global__ void k_rhs(int N, const double *__restrict__ diag, const double *__restrict__ bcrhs,
+                      const double *__restrict__ src, double *__restrict__ b, double *__restrict__ keep) {
+    rhs_body(blockIdx.x, gridDim.x, N, diag, bcrhs, src, b, keep);
 }
 
 void launch_source_update(Ctx &c, const double *d_source) {
@@ -95,14 +102,14 @@ void launch_ilu_factor(Ctx &c) {
 }
 
 template <bool NORM>
-__global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__restrict__ b,
-                                                     const double *__restrict__ x, double *__restrict__ r,
-                                                     double *__restrict__ partial, const int *done) {
+__device__ __forceinline__ void residual_body(int bid, int nblk, Fine g, const double *__restrict__ b,
+                                              const double *__restrict__ x, double *__restrict__ r,
+                                              double *__restrict__ partial, const int *done) {
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     double acc = 0.0;
-    const int lb = xcd_block();
-    for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += gridDim.x * blockDim.x) {
+    const int lb = xcd_block(bid, nblk);
+    for (int t = lb * blockDim.x + threadIdx.x; t < g.N; t += nblk * blockDim.x) {
         const int i = xzy_cell(t, g.nx, g.ny, g.nz);
         const double d = g.diag[i], bi = b[i];
         const double ax = ax_row(g, x, i, d);
@@ -114,6 +121,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
         const double s = block_sum(acc, lds);
         if (threadIdx.x == 0) partial[lb] = s;
     }
+}
+
+template <bool NORM>
+__global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__restrict__ b,
+                                                     const double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ partial, const int *done) {
+    residual_body<NORM>(blockIdx.x, gridDim.x, g, b, x, r, partial, done);
 }
 
 // r = b - A x with one wavefront per grid row (y, z) of at most 64 cells,
@@ -496,22 +510,52 @@ void launch_smooth(Ctx &c, const double *r, double *x, const int *done, bool ass
     else smooth_dispatch<false>(c, r, x, done);
 }
 
-__global__ void k_zero_inactive(int N, const double *__restrict__ diag, double *__restrict__ x) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void zero_inactive_body(int bid, int nblk, int N, const double *__restrict__ diag,
+                                                   double *__restrict__ x) {
+    const int i = bid * blockDim.x + threadIdx.x;
     if (i < N && !(diag[i] > 0.0)) x[i] = 0.0;
+}
+
+__global__ void k_zero_inactive(int N, const double *__restrict__ diag, double *__restrict__ x) {
+    zero_inactive_body(blockIdx.x, gridDim.x, N, diag, x);
 }
 
 void launch_zero_inactive(Ctx &c, double *x) {
     hipLaunchKernelGGL(k_zero_inactive, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, c.N, c.diag, x);
 }
 
+// Start of a solve: status cleared, x zeroed on inactive cells, ||b||^2 into
+// scal[1] and ||b|| (1 if b = 0) as the reference of the relative residual.
+__device__ __forceinline__ void reset_body(Status *st, int *flag) {
+    st->done = 0;
+    st->iters = 0;
+    st->flag = 0;
+    st->jcur = 0;
+    st->relres = 0.0;
+    *flag = 0;
+}
+
+__global__ void k_reset(Status *st, int *flag) { reset_body(st, flag); }
+
+__device__ __forceinline__ void set_bnorm_body(Status *st, const double *sq) {
+    const double n = sqrt(*sq);
+    st->bnorm = n > 0.0 ? n : 1.0;
+}
+
+__global__ void k_set_bnorm(Status *st, const double *sq) { set_bnorm_body(st, sq); }
+
 // Fixed-order sum of the per-block partials of the last norm kernel.
-__global__ __launch_bounds__(kBlock) void k_norm_finish(const double *__restrict__ partial, int np, double *out,
-                                                        const int *done) {
+__device__ __forceinline__ void norm_finish_body(const double *__restrict__ partial, int np, double *out,
+                                                 const int *done) {
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     const double s = sum_partials(partial, np, lds);
     if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_finish(const double *__restrict__ partial, int np, double *out,
+                                                        const int *done) {
+    norm_finish_body(partial, np, out, done);
 }
 
 void launch_norm_finish(Ctx &c, double *out_sq, const int *done) {
@@ -562,9 +606,9 @@ void launch_fluxes(Ctx &c, const double *p, double *face, double *bcf) {
 
 // partial[j][block] = sum over the block's cells of V_j w, eight vectors per
 // pass over w (register accumulators, one combined reduction per pass).
-__global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__restrict__ V, int k,
-                                                     const double *__restrict__ w, double *__restrict__ partial,
-                                                     const int *done) {
+__device__ __forceinline__ void multidot_body(int bid, int nblk, int N, const double *__restrict__ V, int k,
+                                              const double *__restrict__ w, double *__restrict__ partial,
+                                              const int *done) {
     __shared__ double red[8][kBlock / 64];
     if (done && *done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -573,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__rest
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        for (int i = bid * blockDim.x + threadIdx.x; i < N; i += nblk * blockDim.x) {
             const double wi = w[i];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
@@ -588,19 +632,30 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__rest
         if ((int)threadIdx.x < nb) {
             double t = 0.0;
             for (int m = 0; m < (int)(blockDim.x >> 6); ++m) t += red[threadIdx.x][m];
-            partial[(long)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+            partial[(long)(j0 + threadIdx.x) * nblk + bid] = t;
         }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_multidot_finish(const double *__restrict__ partial, int np,
-                                                            double *__restrict__ h, const int *done) {
+__global__ __launch_bounds__(kBlock) void k_multidot(int N, const double *__restrict__ V, int k,
+                                                     const double *__restrict__ w, double *__restrict__ partial,
+                                                     const int *done) {
+    multidot_body(blockIdx.x, gridDim.x, N, V, k, w, partial, done);
+}
+
+__device__ __forceinline__ void multidot_finish_body(int bid, int nblk, const double *__restrict__ partial, int np,
+                                                     double *__restrict__ h, const int *done) {
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
-    const int j = blockIdx.x;
+    const int j = bid;
     const double s = sum_partials(partial + (long)j * np, np, lds);
     if (threadIdx.x == 0) h[j] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_multidot_finish(const double *__restrict__ partial, int np,
+                                                            double *__restrict__ h, const int *done) {
+    multidot_finish_body(blockIdx.x, gridDim.x, partial, np, h, done);
 }
 
 // Scalar layout in c.scal (device doubles):
@@ -618,17 +673,16 @@ void launch_multidot(Ctx &c, const double *V, int k, const double *w, double *h_
 }
 
 template <bool NORM, typename VT>
-__global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const VT *__restrict__ V, int k,
-                                                      const double *__restrict__ h, double sign,
-                                                      double *__restrict__ w, double *__restrict__ partial,
-                                                      const int *done) {
+__device__ __forceinline__ void multiaxpy_body(int bid, int nblk, int N, const VT *__restrict__ V, int k,
+                                               const double *__restrict__ h, double sign, double *__restrict__ w,
+                                               double *__restrict__ partial, const int *done) {
     __shared__ double hs[kMaxRestart + 1];
     __shared__ double lds[kBlock / 64];
     if (done && *done) return;
     for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
     __syncthreads();
     double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    for (int i = bid * blockDim.x + threadIdx.x; i < N; i += nblk * blockDim.x) {
         double s = 0.0;
         for (int j = 0; j < k; ++j) s += hs[j] * (double)V[(long)j * N + i];
         const double v = w[i] + sign * s;
@@ -637,8 +691,16 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const VT *__restric
     }
     if (NORM) {
         const double s = block_sum(acc, lds);
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[bid] = s;
     }
+}
+
+template <bool NORM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_multiaxpy(int N, const VT *__restrict__ V, int k,
+                                                      const double *__restrict__ h, double sign,
+                                                      double *__restrict__ w, double *__restrict__ partial,
+                                                      const int *done) {
+    multiaxpy_body<NORM, VT>(blockIdx.x, gridDim.x, N, V, k, h, sign, w, partial, done);
 }
 
 template <typename VT>
@@ -666,7 +728,7 @@ void launch_multiaxpy(Ctx &c, const float *V, int k, const double *h, double *w,
 // Start of a restart cycle: beta = ||r|| (scal[0] holds ||r||^2), v0 = r/beta,
 // g = beta e1.  Sets done when the current iterate already meets rtol or the
 // iteration budget is spent; clears it otherwise.
-__global__ void k_gmres_begin(Status *st, double *scal, double rtol, int max_iters) {
+__device__ __forceinline__ void gmres_begin_body(Status *st, double *scal, double rtol, int max_iters) {
     const double beta = sqrt(scal[0]);
     const double rel = beta / st->bnorm;
     st->relres = rel;
@@ -675,6 +737,10 @@ __global__ void k_gmres_begin(Status *st, double *scal, double rtol, int max_ite
     scal[S_G] = beta;
     scal[S_INV] = beta > 0.0 ? 1.0 / beta : 0.0;
     st->done = (rel <= rtol || st->iters >= max_iters || !(rel == rel)) ? 1 : 0;
+}
+
+__global__ void k_gmres_begin(Status *st, double *scal, double rtol, int max_iters) {
+    gmres_begin_body(st, scal, rtol, max_iters);
 }
 
 __global__ void k_scale(int N, const double *__restrict__ w, double *__restrict__ v, const double *s, const int *done) {
@@ -736,7 +802,7 @@ void launch_gmres_scale(Ctx &c, const double *w, double *v, int /*j*/) {
 // w = T^-1 y, so that M^-1 Q y = Z w for the stored candidates Z.  One
 // wavefront stages the triangles and g in LDS; lane 0 then substitutes in the
 // same order as a plain loop would (the global loads were its latency).
-__global__ __launch_bounds__(64) void k_gmres_solve_small(Status *st, double *scal, int zform) {
+__device__ __forceinline__ void gmres_solve_small_body(Status *st, double *scal, int zform) {
     constexpr int KM = kMaxRestart;
     __shared__ double Hs[KM * KM];
     __shared__ double gs[KM], ys[KM];
@@ -777,6 +843,10 @@ __global__ __launch_bounds__(64) void k_gmres_solve_small(Status *st, double *sc
             w[i] = gs[i];
         }
     }
+}
+
+__global__ __launch_bounds__(64) void k_gmres_solve_small(Status *st, double *scal, int zform) {
+    gmres_solve_small_body(st, scal, zform);
 }
 
 void launch_gmres_solve_small(Ctx &c, int /*restart*/, bool zform) {
@@ -1135,12 +1205,13 @@ __global__ __launch_bounds__(kBlock) void k_gmres_step2(Status *st, double *scal
 constexpr int S_HU = 8192, S_DA = 12500, S_DC = 12700, S_RHO = 12800;
 
 template <int KM, bool MV, typename VT>
-__global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__restrict__ z, double *__restrict__ w,
-                                                    const VT *__restrict__ Q, const double *__restrict__ u,
-                                                    int j, double *__restrict__ partial, const int *done) {
+__device__ __forceinline__ void dpass_a_body(int bid, int nblk, Fine g, const double *__restrict__ z,
+                                             double *__restrict__ w, const VT *__restrict__ Q,
+                                             const double *__restrict__ u, int j, double *__restrict__ partial,
+                                             const int *done) {
     __shared__ double red[(kBlock / 64 + 1) * KM];
     if (done && *done) return;
-    const int G = gridDim.x;
+    const int G = nblk;
     double as[KM], at[KM];
 #pragma unroll
     for (int q = 0; q < KM; ++q) {
@@ -1148,7 +1219,7 @@ __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__rest
         at[q] = 0.0;
     }
     const int jc = j > 0 ? j - 1 : 0;
-    const int lb = xcd_block();
+    const int lb = xcd_block(bid, nblk);
     const int ch = ((g.N + G - 1) / G + 63) & ~63;
     const int i0 = lb * ch, i1 = min(g.N, i0 + ch);
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
@@ -1207,13 +1278,25 @@ __global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__rest
     }
 }
 
+template <int KM, bool MV, typename VT>
+__global__ __launch_bounds__(kBlock) void k_dpass_a(Fine g, const double *__restrict__ z, double *__restrict__ w,
+                                                    const VT *__restrict__ Q, const double *__restrict__ u,
+                                                    int j, double *__restrict__ partial, const int *done) {
+    dpass_a_body<KM, MV, VT>(blockIdx.x, gridDim.x, g, z, w, Q, u, j, partial, done);
+}
+
 // out[q] = sum over blocks of partial[q*G + b], one workgroup per quantity.
-__global__ __launch_bounds__(kBlock) void k_finish_n(const double *__restrict__ partial, int G,
-                                                     double *__restrict__ out, const Status *st) {
+__device__ __forceinline__ void finish_n_body(int bid, int nblk, const double *__restrict__ partial, int G,
+                                              double *__restrict__ out, const Status *st) {
     __shared__ double lds[kBlock / 64];
     if (st->done) return;
-    const double t = sum_partials(partial + (long)blockIdx.x * G, G, lds);
-    if (threadIdx.x == 0) out[blockIdx.x] = t;
+    const double t = sum_partials(partial + (long)bid * G, G, lds);
+    if (threadIdx.x == 0) out[bid] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_n(const double *__restrict__ partial, int G,
+                                                     double *__restrict__ out, const Status *st) {
+    finish_n_body(blockIdx.x, gridDim.x, partial, G, out, st);
 }
 
 // Finalise column j-1 and (unless final) prepare column j.  The pass-A
@@ -1234,8 +1317,8 @@ constexpr int kDstepFuseBlocks = 256;
 // reductions; 512 was close, and 640 or 384 (uneven per CU) slower.
 constexpr int kPassABlocks = 768;
 
-__global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int j, double rtol, int max_iters,
-                                                  int final_, const double *__restrict__ partial, int G) {
+__device__ __forceinline__ void dstep_body(Status *st, double *scal, int j, double rtol, int max_iters, int final_,
+                                           const double *__restrict__ partial, int G) {
     constexpr int HL = kDcgsMax + 2;  // rows of the staged Hessenberg block
     __shared__ double Hs[HL][HL];     // Hs[l][i] = Hu(l, i)
     __shared__ double rcs[kDcgsMax + 1], rsn[kDcgsMax + 1], gv[kDcgsMax + 2];
@@ -1361,14 +1444,18 @@ __global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int 
     if (tid == 0) scal[S_RHO] = irho;
 }
 
+__global__ __launch_bounds__(kBlock) void k_dstep(Status *st, double *scal, int j, double rtol, int max_iters,
+                                                  int final_, const double *__restrict__ partial, int G) {
+    dstep_body(st, scal, j, rtol, max_iters, final_, partial, G);
+}
+
 // q_j = (u_j - Q s) / rho into qout, u_{j+1} = w / rho - Q c(0..j-1) - c_j q_j
 // into unext (qout may alias u).  q_j enters u_{j+1} as stored (rounded to
 // VT), so u_{j+1} is formed against the basis that is kept.
 template <int KM, typename VT>
-__global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict__ Q, const double *u,
-                                                    const double *__restrict__ w, int j, VT *qout,
-                                                    double *__restrict__ unext, const double *__restrict__ scal,
-                                                    const Status *st) {
+__device__ __forceinline__ void dpass_b_body(int bid, int nblk, int N, const VT *__restrict__ Q, const double *u,
+                                             const double *__restrict__ w, int j, VT *qout, double *__restrict__ unext,
+                                             const double *__restrict__ scal, const Status *st) {
     if (st->done) return;
     const int jc = j > 0 ? j - 1 : 0;
     double sq[KM - 1], cq[KM - 1];
@@ -1379,8 +1466,8 @@ __global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict_
         cq[q] = q < j ? cv : 0.0;
     }
     const double cj = scal[S_DC + j], irho = scal[S_RHO];
-    const int ch = ((N + (int)gridDim.x - 1) / (int)gridDim.x + 63) & ~63;
-    const int i0 = xcd_block() * ch, i1 = min(N, i0 + ch);
+    const int ch = ((N + nblk - 1) / nblk + 63) & ~63;
+    const int i0 = xcd_block(bid, nblk) * ch, i1 = min(N, i0 + ch);
     for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double vq[KM - 1];
 #pragma unroll
@@ -1399,6 +1486,14 @@ __global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict_
         qout[i] = qs;
         unext[i] = wi * irho - (b + cj * (double)qs);
     }
+}
+
+template <int KM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_dpass_b(int N, const VT *__restrict__ Q, const double *u,
+                                                    const double *__restrict__ w, int j, VT *qout,
+                                                    double *__restrict__ unext, const double *__restrict__ scal,
+                                                    const Status *st) {
+    dpass_b_body<KM, VT>(blockIdx.x, gridDim.x, N, Q, u, w, j, qout, unext, scal, st);
 }
 
 template <int KM, typename VT>
@@ -1496,8 +1591,233 @@ void launch_arnoldi(Ctx &c, const double *z, double *w, int j, double rtol, int 
 }
 
 // exported for the solver driver
+void launch_begin_solve(Ctx &c, const double *b, double *x) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, c.stream, c.status, c.flag);
+    launch_zero_inactive(c, x);
+    launch_multidot(c, b, 1, b, c.scal + 1, nullptr);  // ||b||^2 (b is 0 on inactive cells)
+    hipLaunchKernelGGL(k_set_bnorm, dim3(1), dim3(1), 0, c.stream, c.status, c.scal + 1);
+}
+
 void launch_gmres_begin(Ctx &c, double rtol, int max_iters) {
     hipLaunchKernelGGL(k_gmres_begin, dim3(1), dim3(1), 0, c.stream, c.status, c.scal, rtol, max_iters);
 }
+
+// ------------------------------------------------------- batched launches ----
+// One launch per kernel over the members of a group; each workgroup runs the
+// body above for its member with the member's own grid size and arguments,
+// so the member's arithmetic and reduction order are those of its own launch.
+
+#define BAT_LOCATE()                              \
+    int m, lb, nb;                                \
+    if (!bat_locate(gp, act, m, lb, nb)) return;  \
+    const BMember &d = D[m]
+
+template <typename F>
+static void each_group(const Groups &gs, F f) {
+    for (const HGroup &h : gs)
+        if (h.g.n > 0) f(h);
+}
+
+// reduction grids of a member: G for norms and dots, GA for pass A of the
+// Arnoldi step; returns whether the step sums pass A's partials itself
+bool bat_member_fine(const Ctx &c, BMember &d) {
+    d.G = red_grid(c.N);
+    d.GA = std::min(d.G, kPassABlocks);
+    return d.GA <= kDstepFuseBlocks;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rhs_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    if (!d.q) return;  // this member keeps its source
+    rhs_body(lb, nb, d.g.N, d.g.diag, d.bcrhs, d.q, d.b, d.src);
+}
+
+void bat_source_update(Batch &B) {
+    each_group(B.cells, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_rhs_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+}
+
+__global__ void k_reset_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    reset_body(d.status, d.flag);
+}
+
+__global__ void k_zero_inactive_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    zero_inactive_body(lb, nb, d.g.N, d.g.diag, d.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bnorm_dot_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    multidot_body(lb, nb, d.g.N, d.b, 1, d.b, d.partial, nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bnorm_finish_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    multidot_finish_body(0, 1, d.partial, d.G, d.scal + 1, nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0) set_bnorm_body(d.status, d.scal + 1);
+}
+
+void bat_begin_solve(Batch &B) {
+    for (const HGroup &h : B.one)
+        hipLaunchKernelGGL(k_reset_b, dim3(h.g.total), dim3(1), 0, B.stream, B.d_mem, h.g, B.d_act);
+    each_group(B.cells, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_zero_inactive_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+    each_group(B.red, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_bnorm_dot_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+    each_group(B.one, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_bnorm_finish_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+}
+
+// restart: r = b - A x into V(0) with its norm, then the restart test
+__global__ __launch_bounds__(kBlock) void k_restart_res_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    residual_body<true>(lb, nb, d.g, d.b, d.x, d.V, d.partial, nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_restart_begin_b(const BMember *D, BGroup gp, const int *act, double rtol,
+                                                            int max_iters) {
+    BAT_LOCATE();
+    norm_finish_body(d.partial, d.G, d.scal, nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0) gmres_begin_body(d.status, d.scal, rtol, max_iters);
+}
+
+void bat_restart_residual(Batch &B, double rtol, int max_iters) {
+    each_group(B.red, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_restart_res_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+    each_group(B.one, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_restart_begin_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act,
+                           rtol, max_iters);
+    });
+}
+
+// One DCGS2 Arnoldi step for column j of every member (final: only finalise
+// column j - 1), with the member's candidate u_j and preconditioned Z(j).
+template <int KM, bool MV, typename VT>
+__global__ __launch_bounds__(kBlock) void k_dpass_a_b(const BMember *D, BGroup gp, const int *act, int j) {
+    BAT_LOCATE();
+    const VT *Q = std::is_same<VT, float>::value ? (const VT *)d.Vf : (const VT *)d.V;
+    dpass_a_body<KM, MV, VT>(lb, nb, d.g, MV ? bvec(d, bvsel(BV_Z, j)) : nullptr, d.tmp, Q,
+                             bvec(d, bvsel(BV_U, j)), j, d.partial, &d.status->done);
+}
+
+// na workgroups per member of a one-per-member group: workgroup q of member
+// k sums quantity q, as in the member's own launch of na workgroups
+__global__ __launch_bounds__(kBlock) void k_finish_n_b(const BMember *D, BGroup gp, const int *act, int na) {
+    const int k = blockIdx.x / na, q = blockIdx.x - k * na;
+    const int m = gp.mem[k];
+    if (!act[m]) return;
+    const BMember &d = D[m];
+    finish_n_body(q, na, d.partial, d.GA, d.scal + S_DA, d.status);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dstep_b(const BMember *D, BGroup gp, const int *act, int j, double rtol,
+                                                    int max_iters, int final_) {
+    BAT_LOCATE();
+    const bool fuse = d.GA <= kDstepFuseBlocks;
+    dstep_body(d.status, d.scal, j, rtol, max_iters, final_, d.partial, fuse ? d.GA : 0);
+}
+
+template <int KM, typename VT>
+__global__ __launch_bounds__(kBlock) void k_dpass_b_b(const BMember *D, BGroup gp, const int *act, int j) {
+    BAT_LOCATE();
+    const long N = d.g.N;
+    const bool f = std::is_same<VT, float>::value;
+    VT *Q = f ? (VT *)d.Vf : (VT *)d.V;
+    VT *qout = Q + (long)j * N;
+    double *unext = d.V + (f ? (long)((j + 1) & 1) : (long)(j + 1)) * N;
+    dpass_b_body<KM, VT>(lb, nb, d.g.N, Q, bvec(d, bvsel(BV_U, j)), d.tmp, j, qout, unext, d.scal, d.status);
+}
+
+template <int KM, typename VT>
+static void bat_dgmres_k(Batch &B, int j, double rtol, int max_iters, bool final_) {
+    const int na = final_ ? j + 1 : 2 * j + 2;
+    each_group(B.passa, [&](const HGroup &h) {
+        if (final_)
+            hipLaunchKernelGGL((k_dpass_a_b<KM, false, VT>), dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem,
+                               h.g, B.d_act, j);
+        else
+            hipLaunchKernelGGL((k_dpass_a_b<KM, true, VT>), dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem,
+                               h.g, B.d_act, j);
+    });
+    // members whose pass-A grid is too large for the step to sum its partials
+    each_group(B.nofuse, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_finish_n_b, dim3(h.g.n * na), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act, na);
+    });
+    each_group(B.one, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_dstep_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act, j, rtol,
+                           max_iters, final_ ? 1 : 0);
+    });
+    if (final_) return;
+    each_group(B.red, [&](const HGroup &h) {
+        hipLaunchKernelGGL((k_dpass_b_b<KM, VT>), dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act,
+                           j);
+    });
+}
+
+template <typename VT>
+static void bat_dgmres_t(Batch &B, int j, double rtol, int max_iters, bool final_) {
+    if (j <= 7) bat_dgmres_k<8, VT>(B, j, rtol, max_iters, final_);
+    else if (j <= 15) bat_dgmres_k<16, VT>(B, j, rtol, max_iters, final_);
+    else bat_dgmres_k<32, VT>(B, j, rtol, max_iters, final_);
+}
+
+void bat_dgmres_step(Batch &B, int j, double rtol, int max_iters, bool final_) {
+    if (B.mixed) bat_dgmres_t<float>(B, j, rtol, max_iters, final_);
+    else bat_dgmres_t<double>(B, j, rtol, max_iters, final_);
+}
+
+// x += Z (T^-1 y) over the k = jcur columns of the restart (none if k = 0)
+__global__ __launch_bounds__(64) void k_solve_small_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    if (d.status->jcur <= 0) return;
+    gmres_solve_small_body(d.status, d.scal, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_x_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    const int k = d.status->jcur;
+    if (k <= 0) return;
+    multiaxpy_body<false, double>(lb, nb, d.g.N, d.Z, k, d.scal + kScalW, 1.0, d.x, d.partial, nullptr);
+}
+
+void bat_solution_update(Batch &B) {
+    each_group(B.one, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_solve_small_b, dim3(h.g.total), dim3(64), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+    each_group(B.red, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_update_x_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+    });
+}
+
+// every member's status and error flag into the batch's arrays (members that
+// have left keep their last copy)
+__global__ void k_gather_status_b(const BMember *D, BGroup gp, const int *act, Status *out, int *flags) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    out[m] = *d.status;
+    flags[m] = d.flag[0];
+}
+
+void bat_gather_status(Batch &B) {
+    each_group(B.one, [&](const HGroup &h) {
+        hipLaunchKernelGGL(k_gather_status_b, dim3(h.g.total), dim3(1), 0, B.stream, B.d_mem, h.g, B.d_act, B.d_st,
+                           B.d_flag);
+    });
+}
+
+#undef BAT_LOCATE
 
 }  // namespace msrsb

@@ -31,6 +31,7 @@
 // natural layout.
 #include <hip/hip_runtime.h>
 
+#include "batch.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
 
@@ -285,10 +286,10 @@ __device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, int
 // active where its 1/p is nonzero (inactive cells and non-positive pivots;
 // their correction is exactly zero).
 template <typename TT, int PHASE, bool ASSIGN>
-__global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, const int *done) {
+__device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT> a, const int *done) {
     __shared__ TT sA[kLineThreads], sB[kLineThreads];
     if (done && *done) return;
-    const int b = xcd_block();
+    const int b = xcd_block(bid, nblk);
     if (b * a.cw >= a.ncol) return;
     const int cl = threadIdx.x % a.cw, ch = threadIdx.x / a.cw;
     int p = b * a.cw + cl;
@@ -392,6 +393,23 @@ __global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, co
         }
 }
 
+template <typename TT, int PHASE, bool ASSIGN>
+__global__ __launch_bounds__(kLineThreads) void k_lilu_reg(LineRegArgs<TT> a, const int *done) {
+    lilu_reg_body<TT, PHASE, ASSIGN>(blockIdx.x, gridDim.x, a, done);
+}
+
+// Register-path geometry of a box with nchp = lilu_reg_chunks(nz) > 0:
+// column slots per row, columns, columns per workgroup, cells per chunk,
+// chunks per column; returns the grid (workgroups).
+static int lilu_reg_geometry(int nx, int ny, int nz, int nchp, int *hx, int *ncol, int *cw, int *L, int *nch) {
+    *hx = (nx + 1) / 2;
+    *ncol = *hx * ny;
+    *cw = kLineThreads / nchp;
+    *L = cdiv(nz, nchp);
+    *nch = cdiv(nz, *L);
+    return xcd_grid(cdiv(*ncol, *cw));
+}
+
 template <typename TT, bool ASSIGN>
 static void lilu_dispatch(Ctx &c, const TT *tx, const TT *ty, const TT *tz, const TT *dinv, const TT *cz,
                           TT *packed, TT *pe, const double *r, double *x, const int *done) {
@@ -403,12 +421,8 @@ static void lilu_dispatch(Ctx &c, const TT *tx, const TT *ty, const TT *tz, cons
         q.g = g;
         q.tx = tx; q.ty = ty;
         q.r = r; q.x = x;
-        q.hx = (c.nx + 1) / 2;
-        q.ncol = q.hx * c.ny;
-        q.cw = kLineThreads / nchp;
-        q.L = cdiv(c.nz, nchp);
-        q.nch = cdiv(c.nz, q.L);
-        const dim3 grid(xcd_grid(cdiv(q.ncol, q.cw))), blk(kLineThreads);
+        const dim3 grid(lilu_reg_geometry(c.nx, c.ny, c.nz, nchp, &q.hx, &q.ncol, &q.cw, &q.L, &q.nch)),
+            blk(kLineThreads);
         TT *e_red = pe, *e_black = pe + S;
         // red forward
         q.pd = packed; q.pc = packed + S; q.pt = packed + 2 * S;
@@ -448,6 +462,64 @@ void launch_lilu_apply(Ctx &c, const double *r, double *x, const int *done, bool
         if (assign) lilu_dispatch<double, true>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, pk, pe, r, x, done);
         else lilu_dispatch<double, false>(c, c.tx, c.ty, c.tz, c.ldinv, c.lcz, pk, pe, r, x, done);
     }
+}
+
+// Batched: x = S r (assign) for every member of the batch, the three passes
+// each one launch over all members.
+template <typename TT, int PHASE>
+__global__ __launch_bounds__(kLineThreads) void k_lilu_reg_b(const BMember *D, BGroup gp, const int *act, int rsel,
+                                                             int xsel) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    const long S = d.l_S;
+    const TT *pk = (const TT *)d.lpack;
+    TT *pe = (TT *)d.lpe;
+    LineRegArgs<TT> q;
+    q.g = d.g;
+    q.tx = (const TT *)d.wtx;
+    q.ty = (const TT *)d.wty;
+    q.r = bvec(d, rsel);
+    q.x = bvec(d, xsel);
+    q.hx = d.l_hx;
+    q.ncol = d.l_ncol;
+    q.cw = d.l_cw;
+    q.nch = d.l_nch;
+    q.L = d.l_L;
+    const int c0 = PHASE == 1 ? 3 : 0;
+    q.pd = pk + c0 * S;
+    q.pc = pk + (c0 + 1) * S;
+    q.pt = pk + (c0 + 2) * S;
+    q.eself = PHASE == 1 ? pe + S : pe;
+    q.eother = PHASE == 1 ? pe : pe + S;
+    lilu_reg_body<TT, PHASE, true>(lb, nb, q, &d.status->done);
+}
+
+// A member's register-path geometry and working-precision operands; returns
+// its grid, 0 if its columns are too tall for the register path.
+int bat_member_lilu(const Ctx &c, BMember &d) {
+    const int nchp = lilu_reg_chunks(c.nz);
+    if (!nchp || !c.lpack) return 0;
+    d.l_S = (long)lilu_slots(c.nx, c.ny, c.nz);
+    d.lpack = c.lpack;
+    d.lpe = c.lpe;
+    return lilu_reg_geometry(c.nx, c.ny, c.nz, nchp, &d.l_hx, &d.l_ncol, &d.l_cw, &d.l_L, &d.l_nch);
+}
+
+template <typename TT>
+static void bat_lilu_t(Batch &B, int rsel, int xsel) {
+    for (const HGroup &h : B.lilu) {
+        if (h.g.n == 0) continue;
+        const dim3 grid(h.g.total), blk(kLineThreads);
+        hipLaunchKernelGGL((k_lilu_reg_b<TT, 0>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act, rsel, xsel);
+        hipLaunchKernelGGL((k_lilu_reg_b<TT, 1>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act, rsel, xsel);
+        hipLaunchKernelGGL((k_lilu_reg_b<TT, 2>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act, rsel, xsel);
+    }
+}
+
+void bat_lilu_assign(Batch &B, int rsel, int xsel) {
+    if (B.mixed) bat_lilu_t<float>(B, rsel, xsel);
+    else bat_lilu_t<double>(B, rsel, xsel);
 }
 
 }  // namespace msrsb

@@ -10,6 +10,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "batch.h"
 #include "cart_util.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -19,8 +20,8 @@ namespace msrsb {
 // ---------------------------------------------------------------- sweeps ----
 
 template <int NS, typename PT>
-__global__ void k_basis_init(CartDev cd, Fine g, PT *__restrict__ P) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void basis_init_body(int bid, int nblk, CartDev cd, Fine g, PT *__restrict__ P) {
+    const int i = bid * blockDim.x + threadIdx.x;
     if (i >= g.N) return;
     int s0 = -1;
     if (g.diag[i] > 0.0) {
@@ -36,6 +37,11 @@ __global__ void k_basis_init(CartDev cd, Fine g, PT *__restrict__ P) {
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) P[(long)s * g.N + i] = (s == s0) ? (PT)1 : (PT)0;
+}
+
+template <int NS, typename PT>
+__global__ void k_basis_init(CartDev cd, Fine g, PT *__restrict__ P) {
+    basis_init_body<NS, PT>(blockIdx.x, gridDim.x, cd, g, P);
 }
 
 // One restricted-smoothing sweep for every cell:
@@ -101,21 +107,19 @@ constexpr int sweep_rows() {
     return sizeof(PT) == 8 ? 4 : 8;
 }
 
-template <int AM, typename PT, int kSweepRows = sweep_rows<PT>()>
-__global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, const PT *__restrict__ tx,
-                                                           const PT *__restrict__ ty, const PT *__restrict__ tz,
-                                                           const PT *__restrict__ Pin, PT *__restrict__ Pout,
-                                                           PT omega, double *__restrict__ part, int *flag,
-                                                           int check_blocks, const int *done, int nxt, int ngy,
-                                                           int nzc, int zc, int nblk,
-                                                           const unsigned long long *__restrict__ xmask,
-                                                           const int *__restrict__ packy,
-                                                           const int *__restrict__ packz) {
+template <int AM, typename PT, int kSweepRows>
+__device__ __forceinline__ void sweep_body(int bid, int ngrid, CartDev cd, Fine g, const PT *__restrict__ tx,
+                                           const PT *__restrict__ ty, const PT *__restrict__ tz,
+                                           const PT *__restrict__ Pin, PT *__restrict__ Pout, PT omega,
+                                           double *__restrict__ part, int *flag, int check_blocks, const int *done,
+                                           int nxt, int ngy, int nzc, int zc, int nblk,
+                                           const unsigned long long *__restrict__ xmask, const int *__restrict__ packy,
+                                           const int *__restrict__ packz) {
     constexpr int NS = 1 << __builtin_popcount(AM);
     constexpr int SZ = sizeof(PT);
     __shared__ double lds[kSweepRows];
     if (*done) return;
-    const int b = xcd_block();
+    const int b = xcd_block(bid, ngrid);
     if (b >= nblk) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy, N = g.N;
     const int NSZ = N * SZ;
@@ -330,6 +334,20 @@ __global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, c
     if (threadIdx.x == 0) part[b] = mx;
 }
 
+template <int AM, typename PT, int kSweepRows = sweep_rows<PT>()>
+__global__ __launch_bounds__(64 * kSweepRows) void k_sweep(CartDev cd, Fine g, const PT *__restrict__ tx,
+                                                           const PT *__restrict__ ty, const PT *__restrict__ tz,
+                                                           const PT *__restrict__ Pin, PT *__restrict__ Pout,
+                                                           PT omega, double *__restrict__ part, int *flag,
+                                                           int check_blocks, const int *done, int nxt, int ngy,
+                                                           int nzc, int zc, int nblk,
+                                                           const unsigned long long *__restrict__ xmask,
+                                                           const int *__restrict__ packy,
+                                                           const int *__restrict__ packz) {
+    sweep_body<AM, PT, kSweepRows>(blockIdx.x, gridDim.x, cd, g, tx, ty, tz, Pin, Pout, omega, part, flag,
+                                   check_blocks, done, nxt, ngy, nzc, zc, nblk, xmask, packy, packz);
+}
+
 // Stop rule after sweep k: done once the change of sweep k is <= tol.  The
 // change is the maximum of the npart per-workgroup maxima in part, or (npart
 // = 0) the value already in maxbits[k]; it is recorded in maxbits[k].
@@ -356,10 +374,9 @@ __global__ __launch_bounds__(256) void k_sweep_check(Status *st, unsigned long l
 // in flag[1].  Sweep k is decided first, exactly as alone; if it stops, the
 // extra sweep k+1 does not count (its result went to the other buffer and its
 // flag is dropped), otherwise sweep k+1 is decided and its flag kept.
-__global__ __launch_bounds__(256) void k_sweep_check_pair(Status *st, unsigned long long *maxbits, int k,
-                                                          int npair, double tol, int max_sweeps,
-                                                          const double *__restrict__ part, int n0, int n1,
-                                                          int stride, int *flag) {
+__device__ __forceinline__ void sweep_check_pair_body(Status *st, unsigned long long *maxbits, int k, int npair,
+                                                      double tol, int max_sweeps, const double *__restrict__ part,
+                                                      int n0, int n1, int stride, int *flag) {
     __shared__ double lds[4];
     if (st->done) return;
     double m0 = 0.0, m1 = 0.0;
@@ -385,6 +402,13 @@ __global__ __launch_bounds__(256) void k_sweep_check_pair(Status *st, unsigned l
             if (m1 <= tol || k + 2 >= max_sweeps) st->done = 1;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_check_pair(Status *st, unsigned long long *maxbits, int k,
+                                                          int npair, double tol, int max_sweeps,
+                                                          const double *__restrict__ part, int n0, int n1,
+                                                          int stride, int *flag) {
+    sweep_check_pair_body(st, maxbits, k, npair, tol, max_sweeps, part, n0, n1, stride, flag);
 }
 
 // Offset of the second sweep's maxima in c.partial (which holds at least
@@ -464,17 +488,26 @@ static void init_dispatch(Ctx &c, Stage &s, PT *P) {
     }
 }
 
-__global__ void k_to_bf16(long n, const float *__restrict__ in, uint16_t *__restrict__ out) {
-    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void to_bf16_body(int bid, int nblk, long n, const float *__restrict__ in,
+                                             uint16_t *__restrict__ out) {
+    const long k = (long)bid * blockDim.x + threadIdx.x;
     if (k < n) out[k] = float_to_bf16(in[k]);
 }
 
-__global__ void k_status_reset(Status *st, int *flag) {
+__global__ void k_to_bf16(long n, const float *__restrict__ in, uint16_t *__restrict__ out) {
+    to_bf16_body(blockIdx.x, gridDim.x, n, in, out);
+}
+
+__device__ __forceinline__ void status_reset_body(Status *st, int *flag) {
     st->done = 0;
     st->iters = 0;
     st->relres = 0.0;
     flag[0] = 0;
     flag[1] = 0;
+}
+
+__global__ void k_status_reset(Status *st, int *flag) {
+    status_reset_body(st, flag);
 }
 
 // Run up to max_sweeps sweeps (device-side stop rule); returns MSRSB status.
@@ -565,4 +598,132 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
     if (change) *change = last;
     return MSRSB_OK;
 }
+// ------------------------------------------------------- batched launches ----
+// Cold basis construction of every member's rectilinear stage: one launch per
+// sweep (per split-axis mask) over all members, the stop rule per member.  A
+// batched sweep walks whole columns (one z chunk per column group); a sweep's
+// values do not depend on the chunks, and its change is a maximum.
+
+// sweep grid and key (split-axis mask) of a member; fills its sweep geometry
+int bat_member_sweep(const Ctx &c, const Stage &s, BMember &d, int *key) {
+    int am = 0;
+    for (int a = 0; a < 3; ++a)
+        if (s.cart.bit[a] >= 0) am |= 1 << a;
+    const int rows = c.opt.precision == MSRSB_MIXED ? sweep_rows<float>() : sweep_rows<double>();
+    d.s_nxt = cdiv(c.nx, 64);
+    d.s_ngy = cdiv(c.ny, rows);
+    d.s_nblk = d.s_nxt * d.s_ngy;
+    d.check_blocks = (int)s.h_present.size() != s.cart.m[0] * s.cart.m[1] * s.cart.m[2];
+    *key = am;
+    return xcd_grid(d.s_nblk);
+}
+
+#define BAT_LOCATE()                              \
+    int m, lb, nb;                                \
+    if (!bat_locate(gp, act, m, lb, nb)) return;  \
+    const BMember &d = D[m]
+
+template <int NS, typename PT>
+__global__ void k_basis_init_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    basis_init_body<NS, PT>(lb, nb, d.cd, d.g, (PT *)d.P[0]);
+}
+
+__global__ __launch_bounds__(256) void k_sweep_reset_b(const BMember *D, BGroup gp, const int *act, int max_sweeps) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    if (threadIdx.x == 0) status_reset_body(d.status, d.flag);
+    for (int k = threadIdx.x; k < max_sweeps; k += blockDim.x) d.maxbits[k] = 0ull;
+}
+
+template <int AM, typename PT>
+__global__ __launch_bounds__(64 * sweep_rows<PT>()) void k_sweep_b(const BMember *D, BGroup gp, const int *act,
+                                                                  int in, int q, PT omega) {
+    BAT_LOCATE();
+    sweep_body<AM, PT, sweep_rows<PT>()>(lb, nb, d.cd, d.g, (const PT *)d.wtx, (const PT *)d.wty, (const PT *)d.wtz,
+                                         (const PT *)d.P[in], (PT *)d.P[in ^ 1], omega,
+                                         d.partial + (size_t)q * kSweepPartStride, d.flag + q, d.check_blocks,
+                                         &d.status->done, d.s_nxt, d.s_ngy, 1, d.g.nz, d.s_nblk,
+                                         (const unsigned long long *)d.cd.xmask, d.cd.pack[1], d.cd.pack[2]);
+}
+
+__global__ __launch_bounds__(256) void k_sweep_check_pair_b(const BMember *D, BGroup gp, const int *act, int k,
+                                                            int npair, double tol, int max_sweeps) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    sweep_check_pair_body(d.status, d.maxbits, k, npair, tol, max_sweeps, d.partial, d.s_nblk, d.s_nblk,
+                          kSweepPartStride, d.flag);
+}
+
+__global__ void k_to_bf16_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    to_bf16_body(lb, nb, (long)d.ns * d.g.N, (const float *)d.P[d.cur], d.Pbf);
+}
+
+#undef BAT_LOCATE
+
+template <typename PT>
+static void bat_init_t(Batch &B, const HGroup &h) {
+    const dim3 grid(h.g.total), blk(kBlock);
+    switch (h.key) {
+    case 1: hipLaunchKernelGGL((k_basis_init_b<1, PT>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act); break;
+    case 2: hipLaunchKernelGGL((k_basis_init_b<2, PT>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act); break;
+    case 4: hipLaunchKernelGGL((k_basis_init_b<4, PT>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act); break;
+    default: hipLaunchKernelGGL((k_basis_init_b<8, PT>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act); break;
+    }
+}
+
+// basis from the partition of unity of the blocks, status and sweep maxima cleared
+void bat_sweep_begin(Batch &B, int max_sweeps) {
+    for (const HGroup &h : B.init) {
+        if (h.g.n == 0) continue;
+        if (B.mixed) bat_init_t<float>(B, h);
+        else bat_init_t<double>(B, h);
+    }
+    for (const HGroup &h : B.one)
+        if (h.g.n > 0)
+            hipLaunchKernelGGL(k_sweep_reset_b, dim3(h.g.total), dim3(256), 0, B.stream, B.d_mem, h.g, B.d_act,
+                               max_sweeps);
+}
+
+template <typename PT>
+static void bat_sweep_t(Batch &B, const HGroup &h, int in, int q, PT om) {
+    const dim3 grid(h.g.total), blk(64 * sweep_rows<PT>());
+#define MSRSB_BSW(AM)                                                                                       \
+    case AM:                                                                                                \
+        hipLaunchKernelGGL((k_sweep_b<AM, PT>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act, in, q, om);  \
+        break
+    switch (h.key) {
+        MSRSB_BSW(0); MSRSB_BSW(1); MSRSB_BSW(2); MSRSB_BSW(3);
+        MSRSB_BSW(4); MSRSB_BSW(5); MSRSB_BSW(6); MSRSB_BSW(7);
+    default: break;
+    }
+#undef MSRSB_BSW
+}
+
+// sweeps k and k+1 (npair = 2) or k alone, then the stop rule of each member
+void bat_sweep_pair(Batch &B, int k, int npair, double omega, double tol, int max_sweeps) {
+    for (int q = 0; q < npair; ++q) {
+        const int in = (k + q) & 1;
+        for (const HGroup &h : B.sweep) {
+            if (h.g.n == 0) continue;
+            if (B.mixed) bat_sweep_t<float>(B, h, in, q, (float)omega);
+            else bat_sweep_t<double>(B, h, in, q, omega);
+        }
+    }
+    for (const HGroup &h : B.one)
+        if (h.g.n > 0)
+            hipLaunchKernelGGL(k_sweep_check_pair_b, dim3(h.g.total), dim3(256), 0, B.stream, B.d_mem, h.g, B.d_act,
+                               k, npair, tol, max_sweeps);
+}
+
+// the BF16 copy of every member's final FP32 basis
+void bat_to_bf16(Batch &B) {
+    for (const HGroup &h : B.bf16)
+        if (h.g.n > 0)
+            hipLaunchKernelGGL(k_to_bf16_b, dim3(h.g.total), dim3(kBlock), 0, B.stream, B.d_mem, h.g, B.d_act);
+}
+
 }  // namespace msrsb

@@ -6,6 +6,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "batch.h"
 #include "cart_util.h"
 #include "dev_util.h"
 #include "msrsb_internal.h"
@@ -39,14 +40,13 @@ namespace msrsb {
 // model.)  Rows of at most 64 cells (NCH = 1) take the x neighbours from the
 // adjacent lanes.
 template <int NS, typename PS, int NCH, bool RES, int W, int U>
-__global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                          const double *__restrict__ rb,
-                                                          const double *__restrict__ x, double *__restrict__ part,
-                                                          const int *done) {
+__device__ __forceinline__ void restrict_rows_body(int bid, int nblk, CartDev cd, Fine g, const PS *__restrict__ P,
+                                                   const double *__restrict__ rb, const double *__restrict__ x,
+                                                   double *__restrict__ part, const int *done) {
     extern __shared__ double red[];  // [W][nx][NS]
     if (done && *done) return;
     const int mx = cd.m[0], my = cd.m[1];
-    const int t = xcd_block();
+    const int t = xcd_block(bid, nblk);
     if (t >= my * g.nz) return;
     const int z = t / my, Ly = t - z * my;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -157,6 +157,14 @@ __global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, co
     }
 }
 
+template <int NS, typename PS, int NCH, bool RES, int W, int U>
+__global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                          const double *__restrict__ rb,
+                                                          const double *__restrict__ x, double *__restrict__ part,
+                                                          const int *done) {
+    restrict_rows_body<NS, PS, NCH, RES, W, U>(blockIdx.x, gridDim.x, cd, g, P, rb, x, part, done);
+}
+
 // NARROW: every dual z-interval has at most 64 layers, so each lane adds at
 // most one layer per slot.  The z split table is staged in LDS, so the only
 // global round trips are the block id and one partial per slot; the partials
@@ -164,13 +172,14 @@ __global__ __launch_bounds__(64 * W) void k_restrict_rows(CartDev cd, Fine g, co
 constexpr int kGatherSplitLds = 1024;  // dual z-intervals held in LDS
 
 template <int NS, bool NARROW>
-__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
-                                                         double *__restrict__ d, const int *done) {
+__device__ __forceinline__ void restrict_gather_body(int bid, int nblk, CartDev cd, Fine g, int M,
+                                                     const double *__restrict__ part, double *__restrict__ d,
+                                                     const int *done) {
     __shared__ int spz[kGatherSplitLds];
     if (done && *done) return;
     const int mx = cd.m[0], my = cd.m[1], mz = cd.m[2];
     for (int t = threadIdx.x; t < mz; t += blockDim.x) spz[t] = cd.split[2][t];
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int j = bid * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int cid = cd.present[min(j, M - 1)];
     __syncthreads();
@@ -216,6 +225,12 @@ __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int
     if (lane == 0) d[j] = v;
 }
 
+template <int NS, bool NARROW>
+__global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int M, const double *__restrict__ part,
+                                                         double *__restrict__ d, const int *done) {
+    restrict_gather_body<NS, NARROW>(blockIdx.x, gridDim.x, cd, g, M, part, d, done);
+}
+
 // x_i += sum_s P_is p_c[block(i, s)], one wavefront per grid row (y, z) with
 // lanes along x.  The y and z parts of the slot -> block map are uniform over
 // the row, and p_c is held per Cartesian block (zero on dropped blocks), so
@@ -226,10 +241,10 @@ __global__ __launch_bounds__(256) void k_restrict_gather(CartDev cd, Fine g, int
 constexpr int kProWaves = 4;
 
 template <int NS, typename PS, int NCH>
-__global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                                 const double *__restrict__ pcc,
-                                                                 double *__restrict__ x, const int *done) {
-    const int row = xcd_block() * kProWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ void prolong_rows_body(int bid, int nblk, CartDev cd, Fine g, const PS *__restrict__ P,
+                                                  const double *__restrict__ pcc, double *__restrict__ x,
+                                                  const int *done) {
+    const int row = xcd_block(bid, nblk) * kProWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (row >= g.ny * g.nz) return;
     const int lane = threadIdx.x & 63;
     const int z = row / g.ny, y = row - z * g.ny;
@@ -269,6 +284,13 @@ __global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fin
         for (int s = 0; s < NS; ++s) acc += (ok[s] ? pv[s] : 0.0) * pcv[s];
         x[i] = xo + acc;
     }
+}
+
+template <int NS, typename PS, int NCH>
+__global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                                 const double *__restrict__ pcc,
+                                                                 double *__restrict__ x, const int *done) {
+    prolong_rows_body<NS, PS, NCH>(blockIdx.x, gridDim.x, cd, g, P, pcc, x, done);
 }
 
 // four wavefronts with one row each in flight measured fastest on the
@@ -659,6 +681,120 @@ void launch_export_cart(Ctx &c, Stage &s, double *d_vals) {
         hipLaunchKernelGGL(k_export_vals, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, s.Pbf, d_vals);
     else
         hipMemcpyAsync(d_vals, s.P64[s.cur], sizeof(double) * n, hipMemcpyDeviceToDevice, c.stream);
+}
+
+// ------------------------------------------------------- batched launches ----
+// Residual restriction and prolongation of every member's rectilinear stage,
+// one launch per template key (slots per cell, 64-cell chunks per row).
+
+// grids and template keys of a member's transfers: [0] residual restriction
+// rows (key NS * 8 + NCH), [1] gather (key NS * 2 + narrow), [2] prolongation
+// (key NS * 8 + NCH); lds = the restriction's dynamic LDS
+void bat_member_transfer(const Ctx &c, const Stage &s, int grid[3], int key[3], size_t *lds) {
+    const int nch = cdiv(c.nx, 64), nchk = nch == 1 ? 1 : (nch == 2 ? 2 : 4);
+    const int ns = s.ns <= 1 ? 1 : (s.ns <= 2 ? 2 : (s.ns <= 4 ? 4 : 8));
+    grid[0] = xcd_grid(s.cart.m[1] * c.nz);
+    key[0] = ns * 8 + nchk;
+    grid[1] = cdiv(s.M, 4);
+    key[1] = ns * 2 + (s.zwide <= 64 ? 1 : 0);
+    grid[2] = xcd_grid(cdiv(c.ny * c.nz, kProWaves));
+    key[2] = ns * 8 + nchk;
+    *lds = sizeof(double) * kRestrictWaves * (size_t)c.nx * s.ns;
+}
+
+#define BAT_LOCATE()                              \
+    int m, lb, nb;                                \
+    if (!bat_locate(gp, act, m, lb, nb)) return;  \
+    const BMember &d = D[m]
+
+template <int NS, typename PS, int NCH>
+__global__ __launch_bounds__(64 * kRestrictWaves) void k_restrict_rows_b(const BMember *D, BGroup gp, const int *act,
+                                                                         int bsel, int xsel) {
+    BAT_LOCATE();
+    restrict_rows_body<NS, PS, NCH, true, kRestrictWaves, kRestrictUnroll>(
+        lb, nb, d.cd, d.g, (const PS *)d.Pt, bvec(d, bsel), bvec(d, xsel), d.rpart, &d.status->done);
+}
+
+template <int NS, bool NARROW>
+__global__ __launch_bounds__(256) void k_restrict_gather_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    restrict_gather_body<NS, NARROW>(lb, nb, d.cd, d.g, d.M, d.rpart, d.dvec, &d.status->done);
+}
+
+template <int NS, typename PS, int NCH>
+__global__ __launch_bounds__(64 * kProWaves) void k_prolong_rows_b(const BMember *D, BGroup gp, const int *act,
+                                                                   int xsel) {
+    BAT_LOCATE();
+    prolong_rows_body<NS, PS, NCH>(lb, nb, d.cd, d.g, (const PS *)d.Pt, d.pc, bvec(d, xsel), &d.status->done);
+}
+
+#undef BAT_LOCATE
+
+template <typename PS>
+static void bat_rrows_t(Batch &B, const HGroup &h, int bsel, int xsel) {
+    const dim3 grid(h.g.total), blk(64 * kRestrictWaves);
+#define MSRSB_BRR(NS, NCH)                                                                                        \
+    case NS * 8 + NCH:                                                                                            \
+        hipLaunchKernelGGL((k_restrict_rows_b<NS, PS, NCH>), grid, blk, h.lds, B.stream, B.d_mem, h.g, B.d_act,   \
+                           bsel, xsel);                                                                           \
+        break
+    switch (h.key) {
+        MSRSB_BRR(1, 1); MSRSB_BRR(1, 2); MSRSB_BRR(1, 4);
+        MSRSB_BRR(2, 1); MSRSB_BRR(2, 2); MSRSB_BRR(2, 4);
+        MSRSB_BRR(4, 1); MSRSB_BRR(4, 2); MSRSB_BRR(4, 4);
+        MSRSB_BRR(8, 1); MSRSB_BRR(8, 2); MSRSB_BRR(8, 4);
+    default: break;
+    }
+#undef MSRSB_BRR
+}
+
+template <typename PS>
+static void bat_prolong_t(Batch &B, const HGroup &h, int xsel) {
+    const dim3 grid(h.g.total), blk(64 * kProWaves);
+#define MSRSB_BPR(NS, NCH)                                                                                        \
+    case NS * 8 + NCH:                                                                                            \
+        hipLaunchKernelGGL((k_prolong_rows_b<NS, PS, NCH>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act, xsel); \
+        break
+    switch (h.key) {
+        MSRSB_BPR(1, 1); MSRSB_BPR(1, 2); MSRSB_BPR(1, 4);
+        MSRSB_BPR(2, 1); MSRSB_BPR(2, 2); MSRSB_BPR(2, 4);
+        MSRSB_BPR(4, 1); MSRSB_BPR(4, 2); MSRSB_BPR(4, 4);
+        MSRSB_BPR(8, 1); MSRSB_BPR(8, 2); MSRSB_BPR(8, 4);
+    default: break;
+    }
+#undef MSRSB_BPR
+}
+
+// d = P^T (b - A x) for every member (b, x: the selected vectors)
+void bat_residual_restrict(Batch &B, int bsel, int xsel) {
+    for (const HGroup &h : B.rrows) {
+        if (h.g.n == 0) continue;
+        if (B.mixed) bat_rrows_t<uint16_t>(B, h, bsel, xsel);
+        else bat_rrows_t<double>(B, h, bsel, xsel);
+    }
+    for (const HGroup &h : B.gather) {
+        if (h.g.n == 0) continue;
+        const dim3 grid(h.g.total), blk(256);
+#define MSRSB_BG(NS, NW)                                                                                          \
+    case NS * 2 + NW:                                                                                             \
+        hipLaunchKernelGGL((k_restrict_gather_b<NS, NW != 0>), grid, blk, 0, B.stream, B.d_mem, h.g, B.d_act);   \
+        break
+        switch (h.key) {
+            MSRSB_BG(1, 0); MSRSB_BG(1, 1); MSRSB_BG(2, 0); MSRSB_BG(2, 1);
+            MSRSB_BG(4, 0); MSRSB_BG(4, 1); MSRSB_BG(8, 0); MSRSB_BG(8, 1);
+        default: break;
+        }
+#undef MSRSB_BG
+    }
+}
+
+// x += P p_c for every member (x: the selected vector)
+void bat_prolong(Batch &B, int xsel) {
+    for (const HGroup &h : B.prolong) {
+        if (h.g.n == 0) continue;
+        if (B.mixed) bat_prolong_t<uint16_t>(B, h, xsel);
+        else bat_prolong_t<double>(B, h, xsel);
+    }
 }
 
 }  // namespace msrsb

@@ -213,6 +213,7 @@ struct ProfScope {
 
 // ---- error helpers (capi.hip) ----
 void set_error(const char *fmt, ...);
+void clear_error();
 int hip_fail(hipError_t e, const char *what);
 
 // ---- fine-grid kernels (k_fine.hip) ----
@@ -236,6 +237,7 @@ void launch_zero_inactive(Ctx &c, double *x);
 void launch_norm_finish(Ctx &c, double *out_sq, const int *done);
 void launch_check(Ctx &c, double rtol, int max_iters, int count);
 void launch_gmres_begin(Ctx &c, double rtol, int max_iters);
+void launch_begin_solve(Ctx &c, const double *b, double *x);
 void launch_symmetrize(Ctx &c, double *A, int M, int Mp);
 size_t rap_part_doubles(int ns, int nbox);
 void *ctx_alloc(Ctx &c, size_t bytes);
@@ -300,3 +302,6 @@ void launch_dyn_rap(Ctx &c, Stage &s);
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace msrsb
+
+// the public context handle is the context itself
+struct msrsb_ctx : public msrsb::Ctx {};
