@@ -36,7 +36,9 @@ struct BMember {
     uint16_t *Pbf;
     double *rpart, *dvec, *pc;
     const int32_t *pc_map;
-    const double *Ainv;
+    double *Ac, *Ainv, *rap_part;  // coarse operator, its inverse, Galerkin partial sums
+    double *cbuf;                  // inverse panel and pivot-block buffers
+    long cbuf_n;
     const double *bcrhs;
     double *b, *src, *x, *r, *tmp, *V, *Z;
     float *Vf;
@@ -127,6 +129,8 @@ struct Batch {
     int32_t *d_tab = nullptr;                     // every group's start/mem lists
     // launch groups
     Groups one, cells, red, passa, lilu, rrows, gather, gemv, prolong, sweep, init, bf16, nofuse;
+    Groups rapbox, rapgather, pad, gjcopy, gjpanel, gjupdate;
+    int max_tiles = 0;             // largest coarse inverse (64-wide tiles)
 };
 
 // ---- batched launchers (each kernel file) ----
@@ -145,9 +149,16 @@ int bat_member_lilu(const Ctx &c, BMember &d);
 void bat_residual_restrict(Batch &B, int bsel, int xsel);
 void bat_prolong(Batch &B, int xsel);
 void bat_member_transfer(const Ctx &c, const Stage &s, int grid[3], int key[3], size_t *lds);
+// Galerkin operator: grids of the box pass, the gather and the identity
+// padding (key: split-axis mask)
+void bat_member_rap(const Stage &s, int grid[3], int *key);
+void bat_rap(Batch &B);
 // k_coarse.hip
 void bat_coarse_solve(Batch &B);
 int bat_member_gemv(const Stage &s, int *key);
+// coarse inverse: grids of the copy, a panel step and an update step
+void bat_member_inverse(const Stage &s, int grid[3]);
+void bat_coarse_inverse(Batch &B);
 // k_sweep.hip
 void bat_sweep_begin(Batch &B, int max_sweeps);
 void bat_sweep_pair(Batch &B, int k, int npair, double omega, double tol, int max_sweeps);

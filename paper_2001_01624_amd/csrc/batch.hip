@@ -3,8 +3,7 @@
 // of the GMRES solve is one batched launch per kernel (per template key) over
 // all members, built from the kernel bodies of the single-context path, with
 // the member-wise stop rules of that path (device status flags, host reads at
-// the same points).  The coarse operators and inverses are built per member
-// (once per basis).
+// the same points), the Galerkin operators and coarse inverses included.
 #include <algorithm>
 #include <map>
 #include <vector>
@@ -24,7 +23,8 @@ struct GroupSpec {
 static void make_groups(const std::vector<GroupSpec> &spec, std::vector<int32_t> &tab, Groups &out,
                         std::vector<std::pair<Groups *, std::vector<size_t>>> &fix) {
     std::map<int, std::vector<GroupSpec>> by;
-    for (const GroupSpec &g : spec) by[g.key].push_back(g);
+    for (const GroupSpec &g : spec)
+        if (g.grid > 0) by[g.key].push_back(g);  // members without work stay out
     std::vector<size_t> offs;
     for (auto &kv : by) {
         HGroup h;
@@ -90,7 +90,11 @@ static void fill_member(const Ctx &c, BMember &d) {
     d.dvec = s.dvec;
     d.pc = s.pc;
     d.pc_map = s.pc_map;
+    d.Ac = s.Ac;
     d.Ainv = s.Ainv;
+    d.rap_part = s.rap_part;
+    d.cbuf = c.cbuf;
+    d.cbuf_n = c.cbuf_n;
     d.bcrhs = c.bcrhs;
     d.b = c.b;
     d.src = c.src;
@@ -210,6 +214,7 @@ int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb
     }
     // launch groups
     std::vector<GroupSpec> one, cells, red, passa, nofuse, lilu, rrows, gather, gemv, prolong, sweep, init, bf16;
+    std::vector<GroupSpec> rapbox, rapgather, pad, gjcopy, gjpanel, gjupdate;
     for (int k = 0; k < n && !rc; ++k) {
         const Ctx &c = *mem[k];
         const Stage &s = c.stages[0];
@@ -238,6 +243,16 @@ int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb
         const int nsk = s.ns <= 1 ? 1 : (s.ns <= 2 ? 2 : (s.ns <= 4 ? 4 : 8));
         init.push_back({k, cdiv(c.N, kBlock), nsk, 0});
         if (B->mixed) bf16.push_back({k, cdiv((long)s.ns * c.N, kBlock), 0, 0});
+        int rg[3], rk = 0, ig[3];
+        bat_member_rap(s, rg, &rk);
+        rapbox.push_back({k, rg[0], rk, 0});
+        rapgather.push_back({k, rg[1], rk, 0});
+        pad.push_back({k, rg[2], 0, 0});
+        bat_member_inverse(s, ig);
+        gjcopy.push_back({k, ig[0], 0, 0});
+        gjpanel.push_back({k, ig[1], 0, 0});
+        gjupdate.push_back({k, ig[2], 0, 0});
+        B->max_tiles = std::max(B->max_tiles, ig[1]);
     }
     std::vector<int32_t> tab;
     std::vector<std::pair<Groups *, std::vector<size_t>>> fix;
@@ -254,6 +269,12 @@ int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb
     make_groups(sweep, tab, B->sweep, fix);
     make_groups(init, tab, B->init, fix);
     make_groups(bf16, tab, B->bf16, fix);
+    make_groups(rapbox, tab, B->rapbox, fix);
+    make_groups(rapgather, tab, B->rapgather, fix);
+    make_groups(pad, tab, B->pad, fix);
+    make_groups(gjcopy, tab, B->gjcopy, fix);
+    make_groups(gjpanel, tab, B->gjpanel, fix);
+    make_groups(gjupdate, tab, B->gjupdate, fix);
     for (const HGroup &h : B->rrows)
         if (h.lds > 65536) {
             set_error("batch rows too long for the restriction's LDS");
@@ -340,16 +361,12 @@ int msrsb_batch_update_basis(msrsb_batch *B, int max_sweeps, double tol, int32_t
     }
     if ((rc = upload_members(*B))) return rc;
     if (B->mixed) bat_to_bf16(*B);
-    // Galerkin operators and inverses, member by member
+    // Galerkin operators and their inverses
     for (const HGroup &h : B->one)
         hipLaunchKernelGGL(k_clear_flag_b, dim3(h.g.total), dim3(1), 0, B->stream, B->d_mem, h.g, B->d_act);
-    for (int m = 0; m < n; ++m) {
-        Ctx &c = *B->mem[m];
-        Stage &s = c.stages[0];
-        s.version++;
-        launch_rap(c, s);
-        launch_coarse_inverse(c, s);
-    }
+    for (int m = 0; m < n; ++m) B->mem[m]->stages[0].version++;
+    bat_rap(*B);
+    bat_coarse_inverse(*B);
     if ((rc = read_statuses(*B))) return rc;
     for (int m = 0; m < n; ++m) {
         if (B->h_flag[m] & 1) {

@@ -175,8 +175,8 @@ __device__ inline void load_tile(double (*S)[kLd], const double *__restrict__ sr
     }
 }
 
-__global__ __launch_bounds__(kGJThreads) void k_gj_diag(const double *__restrict__ A, int Mp, int k0,
-                                                        double *__restrict__ Dinv, int *flag, bool general) {
+__device__ __forceinline__ void gj_diag_body(const double *__restrict__ A, int Mp, int k0, double *__restrict__ Dinv,
+                                             int *flag, bool general) {
     __shared__ double Ms[T_][kLd], Ws[16][kLd], Cb[T_][17];
     load_tile(Ms, A + (long)k0 * Mp + k0, Mp);
     __syncthreads();
@@ -184,12 +184,17 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_diag(const double *__restrict
     for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dinv[e] = Ms[e / T_][e % T_];
 }
 
+__global__ __launch_bounds__(kGJThreads) void k_gj_diag(const double *__restrict__ A, int Mp, int k0,
+                                                        double *__restrict__ Dinv, int *flag, bool general) {
+    gj_diag_body(A, Mp, k0, Dinv, flag, general);
+}
+
 // Workgroup t: row panel A[K,t] <- D^{-1} A[K,t] and a copy C[t] = A[t,K]
 // of the column panel (taken before the update).
-__global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A, int Mp, int K,
-                                                         const double *__restrict__ Dinv, double *__restrict__ C) {
+__device__ __forceinline__ void gj_panel_body(int bid, int nblk, double *__restrict__ A, int Mp, int K,
+                                              const double *__restrict__ Dinv, double *__restrict__ C) {
     __shared__ double Ds[T_][kLd], Bs[T_][kLd];
-    const int t = blockIdx.x;
+    const int t = bid;
     if (t == K) return;
     const int k0 = K * T_, c0 = t * T_;
     load_tile(Ds, Dinv, T_);
@@ -218,16 +223,20 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A,
             for (int r = 0; r < 4; ++r) A[(long)(k0 + mm_row(bi, r)) * Mp + c0 + mm_col(bj)] = acc[bi][bj][r];
 }
 
+__global__ __launch_bounds__(kGJThreads) void k_gj_panel(double *__restrict__ A, int Mp, int K,
+                                                         const double *__restrict__ Dinv, double *__restrict__ C) {
+    gj_panel_body(blockIdx.x, gridDim.x, A, Mp, K, Dinv, C);
+}
+
 // Trailing update of step K over all tiles (I, J).  Workgroup 0 takes tile
 // (K+1, K+1) and, after its update, inverts it into Dnext.
-__global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A, int Mp, int K, int nt,
-                                                          const double *__restrict__ Dinv,
-                                                          const double *__restrict__ C, double *__restrict__ Dnext,
-                                                          int *flag, bool general) {
+__device__ __forceinline__ void gj_update_body(int bid, int nblk, double *__restrict__ A, int Mp, int K, int nt,
+                                               const double *__restrict__ Dinv, const double *__restrict__ C,
+                                               double *__restrict__ Dnext, int *flag, bool general) {
     __shared__ double Cs[T_][kLd], Bs[T_][kLd];
     // tile of this workgroup: 0 -> (K+1, K+1) (when it exists), then the rest
     const int L = K + 1 < nt ? K + 1 : -1;
-    int b = blockIdx.x, I, J;
+    int b = bid, I, J;
     if (L >= 0) {
         if (b == 0) {
             I = J = L;
@@ -301,6 +310,13 @@ __global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A
         gj_invert_lds(Cs, Bs, reinterpret_cast<double (*)[17]>(&Bs[16][0]), flag, general);
         for (int e = threadIdx.x; e < T_ * T_; e += blockDim.x) Dnext[e] = Cs[e / T_][e % T_];
     }
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_update(double *__restrict__ A, int Mp, int K, int nt,
+                                                          const double *__restrict__ Dinv,
+                                                          const double *__restrict__ C, double *__restrict__ Dnext,
+                                                          int *flag, bool general) {
+    gj_update_body(blockIdx.x, gridDim.x, A, Mp, K, nt, Dinv, C, Dnext, flag, general);
 }
 
 void launch_coarse_inverse(Ctx &c, Stage &s) { launch_coarse_inverse_of(c, s.Ac, s.Ainv, s.Mp, false); }
@@ -429,6 +445,73 @@ void bat_coarse_solve(Batch &B) {
         default: break;
         }
 #undef MSRSB_BGEMV
+    }
+}
+
+// Coarse inverses of every member: the copy, the first pivot block, then per
+// step K one panel launch and one update launch over all members whose
+// matrices have more than K tiles (the others' workgroups return).
+void bat_member_inverse(const Stage &s, int grid[3]) {
+    const int nt = s.Mp / T_;
+    grid[0] = cdiv((long)s.Mp * s.Mp, 2048);  // 8 entries per thread
+    grid[1] = nt;
+    grid[2] = nt * nt;
+}
+
+#define BAT_LOCATE()                              \
+    int m, lb, nb;                                \
+    if (!bat_locate(gp, act, m, lb, nb)) return;  \
+    const BMember &d = D[m]
+
+__device__ inline double *bat_dbuf(const BMember &d, int i) { return d.cbuf + (size_t)(d.cbuf_n + i * T_) * T_; }
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_copy_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    (void)nb;
+    static_assert(kGJThreads == 256, "2048 entries per workgroup");
+    const long n = (long)d.Mp * d.Mp, e0 = (long)lb * 2048 + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const long e = e0 + (long)q * kGJThreads;
+        if (e < n) d.Ainv[e] = d.Ac[e];
+    }
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_diag_b(const BMember *D, BGroup gp, const int *act) {
+    BAT_LOCATE();
+    (void)lb;
+    (void)nb;
+    gj_diag_body(d.Ainv, d.Mp, 0, bat_dbuf(d, 0), d.flag, false);
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_panel_b(const BMember *D, BGroup gp, const int *act, int K) {
+    BAT_LOCATE();
+    if (K >= d.Mp / T_) return;
+    gj_panel_body(lb, nb, d.Ainv, d.Mp, K, bat_dbuf(d, K & 1), d.cbuf);
+}
+
+__global__ __launch_bounds__(kGJThreads) void k_gj_update_b(const BMember *D, BGroup gp, const int *act, int K) {
+    BAT_LOCATE();
+    const int nt = d.Mp / T_;
+    if (K >= nt) return;
+    gj_update_body(lb, nb, d.Ainv, d.Mp, K, nt, bat_dbuf(d, K & 1), d.cbuf, bat_dbuf(d, (K + 1) & 1), d.flag,
+                   false);
+}
+
+#undef BAT_LOCATE
+
+void bat_coarse_inverse(Batch &B) {
+    for (const HGroup &h : B.gjcopy)
+        hipLaunchKernelGGL(k_gj_copy_b, dim3(h.g.total), dim3(kGJThreads), 0, B.stream, B.d_mem, h.g, B.d_act);
+    for (const HGroup &h : B.one)
+        hipLaunchKernelGGL(k_gj_diag_b, dim3(h.g.total), dim3(kGJThreads), 0, B.stream, B.d_mem, h.g, B.d_act);
+    for (int K = 0; K < B.max_tiles; ++K) {
+        for (const HGroup &h : B.gjpanel)
+            hipLaunchKernelGGL(k_gj_panel_b, dim3(h.g.total), dim3(kGJThreads), 0, B.stream, B.d_mem, h.g, B.d_act,
+                               K);
+        for (const HGroup &h : B.gjupdate)
+            hipLaunchKernelGGL(k_gj_update_b, dim3(h.g.total), dim3(kGJThreads), 0, B.stream, B.d_mem, h.g, B.d_act,
+                               K);
     }
 }
 

@@ -416,12 +416,12 @@ __device__ inline void box_range(const CartDev &cd, int a, int L, int &lo, int &
 }
 
 template <int AM, typename PS>
-__global__ __launch_bounds__(kRapThreads) void k_rap_box(CartDev cd, Fine g, const PS *__restrict__ P,
-                                                         double *__restrict__ part, int nbox) {
+__device__ __forceinline__ void rap_box_body(int bid, int nblk, CartDev cd, Fine g, const PS *__restrict__ P,
+                                             double *__restrict__ part, int nbox) {
     constexpr int NS = 1 << __builtin_popcount(AM);
     using Lay = RapLayout<NS>;
     __shared__ double red[(kRapThreads / 64) * 64];
-    const int box = xcd_block();
+    const int box = xcd_block(bid, nblk);
     if (box >= nbox) return;
     const int Lc[3] = {box % cd.m[0], (box / cd.m[0]) % cd.m[1], box / (cd.m[0] * cd.m[1])};
     int lo[3], hi[3], ext[3];
@@ -515,14 +515,20 @@ __global__ __launch_bounds__(kRapThreads) void k_rap_box(CartDev cd, Fine g, con
     }
 }
 
+template <int AM, typename PS>
+__global__ __launch_bounds__(kRapThreads) void k_rap_box(CartDev cd, Fine g, const PS *__restrict__ P,
+                                                         double *__restrict__ part, int nbox) {
+    rap_box_body<AM, PS>(blockIdx.x, gridDim.x, cd, g, P, part, nbox);
+}
+
 template <int AM>
-__global__ __launch_bounds__(128) void k_rap_gather(CartDev cd, const double *__restrict__ part,
-                                                    double *__restrict__ Ac, int M, int Mp) {
+__device__ __forceinline__ void rap_gather_body(int bid, int nblk, CartDev cd, const double *__restrict__ part,
+                                                double *__restrict__ Ac, int M, int Mp) {
     constexpr int NS = 1 << __builtin_popcount(AM);
     constexpr int NB = __builtin_popcount(AM);
     constexpr int NOFF = NB == 0 ? 1 : (NB == 1 ? 5 : (NB == 2 ? 25 : 125));
     using Lay = RapLayout<NS>;
-    const int j = blockIdx.x, o = threadIdx.x;
+    const int j = bid, o = threadIdx.x;
     if (j >= M || o >= NOFF) return;
     const int m[3] = {cd.m[0], cd.m[1], cd.m[2]};
     const int cid = cd.present[j];
@@ -597,9 +603,19 @@ __global__ __launch_bounds__(128) void k_rap_gather(CartDev cd, const double *__
     Ac[(long)kc * Mp + j] = sum;
 }
 
-__global__ void k_pad_identity(double *A, int M, int Mp) {
-    const int k = M + blockIdx.x * blockDim.x + threadIdx.x;
+template <int AM>
+__global__ __launch_bounds__(128) void k_rap_gather(CartDev cd, const double *__restrict__ part,
+                                                    double *__restrict__ Ac, int M, int Mp) {
+    rap_gather_body<AM>(blockIdx.x, gridDim.x, cd, part, Ac, M, Mp);
+}
+
+__device__ __forceinline__ void pad_identity_body(int bid, int nblk, double *A, int M, int Mp) {
+    const int k = M + bid * blockDim.x + threadIdx.x;
     if (k < Mp) A[(long)k * Mp + k] = 1.0;
+}
+
+__global__ void k_pad_identity(double *A, int M, int Mp) {
+    pad_identity_body(blockIdx.x, gridDim.x, A, M, Mp);
 }
 
 // A := (A + A^T)/2 on the leading M x M part (rows are built independently).
@@ -795,6 +811,94 @@ void bat_prolong(Batch &B, int xsel) {
         if (B.mixed) bat_prolong_t<uint16_t>(B, h, xsel);
         else bat_prolong_t<double>(B, h, xsel);
     }
+}
+
+// Galerkin operators of every member: the box pass and the gather per
+// split-axis mask, then the identity on the padding rows.
+void bat_member_rap(const Stage &s, int grid[3], int *key) {
+    const CartDev &cd = s.cart;
+    int am = 0;
+    for (int a = 0; a < 3; ++a)
+        if (cd.bit[a] >= 0) am |= 1 << a;
+    grid[0] = xcd_grid(cd.m[0] * cd.m[1] * cd.m[2]);
+    grid[1] = s.M;
+    grid[2] = s.Mp > s.M ? cdiv(s.Mp - s.M, 64) : 0;
+    *key = am;
+}
+
+template <int AM, typename PS>
+__global__ __launch_bounds__(kRapThreads) void k_rap_box_b(const BMember *D, BGroup gp, const int *act) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    rap_box_body<AM, PS>(lb, nb, d.cd, d.g, (const PS *)d.Pt, d.rap_part, d.cd.m[0] * d.cd.m[1] * d.cd.m[2]);
+}
+
+template <int AM>
+__global__ __launch_bounds__(128) void k_rap_gather_b(const BMember *D, BGroup gp, const int *act) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    rap_gather_body<AM>(lb, nb, d.cd, d.rap_part, d.Ac, d.M, d.Mp);
+}
+
+__global__ void k_pad_identity_b(const BMember *D, BGroup gp, const int *act) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    pad_identity_body(lb, nb, d.Ac, d.M, d.Mp);
+}
+
+// A_c = 0 before the gather adds its entries (grid: the coarse copy's,
+// 2048 entries per workgroup)
+__global__ __launch_bounds__(256) void k_zero_ac_b(const BMember *D, BGroup gp, const int *act) {
+    int m, lb, nb;
+    if (!bat_locate(gp, act, m, lb, nb)) return;
+    const BMember &d = D[m];
+    const long n = (long)d.Mp * d.Mp, e0 = (long)lb * 2048 + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const long e = e0 + (long)q * 256;
+        if (e < n) d.Ac[e] = 0.0;
+    }
+}
+
+template <typename PS>
+static void bat_rap_t(Batch &B) {
+    for (const HGroup &h : B.gjcopy)
+        hipLaunchKernelGGL(k_zero_ac_b, dim3(h.g.total), dim3(256), 0, B.stream, B.d_mem, h.g, B.d_act);
+    for (const HGroup &h : B.rapbox) {
+#define MSRSB_BRB(AM)                                                                                           \
+    case AM:                                                                                                    \
+        hipLaunchKernelGGL((k_rap_box_b<AM, PS>), dim3(h.g.total), dim3(kRapThreads), 0, B.stream, B.d_mem, h.g, \
+                           B.d_act);                                                                            \
+        break
+        switch (h.key) {
+            MSRSB_BRB(0); MSRSB_BRB(1); MSRSB_BRB(2); MSRSB_BRB(3);
+            MSRSB_BRB(4); MSRSB_BRB(5); MSRSB_BRB(6); MSRSB_BRB(7);
+        default: break;
+        }
+#undef MSRSB_BRB
+    }
+    for (const HGroup &h : B.rapgather) {
+#define MSRSB_BRG(AM)                                                                                           \
+    case AM:                                                                                                    \
+        hipLaunchKernelGGL((k_rap_gather_b<AM>), dim3(h.g.total), dim3(128), 0, B.stream, B.d_mem, h.g, B.d_act); \
+        break
+        switch (h.key) {
+            MSRSB_BRG(0); MSRSB_BRG(1); MSRSB_BRG(2); MSRSB_BRG(3);
+            MSRSB_BRG(4); MSRSB_BRG(5); MSRSB_BRG(6); MSRSB_BRG(7);
+        default: break;
+        }
+#undef MSRSB_BRG
+    }
+    for (const HGroup &h : B.pad)
+        hipLaunchKernelGGL(k_pad_identity_b, dim3(h.g.total), dim3(64), 0, B.stream, B.d_mem, h.g, B.d_act);
+}
+
+void bat_rap(Batch &B) {
+    if (B.mixed) bat_rap_t<uint16_t>(B);
+    else bat_rap_t<double>(B);
 }
 
 }  // namespace msrsb
