@@ -536,15 +536,18 @@ def ensemble_leg(args):
     kernel over all members); reported device-resident (basis + solve, as the
     request legs) and end to end (with set-up and teardown).  For comparison
     the same members through the serving loop, eight concurrent contexts.
-    Per solve, the largest difference of the mixed solution from the FP64
-    one relative to the FP64 solution's largest entry."""
+    End to end, the pipelined form (serve.run_ensemble: batches of 64
+    members, the next batch set up and the previous one torn down on host
+    threads while the current one runs).  Per solve, the largest difference
+    of the mixed solution from the FP64 one relative to the FP64 solution's
+    largest entry."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
     import torch
 
     from paper_2001_01624_amd import capi
-    from paper_2001_01624_amd.serve import Server
+    from paper_2001_01624_amd.serve import Server, run_ensemble
     from workloads.requests import ensemble_batch
 
     out, sols = {}, {}
@@ -573,11 +576,15 @@ def ensemble_leg(args):
             for g in gs:
                 g.close()
             t4 = time.perf_counter()
-            rec = {"cells_per_s": cells / (t3 - t1), "cells_per_s_end_to_end": cells / (t4 - t0),
+            rec = {"cells_per_s": cells / (t3 - t1), "cells_per_s_one_batch_end_to_end": cells / (t4 - t0),
                    "basis_s": t2 - t1, "solve_s": t3 - t2, "setup_s": t1 - t0, "teardown_s": t4 - t3,
                    "iters_mean": float(np.mean(it)), "iters_max": int(max(it)), "sweeps_max": int(max(sweeps)),
                    "all_converged": all(s == 0 for s in st), "max_relres": float(max(rel))}
         sols[prec] = x_host
+        reqs = ensemble_batch(args.ensemble_members, seed=0)
+        pipe = run_ensemble(reqs, opt, chunk=64, threads=8, rtol=RTOL)
+        rec["pipelined_end_to_end"] = {"cells_per_s": pipe["cells_per_s"], "makespan_s": pipe["makespan_s"],
+                                       "all_converged": pipe["all_converged"], "chunk": 64, "host_threads": 8}
         reqs = ensemble_batch(args.ensemble_members, seed=0)
         sv = Server(slots=8, options=opt, rtol=RTOL, dynamic=False).run(reqs, realtime=False)
         out[prec] = {"batched": rec,

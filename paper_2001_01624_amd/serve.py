@@ -157,3 +157,75 @@ class Server:
             "all_converged": all(all(s == 0 for s in r.status) for r in ok),
             "max_relres": max((max(r.relres) for r in ok if r.relres), default=0.0),
         }
+
+
+def run_ensemble(requests, options=None, chunk=64, threads=8, rtol=1e-6, max_iters=3000, max_sweeps=100,
+                 basis_tol=1e-3, keep_solutions=False):
+    """Solve an ensemble available at once (one stage and one source per
+    request) in batches of ``chunk`` members (``msrsb_batch_*``: one launch
+    per kernel over a batch), pipelined: ``threads - 1`` host threads set up
+    the next batch's contexts and tear down the previous one's while the
+    current batch runs on the device.  Each member's results are those of
+    solving it alone, bit for bit.  Returns aggregate statistics; per-request
+    results are stored on the request objects."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    opts = options if options is not None else capi.default_options(smoother="ilu0_line", outer="gmres")
+    reqs = list(requests)
+    groups = [reqs[k:k + chunk] for k in range(0, len(reqs), chunk)]
+    # each set-up thread enqueues on a stream of its own, each batch runs on
+    # its own stream: set-up, device work and teardown never wait for each
+    # other's queued work
+    local = threading.local()
+    t0 = time.perf_counter()
+
+    def setup(r):
+        if not hasattr(local, "stream"):
+            local.stream = torch.cuda.Stream()
+        return capi.Solver(r.problem, r.partitions, opts, stream=local.stream)
+
+    def teardown(gs, xs, rs):
+        for g, x, r in zip(gs, xs, rs):
+            if keep_solutions:
+                r.solutions.append(x.cpu().numpy())
+            g.close()
+            r.finished = time.perf_counter() - t0
+
+    with ThreadPoolExecutor(max(1, threads - 1)) as ex:
+        pending = [ex.submit(setup, r) for r in groups[0]] if groups else []
+        tails = []
+        for k, grp in enumerate(groups):
+            gs = [f.result() for f in pending]
+            pending = [ex.submit(setup, r) for r in groups[k + 1]] if k + 1 < len(groups) else []
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                xs = [torch.zeros(g.N, dtype=torch.float64, device="cuda") for g in gs]
+                qs = [torch.as_tensor(np.asarray(r.sources[0], dtype=np.float64)).to("cuda", non_blocking=False)
+                      for r in grp]
+            b = capi.Batch(gs, stream=stream)
+            try:
+                b.update_basis(max_sweeps=max_sweeps, tol=basis_tol)
+                it, rel, st = b.solve(xs, sources=qs, rtol=rtol, max_iters=max_iters)
+            finally:
+                b.close()
+            for r, i, e, s in zip(grp, it, rel, st):
+                r.iters.append(i)
+                r.relres.append(e)
+                r.status.append(s)
+            tails.append(ex.submit(teardown, gs, xs, grp))
+        for f in tails:
+            f.result()
+    makespan = time.perf_counter() - t0
+    cells = sum(r.cells for r in reqs)
+    return {
+        "requests": len(reqs),
+        "completed": len(reqs),
+        "solves": len(reqs),
+        "cells": cells,
+        "makespan_s": makespan,
+        "cells_per_s": cells / makespan if makespan > 0 else 0.0,
+        "all_converged": all(all(s == 0 for s in r.status) for r in reqs),
+        "max_relres": max((max(r.relres) for r in reqs if r.relres), default=0.0),
+    }

@@ -165,3 +165,22 @@ def test_batch_rejects(capi):
         assert e.value.code == capi.E_INVAL and "member 1" in str(e.value), k
     for g in gs + bad:
         g.close()
+
+
+def test_pipelined_ensemble_equals_alone(capi):
+    # batches of two members, set up and torn down on host threads while the
+    # previous batch runs: every member's result is that of its own solve
+    from paper_2001_01624_amd.serve import run_ensemble
+    from workloads.requests import Request
+
+    ms = members()[:5]
+    srcs = sources_for(ms, k=1)
+    opt = capi.default_options(smoother="ilu0_line", outer="gmres", precision="mixed", restart=16)
+    a = alone(capi, ms, srcs, opt, 1e-6, 400, keep=(False,))
+    reqs = [Request(k, 0.0, p, [{"kind": "cartesian", "coarse_dims": cd}], [q[0]], "member")
+            for k, ((p, cd), q) in enumerate(zip(ms, srcs))]
+    st = run_ensemble(reqs, opt, chunk=2, threads=3, rtol=1e-6, max_iters=400, keep_solutions=True)
+    assert st["all_converged"] and st["completed"] == len(ms)
+    for r, ra in zip(reqs, a):
+        assert r.iters == ra["it"] and r.relres == ra["rel"]
+        assert np.array_equal(r.solutions[0], ra["x"][0].cpu().numpy()), r.rid
