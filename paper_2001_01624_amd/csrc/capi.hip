@@ -700,7 +700,18 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
     s.xnmap = (uint8_t *)ctx_alloc(c, (size_t)6 * ns * N);
     if (!s.xcnt || !s.xnmap) return MSRSB_E_NOMEM;
     launch_xmap_build(c, s);
-    // chunk tables of the support lists
+    // chunk tables of the support lists.  Galerkin rows: the shortest chunk
+    // (more wavefronts) whose partial rows fit the stage's partial-row bytes
+    int rch = kXRapChunkMin;
+    for (; rch < kXRapChunk; rch *= 2) {
+        size_t rows = 0;
+        for (int j = 0; j < M; ++j) {
+            const int nr = cdiv(cnt[j + 1] - cnt[j], rch);
+            if (nr > 1) rows += nr;
+        }
+        if (rows * (size_t)s.Mp * 8 <= xrap_part_bytes((size_t)cnt[M], s.Mp)) break;
+    }
+    s.xrchunk = rch;
     std::vector<int32_t> cblk, cfirst(M + 1), rcblk, rcfirst(M + 1), rrow;
     int nrow = 0;
     for (int j = 0; j < M; ++j) {
@@ -708,7 +719,7 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
         cfirst[j] = (int32_t)cblk.size();
         for (int k = 0; k < std::max(1, cdiv(len, kXChunk)); ++k) cblk.push_back(j);
         rcfirst[j] = (int32_t)rcblk.size();
-        const int nr = std::max(1, cdiv(len, kXRapChunk));
+        const int nr = std::max(1, cdiv(len, rch));
         for (int k = 0; k < nr; ++k) {
             rcblk.push_back(j);
             rrow.push_back(nr > 1 ? nrow++ : -1);
@@ -1293,7 +1304,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             const size_t nsN = (size_t)8 * N;
             b += (o.precision == MSRSB_MIXED ? nsN * 10 : nsN * 16) + nsN * 9 + N * 4 + 16 * (size_t)Mp * Mp + 16 * Mp;
             b += 6 * nsN + N;  // neighbour slot maps
-            b += (2 * nsN / kXRapChunk + 1) * (size_t)Mp * 8 + (nsN / kXChunk + M) * 8;  // chunk partials
+            b += xrap_part_bytes(nsN, Mp) + (nsN / kXChunk + M) * 8;  // chunk partials
             cb = std::max(cb, Mp);
             continue;
         }
@@ -1303,7 +1314,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             const long Mf = 2L * pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
             b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
             b += (size_t)6 * 16 * N + N;  // neighbour slot maps
-            b += (2 * 16 * N / kXRapChunk + 1) * (size_t)cdiv(Mf, kTile) * kTile * 8 + (16 * N / kXChunk + Mf) * 8;
+            b += xrap_part_bytes((size_t)16 * N, (long)cdiv(Mf, kTile) * kTile) + (16 * N / kXChunk + Mf) * 8;
         }
         long M = (long)pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
         if (parts[k].kind == MSRSB_PART_FAULT_CUT) M *= 2;

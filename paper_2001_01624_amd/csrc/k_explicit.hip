@@ -253,8 +253,12 @@ void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done) {
 // one wavefront walks the support list of block j; every face (a, b) with
 // P_aj - P_bj != 0 is taken once (from a, and from b only when a is not in
 // the support), and its contributions T g_j g_k are summed per column k by
-// fixed-shape wave reductions committed in a fixed order.
-// One wavefront per chunk of at most kXRapChunk entries of a block's list; a
+// fixed-shape wave reductions committed in a fixed order.  A lane first adds
+// up its cell's contributions to the columns of the cell's own slots (the
+// boundary term and the six faces), so those take one reduction per slot
+// and entry rather than one per face; columns that only a neighbour holds
+// are committed face by face.
+// One wavefront per chunk of `chunk` entries of a block's list; a
 // block with several chunks sums each into a partial row of its own, added
 // in chunk order by k_xrap_finish.
 // LDSROW: the row is accumulated in LDS (Mp doubles) and stored once at the
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
                                              const int32_t *__restrict__ cell,
                                              const uint8_t *__restrict__ slot, const PS *__restrict__ P,
                                              const double *__restrict__ bcdiag, double *__restrict__ Ac,
-                                             double *__restrict__ rpart, int Mp) {
+                                             double *__restrict__ rpart, int Mp, int chunk) {
     extern __shared__ double srow[];
     const int ch = blockIdx.x, j = rcblk[ch], lane = threadIdx.x;
     const long N = g.N;
@@ -277,7 +281,7 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
         for (int k = lane; k < Mp; k += 64) srow[k] = 0.0;
         __syncthreads();
     }
-    const int k0 = ptr[j] + (ch - rcfirst[j]) * kXRapChunk, k1 = min(k0 + kXRapChunk, ptr[j + 1]);
+    const int k0 = ptr[j] + (ch - rcfirst[j]) * chunk, k1 = min(k0 + chunk, ptr[j + 1]);
     // each wavefront sums one row's contributions per column k with a
     // ballot over the lanes' columns and a wave sum per distinct column
     auto commit = [&](int kb, double v) {
@@ -305,15 +309,14 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
             pa[t] = t < ns ? ld_basis(P, (long)t * N + a) : 0.0;
         }
         const double Paj = live ? ld_basis(P, (long)slot[k] * N + a) : 0.0;
+        // the lane's contributions to the columns of a's own slots, summed
+        // over the boundary term and the six faces before one commit per slot
+        double acc[NSX];
         // boundary term: bc_a P_aj P_ak over a's slots
         {
             const double bc = live ? bcdiag[a] : 0.0;
 #pragma unroll
-            for (int t = 0; t < NSX; ++t) {
-                if (t >= ns) break;
-                const bool on = live && bc > 0.0 && la[t] >= 0;
-                commit(on ? la[t] : -1, on ? bc * Paj * pa[t] : 0.0);
-            }
+            for (int t = 0; t < NSX; ++t) acc[t] = live && bc > 0.0 && la[t] >= 0 ? bc * Paj * pa[t] : 0.0;
         }
         for (int q = 0; q < 6; ++q) {
             const int ax = q >> 1;
@@ -355,21 +358,17 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
             const bool take = T != 0.0 && !(bin && b < a);
             const double gj = take ? Paj - Pbj : 0.0;
             const bool act = take && gj != 0.0;
-            // columns: blocks of a (with b's value of the same block), then blocks only of b
+            // columns: blocks of a (with b's value of the same block) into the
+            // lane's sums, then blocks only of b
 #pragma unroll
             for (int t = 0; t < NSX; ++t) {
-                if (t >= ns) break;
-                int kb = -1;
-                double v = 0.0;
                 if (act && la[t] >= 0) {
-                    kb = la[t];
                     double po = 0.0;
 #pragma unroll
                     for (int u = 0; u < NSX; ++u)
-                        if (lb[u] == kb) po = pb[u];
-                    v = T * gj * (pa[t] - po);
+                        if (lb[u] == la[t]) po = pb[u];
+                    acc[t] += T * gj * (pa[t] - po);
                 }
-                commit(kb, v);
             }
 #pragma unroll
             for (int t = 0; t < NSX; ++t) {
@@ -388,6 +387,11 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
                 }
                 commit(kb, v);
             }
+        }
+#pragma unroll
+        for (int t = 0; t < NSX; ++t) {
+            if (t >= ns) break;
+            commit(live && la[t] >= 0 ? la[t] : -1, acc[t]);
         }
     }
     if (LDSROW) {
@@ -427,7 +431,8 @@ void launch_xrap(Ctx &c, Stage &s) {
     const size_t lds = sizeof(double) * (size_t)s.Mp;
 #define MSRSB_XRAP1(NSX, PS, PP, L)                                                                             \
     hipLaunchKernelGGL((k_xrap<NSX, PS, L>), dim3(s.nxrch), dim3(64), L ? lds : 0, c.stream, g, s.ns, s.xsb,     \
-                       s.xptr, s.xrcblk, s.xrcfirst, s.xrrow, s.xcell, s.xslot, PP, c.bcdiag, s.Ac, s.xrpart, s.Mp)
+                       s.xptr, s.xrcblk, s.xrcfirst, s.xrrow, s.xcell, s.xslot, PP, c.bcdiag, s.Ac, s.xrpart, s.Mp,  \
+                       s.xrchunk)
 #define MSRSB_XRAP(PS, PP, L)                                \
     {                                                        \
         if (s.ns <= 8) MSRSB_XRAP1(8, PS, PP, L);            \

@@ -19,7 +19,15 @@ constexpr int kMaxRestart = 64;
 constexpr int kMaxXSlots = 32;   // slots per cell of an explicit (fault-cut) stage
 constexpr int kMaxXBlocks = 32768;  // blocks of an explicit stage (dense coarse operator)
 constexpr int kXChunk = 2048;    // support-list entries per restriction workgroup (explicit stages)
-constexpr int kXRapChunk = 8192; // support-list entries per Galerkin-row wavefront (explicit stages)
+constexpr int kXRapChunk = 8192; // support-list entries per Galerkin-row wavefront (at most)
+constexpr int kXRapChunkMin = 1024;  // shortest Galerkin-row chunk of an explicit stage
+// bytes of Galerkin partial rows an explicit stage of `entries` support
+// entries and Mp padded blocks may hold: what the longest chunks need, or
+// 16 bytes per entry (room for the shorter chunks) if that is more
+inline size_t xrap_part_bytes(size_t entries, long Mp) {
+    const size_t b = (2 * entries / kXRapChunk + 1) * (size_t)Mp * 8;
+    return b > 16 * entries ? b : 16 * entries;
+}
 
 // Geometry of the fine box as the kernels see it.
 struct Fine {
@@ -94,6 +102,7 @@ struct Stage {
     // of each block; Galerkin chunks of blocks with more than one chunk sum
     // into partial rows (xrrow: row of each chunk, -1 = straight into A_c)
     int nxch = 0, nxrch = 0, nxrrow = 0;
+    int xrchunk = kXRapChunk;     // entries per Galerkin-row chunk
     int32_t *xcblk = nullptr, *xcfirst = nullptr;
     int32_t *xrcblk = nullptr, *xrcfirst = nullptr, *xrrow = nullptr;
     double *xpart = nullptr, *xrpart = nullptr;
