@@ -598,10 +598,9 @@ def ensemble_leg(args):
     return out
 
 
-def kernel_source_hash(path, name):
-    """sha256 of the text of the kernel template `name` in `path`: from the
-    template line before its definition to the closing brace at column 0."""
-    text = open(path).read()
+def _template_text(text, name):
+    """Text of the template `name` in a source: from the template line
+    before its definition to the closing brace at column 0 (None if absent)."""
     k = text.find(f" void {name}(")
     if k < 0:
         return None
@@ -609,7 +608,18 @@ def kernel_source_hash(path, name):
     end = text.find("\n}\n", k)
     if start < 0 or end < 0:
         return None
-    return hashlib.sha256(text[start:end + 3].encode()).hexdigest()
+    return text[start:end + 3]
+
+
+def kernel_source_hash(path, name):
+    """sha256 of the text of the kernel template `name` in `path` and of the
+    device body it runs (`name` without its k_ prefix, + `_body`), if any."""
+    text = open(path).read()
+    kern = _template_text(text, name)
+    if kern is None:
+        return None
+    body = _template_text(text, name[2:] + "_body") if name.startswith("k_") else None
+    return hashlib.sha256(((body or "") + kern).encode()).hexdigest()
 
 
 def traffic_record(kernel, precision):
