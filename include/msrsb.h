@@ -334,7 +334,10 @@ int msrsb_solve_async(msrsb_ctx *ctx, const double *d_source, double *d_p, doubl
  * every member converged, E_NOCONV when some did not (the others hold their
  * solutions), E_STATE before msrsb_batch_update_basis, E_INVAL, E_DEVICE.
  *
- * msrsb_batch_destroy frees the batch's own tables (not the members).
+ * msrsb_batch_destroy frees the batch's own tables (not the members).  The
+ * batch's tables (member descriptors and launch groups, a few hundred bytes
+ * per member) come from hipMalloc / hipHostMalloc at create, not from the
+ * members' allocators.  A batch is not thread-safe.
  */
 typedef struct msrsb_batch msrsb_batch;
 int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb_batch **out);
