@@ -697,8 +697,9 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
     s.xslot = (uint8_t *)ctx_alloc(c, std::max<size_t>(slot.size(), 1));
     if (!s.xslot || !upload(c, s.xslot, slot.data(), slot.size())) return MSRSB_E_NOMEM;
     s.xcnt = (uint8_t *)ctx_alloc(c, (size_t)N);
-    s.xnmap = (uint8_t *)ctx_alloc(c, (size_t)6 * ns * N);
-    if (!s.xcnt || !s.xnmap) return MSRSB_E_NOMEM;
+    if (ns <= kXNibSlots) s.xnib = (uint64_t *)ctx_alloc(c, (size_t)6 * 8 * N);
+    else s.xnmap = (uint8_t *)ctx_alloc(c, (size_t)6 * ns * N);
+    if (!s.xcnt || !(s.xnmap || s.xnib)) return MSRSB_E_NOMEM;
     launch_xmap_build(c, s);
     // chunk tables of the support lists.  Galerkin rows: the shortest chunk
     // (more wavefronts) whose partial rows fit the stage's partial-row bytes

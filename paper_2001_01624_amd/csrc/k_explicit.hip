@@ -22,9 +22,11 @@ __global__ void k_xinit(int N, int ns, const int32_t *__restrict__ sb, const int
 
 // Neighbour slot maps (once per stage; the structure does not change): the
 // slot count of every cell, and for face q (axis q/2, +/- as q%2) and slot s
-// of cell i the slot of the same block in the face neighbour's list, or 255.
+// of cell i the slot of the same block in the face neighbour's list, or none:
+// byte map[(q ns + s) N + i] (255: none), or with at most kXNibSlots slots
+// nibble s of the word nib[q N + i] (15: none).
 __global__ void k_xmap_build(Fine g, int ns, const int32_t *__restrict__ sb, uint8_t *__restrict__ cnt,
-                             uint8_t *__restrict__ map) {
+                             uint8_t *__restrict__ map, uint64_t *__restrict__ nib) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.N) return;
     const long N = g.N;
@@ -37,6 +39,7 @@ __global__ void k_xmap_build(Fine g, int ns, const int32_t *__restrict__ sb, uin
         const int step = a == 0 ? 1 : (a == 1 ? g.nx : g.nxy);
         const int l = (q & 1) ? i + step : i - step;
         const bool in = (q & 1) ? l < g.N : i >= step;
+        uint64_t w = 0;
         for (int s = 0; s < ns; ++s) {
             int u = 255;
             if (in && s < c) {
@@ -50,7 +53,12 @@ __global__ void k_xmap_build(Fine g, int ns, const int32_t *__restrict__ sb, uin
                     }
                 }
             }
-            map[(size_t)(q * ns + s) * N + i] = (uint8_t)u;
+            if (nib) w |= (uint64_t)(u == 255 ? 15 : u) << (4 * s);
+            else map[(size_t)(q * ns + s) * N + i] = (uint8_t)u;
+        }
+        if (nib) {
+            for (int s = ns; s < 16; ++s) w |= (uint64_t)15 << (4 * s);
+            nib[(size_t)q * N + i] = w;
         }
     }
 }
@@ -58,15 +66,17 @@ __global__ void k_xmap_build(Fine g, int ns, const int32_t *__restrict__ sb, uin
 void launch_xmap_build(Ctx &c, Stage &s) {
     Fine g{c.nx, c.ny, c.nz, c.nx * c.ny, c.N, c.tx, c.ty, c.tz, c.diag};
     hipLaunchKernelGGL(k_xmap_build, dim3(cdiv(c.N, kBlock)), dim3(kBlock), 0, c.stream, g, s.ns, s.xsb, s.xcnt,
-                       s.xnmap);
+                       s.xnmap, s.xnib);
 }
 
 // One restricted-smoothing sweep (same definition as the rectilinear one):
 // the neighbour's value of block j is read at the slot the neighbour slot map
 // gives (each face adds to a slot at most once, faces in a fixed order).
-template <int NSX, typename PT>
+// NIB: the packed map, one word per face, all six loaded before the first
+// gather; else the byte map.
+template <int NSX, typename PT, bool NIB>
 __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const uint8_t *__restrict__ cntv,
-                                                   const uint8_t *__restrict__ nmap,
+                                                   const uint8_t *__restrict__ nmap, const uint64_t *__restrict__ nib,
                                                    const PT *__restrict__ tx, const PT *__restrict__ ty,
                                                    const PT *__restrict__ tz, const PT *__restrict__ Pin,
                                                    PT *__restrict__ Pout, PT omega, double *__restrict__ part,
@@ -88,6 +98,11 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const uint8_t
             for (int s = 0; s < ns; ++s) Pout[s * N + i] = (PT)0;
         } else {
             PT db = (PT)0;
+            uint64_t wq[6];
+            if (NIB) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) wq[q] = nib[(size_t)q * N + i];
+            }
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const int a = q >> 1;
@@ -106,12 +121,20 @@ __global__ __launch_bounds__(kBlock) void k_xsweep(Fine g, int ns, const uint8_t
                 }
                 if (T == (PT)0) continue;
                 db += T;
-                const uint8_t *mq = nmap + (size_t)q * ns * N + i;
+                if (NIB) {
 #pragma unroll
-                for (int s = 0; s < NSX; ++s) {
-                    if (s >= cn) break;
-                    const int u = mq[(size_t)s * N];
-                    if (u != 255) acc[s] += T * Pin[u * N + l];
+                    for (int s = 0; s < NSX; ++s) {
+                        const int u = (int)(wq[q] >> (4 * s)) & 15;
+                        if (s < cn && u != 15) acc[s] += T * Pin[u * N + l];
+                    }
+                } else {
+                    const uint8_t *mq = nmap + (size_t)q * ns * N + i;
+#pragma unroll
+                    for (int s = 0; s < NSX; ++s) {
+                        if (s >= cn) break;
+                        const int u = mq[(size_t)s * N];
+                        if (u != 255) acc[s] += T * Pin[u * N + l];
+                    }
                 }
             }
             const PT idb = db > (PT)0 ? (PT)1 / db : (PT)0;
@@ -151,15 +174,17 @@ static int xsweep_dispatch(Ctx &c, Stage &s, const PT *tx, const PT *ty, const P
     const PT om = (PT)c.opt.omega;
     const int *done = &c.status->done;
     double *part = c.partial;
-    if (s.ns <= 8)
-        hipLaunchKernelGGL((k_xsweep<8, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out, om, part,
-                           c.flag, done);
-    else if (s.ns <= 16)
-        hipLaunchKernelGGL((k_xsweep<16, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out, om, part,
-                           c.flag, done);
-    else
-        hipLaunchKernelGGL((k_xsweep<kMaxXSlots, PT>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, tx, ty, tz, in, out,
-                           om, part, c.flag, done);
+#define MSRSB_XSW(NSX, NIB)                                                                                    \
+    hipLaunchKernelGGL((k_xsweep<NSX, PT, NIB>), grid, blk, 0, c.stream, g, s.ns, s.xcnt, s.xnmap, s.xnib, tx, ty, \
+                       tz, in, out, om, part, c.flag, done)
+    if (s.xnib) {
+        if (s.ns <= 8) MSRSB_XSW(8, true);
+        else MSRSB_XSW(16, true);
+    } else {
+        if (s.ns <= 16) MSRSB_XSW(16, false);
+        else MSRSB_XSW(kMaxXSlots, false);
+    }
+#undef MSRSB_XSW
     return (int)grid.x;
 }
 

@@ -17,6 +17,7 @@ constexpr int kRedBlocks = 2048;   // fixed grid of the norm/dot kernels (determ
 constexpr int kTile = 64;          // coarse inverse tile / panel width
 constexpr int kMaxRestart = 64;
 constexpr int kMaxXSlots = 32;   // slots per cell of an explicit (fault-cut) stage
+constexpr int kXNibSlots = 15;   // explicit stages up to this many slots keep packed neighbour maps
 constexpr int kMaxXBlocks = 32768;  // blocks of an explicit stage (dense coarse operator)
 constexpr int kXChunk = 2048;    // support-list entries per restriction workgroup (explicit stages)
 constexpr int kXRapChunk = 8192; // support-list entries per Galerkin-row wavefront (at most)
@@ -96,6 +97,9 @@ struct Stage {
     // per cell: its slot count, and for each of its six faces and each of its
     // slots the slot of the same block in the face neighbour's list (255: none)
     uint8_t *xcnt = nullptr, *xnmap = nullptr;
+    // the same maps packed four bits per slot, one word per cell and face
+    // (15: none), for stages of at most kXNibSlots slots (xnmap is then null)
+    uint64_t *xnib = nullptr;
     uint8_t *xslot = nullptr;
     // the support lists cut into chunks of at most kXChunk entries (restriction)
     // and kXRapChunk entries (Galerkin rows): block of each chunk, first chunk
