@@ -734,6 +734,9 @@ static int explicit_stage_tables(Ctx &c, Stage &s, int M, const std::vector<std:
     if (!upi(s.xcblk, cblk) || !upi(s.xcfirst, cfirst) || !upi(s.xrcblk, rcblk) || !upi(s.xrcfirst, rcfirst) ||
         !upi(s.xrrow, rrow))
         return MSRSB_E_NOMEM;
+    s.nxent = cnt[M];
+    s.xplist = ctx_alloc(c, (size_t)std::max(cnt[M], 1) * (c.opt.precision == MSRSB_MIXED ? 2 : 8));
+    if (!s.xplist) return MSRSB_E_NOMEM;
     s.xpart = (double *)ctx_alloc(c, sizeof(double) * (size_t)s.nxch);
     s.xrpart = (double *)ctx_alloc(c, sizeof(double) * std::max<size_t>((size_t)nrow * s.Mp, 1));
     if (!s.xpart || !s.xrpart) return MSRSB_E_NOMEM;
@@ -1306,6 +1309,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             b += (o.precision == MSRSB_MIXED ? nsN * 10 : nsN * 16) + nsN * 9 + N * 4 + 16 * (size_t)Mp * Mp + 16 * Mp;
             b += 6 * nsN + N;  // neighbour slot maps
             b += xrap_part_bytes(nsN, Mp) + (nsN / kXChunk + M) * 8;  // chunk partials
+            b += nsN * 8;  // basis values in list order
             cb = std::max(cb, Mp);
             continue;
         }
@@ -1315,6 +1319,7 @@ size_t msrsb_footprint_bytes(const msrsb_grid *g, int n_part, const msrsb_partit
             const long Mf = 2L * pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];
             b += (size_t)16 * 8 * N;  // slot tables, lists (16 slots)
             b += (size_t)6 * 16 * N + N;  // neighbour slot maps
+            b += (size_t)16 * N * 8;      // basis values in list order
             b += xrap_part_bytes((size_t)16 * N, (long)cdiv(Mf, kTile) * kTile) + (16 * N / kXChunk + Mf) * 8;
         }
         long M = (long)pk.coarse_dims[0] * pk.coarse_dims[1] * pk.coarse_dims[2];

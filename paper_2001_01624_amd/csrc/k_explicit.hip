@@ -203,16 +203,37 @@ int launch_xsweep(Ctx &c, Stage &s, int in, int out) {
     return xsweep_dispatch<double>(c, s, c.tx, c.ty, c.tz, s.P64[in], s.P64[out]);
 }
 
+// The basis value of every support-list entry in list order: Pl[k] =
+// P[slot[k] N + cell[k]] (after each run of sweeps), so that the
+// restriction reads the values of a block contiguously.
+template <typename PS>
+__global__ void k_xlist(int n, long N, const int32_t *__restrict__ cell, const uint8_t *__restrict__ slot,
+                        const PS *__restrict__ P, PS *__restrict__ Pl) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) Pl[k] = P[(long)slot[k] * N + cell[k]];
+}
+
+void launch_xlist(Ctx &c, Stage &s) {
+    const int n = s.nxent;
+    if (n <= 0) return;
+    if (c.opt.precision == MSRSB_MIXED)
+        hipLaunchKernelGGL(k_xlist<uint16_t>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, (long)c.N,
+                           s.xcell, s.xslot, s.Pbf, (uint16_t *)s.xplist);
+    else
+        hipLaunchKernelGGL(k_xlist<double>, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, (long)c.N, s.xcell,
+                           s.xslot, s.P64[s.cur], (double *)s.xplist);
+}
+
 // d_j = sum over the support list of block j of P_ij r_i, in two fixed-order
 // passes: one workgroup per chunk of at most kXChunk list entries (a block
 // whose support spans the grid is spread over many workgroups), then one
-// thread per block adds its chunks in order.
+// thread per block adds its chunks in order.  The basis values come from the
+// list-ordered copy (contiguous per block).
 template <typename PS>
-__global__ __launch_bounds__(kBlock) void k_xrestrict(int N, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(kBlock) void k_xrestrict(const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ cblk,
                                                       const int32_t *__restrict__ cfirst,
-                                                      const int32_t *__restrict__ cell,
-                                                      const uint8_t *__restrict__ slot, const PS *__restrict__ P,
+                                                      const int32_t *__restrict__ cell, const PS *__restrict__ Pl,
                                                       const double *__restrict__ r, double *__restrict__ part,
                                                       const int *done) {
     __shared__ double lds[kBlock / 64];
@@ -220,10 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_xrestrict(int N, const int32_t *__re
     const int ch = blockIdx.x, j = cblk[ch];
     const int k0 = ptr[j] + (ch - cfirst[j]) * kXChunk, k1 = min(k0 + kXChunk, ptr[j + 1]);
     double acc = 0.0;
-    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-        const int i = cell[k];
-        acc += ld_basis(P, (long)slot[k] * N + i) * r[i];
-    }
+    for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) acc += ld_basis(Pl, (long)k) * r[cell[k]];
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part[ch] = s;
 }
@@ -256,11 +274,11 @@ __global__ __launch_bounds__(kBlock) void k_xprolong(int N, int ns, const int32_
 
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done) {
     if (c.opt.precision == MSRSB_MIXED)
-        hipLaunchKernelGGL(k_xrestrict<uint16_t>, dim3(s.nxch), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcblk,
-                           s.xcfirst, s.xcell, s.xslot, s.Pbf, r, s.xpart, done);
+        hipLaunchKernelGGL(k_xrestrict<uint16_t>, dim3(s.nxch), dim3(kBlock), 0, c.stream, s.xptr, s.xcblk, s.xcfirst,
+                           s.xcell, (const uint16_t *)s.xplist, r, s.xpart, done);
     else
-        hipLaunchKernelGGL(k_xrestrict<double>, dim3(s.nxch), dim3(kBlock), 0, c.stream, c.N, s.xptr, s.xcblk,
-                           s.xcfirst, s.xcell, s.xslot, s.P64[s.cur], r, s.xpart, done);
+        hipLaunchKernelGGL(k_xrestrict<double>, dim3(s.nxch), dim3(kBlock), 0, c.stream, s.xptr, s.xcblk, s.xcfirst,
+                           s.xcell, (const double *)s.xplist, r, s.xpart, done);
     hipLaunchKernelGGL(k_xrestrict_finish, dim3(cdiv(s.M, kBlock)), dim3(kBlock), 0, c.stream, s.M, s.xcfirst, s.xpart,
                        s.dvec, done);
 }
@@ -294,7 +312,7 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
                                              const int32_t *__restrict__ ptr, const int32_t *__restrict__ rcblk,
                                              const int32_t *__restrict__ rcfirst, const int32_t *__restrict__ rrow,
                                              const int32_t *__restrict__ cell,
-                                             const uint8_t *__restrict__ slot, const PS *__restrict__ P,
+                                             const PS *__restrict__ Pl, const PS *__restrict__ P,
                                              const double *__restrict__ bcdiag, double *__restrict__ Ac,
                                              double *__restrict__ rpart, int Mp, int chunk) {
     extern __shared__ double srow[];
@@ -333,7 +351,7 @@ __global__ __launch_bounds__(64) void k_xrap(Fine g, int ns, const int32_t *__re
             la[t] = t < ns ? sb[(long)t * N + a] : -1;
             pa[t] = t < ns ? ld_basis(P, (long)t * N + a) : 0.0;
         }
-        const double Paj = live ? ld_basis(P, (long)slot[k] * N + a) : 0.0;
+        const double Paj = live ? ld_basis(Pl, (long)k) : 0.0;
         // the lane's contributions to the columns of a's own slots, summed
         // over the boundary term and the six faces before one commit per slot
         double acc[NSX];
@@ -456,8 +474,8 @@ void launch_xrap(Ctx &c, Stage &s) {
     const size_t lds = sizeof(double) * (size_t)s.Mp;
 #define MSRSB_XRAP1(NSX, PS, PP, L)                                                                             \
     hipLaunchKernelGGL((k_xrap<NSX, PS, L>), dim3(s.nxrch), dim3(64), L ? lds : 0, c.stream, g, s.ns, s.xsb,     \
-                       s.xptr, s.xrcblk, s.xrcfirst, s.xrrow, s.xcell, s.xslot, PP, c.bcdiag, s.Ac, s.xrpart, s.Mp,  \
-                       s.xrchunk)
+                       s.xptr, s.xrcblk, s.xrcfirst, s.xrrow, s.xcell, (const PS *)s.xplist, PP, c.bcdiag, s.Ac,    \
+                       s.xrpart, s.Mp, s.xrchunk)
 #define MSRSB_XRAP(PS, PP, L)                                \
     {                                                        \
         if (s.ns <= 8) MSRSB_XRAP1(8, PS, PP, L);            \

@@ -592,6 +592,7 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
         const long n = (long)s.ns * c.N;
         hipLaunchKernelGGL(k_to_bf16, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, c.stream, n, s.P32[s.cur], s.Pbf);
     }
+    if (s.kind == 2) launch_xlist(c, s);
     s.sweeps = done_sweeps;
     s.change = last;
     if (sweeps) *sweeps = done_sweeps;

@@ -100,6 +100,10 @@ struct Stage {
     // the same maps packed four bits per slot, one word per cell and face
     // (15: none), for stages of at most kXNibSlots slots (xnmap is then null)
     uint64_t *xnib = nullptr;
+    // the basis value of every support-list entry, in list order (working
+    // precision of the transfers: BF16 or FP64), rebuilt after each sweep run
+    void *xplist = nullptr;
+    int nxent = 0;                // support-list entries
     uint8_t *xslot = nullptr;
     // the support lists cut into chunks of at most kXChunk entries (restriction)
     // and kXRapChunk entries (Galerkin rows): block of each chunk, first chunk
@@ -290,6 +294,7 @@ int launch_xsweep(Ctx &c, Stage &s, int in, int out);
 void launch_xrestrict(Ctx &c, Stage &s, const double *r, const int *done);
 void launch_xprolong(Ctx &c, Stage &s, double *x, const int *done);
 void launch_xrap(Ctx &c, Stage &s);
+void launch_xlist(Ctx &c, Stage &s);
 
 // ---- finite-volume restriction and flux reconstruction (k_fv.hip) ----
 constexpr int kFvMaxCells = 8192;  // cells of one block in the local solves (LDS-resident direction)
