@@ -393,12 +393,33 @@ static int build_cart_stage(Ctx &c, const msrsb_partition &p, Stage &s) {
     // blocks with active cells, compacted in Cartesian order; active cells per block
     const int M0 = cd.m[0] * cd.m[1] * cd.m[2];
     std::vector<int64_t> cnt(M0, 0);
-    for (int i = 0; i < c.N; ++i) {
-        if (!c.h_active[i]) continue;
-        const int cx = i % c.nx, cy = (i / c.nx) % c.ny, cz = i / (c.nx * c.ny);
-        const int J = (int)((long)cx * cd.m[0] / c.nx) + cd.m[0] * ((int)((long)cy * cd.m[1] / c.ny) +
-                                                                    cd.m[1] * (int)((long)cz * cd.m[2] / c.nz));
-        cnt[J]++;
+    {
+        // block of each coordinate per axis (floor(i m / n)); a full box has
+        // the product of the block widths in every block
+        std::vector<int32_t> bax[3];
+        for (int a = 0; a < 3; ++a) {
+            bax[a].resize(n[a]);
+            for (int i = 0; i < n[a]; ++i) bax[a][i] = (int32_t)(((long)i * cd.m[a]) / n[a]);
+        }
+        if (c.n_active == c.N) {
+            std::vector<int64_t> w[3];
+            for (int a = 0; a < 3; ++a) {
+                w[a].assign(cd.m[a], 0);
+                for (int i = 0; i < n[a]; ++i) w[a][bax[a][i]]++;
+            }
+            for (int J2 = 0; J2 < cd.m[2]; ++J2)
+                for (int J1 = 0; J1 < cd.m[1]; ++J1)
+                    for (int J0 = 0; J0 < cd.m[0]; ++J0)
+                        cnt[J0 + cd.m[0] * (J1 + cd.m[1] * J2)] = w[0][J0] * w[1][J1] * w[2][J2];
+        } else {
+            const uint8_t *act = c.h_active.data();
+            for (int z = 0, i = 0; z < c.nz; ++z)
+                for (int y = 0; y < c.ny; ++y) {
+                    const int Jyz = cd.m[0] * (bax[1][y] + cd.m[1] * bax[2][z]);
+                    for (int x = 0; x < c.nx; ++x, ++i)
+                        if (act[i]) cnt[bax[0][x] + Jyz]++;
+                }
+        }
     }
     const int cmap_off = (int)tab.size();
     s.h_present.clear();
@@ -1375,7 +1396,6 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
     std::vector<double> src(N, 0.0);
     if (g->source)
         for (int i = 0; i < N; ++i) src[i] = c->h_active[i] ? g->source[i] : 0.0;
-    std::vector<float> t32(N);
     auto fail = [&](int code) {
         msrsb_destroy(c);
         return code;
@@ -1384,14 +1404,12 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         dst = (double *)ctx_alloc(*c, sizeof(double) * N);
         return dst && upload(*c, dst, h, sizeof(double) * N);
     };
-    std::vector<float> t32b(N), t32c(N);
-    std::vector<float> *t32s[3] = {&t32, &t32b, &t32c};
-    int n32 = 0;
-    auto up32 = [&](float *&dst, const double *h) -> bool {
-        std::vector<float> &t = *t32s[n32++];  // one host buffer per array, alive until the set-up's final wait
-        for (int i = 0; i < N; ++i) t[i] = (float)h[i];
+    // FP32 copies converted on the device (round to nearest, as on the host)
+    auto dev32 = [&](float *&dst, const double *d) -> bool {
         dst = (float *)ctx_alloc(*c, sizeof(float) * N);
-        return dst && upload(*c, dst, t.data(), sizeof(float) * N);
+        if (!dst) return false;
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, c->stream, (long)N, d, dst);
+        return true;
     };
     // the set-up's buffers come from one arena of the estimated set-up size
     {
@@ -1408,8 +1426,8 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         c->arena_open = true;
     }
     if (!up(c->tx, g->tx) || !up(c->ty, g->ty) || !up(c->tz, g->tz) || !up(c->bcdiag, bcd.data()) ||
-        !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !up32(c->tx32, g->tx) || !up32(c->ty32, g->ty) ||
-        !up32(c->tz32, g->tz))
+        !up(c->bcrhs, bcr.data()) || !up(c->src, src.data()) || !dev32(c->tx32, c->tx) || !dev32(c->ty32, c->ty) ||
+        !dev32(c->tz32, c->tz))
         return fail(MSRSB_E_NOMEM);
     auto dalloc = [&](size_t bytes) { return ctx_alloc(*c, bytes); };
     c->diag = (double *)dalloc(8 * (size_t)N);
