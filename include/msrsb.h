@@ -29,7 +29,9 @@
  *    default memory pool: at setup one arena of about msrsb_footprint_bytes
  *    that the set-up buffers are carved from (anything beyond it is
  *    allocated on its own), and further blocks when dynamic bases are added
- *    or a stage is exported.
+ *    or a stage is exported.  Pool arenas of destroyed contexts are kept
+ *    (at most 4 GiB per device, until the process ends) and reused by later
+ *    set-ups that need at least three quarters of one.
  */
 #ifndef MSRSB_H
 #define MSRSB_H
@@ -559,8 +561,9 @@ int msrsb_profile_end(msrsb_ctx *ctx, double *total_ms, int *launches);
 int msrsb_set_stream(msrsb_ctx *ctx, void *hip_stream);
 
 /* Synchronise the context's stream and return all its device memory to the
- * device's memory pool, in the stream's order (no device-wide
- * synchronisation; NULL is ignored). */
+ * device's memory pool (or to the caller's allocator), in the stream's order
+ * (no device-wide synchronisation; NULL is ignored); a pool arena may
+ * instead be kept for a later set-up (see the conventions above). */
 void msrsb_destroy(msrsb_ctx *ctx);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -86,6 +86,47 @@ static void raw_free(Ctx &c, void *p, size_t bytes) {
     else (void)hipFreeAsync(p, c.stream);
 }
 
+// Set-up arenas of destroyed contexts (pool memory only) are kept per device
+// for the next set-ups: for contexts of a few MB the pool's own allocation
+// and stream-ordered free cost 0.02-0.9 ms each, as much as the rest of the
+// set-up.  At most kArenaCacheBytes per device are held (until the process
+// ends); an arena is reused by a set-up that needs at least 3/4 of it.
+constexpr size_t kArenaCacheBytes = (size_t)4 << 30;
+struct CachedArena {
+    int device;
+    size_t bytes;
+    void *p;
+};
+static std::mutex g_arena_mu;
+static std::vector<CachedArena> g_arenas;
+
+static void *arena_take(int device, size_t need, size_t *got) {
+    std::lock_guard<std::mutex> lock(g_arena_mu);
+    size_t best = g_arenas.size();
+    for (size_t k = 0; k < g_arenas.size(); ++k) {
+        const CachedArena &a = g_arenas[k];
+        if (a.device == device && a.bytes >= need && a.bytes / 4 * 3 <= need &&
+            (best == g_arenas.size() || a.bytes < g_arenas[best].bytes))
+            best = k;
+    }
+    if (best == g_arenas.size()) return nullptr;
+    void *p = g_arenas[best].p;
+    *got = g_arenas[best].bytes;
+    g_arenas.erase(g_arenas.begin() + best);
+    return p;
+}
+
+// true: the cache keeps the (idle) arena
+static bool arena_give(int device, void *p, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_arena_mu);
+    size_t held = 0;
+    for (const CachedArena &a : g_arenas)
+        if (a.device == device) held += a.bytes;
+    if (held + bytes > kArenaCacheBytes) return false;
+    g_arenas.push_back({device, bytes, p});
+    return true;
+}
+
 void *ctx_alloc(Ctx &c, size_t bytes) {
     if (bytes == 0) bytes = 8;
     const size_t rb = (bytes + 255) & ~(size_t)255;
@@ -1416,10 +1457,18 @@ int msrsb_setup(const msrsb_grid *g, int n_part, const msrsb_partition *parts, c
         const size_t est = msrsb_footprint_bytes(g, n_part, parts, &o);
         if (est > 0) {
             const size_t sz = est + est / 32 + ((size_t)1 << 20);
-            void *a = raw_alloc(*c, sz);  // on failure the buffers are allocated one by one
+            size_t got = 0;
+            void *a = c->ua.alloc ? nullptr : arena_take(c->device, sz, &got);
+            if (a) {
+                c->allocs.push_back(a);
+                c->alloc_bytes.push_back(got);
+            } else {
+                got = sz;
+                a = raw_alloc(*c, sz);  // on failure the buffers are allocated one by one
+            }
             if (a) {
                 c->arena = (char *)a;
-                c->arena_size = sz;
+                c->arena_size = got;
             }
             g_err.clear();
         }
@@ -2282,7 +2331,12 @@ int msrsb_set_stream(msrsb_ctx *c, void *hip_stream) {
 void msrsb_destroy(msrsb_ctx *c) {
     if (!c) return;
     hipStreamSynchronize(c->stream);
-    for (size_t k = 0; k < c->allocs.size(); ++k) raw_free(*c, c->allocs[k], c->alloc_bytes[k]);
+    for (size_t k = 0; k < c->allocs.size(); ++k) {
+        if (!c->ua.alloc && c->allocs[k] == (void *)c->arena &&
+            arena_give(c->device, c->allocs[k], c->alloc_bytes[k]))
+            continue;  // idle after the synchronisation: kept for the next set-up
+        raw_free(*c, c->allocs[k], c->alloc_bytes[k]);
+    }
     for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
     release_pinned_status(c->h_status);
     delete c;
