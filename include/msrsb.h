@@ -318,8 +318,9 @@ int msrsb_solve_async(msrsb_ctx *ctx, const double *d_source, double *d_p, doubl
  * ILU(0) smoother with columns of at most 512 cells, and the same
  * precision, omega and restart as the others.  The members' streams are
  * switched to `hip_stream` (hipStream_t, NULL = null stream; each member's
- * old stream is synchronised first) and stay on it.  Errors: E_INVAL (with
- * the offending member in the message), E_NOMEM, E_DEVICE.
+ * old stream is synchronised first) and stay on it after the batch is
+ * destroyed (a failed create leaves them on their own).  Errors: E_INVAL
+ * (with the offending member in the message), E_NOMEM, E_DEVICE.
  *
  * msrsb_batch_update_basis: builds every member's basis from scratch (up to
  * max_sweeps sweeps each, member-wise stop at tol as in msrsb_update_basis

@@ -204,12 +204,14 @@ int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb
     B->mem = mem;
     B->h_mem.resize(n);
     int rc = MSRSB_OK;
+    std::vector<hipStream_t> old(n);  // restored if the batch is not made
+    for (int k = 0; k < n; ++k) old[k] = mem[k]->stream;
     for (int k = 0; k < n && !rc; ++k) {
         Ctx &c = *mem[k];
         if (c.stream != B->stream) {
             hipError_t e = hipStreamSynchronize(c.stream);
             if (e != hipSuccess) rc = hip_fail(e, "member stream");
-            c.stream = B->stream;
+            else c.stream = B->stream;
         }
     }
     // launch groups
@@ -308,6 +310,8 @@ int msrsb_batch_create(int n, msrsb_ctx *const *members, void *hip_stream, msrsb
         if (!rc) rc = upload_members(*B);
     }
     if (rc) {
+        (void)hipStreamSynchronize(B->stream);
+        for (int k = 0; k < n; ++k) mem[k]->stream = old[k];
         free_batch(B);
         return rc;
     }
