@@ -22,8 +22,9 @@ struct BMember {
     CartDev cd;                    // the member's rectilinear stage
     int M, Mp, ns;
     int G, GA;                     // reduction grid, pass-A grid of the Arnoldi step
-    // sweep geometry of the batched sweep (one z chunk per column group)
-    int s_nxt, s_ngy, s_nblk, check_blocks;
+    // sweep geometry of the batched sweep: x tiles, row groups, z chunks and
+    // their length, workgroups
+    int s_nxt, s_ngy, s_nzc, s_zc, s_nblk, check_blocks;
     // z-line ILU(0) register path
     int l_hx, l_ncol, l_cw, l_nch, l_L;
     long l_S;

@@ -602,8 +602,15 @@ int launch_sweeps(Ctx &c, Stage &s, int max_sweeps, double tol, bool warm, int *
 // ------------------------------------------------------- batched launches ----
 // Cold basis construction of every member's rectilinear stage: one launch per
 // sweep (per split-axis mask) over all members, the stop rule per member.  A
-// batched sweep walks whole columns (one z chunk per column group); a sweep's
+// batched sweep walks each column in a few chunks; a sweep's
 // values do not depend on the chunks, and its change is a maximum.
+
+// z chunks per column group of a batched sweep (FP64 rows come four to a
+// workgroup, FP32 rows eight: the FP32 form has half as many workgroups)
+template <typename PT>
+constexpr int batch_sweep_zchunks() {
+    return sizeof(PT) == 8 ? 1 : 2;
+}
 
 // sweep grid and key (split-axis mask) of a member; fills its sweep geometry
 int bat_member_sweep(const Ctx &c, const Stage &s, BMember &d, int *key) {
@@ -613,7 +620,11 @@ int bat_member_sweep(const Ctx &c, const Stage &s, BMember &d, int *key) {
     const int rows = c.opt.precision == MSRSB_MIXED ? sweep_rows<float>() : sweep_rows<double>();
     d.s_nxt = cdiv(c.nx, 64);
     d.s_ngy = cdiv(c.ny, rows);
-    d.s_nblk = d.s_nxt * d.s_ngy;
+    const int nzc = std::min(c.nz, c.opt.precision == MSRSB_MIXED ? batch_sweep_zchunks<float>()
+                                                                   : batch_sweep_zchunks<double>());
+    d.s_zc = cdiv(c.nz, nzc);
+    d.s_nzc = cdiv(c.nz, d.s_zc);
+    d.s_nblk = d.s_nzc * d.s_nxt * d.s_ngy;
     d.check_blocks = (int)s.h_present.size() != s.cart.m[0] * s.cart.m[1] * s.cart.m[2];
     *key = am;
     return xcd_grid(d.s_nblk);
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(64 * sweep_rows<PT>()) void k_sweep_b(const BMember
     sweep_body<AM, PT, sweep_rows<PT>()>(lb, nb, d.cd, d.g, (const PT *)d.wtx, (const PT *)d.wty, (const PT *)d.wtz,
                                          (const PT *)d.P[in], (PT *)d.P[in ^ 1], omega,
                                          d.partial + (size_t)q * kSweepPartStride, d.flag + q, d.check_blocks,
-                                         &d.status->done, d.s_nxt, d.s_ngy, 1, d.g.nz, d.s_nblk,
+                                         &d.status->done, d.s_nxt, d.s_ngy, d.s_nzc, d.s_zc, d.s_nblk,
                                          (const unsigned long long *)d.cd.xmask, d.cd.pack[1], d.cd.pack[2]);
 }
 
