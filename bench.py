@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1200)
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched ensemble (also skipped by --no-serve)")
     ap.add_argument("--ensemble-members", type=int, default=256)
+    ap.add_argument("--ensemble-batch-only", action="store_true",
+                    help="profiling aid: run only the batched ensemble (set-up on one thread) and print its record")
     ap.add_argument("--no-static", action="store_true", help="skip the static-stage (well, indicator) leg")
     ap.add_argument("--no-fv", action="store_true", help="skip the finite-volume leg")
     ap.add_argument("--no-twophase", action="store_true", help="skip the two-phase CPR leg")
@@ -560,7 +562,7 @@ def ensemble_leg(args):
         for rep in range(2):  # the second run is reported (the first pages in code and pool memory)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            with ThreadPoolExecutor(8) as ex:
+            with ThreadPoolExecutor(1 if args.ensemble_batch_only else 8) as ex:
                 gs = list(ex.map(lambda r: capi.Solver(r.problem, r.partitions, opt, stream=stream), reqs))
             xs = [torch.zeros(g.N, dtype=torch.float64, device="cuda") for g in gs]
             qs = [torch.as_tensor(r.sources[0]).to("cuda") for r in reqs]
@@ -581,6 +583,9 @@ def ensemble_leg(args):
                    "iters_mean": float(np.mean(it)), "iters_max": int(max(it)), "sweeps_max": int(max(sweeps)),
                    "all_converged": all(s == 0 for s in st), "max_relres": float(max(rel))}
         sols[prec] = x_host
+        if args.ensemble_batch_only:
+            out[prec] = {"batched": rec}
+            continue
         reqs = ensemble_batch(args.ensemble_members, seed=0)
         pipe = run_ensemble(reqs, opt, chunk=64, threads=8, rtol=RTOL)
         rec["pipelined_end_to_end"] = {"cells_per_s": pipe["cells_per_s"], "makespan_s": pipe["makespan_s"],
@@ -732,6 +737,10 @@ def main():
     if args.faulted_only:
         rec = faulted_leg(args)
         print(json.dumps({"leg": "faulted", "metric": METRIC, **rec}))
+        return
+    if args.ensemble_batch_only:
+        rec = ensemble_leg(args)
+        print(json.dumps({"leg": "ensemble_batch", **rec}))
         return
     if args.extras_only:
         for name, fn, skip in (("static", static_leg, args.no_static), ("fv", fv_leg, args.no_fv),
