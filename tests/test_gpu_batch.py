@@ -5,8 +5,8 @@ are compared with the same member solved on its own context, bit for bit:
 the batched kernels run the single-context kernel bodies on each member's own
 grid, so any difference is a defect.  The members span the launch shapes the
 batch groups by (rows of at most / more than 64 cells, coarse GEMV widths,
-Arnoldi steps that do / do not sum their own partials, odd x sizes, inactive
-cells and dropped blocks).  The batch solutions also meet the tolerance on
+Arnoldi steps that do / do not sum their own partials, eight and four slots
+per cell, odd x sizes, a single layer, inactive cells and dropped blocks).  The batch solutions also meet the tolerance on
 the FP64 residual recomputed by the oracle."""
 import numpy as np
 import pytest
@@ -36,6 +36,9 @@ def members():
         (make_lognormal_box((33, 47, 16), rng_for(7, 4), sigma=2.0, corr=(2, 2, 2)), (4, 6, 4)),
         (make_config2(dims=(30, 44, 12), seed=3), (4, 5, 3)),
         (make_config1(dims=(20, 36, 14), seed=1), (4, 3, 2)),
+        # four slots per cell: no split along z (3-D and a single layer)
+        (make_lognormal_box((40, 30, 10), rng_for(7, 5), sigma=2.0, corr=(2, 2, 2)), (5, 3, 1)),
+        (make_lognormal_box((48, 40, 1), rng_for(7, 6), sigma=2.0, corr=(2, 2, 1)), (6, 5, 1)),
     ]
 
 
