@@ -187,3 +187,37 @@ def test_pipelined_ensemble_equals_alone(capi):
     for r, ra in zip(reqs, a):
         assert r.iters == ra["it"] and r.relres == ra["rel"]
         assert np.array_equal(r.solutions[0], ra["x"][0].cpu().numpy()), r.rid
+
+
+def test_batch_edge_cases(capi):
+    # a batch of one member; no sweeps (the indicator basis); no iterations
+    # (the initial residual only); then an ordinary solve: each as alone
+    prob, cd = members()[3]
+    q = source_sequence(prob, rng_for(8, 40), 1)[0]
+    opt = capi.default_options(smoother="ilu0_line", outer="gmres", precision="fp64", restart=16)
+    parts = [{"kind": "cartesian", "coarse_dims": cd}]
+    res = {}
+    for mode in ("alone", "batch"):
+        g = capi.Solver(prob, parts, opt)
+        x = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+        out = []
+        if mode == "alone":
+            sw, _ = g.update_basis(stage=0, max_sweeps=0, tol=1e-3)
+            out.append(g.solve(x, source=dev(q), rtol=1e-6, max_iters=0))
+            out.append(g.solve(x, source=None, rtol=1e-6, max_iters=400))
+        else:
+            B = capi.Batch([g])
+            sw = B.update_basis(max_sweeps=0, tol=1e-3)[0]
+            it, rel, st = B.solve([x], sources=[dev(q)], rtol=1e-6, max_iters=0)
+            out.append((it[0], rel[0], st[0]))
+            it, rel, st = B.solve([x], rtol=1e-6, max_iters=400)
+            out.append((it[0], rel[0], st[0]))
+            B.close()
+        torch.cuda.synchronize()
+        res[mode] = (sw, out, x.clone())
+        g.close()
+    a, b = res["alone"], res["batch"]
+    assert a[0] == b[0] == 0
+    assert a[1] == b[1], (a[1], b[1])
+    assert a[1][0][0] == 0 and a[1][0][2] == capi.E_NOCONV and a[1][1][2] == 0
+    assert torch.equal(a[2], b[2])
