@@ -221,3 +221,34 @@ def test_batch_edge_cases(capi):
     assert a[1] == b[1], (a[1], b[1])
     assert a[1][0][0] == 0 and a[1][0][2] == capi.E_NOCONV and a[1][1][2] == 0
     assert torch.equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ensemble_configuration_sampled(capi, precision):
+    # the benchmark's ensemble configuration (members of 32..128 x 32..128 x
+    # 8..16 cells, one 8x8x4 stage, GMRES(16), z-line ILU(0)) in one batch of
+    # 32 members; four sampled members solved alone give the same sweeps,
+    # iterations, residuals and solutions
+    from workloads.requests import ensemble_batch
+
+    reqs = ensemble_batch(32, seed=0)
+    opt = capi.default_options(smoother="ilu0_line", outer="gmres", precision=precision, restart=16)
+    gs = [capi.Solver(r.problem, r.partitions, opt) for r in reqs]
+    B = capi.Batch(gs)
+    sw = B.update_basis(max_sweeps=100, tol=1e-3)
+    xs = [torch.zeros(g.N, dtype=torch.float64, device="cuda") for g in gs]
+    it, rel, st = B.solve(xs, sources=[dev(r.sources[0]) for r in reqs], rtol=1e-6, max_iters=3000)
+    torch.cuda.synchronize()
+    B.close()
+    assert all(s == 0 for s in st)
+    for k in (0, 7, 15, 31):
+        g = capi.Solver(reqs[k].problem, reqs[k].partitions, opt)
+        swk, _ = g.update_basis(stage=0, max_sweeps=100, tol=1e-3)
+        x = torch.zeros(g.N, dtype=torch.float64, device="cuda")
+        itk, relk, rck = g.solve(x, source=dev(reqs[k].sources[0]), rtol=1e-6, max_iters=3000)
+        torch.cuda.synchronize()
+        assert (swk, itk, relk, rck) == (sw[k], it[k], rel[k], st[k]), k
+        assert torch.equal(x, xs[k]), k
+        g.close()
+    for g in gs:
+        g.close()
