@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Fine g, const double *__res
 // before) from the adjacent lanes, every load issued before the skip flag is
 // read.  Faces follow cell_faces (boundary faces carry T = 0 in the data), so
 // a lane at a row end may take its own x with the zero coefficient: the
-// operations and their order are those of residual_cell, bit for bit.
+// operations and their order are those of residual_cell.
 constexpr int kResRows = 4;  // rows (wavefronts) per workgroup
 
 __global__ __launch_bounds__(64 * kResRows) void k_residual_rows(Fine g, const double *__restrict__ b,

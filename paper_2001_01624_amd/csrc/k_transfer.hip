@@ -30,7 +30,8 @@ namespace msrsb {
 // Pass 2 (k_restrict_gather): d_J = sum over s, and over the layers z of the
 // dual interval J_z - s_z, of part[z, J_y - s_y, J_x - s_x, s] (fixed order).
 // RES: r is not read but formed per cell as b - A x, with the operations of
-// the residual kernel (so the restricted vector is the same bit for bit).
+// the residual kernel in the same order (the compiler's fused multiply-adds
+// may still round differently from a stored residual's).
 // W wavefronts per workgroup, U rows per wavefront in flight.  One workgroup
 // per (dual y-interval Ly, layer z), numbered with Ly fastest and spread over
 // the XCDs in contiguous ranges: the workgroups in flight on an XCD read
