@@ -280,6 +280,28 @@ __device__ inline TT xy_sum_r(const LineRegArgs<TT> &a, int i, int x, int y, int
     return s;
 }
 
+// Apply the chunk maps (sA, sB) of chunks c0, c0 + dir, ... (cnt of them,
+// dir = +1 or -1) in that order to v.  Eight maps are read from LDS before
+// the first is applied, so the walk waits on one LDS round trip per eight
+// chunks instead of one per chunk; the arithmetic and its order are those of
+// applying the maps one by one.
+template <typename TT>
+__device__ inline TT chunk_combine(const TT *sA, const TT *sB, int cw, int cl, int c0, int dir, int cnt, TT v) {
+    for (int base = 0; base < cnt; base += 8) {
+        TT ga[8], gb[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int c = c0 + dir * min(base + t, cnt - 1);
+            ga[t] = sA[c * cw + cl];
+            gb[t] = sB[c * cw + cl];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (base + t < cnt) v = ga[t] + gb[t] * v;
+    }
+    return v;
+}
+
 // PHASE 0: red forward (writes w = y / p); 1: black forward and backward
 // (writes z); 2: red backward (reads w, writes x of both colours).  Thread layout:
 // column slot cl = threadIdx % cw, chunk ch = threadIdx / cw.  A cell is
@@ -304,6 +326,7 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
     const int col = x + a.g.nx * y, nxy = a.g.nxy, nz = a.g.nz;
     auto layer = [&](int t) { return min(z0 + min(t, max(n - 1, 0)), nz - 1); };
     TT al[kLineLMax], be[kLineLMax], dv[kLineLMax];
+    TT bt[PHASE == 1 ? kLineLMax : 1];  // black: Tz/p, loaded with the forward operands
     TT v;
     if (PHASE <= 1) {
         // forward: y_k = al_k + be_k y_{k-1}
@@ -317,6 +340,7 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
             al[t] = s;
             be[t] = a.pc[kq + p];
             dv[t] = a.pd[kq + p];
+            if (PHASE == 1) bt[t] = a.pt[kq + p];
         }
         TT A = (TT)0, B = (TT)1;
 #pragma unroll
@@ -328,8 +352,7 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
         sA[threadIdx.x] = A;
         sB[threadIdx.x] = B;
         __syncthreads();
-        v = (TT)0;
-        for (int c = 0; c < ch; ++c) v = sA[c * a.cw + cl] + sB[c * a.cw + cl] * v;
+        v = chunk_combine(sA, sB, a.cw, cl, 0, 1, ch, (TT)0);
 #pragma unroll
         for (int t = 0; t < kLineLMax; ++t)
             if (t < n) {
@@ -340,6 +363,16 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
         if (PHASE == 0) return;
         __syncthreads();  // LDS reuse
     }
+    // x is updated in whole pairs {x, x ^ 1} of a row: the red pass writes
+    // its cell and the black partner (black slot p as well: x ^ 1 = 2j + 1 -
+    // par), so x is read and written once; the black pass writes x only
+    // where the partner lies outside the row (odd nx).  No other thread
+    // writes either cell of the pair, so the red pass loads the partner's z
+    // and, when adding, both cells' x together with its other operands.
+    const bool partner = (x ^ 1) < a.g.nx;
+    const int ib = partner ? (x ^ 1) + a.g.nx * y : col;
+    TT zp[PHASE == 2 ? kLineLMax : 1];
+    double xo[PHASE == 2 && !ASSIGN ? kLineLMax : 1], xq[PHASE == 2 && !ASSIGN ? kLineLMax : 1];
     // backward: z_k = al_k + be_k z_{k+1}, be_k = Tz_k / p_k
 #pragma unroll
     for (int t = 0; t < kLineLMax; ++t) {
@@ -349,10 +382,16 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
             const int i = col + nxy * k;
             dv[t] = a.pd[kq + p];
             al[t] = a.eself[kq + p] + dv[t] * xy_sum_r(a, i, x, y, j, par, kq);
+            be[t] = a.pt[kq + p];
+            zp[t] = a.eother[kq + p];
+            if (!ASSIGN) {
+                xo[t] = a.x[i];
+                xq[t] = a.x[ib + nxy * k];
+            }
         } else {
             al[t] = al[t] * dv[t];
+            be[t] = bt[PHASE == 1 ? t : 0];
         }
-        be[t] = a.pt[kq + p];
     }
     TT A = (TT)0, B = (TT)1;
 #pragma unroll
@@ -365,15 +404,8 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
     sB[threadIdx.x] = B;
     __syncthreads();
     if (!mine) return;
-    v = (TT)0;
-    for (int c = a.nch - 1; c > ch; --c) v = sA[c * a.cw + cl] + sB[c * a.cw + cl] * v;
-    // x is updated in whole pairs {x, x ^ 1} of a row: the red pass writes
-    // its cell and the black partner (black slot p as well: x ^ 1 = 2j + 1 -
-    // par), so x is read and written once; the black pass writes x only
-    // where the partner lies outside the row (odd nx).  A correction is
-    // exactly zero where 1/p is.
-    const bool partner = (x ^ 1) < a.g.nx;
-    const int ib = (x ^ 1) + a.g.nx * y;
+    v = chunk_combine(sA, sB, a.cw, cl, a.nch - 1, -1, a.nch - 1 - ch, (TT)0);
+    // A correction is exactly zero where 1/p is.
 #pragma unroll
     for (int t = kLineLMax - 1; t >= 0; --t)
         if (t < n) {
@@ -381,14 +413,16 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
             const size_t q = (size_t)(z0 + t) * a.ncol + p;
             const int i = col + nxy * (z0 + t);
             if (PHASE == 1) a.eself[q] = v;
-            if (PHASE == 2 || !partner) {
+            if (PHASE == 2) {
+                if (dv[t] != (TT)0) a.x[i] = ASSIGN ? (double)v : xo[PHASE == 2 && !ASSIGN ? t : 0] + (double)v;
+                else if (ASSIGN) a.x[i] = 0.0;
+                if (partner) {
+                    const double zb = (double)zp[t];
+                    a.x[ib + nxy * (z0 + t)] = ASSIGN ? zb : xq[PHASE == 2 && !ASSIGN ? t : 0] + zb;
+                }
+            } else if (!partner) {
                 if (dv[t] != (TT)0) a.x[i] = ASSIGN ? (double)v : a.x[i] + (double)v;
                 else if (ASSIGN) a.x[i] = 0.0;
-            }
-            if (PHASE == 2 && partner) {
-                const int i2 = ib + nxy * (z0 + t);
-                const double zb = (double)a.eother[q];
-                a.x[i2] = ASSIGN ? zb : a.x[i2] + zb;
             }
         }
 }
