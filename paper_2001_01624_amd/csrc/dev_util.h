@@ -47,6 +47,21 @@ __device__ inline double sum_partials(const double *__restrict__ p, int n, doubl
     return block_sum(s, lds);
 }
 
+// Sum of p[lane], p[lane + 64], ... (indices below n) in that order, as the
+// plain strided loop adds them, with eight loads issued before their adds.
+__device__ inline double lane_strided_sum(const double *__restrict__ p, int lane, int n) {
+    double v = 0.0;
+    for (int b0 = lane; b0 < n; b0 += 8 * 64) {
+        double t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = p[min(b0 + 64 * q, n - 1)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (b0 + 64 * q < n) v += t[q];
+    }
+    return v;
+}
+
 __device__ inline double block_max(double v, double *lds) {
     v = wave_max(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -1337,8 +1337,7 @@ __device__ __forceinline__ void dstep_body(Status *st, double *scal, int j, doub
     if (G > 0) {
         const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
         for (int q = wv; q < na; q += nwv) {
-            double v = 0.0;
-            for (int b = lane; b < G; b += 64) v += partial[(long)q * G + b];
+            double v = lane_strided_sum(partial + (long)q * G, lane, G);
             v = wave_sum(v);
             if (lane == 0) {
                 A[q] = v;
