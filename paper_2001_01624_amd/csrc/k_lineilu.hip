@@ -310,7 +310,12 @@ __device__ inline TT chunk_combine(const TT *sA, const TT *sB, int cw, int cl, i
 template <typename TT, int PHASE, bool ASSIGN>
 __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT> a, const int *done) {
     __shared__ TT sA[kLineThreads], sB[kLineThreads];
-    if (done && *done) return;
+    // The skip flag: the FP32 red backward pass reads it once its operands
+    // are in flight (every thread of the workgroup sees the same value, before
+    // any barrier); the other passes measured as fast or faster reading it
+    // first.
+    constexpr bool kLateSkip = sizeof(TT) == 4 && PHASE == 2;
+    if (!kLateSkip && done && *done) return;
     const int b = xcd_block(bid, nblk);
     if (b * a.cw >= a.ncol) return;
     const int cl = threadIdx.x % a.cw, ch = threadIdx.x / a.cw;
@@ -393,6 +398,7 @@ __device__ __forceinline__ void lilu_reg_body(int bid, int nblk, LineRegArgs<TT>
             be[t] = bt[PHASE == 1 ? t : 0];
         }
     }
+    if (kLateSkip && done && *done) return;
     TT A = (TT)0, B = (TT)1;
 #pragma unroll
     for (int t = kLineLMax - 1; t >= 0; --t)

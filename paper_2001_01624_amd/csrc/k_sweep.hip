@@ -118,7 +118,6 @@ __device__ __forceinline__ void sweep_body(int bid, int ngrid, CartDev cd, Fine 
     constexpr int NS = 1 << __builtin_popcount(AM);
     constexpr int SZ = sizeof(PT);
     __shared__ double lds[kSweepRows];
-    if (*done) return;
     const int b = xcd_block(bid, ngrid);
     if (b >= nblk) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz, nxy = g.nxy, N = g.N;
@@ -180,6 +179,7 @@ __device__ __forceinline__ void sweep_body(int bid, int ngrid, CartDev cd, Fine 
         Pm[s] = bload<PT>(rP, ib * SZ, s * NSZ);
     }
     const PT tzm0 = bload<PT>(rZ, (dir > 0 ? ib : i) * SZ, 0);
+    if (*done) return;  // read once the first layers are in flight, before any barrier
     PT tzm = hasb ? tzm0 : (PT)0;
     double chg = 0.0;
 
